@@ -1,0 +1,183 @@
+"""FP64 CPU oracle for the dynamical polarizability in the dominant-product basis.
+
+TEST INFRASTRUCTURE.  This package is the independent reference that the HIP
+path is checked against.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import it; the product path (the HIP library and its
+Python binding) never calls it, and it shares no code with that path.  Its
+inputs come from `paper_1005_5340_amd.synth`, which draws inputs only.
+
+Everything is plain NumPy in float64 / complex128, unblocked and unfused; the
+only library primitives are matrix products and a dense LU solve.
+
+What is computed, in the paper's notation (Koval, Foerster, Coulaud 2010):
+
+* Transition vertices (numerator of eq. response-mat, Sec. 3):
+      v_mu^{EF} = X_a^E V_mu^{ab} X_b^F.
+* Kohn-Sham response in the product basis (eq. response-mat, with the
+  occupation factors and the rule of eq. response-eig, Sec. 2, that only
+  pairs with one occupied and one virtual state contribute):
+      chi0_{mu nu}(w) = sum_{E,F} (n_F - n_E) v_mu^{EF} v_nu^{FE} / (w - (E - F) + i eps).
+  Taking both orders of each (occupied E, virtual F) pair and using
+  v^{EF} = v^{FE} (V symmetric) folds this into a sum over E occupied,
+  F virtual with the factor
+      L_EF(w) = n [1/(w - D_EF + i eps) - 1/(w + D_EF + i eps)],  D_EF = e_F - e_E > 0.
+* The response system (eq. sle, Sec. 4.1):
+      (1 - chi0(w) f) X(w) = chi0(w) d,    P(w) = d^mu X_mu(w)
+  solved here by a dense LU factorisation (no Krylov method).  The paper's
+  P = d.X is bilinear (no complex conjugate).
+
+Readings taken where the paper is silent (each listed in the design notes):
+  * the sign of the reported polarizability: alpha = -P, so that Im alpha >= 0
+    for w > 0 with the paper's chi0 convention (Im P <= 0 there);
+  * occupation factor n = 2 for occupied and 0 for virtual states (closed shell);
+  * energies are given already shifted so that occupied < 0 < virtual.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "occupations", "transition_energies", "lorentzian", "transition_vertices",
+    "chi0_matrix", "chi0_apply", "response_matrix", "solve_response",
+    "polarizability", "residual_norm",
+]
+
+
+def occupations(sys) -> np.ndarray:
+    """n_E: `occ_factor` for the n_occ lowest states, 0 otherwise (Sec. 2)."""
+    n = np.zeros(sys.n_orb)
+    n[:sys.n_occ] = sys.occ_factor
+    return n
+
+
+def transition_energies(sys) -> np.ndarray:
+    """D_EF = e_F - e_E for E occupied, F virtual; shape [N_occ, N_virt]."""
+    e = sys.eigenvalues
+    return e[None, sys.n_occ:] - e[:sys.n_occ, None]
+
+
+def lorentzian(omega: float, eps: float, delta: np.ndarray, n: float) -> np.ndarray:
+    """Folded resonant minus antiresonant factor of eq. response-mat (Sec. 3).
+
+    The (E occ, F virt) term carries (n_F - n_E) = -n over (w + D + i eps);
+    the mirrored (F, E) term carries +n over (w - D + i eps).
+    """
+    return n * (1.0 / (omega - delta + 1j * eps) - 1.0 / (omega + delta + 1j * eps))
+
+
+def transition_vertices(sys, occ=None) -> np.ndarray:
+    """v_mu^{EF} = X_a^E V_mu^{ab} X_b^F for E in `occ` (default all occupied), F virtual.
+
+    Returns [n_prod, len(occ), N_virt].  Only the AOs of product mu's support
+    carry a non-zero vertex (eq. vertex-ansatz), so the sums over a, b run
+    over that support.
+    """
+    occ = np.arange(sys.n_occ) if occ is None else np.asarray(occ)
+    X = sys.X
+    Xv_all = X[:, sys.n_occ:]
+    out = np.empty((sys.n_prod, occ.size, sys.n_orb - sys.n_occ))
+    for mu in range(sys.n_prod):
+        I = sys.support(mu)
+        V = sys.vertex(mu)
+        out[mu] = X[np.ix_(I, occ)].T @ V @ Xv_all[I, :]
+    return out
+
+
+def _occ_chunks(sys, max_bytes=1 << 29):
+    nv = sys.n_orb - sys.n_occ
+    per_e = max(1, sys.n_prod * nv * 8)
+    step = max(1, min(sys.n_occ, max_bytes // per_e))
+    for e0 in range(0, sys.n_occ, step):
+        yield np.arange(e0, min(sys.n_occ, e0 + step))
+
+
+def chi0_matrix(sys, omega: float, eps: float | None = None) -> np.ndarray:
+    """Dense chi0_{mu nu}(w) of eq. response-mat, [n_prod, n_prod] complex.
+
+    chi0 = sum_{E,F} v^{EF} L_EF v^{EF}^T, accumulated over chunks of
+    occupied states so that the transition vertices never need to be held
+    in full.
+    """
+    eps = sys.eps if eps is None else eps
+    D = transition_energies(sys)
+    P = sys.n_prod
+    re = np.zeros((P, P))
+    im = np.zeros((P, P))
+    for occ in _occ_chunks(sys):
+        Vt = transition_vertices(sys, occ).reshape(P, -1)
+        L = lorentzian(omega, eps, D[occ], sys.occ_factor).ravel()
+        re += (Vt * L.real) @ Vt.T
+        im += (Vt * L.imag) @ Vt.T
+    return re + 1j * im
+
+
+def chi0_apply(sys, omega: float, z: np.ndarray, eps: float | None = None) -> np.ndarray:
+    """chi0(w) z for one or more vectors z ([n_prod] or [n_prod, k]).
+
+    Same sum as `chi0_matrix`, contracted with z before the second vertex
+    factor: sum_{EF} v^{EF} L_EF (v^{EF} . z).  Cheaper in memory for large
+    systems; identical mathematics.
+    """
+    eps = sys.eps if eps is None else eps
+    D = transition_energies(sys)
+    z = np.asarray(z, dtype=complex)
+    vec = z.ndim == 1
+    Z = z.reshape(sys.n_prod, -1)
+    out = np.zeros_like(Z)
+    for occ in _occ_chunks(sys):
+        Vt = transition_vertices(sys, occ).reshape(sys.n_prod, -1)
+        L = lorentzian(omega, eps, D[occ], sys.occ_factor).ravel()
+        t = Vt.T @ Z.real + 1j * (Vt.T @ Z.imag)
+        t *= L[:, None]
+        out += Vt @ t.real + 1j * (Vt @ t.imag)
+    return out[:, 0] if vec else out
+
+
+def response_matrix(sys, omega: float, eps: float | None = None, chi0=None) -> np.ndarray:
+    """A(w) = 1 - chi0(w) f_Hxc (Sec. 4, eq. sle); f_Hxc is the kernel K."""
+    chi0 = chi0_matrix(sys, omega, eps) if chi0 is None else chi0
+    return np.eye(sys.n_prod) - chi0 @ sys.K
+
+
+def solve_response(sys, omega: float, drives: np.ndarray, eps: float | None = None):
+    """Solve (1 - chi0 K) X = chi0 d for each drive d (rows of `drives`).
+
+    Dense LU with partial pivoting; one factorisation serves all drives.
+    Returns X as [n_drive, n_prod] complex.
+    """
+    chi0 = chi0_matrix(sys, omega, eps)
+    A = response_matrix(sys, omega, eps, chi0)
+    B = chi0 @ np.asarray(drives, dtype=float).T
+    return np.linalg.solve(A, B).T
+
+
+def polarizability(sys, omegas, drives: np.ndarray | None = None,
+                   eps: float | None = None) -> np.ndarray:
+    """alpha_{ki}(w) = -d_k . X_i(w) (eq. eqpolarizability, sign reading alpha = -P).
+
+    Returns [n_omega, n_drive, n_drive] complex; drives default to the
+    workload's Cartesian dipoles.
+    """
+    D = sys.drives() if drives is None else np.atleast_2d(np.asarray(drives, float))
+    omegas = np.atleast_1d(np.asarray(omegas, float))
+    out = np.empty((omegas.size, D.shape[0], D.shape[0]), dtype=complex)
+    for k, w in enumerate(omegas):
+        Xs = solve_response(sys, float(w), D, eps)
+        out[k] = -(D @ Xs.T)
+    return out
+
+
+def residual_norm(sys, omega: float, drive: np.ndarray, x: np.ndarray,
+                  eps: float | None = None) -> float:
+    """|| chi0 d - (x - chi0 K x) || / || chi0 d ||: how well x solves eq. sle.
+
+    Uses only chi0 applications, so it is usable at sizes where the dense
+    chi0 matrix is too expensive.
+    """
+    drive = np.asarray(drive, float)
+    x = np.asarray(x, complex)
+    Z = np.stack([drive.astype(complex), sys.K @ x], axis=1)
+    Y = chi0_apply(sys, omega, Z, eps)
+    b = Y[:, 0]
+    r = b - (x - Y[:, 1])
+    return float(np.linalg.norm(r) / np.linalg.norm(b))
