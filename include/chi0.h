@@ -1,0 +1,198 @@
+/*
+ * chi0.h -- C-ABI of the MI355X (gfx950) iterative polarizability library.
+ *
+ * The library computes the interacting dynamical polarizability of a
+ * molecule described in a basis of dominant products, following
+ * P. Koval, D. Foerster, O. Coulaud, "A Parallel Iterative Method for
+ * Computing Molecular Absorption Spectra" (2010):
+ *
+ *   chi0_{mu nu}(w) = sum_{E occ, F virt} v_mu^{EF} L_EF(w) v_nu^{EF},
+ *       v_mu^{EF} = X_a^E V_mu^{ab} X_b^F                     (Sec. 3, eq. response-mat)
+ *       L_EF(w)   = n [1/(w - D_EF + i eps) - 1/(w + D_EF + i eps)],  D_EF = e_F - e_E
+ *   (1 - chi0(w) K) x(w) = chi0(w) d                           (Sec. 4.1, eq. sle)
+ *   alpha_{ki}(w) = -d_k . x_i(w)       (eq. eqpolarizability; sign: alpha = -P)
+ *
+ * chi0 is never formed: chi0(w) z is applied matrix-free by the factored
+ * sequence of Sec. 4.2 (Table t:flops): vertex contraction, the occupied and
+ * virtual orbital transforms, the frequency factor, and the contraction back
+ * onto products.  The linear system is solved by GMRES (Sec. 4.1).
+ *
+ * Conventions
+ *   - Units: Hartree and Bohr.  Energies must already be shifted so that the
+ *     n_occ occupied eigenvalues are < 0 and the virtual ones > 0 (Sec. 2).
+ *   - Complex numbers are interleaved (re, im) pairs of double, i.e. the
+ *     layout of C99 `double _Complex` / std::complex<double> / torch.complex128.
+ *   - Matrices are row-major.
+ *   - Return codes: 0 success, > 0 warning, < 0 error.  No exception or
+ *     abort crosses the ABI; chi0_last_error() gives a message.
+ *   - A context is not thread-safe: use one context per host thread.  Calls
+ *     that take a hipStream_t enqueue work on that stream and return without
+ *     synchronising it; every other call is synchronous.
+ */
+#ifndef CHI0_H
+#define CHI0_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define CHI0_OK               0
+#define CHI0_NOT_CONVERGED    1   /* warning: some points missed the tolerance; results still written */
+#define CHI0_EINVAL          (-1) /* bad size, pointer, index or parameter */
+#define CHI0_ENOSYS          (-2) /* no system set on this context (or host-only context) */
+#define CHI0_ENOMEM          (-3) /* device or host allocation failed */
+#define CHI0_EHIP            (-4) /* a HIP runtime call failed; message names it */
+#define CHI0_ENONFINITE      (-5) /* NaN or Inf in an input */
+#define CHI0_EASYM           (-6) /* vertex block or kernel matrix not symmetric */
+
+/* Arithmetic used for the orbital transforms inside chi0 (the rest is FP64). */
+#define CHI0_PREC_FP64        0
+
+typedef struct chi0_ctx chi0_ctx;      /* opaque */
+
+/*
+ * Create a context bound to HIP device `device` (an index as for
+ * hipSetDevice).  device = -1 creates a host-only context: chi0_set_system
+ * then validates its inputs and builds the host-side block maps but uploads
+ * nothing; calls that compute return CHI0_ENOSYS.  *out is NULL on failure.
+ */
+int chi0_create(chi0_ctx **out, int device);
+
+/* Release every device and host resource of the context (NULL is a no-op). */
+void chi0_destroy(chi0_ctx *ctx);
+
+/* Message of the last failing call on this context ("" if none).  The
+ * pointer stays valid until the next call on the same context.  ctx may be
+ * NULL, then the message of the last failed chi0_create is returned. */
+const char *chi0_last_error(const chi0_ctx *ctx);
+
+/*
+ * Define the molecule (Sec. 2-3).  All pointers are host memory, read during
+ * the call and not retained; the context keeps its own device copies.  A
+ * later call replaces the system.
+ *
+ *  n_atoms, positions   number of atoms; positions [n_atoms][3] in Bohr (may
+ *                       be NULL; only checked for finiteness).
+ *  n_orb, n_occ         atomic orbitals N (= molecular orbitals) and occupied
+ *                       states, 1 <= n_occ < n_orb.
+ *  occ_factor           occupation n of an occupied state (2 for a closed
+ *                       shell); virtual states carry 0.
+ *  eigenvalues          [n_orb] Kohn-Sham energies, the first n_occ < 0 and
+ *                       the rest > 0.
+ *  X                    [n_orb][n_orb], X[a*n_orb + E] = X_a^E, coefficient of
+ *                       atomic orbital a in molecular orbital E (eq. lcao).
+ *  atom_orb_offset      [n_atoms+1] atomic orbitals of atom A are
+ *                       [offset[A], offset[A+1]); offset[0] = 0,
+ *                       offset[n_atoms] = n_orb, strictly increasing.
+ *  n_prod, prod_atoms   number of dominant products; prod_atoms[2*mu] = atom
+ *                       A of product mu, prod_atoms[2*mu+1] = atom B != A of
+ *                       a bilocal product or -1 for a local one (Sec. 3).
+ *  vblock_offset        [n_prod+1] start of each product's vertex block in
+ *                       `vblock`; vblock_offset[0] = 0 and consecutive
+ *                       differences equal s_mu^2.
+ *  vblock               the vertex V_mu^{ab} of each product as a dense
+ *                       symmetric s_mu x s_mu row-major block over its support:
+ *                       the orbitals of A, then (bilocal) those of B; s_mu is
+ *                       the number of those orbitals (eq. vertex-ansatz).
+ *  K                    [n_prod][n_prod] symmetric interaction kernel f_Hxc
+ *                       (Sec. 5), frequency independent.
+ *
+ * Errors: CHI0_EINVAL (sizes, offsets, indices, energies not shifted,
+ * occ_factor <= 0), CHI0_ENONFINITE, CHI0_EASYM (a block or K asymmetric by
+ * more than 1e-12 of its largest entry), CHI0_ENOMEM, CHI0_EHIP.  On error
+ * the previous system is gone and the context has none.
+ */
+int chi0_set_system(chi0_ctx *ctx,
+                    int32_t n_atoms, const double *positions,
+                    int32_t n_orb, int32_t n_occ, double occ_factor,
+                    const double *eigenvalues, const double *X,
+                    const int32_t *atom_orb_offset,
+                    int32_t n_prod, const int32_t *prod_atoms,
+                    const int64_t *vblock_offset, const double *vblock,
+                    const double *K);
+
+/* Sizes of the current system: any pointer may be NULL.  CHI0_ENOSYS if none. */
+int chi0_get_sizes(const chi0_ctx *ctx, int32_t *n_orb, int32_t *n_occ,
+                   int32_t *n_prod, int32_t *n_atoms);
+
+/*
+ * out_r = chi0(omega[r]) z_r for r < n_rhs (Sec. 4.2, matrix-free).
+ *
+ *  omega   host [n_rhs] frequencies (Ha), any real values.
+ *  eps     broadening (Ha), > 0.
+ *  z, out  DEVICE buffers of n_rhs * n_prod complex values (interleaved
+ *          doubles), row r at offset r*n_prod.  Owned by the caller; may not
+ *          overlap.  Work is enqueued on `stream` (a hipStream_t, NULL = the
+ *          default stream) and the call returns before it completes.  The
+ *          context's workspace is shared by all calls on the context, so do
+ *          not overlap two calls on one context on different streams.
+ *  precision  CHI0_PREC_FP64.
+ */
+int chi0_apply(chi0_ctx *ctx, int32_t n_rhs, const double *omega, double eps,
+               const double *z, double *out, int32_t precision, void *stream);
+
+/* Options of chi0_solve_response.  Zero-initialise, then set what you need;
+ * chi0_solve_opts_default() fills the defaults. */
+typedef struct chi0_solve_opts {
+    int32_t restart;      /* GMRES(m) Krylov dimension per cycle, >= 1 (default 30) */
+    int32_t max_iter;     /* cap on matrix-vector products per point (default 10000) */
+    double  tol;          /* stop when ||chi0 d - A x||_2 <= tol ||chi0 d||_2 (default 1e-10) */
+    int32_t precision;    /* CHI0_PREC_* for chi0 inside the solve (default FP64) */
+    int32_t batch;        /* (omega, drive) points solved concurrently; 1 = one at a time (default 1) */
+    int32_t reserved[8];  /* must be zero */
+} chi0_solve_opts;
+
+/* Per-point solver record (one per omega and drive). */
+typedef struct chi0_point_stats {
+    int32_t iterations;   /* Arnoldi steps (operator applications, excluding b and residual checks) */
+    int32_t restarts;     /* completed GMRES cycles */
+    int32_t converged;    /* 1 if the true relative residual met tol */
+    int32_t breakdown;    /* 1 if the Krylov space became invariant (exact solution) */
+    double  rel_residual; /* true ||b - A x|| / ||b|| at exit */
+} chi0_point_stats;
+
+void chi0_solve_opts_default(chi0_solve_opts *opts);
+
+/*
+ * Polarizability tensor over a frequency grid (Sec. 4.1 and Algorithm a:main):
+ * for each omega[w] and each drive i, GMRES solves (1 - chi0 K) x = chi0 d_i
+ * from x = 0, then alpha[w][k][i] = -d_k . x for every drive k.
+ *
+ *  omega    host [n_omega] (Ha).
+ *  eps      broadening (Ha), > 0.
+ *  n_drive  1..3 drives; V_ext host [n_drive][n_prod] real dipole vectors.
+ *  opts     NULL for the defaults.
+ *  alpha    host [n_omega][n_drive][n_drive] complex (interleaved), written.
+ *  stats    host [n_omega][n_drive] records, may be NULL.
+ * Returns CHI0_OK, CHI0_NOT_CONVERGED (alpha from the last iterate), or an
+ * error.  Synchronous; uses the context's own stream.
+ */
+int chi0_solve_response(chi0_ctx *ctx, int32_t n_omega, const double *omega, double eps,
+                        int32_t n_drive, const double *V_ext,
+                        const chi0_solve_opts *opts,
+                        double *alpha, chi0_point_stats *stats);
+
+/*
+ * Kernel timing (tracing).  When enabled, every kernel launch of the
+ * library is bracketed by HIP events on the stream it runs on, and the
+ * durations are accumulated per kernel name.  chi0_kernel_stats copies up
+ * to `cap` records (name, launches, total milliseconds) and returns how
+ * many kernels have records.  Reading the records synchronises the
+ * context's streams.  Disabled by default; enabling resets the records.
+ */
+typedef struct chi0_kernel_record {
+    char    name[48];
+    int64_t launches;
+    double  total_ms;
+} chi0_kernel_record;
+
+int chi0_set_timing(chi0_ctx *ctx, int32_t enable);
+int chi0_kernel_stats(chi0_ctx *ctx, chi0_kernel_record *records, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHI0_H */

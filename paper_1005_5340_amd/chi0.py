@@ -1,0 +1,239 @@
+"""Python binding of libchi0 (argument marshalling only).
+
+Every computation runs inside the HIP library; this module converts NumPy
+arrays and PyTorch device tensors into the pointers of the C-ABI declared in
+include/chi0.h and turns return codes into exceptions.  It loads the in-tree
+`libchi0.so` and raises if it is missing: there is no fallback.
+
+Names follow the C-ABI: `Context.set_system`, `Context.apply`,
+`Context.solve_response` (chi0_set_system, chi0_apply, chi0_solve_response).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["Chi0Error", "Context", "lib", "LIB_PATH", "PREC_FP64", "SolveStats",
+           "NOT_CONVERGED"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
+PREC_FP64 = 0
+NOT_CONVERGED = 1
+_ERRORS = {-1: "EINVAL", -2: "ENOSYS", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EASYM"}
+
+_dp = C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
+                ("precision", C.c_int32), ("batch", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class PointStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("breakdown", C.c_int32), ("rel_residual", C.c_double)]
+
+
+class KernelRecord(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+SolveStats = np.dtype([("iterations", np.int32), ("restarts", np.int32), ("converged", np.int32),
+                       ("breakdown", np.int32), ("rel_residual", np.float64)])
+
+_LIB = None
+
+
+def lib():
+    """Load libchi0.so (once).  Raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    L.chi0_create.argtypes = [C.POINTER(C.c_void_p), C.c_int]
+    L.chi0_create.restype = C.c_int
+    L.chi0_destroy.argtypes = [C.c_void_p]
+    L.chi0_destroy.restype = None
+    L.chi0_last_error.argtypes = [C.c_void_p]
+    L.chi0_last_error.restype = C.c_char_p
+    L.chi0_set_system.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_int32, C.c_int32, C.c_double,
+                                  _dp, _dp, _i32p, C.c_int32, _i32p, _i64p, _dp, _dp]
+    L.chi0_set_system.restype = C.c_int
+    L.chi0_get_sizes.argtypes = [C.c_void_p, _i32p, _i32p, _i32p, _i32p]
+    L.chi0_get_sizes.restype = C.c_int
+    L.chi0_apply.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_double, C.c_void_p, C.c_void_p,
+                             C.c_int32, C.c_void_p]
+    L.chi0_apply.restype = C.c_int
+    L.chi0_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
+    L.chi0_solve_opts_default.restype = None
+    L.chi0_solve_response.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_double, C.c_int32, _dp,
+                                      C.POINTER(SolveOpts), _dp, C.POINTER(PointStats)]
+    L.chi0_solve_response.restype = C.c_int
+    L.chi0_set_timing.argtypes = [C.c_void_p, C.c_int32]
+    L.chi0_set_timing.restype = C.c_int
+    L.chi0_kernel_stats.argtypes = [C.c_void_p, C.POINTER(KernelRecord), C.c_int32]
+    L.chi0_kernel_stats.restype = C.c_int
+    _LIB = L
+    return L
+
+
+class Chi0Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"chi0 error {code} ({_ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None and a.size != int(np.prod(shape)):
+        raise ValueError(f"expected {shape}, got {a.shape}")
+    return a
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+class Context:
+    """One chi0 context bound to a HIP device (device=-1: host-only validation)."""
+
+    def __init__(self, device: int = 0):
+        self._L = lib()
+        h = C.c_void_p()
+        rc = self._L.chi0_create(C.byref(h), int(device))
+        if rc != 0:
+            raise Chi0Error(rc, self._L.chi0_last_error(None).decode())
+        self._h = h
+        self.device = device
+
+    # ------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.chi0_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc: int, allow_warning: bool = False) -> int:
+        if rc < 0 or (rc > 0 and not allow_warning):
+            raise Chi0Error(rc, self._L.chi0_last_error(self._h).decode())
+        return rc
+
+    @property
+    def last_error(self) -> str:
+        return self._L.chi0_last_error(self._h).decode()
+
+    # ---------------------------------------------------------------- system
+    def set_system(self, n_atoms, positions, n_orb, n_occ, occ_factor, eigenvalues, X,
+                   atom_orb_offset, n_prod, prod_atoms, vblock_offset, vblock, K):
+        """chi0_set_system; host arrays are copied."""
+        pos = None if positions is None else _f64(positions, (n_atoms, 3))
+        eig = _f64(eigenvalues, (n_orb,))
+        Xa = _f64(X, (n_orb, n_orb))
+        aoff = np.ascontiguousarray(atom_orb_offset, dtype=np.int32)
+        pat = np.ascontiguousarray(prod_atoms, dtype=np.int32)
+        voff = np.ascontiguousarray(vblock_offset, dtype=np.int64)
+        vb = _f64(vblock)
+        Ka = _f64(K, (n_prod, n_prod))
+        if aoff.size != n_atoms + 1 or pat.size != 2 * n_prod or voff.size != n_prod + 1:
+            raise ValueError("inconsistent array sizes")
+        self._keep = (pos, eig, Xa, aoff, pat, voff, vb, Ka)
+        rc = self._L.chi0_set_system(self._h, int(n_atoms), _ptr(pos), int(n_orb), int(n_occ),
+                                     float(occ_factor), _ptr(eig), _ptr(Xa), _ptr(aoff, _i32p),
+                                     int(n_prod), _ptr(pat, _i32p), _ptr(voff, _i64p), _ptr(vb),
+                                     _ptr(Ka))
+        self._keep = None
+        self._check(rc)
+
+    def set_system_from(self, sys):
+        """Convenience: pass a `synth.System` (or anything with the same fields)."""
+        self.set_system(sys.n_atoms, sys.positions, sys.n_orb, sys.n_occ, sys.occ_factor,
+                        sys.eigenvalues, sys.X, sys.atom_orb_offset, sys.n_prod, sys.prod_atoms,
+                        sys.vblock_offset, sys.vblock, sys.K)
+
+    def sizes(self):
+        v = [C.c_int32() for _ in range(4)]
+        self._check(self._L.chi0_get_sizes(self._h, *[C.byref(x) for x in v]))
+        return dict(n_orb=v[0].value, n_occ=v[1].value, n_prod=v[2].value, n_atoms=v[3].value)
+
+    # ----------------------------------------------------------------- apply
+    def apply(self, omega, eps: float, z, out=None, precision: int = PREC_FP64, stream=None):
+        """out[r] = chi0(omega[r]) z[r] for torch complex128 CUDA tensors z [n_rhs, n_prod].
+
+        Enqueued on `stream` (default: torch's current stream); returns `out`.
+        """
+        import torch
+        om = _f64(np.atleast_1d(omega))
+        if not (z.is_cuda and z.dtype == torch.complex128 and z.is_contiguous() and z.dim() == 2):
+            raise ValueError("z must be a contiguous complex128 CUDA tensor [n_rhs, n_prod]")
+        if z.shape[0] != om.size:
+            raise ValueError("one frequency per row of z")
+        if out is None:
+            out = torch.empty_like(z)
+        if not (out.is_cuda and out.dtype == torch.complex128 and out.is_contiguous()
+                and out.shape == z.shape):
+            raise ValueError("out must match z")
+        if stream is None:
+            stream = torch.cuda.current_stream(z.device)
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        rc = self._L.chi0_apply(self._h, int(om.size), _ptr(om), float(eps),
+                                C.c_void_p(z.data_ptr()), C.c_void_p(out.data_ptr()),
+                                int(precision), C.c_void_p(handle))
+        self._check(rc)
+        return out
+
+    # ---------------------------------------------------------------- solve
+    def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
+                       tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64):
+        """GMRES polarizability over a frequency grid.
+
+        Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
+        where rc is 0 or NOT_CONVERGED.
+        """
+        om = _f64(np.atleast_1d(omega))
+        D = _f64(np.atleast_2d(V_ext))
+        nd = D.shape[0]
+        o = SolveOpts()
+        self._L.chi0_solve_opts_default(C.byref(o))
+        o.restart, o.max_iter, o.tol = int(restart), int(max_iter), float(tol)
+        o.batch, o.precision = int(batch), int(precision)
+        alpha = np.zeros((om.size, nd, nd, 2))
+        st = (PointStats * max(1, om.size * nd))()
+        rc = self._L.chi0_solve_response(self._h, int(om.size), _ptr(om), float(eps), int(nd),
+                                         _ptr(D), C.byref(o), _ptr(alpha), st)
+        self._check(rc, allow_warning=True)
+        stats = np.zeros((om.size, nd), dtype=SolveStats)
+        flat = stats.reshape(-1)
+        for i in range(om.size * nd):
+            flat[i] = (st[i].iterations, st[i].restarts, st[i].converged, st[i].breakdown,
+                       st[i].rel_residual)
+        return alpha[..., 0] + 1j * alpha[..., 1], stats, rc
+
+    # --------------------------------------------------------------- tracing
+    def set_timing(self, enable: bool):
+        self._check(self._L.chi0_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_stats(self) -> dict:
+        n = self._L.chi0_kernel_stats(self._h, None, 0)
+        self._check(min(n, 0))
+        recs = (KernelRecord * max(1, n))()
+        n = self._L.chi0_kernel_stats(self._h, recs, n)
+        return {recs[i].name.decode(): (int(recs[i].launches), float(recs[i].total_ms))
+                for i in range(n)}

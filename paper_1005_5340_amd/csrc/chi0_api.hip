@@ -1,0 +1,828 @@
+// Host runtime of libchi0: the C-ABI declared in include/chi0.h.
+//
+// set_system validates the molecule, builds the atom-pair block maps of the
+// sparse vertex (Sec. 3) and uploads padded device copies.  apply runs the
+// matrix-free chi0(w) z sequence of Sec. 4.2 on a batch of vectors.
+// solve_response drives GMRES (Sec. 4.1) for many (frequency, drive) points
+// concurrently: each point owns a slot (Krylov basis, Hessenberg matrix,
+// solution); every step applies the operator to one vector per active slot
+// in a single batched pass, and a slot is refilled with the next point as
+// soon as its point converges, so the batched transforms stay full.
+#include "common.h"
+#include "chi0.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace chi0;
+
+// ================================================================== tracing
+struct chi0::Tracer {
+    bool on = false;
+    struct Pending { const char *name; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<int64_t, double>> recs;
+    const char *cur_name = nullptr;
+    hipEvent_t cur_a = nullptr;
+
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void harvest() {
+        for (auto &p : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                auto &r = recs[p.name];
+                r.first += 1;
+                r.second += ms;
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+    void clear() {
+        harvest();
+        recs.clear();
+    }
+    ~Tracer() {
+        harvest();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+void chi0::trace_begin(Tracer *t, const char *name, hipStream_t s) {
+    if (!t || !t->on) return;
+    t->cur_name = name;
+    t->cur_a = t->get();
+    if (t->cur_a) (void)hipEventRecord(t->cur_a, s);
+}
+
+void chi0::trace_end(Tracer *t, hipStream_t s) {
+    if (!t || !t->on || !t->cur_a) return;
+    hipEvent_t b = t->get();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    t->pending.push_back({t->cur_name, t->cur_a, b});
+    t->cur_a = nullptr;
+    if (t->pending.size() >= 16384) t->harvest();
+}
+
+// ================================================================== context
+struct DevBuf {
+    std::vector<void *> ptrs;
+    void release() {
+        for (void *p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+};
+
+struct chi0_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::string err;
+    Tracer tracer;
+
+    // system
+    bool has_system = false;
+    int n_atoms = 0, N = 0, No = 0, Nv = 0, P = 0;
+    int N_pad = 0, No_pad = 0, Nv_pad = 0, P_pad = 0;
+    double occ = 2.0;
+    int n_blk = 0, n_g = 0, max_rows = 0;
+    int64_t nnzB = 0, npart = 0;
+    DevBuf sysbuf;
+    double *Xo = nullptr, *Xv = nullptr, *Xvt = nullptr, *Dlt = nullptr, *K = nullptr;
+    BlockMapDev bm{};
+
+    // operator workspace, sized for nc_cap real columns
+    DevBuf wsbuf;
+    int nc_cap = 0;
+    double *Vb = nullptr, *Zin = nullptr, *Yout = nullptr, *dV = nullptr, *W = nullptr;
+    double *Tt = nullptr, *at = nullptr, *Ut = nullptr, *part = nullptr, *omega_dev = nullptr;
+
+    // solver workspace
+    DevBuf slotbuf;
+    int slot_n = 0, slot_m = 0;
+    SlotsDev slots{};
+    Job *jobs_dev = nullptr, *fin_dev = nullptr, *upd_dev = nullptr;
+    StepStatus *status_dev = nullptr;
+    Job *jobs_h = nullptr, *fin_h = nullptr, *upd_h = nullptr;
+    StepStatus *status_h = nullptr;
+    double *omega_h = nullptr;
+    int host_cap = 0;
+
+    ~chi0_ctx() {
+        if (device >= 0) {
+            (void)hipSetDevice(device);
+            if (stream) (void)hipStreamSynchronize(stream);
+        }
+        slotbuf.release();
+        wsbuf.release();
+        sysbuf.release();
+        if (jobs_h) (void)hipHostFree(jobs_h);
+        if (fin_h) (void)hipHostFree(fin_h);
+        if (upd_h) (void)hipHostFree(upd_h);
+        if (status_h) (void)hipHostFree(status_h);
+        if (omega_h) (void)hipHostFree(omega_h);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+static thread_local std::string g_create_error;
+
+static int fail(chi0_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? CHI0_ENOMEM : CHI0_EHIP,          \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+template <class T>
+static int dalloc(chi0_ctx *c, DevBuf &buf, T **p, int64_t n) {
+    void *q = nullptr;
+    const size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess)
+        return fail(c, CHI0_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                        hipGetErrorString(e));
+    buf.ptrs.push_back(q);
+    e = hipMemset(q, 0, bytes);
+    if (e != hipSuccess) return fail(c, CHI0_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
+    *p = static_cast<T *>(q);
+    return CHI0_OK;
+}
+
+#define CHK(x)                      \
+    do {                            \
+        int r_ = (x);               \
+        if (r_ != CHI0_OK) return r_; \
+    } while (0)
+
+// ================================================================ lifecycle
+extern "C" int chi0_create(chi0_ctx **out, int device) {
+    if (!out) { g_create_error = "out is NULL"; return CHI0_EINVAL; }
+    *out = nullptr;
+    if (device < -1) { g_create_error = "device must be >= -1"; return CHI0_EINVAL; }
+    chi0_ctx *c = new (std::nothrow) chi0_ctx();
+    if (!c) { g_create_error = "out of host memory"; return CHI0_ENOMEM; }
+    if (device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || device >= n) {
+            g_create_error = "HIP device " + std::to_string(device) + " not available (" +
+                             std::to_string(e == hipSuccess ? n : 0) + " devices)";
+            delete c;
+            return e == hipSuccess ? CHI0_EINVAL : CHI0_EHIP;
+        }
+        e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            g_create_error = std::string("HIP setup failed: ") + hipGetErrorString(e);
+            delete c;
+            return CHI0_EHIP;
+        }
+        c->device = device;
+    }
+    *out = c;
+    return CHI0_OK;
+}
+
+extern "C" void chi0_destroy(chi0_ctx *ctx) { delete ctx; }
+
+extern "C" const char *chi0_last_error(const chi0_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" int chi0_get_sizes(const chi0_ctx *ctx, int32_t *n_orb, int32_t *n_occ,
+                              int32_t *n_prod, int32_t *n_atoms) {
+    if (!ctx) return CHI0_EINVAL;
+    if (!ctx->has_system) return CHI0_ENOSYS;
+    if (n_orb) *n_orb = ctx->N;
+    if (n_occ) *n_occ = ctx->No;
+    if (n_prod) *n_prod = ctx->P;
+    if (n_atoms) *n_atoms = ctx->n_atoms;
+    return CHI0_OK;
+}
+
+extern "C" void chi0_solve_opts_default(chi0_solve_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->restart = 30;
+    o->max_iter = 10000;
+    o->tol = 1e-10;
+    o->precision = CHI0_PREC_FP64;
+    o->batch = 1;
+}
+
+extern "C" int chi0_set_timing(chi0_ctx *ctx, int32_t enable) {
+    if (!ctx) return CHI0_EINVAL;
+    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+    ctx->tracer.clear();
+    ctx->tracer.on = enable != 0;
+    return CHI0_OK;
+}
+
+extern "C" int chi0_kernel_stats(chi0_ctx *ctx, chi0_kernel_record *rec, int32_t cap) {
+    if (!ctx || cap < 0 || (cap > 0 && !rec)) return fail(ctx, CHI0_EINVAL, "bad arguments");
+    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+    ctx->tracer.harvest();
+    int i = 0;
+    for (auto &kv : ctx->tracer.recs) {
+        if (i < cap) {
+            std::memset(&rec[i], 0, sizeof(rec[i]));
+            std::snprintf(rec[i].name, sizeof(rec[i].name), "%s", kv.first.c_str());
+            rec[i].launches = kv.second.first;
+            rec[i].total_ms = kv.second.second;
+        }
+        ++i;
+    }
+    return i;
+}
+
+// =============================================================== set_system
+namespace {
+
+struct HostMaps {
+    std::vector<int32_t> blk_nprod, blk_na, blk_nb, pidx, col_gstart, g_xrow, atom_off;
+    std::vector<int64_t> blk_pstart, blk_vstart, blk_ent, g_ent, prod_pstart, prod_plist;
+    std::vector<double> Vp;
+    int max_rows = 0;
+};
+
+bool all_finite(const double *p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+static void drop_system(chi0_ctx *c) {
+    if (c->device >= 0) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+    }
+    c->slotbuf.release();
+    c->slot_n = c->slot_m = 0;
+    c->wsbuf.release();
+    c->nc_cap = 0;
+    c->sysbuf.release();
+    c->has_system = false;
+}
+
+extern "C" int chi0_set_system(chi0_ctx *c, int32_t n_atoms, const double *positions,
+                               int32_t n_orb, int32_t n_occ, double occ_factor,
+                               const double *eig, const double *X, const int32_t *aoff,
+                               int32_t n_prod, const int32_t *pat, const int64_t *voff,
+                               const double *vblock, const double *K) {
+    if (!c) return CHI0_EINVAL;
+    drop_system(c);
+    // ---------------------------------------------------------- validation
+    if (n_atoms < 1 || n_orb < 2 || n_occ < 1 || n_occ >= n_orb || n_prod < 1)
+        return fail(c, CHI0_EINVAL, "need n_atoms >= 1, n_orb >= 2, 1 <= n_occ < n_orb, n_prod >= 1");
+    if (!eig || !X || !aoff || !pat || !voff || !vblock || !K)
+        return fail(c, CHI0_EINVAL, "NULL input pointer");
+    if (!(occ_factor > 0.0) || !std::isfinite(occ_factor))
+        return fail(c, CHI0_EINVAL, "occ_factor must be finite and > 0");
+    if (aoff[0] != 0 || aoff[n_atoms] != n_orb)
+        return fail(c, CHI0_EINVAL, "atom_orb_offset must start at 0 and end at n_orb");
+    for (int A = 0; A < n_atoms; ++A) {
+        const int na = aoff[A + 1] - aoff[A];
+        if (na < 1) return fail(c, CHI0_EINVAL, "atom_orb_offset must be strictly increasing");
+        if (na > NB_MAX)
+            return fail(c, CHI0_EINVAL, "atom " + std::to_string(A) + " has " + std::to_string(na) +
+                                            " orbitals; at most " + std::to_string(NB_MAX) + " supported");
+    }
+    std::vector<int> s_mu(n_prod);
+    for (int mu = 0; mu < n_prod; ++mu) {
+        const int A = pat[2 * mu], B = pat[2 * mu + 1];
+        if (A < 0 || A >= n_atoms || B < -1 || B >= n_atoms || B == A)
+            return fail(c, CHI0_EINVAL, "bad prod_atoms entry for product " + std::to_string(mu));
+        s_mu[mu] = (aoff[A + 1] - aoff[A]) + (B >= 0 ? aoff[B + 1] - aoff[B] : 0);
+    }
+    if (voff[0] != 0) return fail(c, CHI0_EINVAL, "vblock_offset[0] must be 0");
+    for (int mu = 0; mu < n_prod; ++mu)
+        if (voff[mu + 1] - voff[mu] != (int64_t)s_mu[mu] * s_mu[mu])
+            return fail(c, CHI0_EINVAL, "vblock_offset of product " + std::to_string(mu) +
+                                            " does not match its support size");
+    const int64_t nv_tot = voff[n_prod];
+    if (positions && !all_finite(positions, 3 * (int64_t)n_atoms))
+        return fail(c, CHI0_ENONFINITE, "non-finite positions");
+    if (!all_finite(eig, n_orb)) return fail(c, CHI0_ENONFINITE, "non-finite eigenvalues");
+    if (!all_finite(X, (int64_t)n_orb * n_orb)) return fail(c, CHI0_ENONFINITE, "non-finite X");
+    if (!all_finite(vblock, nv_tot)) return fail(c, CHI0_ENONFINITE, "non-finite vertex");
+    if (!all_finite(K, (int64_t)n_prod * n_prod)) return fail(c, CHI0_ENONFINITE, "non-finite K");
+    for (int E = 0; E < n_orb; ++E) {
+        if (E < n_occ && !(eig[E] < 0.0))
+            return fail(c, CHI0_EINVAL, "occupied eigenvalues must be < 0 (energies shifted to the gap)");
+        if (E >= n_occ && !(eig[E] > 0.0))
+            return fail(c, CHI0_EINVAL, "virtual eigenvalues must be > 0 (energies shifted to the gap)");
+    }
+    for (int mu = 0; mu < n_prod; ++mu) {
+        const int s = s_mu[mu];
+        const double *b = vblock + voff[mu];
+        double mx = 0.0;
+        for (int i = 0; i < s * s; ++i) mx = std::max(mx, std::fabs(b[i]));
+        for (int i = 0; i < s; ++i)
+            for (int j = i + 1; j < s; ++j)
+                if (std::fabs(b[i * s + j] - b[j * s + i]) > 1e-12 * mx)
+                    return fail(c, CHI0_EASYM, "vertex block of product " + std::to_string(mu) + " is not symmetric");
+    }
+    {
+        double mx = 0.0;
+        for (int64_t i = 0; i < (int64_t)n_prod * n_prod; ++i) mx = std::max(mx, std::fabs(K[i]));
+        for (int i = 0; i < n_prod; ++i)
+            for (int j = i + 1; j < n_prod; ++j)
+                if (std::fabs(K[(int64_t)i * n_prod + j] - K[(int64_t)j * n_prod + i]) > 1e-12 * mx)
+                    return fail(c, CHI0_EASYM, "kernel matrix K is not symmetric");
+    }
+
+    // ------------------------------------------------------- block maps
+    HostMaps hm;
+    hm.atom_off.assign(aoff, aoff + n_atoms + 1);
+    std::map<std::pair<int, int>, int> blk_of;
+    std::vector<std::pair<int, int>> blocks;
+    for (int A = 0; A < n_atoms; ++A) { blk_of[{A, A}] = (int)blocks.size(); blocks.push_back({A, A}); }
+    {
+        std::vector<std::pair<int, int>> offd;
+        for (int mu = 0; mu < n_prod; ++mu)
+            if (pat[2 * mu + 1] >= 0) {
+                const int A = pat[2 * mu], B = pat[2 * mu + 1];
+                offd.push_back({A, B});
+                offd.push_back({B, A});
+            }
+        std::sort(offd.begin(), offd.end());
+        offd.erase(std::unique(offd.begin(), offd.end()), offd.end());
+        for (auto &ab : offd) { blk_of[ab] = (int)blocks.size(); blocks.push_back(ab); }
+    }
+    const int nblk = (int)blocks.size();
+    struct Ent { int mu, ro, co; };
+    std::vector<std::vector<Ent>> ents(nblk);
+    for (int mu = 0; mu < n_prod; ++mu) {
+        const int A = pat[2 * mu], B = pat[2 * mu + 1];
+        const int na = aoff[A + 1] - aoff[A];
+        ents[blk_of[{A, A}]].push_back({mu, 0, 0});
+        if (B >= 0) {
+            ents[blk_of[{A, B}]].push_back({mu, 0, na});
+            ents[blk_of[{B, A}]].push_back({mu, na, 0});
+            ents[blk_of[{B, B}]].push_back({mu, na, na});
+        }
+    }
+    hm.blk_nprod.resize(nblk); hm.blk_na.resize(nblk); hm.blk_nb.resize(nblk);
+    hm.blk_pstart.resize(nblk); hm.blk_vstart.resize(nblk); hm.blk_ent.resize(nblk);
+    std::vector<std::vector<int64_t>> pos_of(n_prod);
+    int64_t pcur = 0, vcur = 0, ecur = 0;
+    for (int k = 0; k < nblk; ++k) {
+        const int A = blocks[k].first, B = blocks[k].second;
+        const int na = aoff[A + 1] - aoff[A], nb = aoff[B + 1] - aoff[B];
+        hm.blk_na[k] = na; hm.blk_nb[k] = nb;
+        hm.blk_nprod[k] = (int)ents[k].size();
+        hm.blk_pstart[k] = pcur; hm.blk_vstart[k] = vcur; hm.blk_ent[k] = ecur;
+        for (auto &e : ents[k]) {
+            const int s = s_mu[e.mu];
+            const double *b = vblock + voff[e.mu];
+            for (int a = 0; a < na; ++a)
+                for (int bb = 0; bb < nb; ++bb) hm.Vp.push_back(b[(e.ro + a) * s + e.co + bb]);
+            hm.pidx.push_back(e.mu);
+            pos_of[e.mu].push_back(pcur);
+            ++pcur;
+            vcur += (int64_t)na * nb;
+        }
+        ecur += (int64_t)na * nb;
+    }
+    hm.prod_pstart.resize(n_prod + 1);
+    hm.prod_pstart[0] = 0;
+    for (int mu = 0; mu < n_prod; ++mu) {
+        for (auto p : pos_of[mu]) hm.prod_plist.push_back(p);
+        hm.prod_pstart[mu + 1] = (int64_t)hm.prod_plist.size();
+    }
+    // gathered rows per column atom B: rows (A, a) over blocks (A, B), A ascending
+    std::vector<std::vector<int>> col_blocks(n_atoms);
+    for (int k = 0; k < nblk; ++k) col_blocks[blocks[k].second].push_back(k);
+    hm.col_gstart.resize(n_atoms + 1);
+    for (int B = 0; B < n_atoms; ++B) {
+        auto &cb = col_blocks[B];
+        std::sort(cb.begin(), cb.end(), [&](int x, int y) { return blocks[x].first < blocks[y].first; });
+        hm.col_gstart[B] = (int32_t)hm.g_xrow.size();
+        const int nb = aoff[B + 1] - aoff[B];
+        for (int k : cb) {
+            const int A = blocks[k].first, na = aoff[A + 1] - aoff[A];
+            for (int a = 0; a < na; ++a) {
+                hm.g_xrow.push_back(aoff[A] + a);
+                hm.g_ent.push_back(hm.blk_ent[k] + (int64_t)a * nb);
+            }
+        }
+        hm.max_rows = std::max(hm.max_rows, (int)hm.g_xrow.size() - hm.col_gstart[B]);
+    }
+    hm.col_gstart[n_atoms] = (int32_t)hm.g_xrow.size();
+
+    c->n_atoms = n_atoms; c->N = n_orb; c->No = n_occ; c->Nv = n_orb - n_occ; c->P = n_prod;
+    c->N_pad = (int)round_up(n_orb, TILE);
+    c->No_pad = (int)round_up(n_occ, TILE);
+    c->Nv_pad = (int)round_up(n_orb - n_occ, TILE);
+    c->P_pad = (int)round_up(n_prod, TILE);
+    c->occ = occ_factor;
+    c->n_blk = nblk; c->n_g = (int)hm.g_xrow.size(); c->max_rows = hm.max_rows;
+    c->nnzB = ecur; c->npart = pcur;
+
+    if (c->device < 0) {   // host-only context: validation and maps only
+        c->has_system = true;
+        c->err.clear();
+        return CHI0_OK;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+
+    // ------------------------------------------------------------ upload
+    const int N = n_orb, No = n_occ, Nv = n_orb - n_occ;
+    DevBuf &sb = c->sysbuf;
+    {
+        std::vector<double> xo((size_t)c->N_pad * c->No_pad, 0.0), xv((size_t)c->N_pad * c->Nv_pad, 0.0),
+            xvt((size_t)c->Nv_pad * c->N_pad, 0.0), dl((size_t)c->No_pad * c->Nv_pad, 1.0);
+        for (int a = 0; a < N; ++a) {
+            for (int E = 0; E < No; ++E) xo[(size_t)a * c->No_pad + E] = X[(size_t)a * N + E];
+            for (int F = 0; F < Nv; ++F) {
+                xv[(size_t)a * c->Nv_pad + F] = X[(size_t)a * N + No + F];
+                xvt[(size_t)F * c->N_pad + a] = X[(size_t)a * N + No + F];
+            }
+        }
+        for (int E = 0; E < No; ++E)
+            for (int F = 0; F < Nv; ++F) dl[(size_t)E * c->Nv_pad + F] = eig[No + F] - eig[E];
+        CHK(dalloc(c, sb, &c->Xo, (int64_t)xo.size()));
+        CHK(dalloc(c, sb, &c->Xv, (int64_t)xv.size()));
+        CHK(dalloc(c, sb, &c->Xvt, (int64_t)xvt.size()));
+        CHK(dalloc(c, sb, &c->Dlt, (int64_t)dl.size()));
+        HIPCHK(c, hipMemcpy(c->Xo, xo.data(), xo.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->Xv, xv.data(), xv.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->Xvt, xvt.data(), xvt.size() * 8, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->Dlt, dl.data(), dl.size() * 8, hipMemcpyHostToDevice));
+    }
+    CHK(dalloc(c, sb, &c->K, (int64_t)c->P_pad * c->P_pad));
+    HIPCHK(c, hipMemcpy2D(c->K, (size_t)c->P_pad * 8, K, (size_t)n_prod * 8, (size_t)n_prod * 8,
+                          (size_t)n_prod, hipMemcpyHostToDevice));
+
+    auto up32 = [&](const std::vector<int32_t> &v, const int32_t **dst) -> int {
+        int32_t *p = nullptr;
+        CHK(dalloc(c, sb, &p, (int64_t)v.size()));
+        if (!v.empty()) HIPCHK(c, hipMemcpy(p, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+        *dst = p;
+        return CHI0_OK;
+    };
+    auto up64 = [&](const std::vector<int64_t> &v, const int64_t **dst) -> int {
+        int64_t *p = nullptr;
+        CHK(dalloc(c, sb, &p, (int64_t)v.size()));
+        if (!v.empty()) HIPCHK(c, hipMemcpy(p, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+        *dst = p;
+        return CHI0_OK;
+    };
+    BlockMapDev &bm = c->bm;
+    CHK(up32(hm.blk_nprod, &bm.blk_nprod));
+    CHK(up64(hm.blk_pstart, &bm.blk_pstart));
+    CHK(up64(hm.blk_vstart, &bm.blk_vstart));
+    CHK(up64(hm.blk_ent, &bm.blk_ent));
+    CHK(up32(hm.blk_na, &bm.blk_na));
+    CHK(up32(hm.blk_nb, &bm.blk_nb));
+    CHK(up32(hm.pidx, &bm.pidx));
+    CHK(up32(hm.col_gstart, &bm.col_gstart));
+    CHK(up32(hm.g_xrow, &bm.g_xrow));
+    CHK(up64(hm.g_ent, &bm.g_ent));
+    CHK(up32(hm.atom_off, &bm.atom_off));
+    CHK(up64(hm.prod_pstart, &bm.prod_pstart));
+    CHK(up64(hm.prod_plist, &bm.prod_plist));
+    {
+        double *vp = nullptr;
+        CHK(dalloc(c, sb, &vp, (int64_t)hm.Vp.size()));
+        HIPCHK(c, hipMemcpy(vp, hm.Vp.data(), hm.Vp.size() * 8, hipMemcpyHostToDevice));
+        bm.Vp = vp;
+    }
+    HIPCHK(c, hipDeviceSynchronize());
+    c->has_system = true;
+    c->err.clear();
+    return CHI0_OK;
+}
+
+// ================================================================ operator
+static int ensure_ws(chi0_ctx *c, int nc) {
+    if (nc <= c->nc_cap) return CHI0_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipDeviceSynchronize());
+    c->wsbuf.release();
+    c->nc_cap = 0;
+    DevBuf &w = c->wsbuf;
+    const int64_t mcol = (int64_t)c->No_pad * nc;
+    CHK(dalloc(c, w, &c->Vb, (int64_t)c->P_pad * nc));
+    CHK(dalloc(c, w, &c->Zin, (int64_t)c->P_pad * nc));
+    CHK(dalloc(c, w, &c->Yout, (int64_t)c->P_pad * nc));
+    CHK(dalloc(c, w, &c->dV, c->nnzB * nc));
+    CHK(dalloc(c, w, &c->W, c->nnzB * nc));
+    CHK(dalloc(c, w, &c->Tt, (int64_t)c->N_pad * mcol));
+    CHK(dalloc(c, w, &c->Ut, (int64_t)c->N_pad * mcol));
+    CHK(dalloc(c, w, &c->at, (int64_t)c->Nv_pad * mcol));
+    CHK(dalloc(c, w, &c->part, c->npart * nc));
+    CHK(dalloc(c, w, &c->omega_dev, nc / 2 + 1));
+    HIPCHK(c, hipDeviceSynchronize());
+    c->nc_cap = nc;
+    return CHI0_OK;
+}
+
+// Y = chi0(omega) Zin for nb column pairs already in Zin; omega_dev filled.
+static void run_chi0(chi0_ctx *c, hipStream_t s, int nb, double eps) {
+    const int nc = 2 * nb;
+    Tracer *t = &c->tracer;
+    const int64_t mcol = (int64_t)c->No_pad * nc;
+    launch_vertex_gather(t, s, c->bm, c->n_blk, c->Zin, c->dV, nc, nc);
+    launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, c->dV, c->Tt, nc, nc);
+    launch_dgemm_lorentz(t, s, c->Nv_pad, (int)mcol, c->N_pad, c->Xvt, c->N_pad, c->Tt, (int)mcol,
+                         c->at, (int)mcol, c->Dlt, c->Nv_pad, c->omega_dev, eps, c->occ, nc);
+    launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, c->at, (int)mcol,
+                 c->Ut, (int)mcol);
+    launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, c->Ut, c->W, nc, nc);
+    launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, c->W, c->part, c->Yout, nc, nc);
+}
+
+static const int kMaxBatch = 256;   // complex columns per operator pass
+
+extern "C" int chi0_apply(chi0_ctx *c, int32_t n_rhs, const double *omega, double eps,
+                          const double *z, double *out, int32_t precision, void *stream) {
+    if (!c) return CHI0_EINVAL;
+    if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no system on a device context");
+    if (n_rhs < 0) return fail(c, CHI0_EINVAL, "n_rhs < 0");
+    if (n_rhs == 0) return CHI0_OK;
+    if (!omega || !z || !out) return fail(c, CHI0_EINVAL, "NULL pointer");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
+    if (precision != CHI0_PREC_FP64) return fail(c, CHI0_EINVAL, "unsupported precision");
+    if (!all_finite(omega, n_rhs)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int cap = std::min(kMaxBatch, std::max(n_rhs, 1));
+    CHK(ensure_ws(c, 2 * std::max(cap, c->nc_cap / 2)));
+    for (int r0 = 0; r0 < n_rhs; r0 += cap) {
+        const int nb = std::min(cap, n_rhs - r0), nc = 2 * nb;
+        HIPCHK(c, hipMemcpyAsync(c->omega_dev, omega + r0, (size_t)nb * 8, hipMemcpyHostToDevice, s));
+        launch_rows_to_cols(&c->tracer, s, z + (int64_t)r0 * c->P * 2, nb, c->P, c->Zin, nc);
+        run_chi0(c, s, nb, eps);
+        launch_cols_to_rows(&c->tracer, s, c->Yout, nb, c->P, nc, out + (int64_t)r0 * c->P * 2);
+    }
+    HIPCHK(c, hipGetLastError());
+    return CHI0_OK;
+}
+
+// ================================================================== solver
+static int ensure_slots(chi0_ctx *c, int n, int m) {
+    if (n <= c->slot_n && m == c->slot_m) return CHI0_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->slotbuf.release();
+    c->slot_n = c->slot_m = 0;
+    DevBuf &b = c->slotbuf;
+    SlotsDev &sl = c->slots;
+    sl.m = m;
+    sl.P_pad = c->P_pad;
+    sl.vstride = (int64_t)(m + 1) * c->P_pad * 2;
+    sl.hstride = (int64_t)m * (m + 3) / 2 * 2;
+    CHK(dalloc(c, b, &sl.V, n * sl.vstride));
+    CHK(dalloc(c, b, &sl.H, n * sl.hstride));
+    CHK(dalloc(c, b, &sl.cs, (int64_t)n * m));
+    CHK(dalloc(c, b, &sl.sn, (int64_t)n * m * 2));
+    CHK(dalloc(c, b, &sl.g, (int64_t)n * (m + 1) * 2));
+    CHK(dalloc(c, b, &sl.x, (int64_t)n * c->P_pad * 2));
+    CHK(dalloc(c, b, &sl.b, (int64_t)n * c->P_pad * 2));
+    CHK(dalloc(c, b, &sl.hbuf, (int64_t)n * (m + 1) * 2));
+    CHK(dalloc(c, b, &sl.y, (int64_t)n * m * 2));
+    CHK(dalloc(c, b, &c->jobs_dev, n));
+    CHK(dalloc(c, b, &c->fin_dev, n));
+    CHK(dalloc(c, b, &c->upd_dev, n));
+    CHK(dalloc(c, b, &c->status_dev, n));
+    if (c->host_cap < n) {
+        if (c->jobs_h) (void)hipHostFree(c->jobs_h);
+        if (c->fin_h) (void)hipHostFree(c->fin_h);
+        if (c->upd_h) (void)hipHostFree(c->upd_h);
+        if (c->status_h) (void)hipHostFree(c->status_h);
+        if (c->omega_h) (void)hipHostFree(c->omega_h);
+        c->jobs_h = c->fin_h = c->upd_h = nullptr;
+        c->status_h = nullptr;
+        c->omega_h = nullptr;
+        c->host_cap = 0;
+        HIPCHK(c, hipHostMalloc((void **)&c->jobs_h, sizeof(Job) * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->fin_h, sizeof(Job) * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->upd_h, sizeof(Job) * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->status_h, sizeof(StepStatus) * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->omega_h, sizeof(double) * n, hipHostMallocDefault));
+        c->host_cap = n;
+    }
+    HIPCHK(c, hipDeviceSynchronize());
+    c->slot_n = n;
+    c->slot_m = m;
+    return CHI0_OK;
+}
+
+namespace {
+enum { S_FREE = 0, S_RHS, S_ARNOLDI, S_RESID };
+struct SlotState {
+    int state = S_FREE;
+    int point = -1;
+    int j = 0;
+    double bnorm = 0.0;
+};
+struct PointState {
+    int iters = 0, restarts = 0, converged = 0, breakdown = 0;
+    double rel = NAN;
+};
+}  // namespace
+
+extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *omega, double eps,
+                                   int32_t n_drive, const double *V_ext, const chi0_solve_opts *opts_in,
+                                   double *alpha, chi0_point_stats *stats) {
+    if (!c) return CHI0_EINVAL;
+    if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no system on a device context");
+    chi0_solve_opts o;
+    chi0_solve_opts_default(&o);
+    if (opts_in) o = *opts_in;
+    if (n_omega < 0 || n_drive < 1 || n_drive > 3) return fail(c, CHI0_EINVAL, "need n_omega >= 0, 1 <= n_drive <= 3");
+    if (n_omega == 0) return CHI0_OK;
+    if (!omega || !V_ext || !alpha) return fail(c, CHI0_EINVAL, "NULL pointer");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
+    if (o.restart < 1 || o.restart > 4000) return fail(c, CHI0_EINVAL, "restart must be in [1, 4000]");
+    if (o.max_iter < 1) return fail(c, CHI0_EINVAL, "max_iter must be >= 1");
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(c, CHI0_EINVAL, "tol must be finite and > 0");
+    if (o.batch < 1) return fail(c, CHI0_EINVAL, "batch must be >= 1");
+    if (o.precision != CHI0_PREC_FP64) return fail(c, CHI0_EINVAL, "unsupported precision");
+    for (int i = 0; i < 8; ++i)
+        if (o.reserved[i] != 0) return fail(c, CHI0_EINVAL, "reserved option fields must be zero");
+    if (!all_finite(omega, n_omega)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
+    if (!all_finite(V_ext, (int64_t)n_drive * c->P)) return fail(c, CHI0_ENONFINITE, "non-finite V_ext");
+    HIPCHK(c, hipSetDevice(c->device));
+
+    const int npts = n_omega * n_drive;
+    const int nsl = std::min(std::min(o.batch, npts), kMaxBatch);
+    const int m = o.restart;
+    const int P = c->P;
+    CHK(ensure_ws(c, 2 * std::max(nsl, c->nc_cap / 2)));
+    CHK(ensure_slots(c, nsl, m));
+    hipStream_t s = c->stream;
+    Tracer *t = &c->tracer;
+
+    // per-call device buffers: drives and alpha
+    DevBuf callbuf;
+    struct Guard { DevBuf *b; ~Guard() { b->release(); } } guard{&callbuf};
+    double *drives = nullptr, *alpha_dev = nullptr;
+    CHK(dalloc(c, callbuf, &drives, (int64_t)n_drive * c->P_pad));
+    CHK(dalloc(c, callbuf, &alpha_dev, (int64_t)npts * n_drive * 2));
+    HIPCHK(c, hipMemcpy2D(drives, (size_t)c->P_pad * 8, V_ext, (size_t)P * 8, (size_t)P * 8,
+                          (size_t)n_drive, hipMemcpyHostToDevice));
+    HIPCHK(c, hipDeviceSynchronize());
+
+    std::vector<SlotState> sl(nsl);
+    std::vector<PointState> ps(npts);
+    int next_point = 0, done = 0;
+    std::vector<Job> fin, upd;
+
+    while (done < npts) {
+        // (1) polarizability of points that finished last step (before their slot is reused)
+        if (!fin.empty()) {
+            std::copy(fin.begin(), fin.end(), c->fin_h);
+            HIPCHK(c, hipMemcpyAsync(c->fin_dev, c->fin_h, sizeof(Job) * fin.size(), hipMemcpyHostToDevice, s));
+            launch_alpha(t, s, c->fin_dev, (int)fin.size(), c->slots, drives, n_drive, c->P_pad, P,
+                         nullptr, alpha_dev);
+            fin.clear();
+        }
+        // (2) x += V y for slots that ended a cycle
+        if (!upd.empty()) {
+            int jm = 0;
+            for (auto &u : upd) jm = std::max(jm, u.j);
+            std::copy(upd.begin(), upd.end(), c->upd_h);
+            HIPCHK(c, hipMemcpyAsync(c->upd_dev, c->upd_h, sizeof(Job) * upd.size(), hipMemcpyHostToDevice, s));
+            launch_update_x(t, s, c->upd_dev, (int)upd.size(), jm, c->slots, P);
+            upd.clear();
+        }
+        // (3) refill free slots
+        for (int k = 0; k < nsl; ++k)
+            if (sl[k].state == S_FREE && next_point < npts) {
+                sl[k].state = S_RHS;
+                sl[k].point = next_point++;
+                sl[k].j = 0;
+            }
+        // (4) one job per active slot
+        int nb = 0, jmax = -1;
+        bool any_arnoldi = false;
+        for (int k = 0; k < nsl; ++k) {
+            if (sl[k].state == S_FREE) continue;
+            Job jb;
+            jb.slot = k;
+            jb.type = sl[k].state == S_RHS ? JOB_RHS : sl[k].state == S_ARNOLDI ? JOB_ARNOLDI : JOB_RESID;
+            jb.j = sl[k].j;
+            jb.drive = sl[k].point % n_drive;
+            if (jb.type == JOB_ARNOLDI) { any_arnoldi = true; jmax = std::max(jmax, jb.j); }
+            c->jobs_h[nb] = jb;
+            c->omega_h[nb] = omega[sl[k].point / n_drive];
+            ++nb;
+        }
+        if (nb == 0) break;
+        const int nc = 2 * nb;
+        HIPCHK(c, hipMemcpyAsync(c->jobs_dev, c->jobs_h, sizeof(Job) * nb, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(c->omega_dev, c->omega_h, sizeof(double) * nb, hipMemcpyHostToDevice, s));
+        // (5) operator: Zin = K v (b jobs: d), Y = chi0 Zin
+        launch_gather_jobs(t, s, c->jobs_dev, nb, c->slots, c->Vb, nc, P);
+        if (nc <= 16)
+            launch_kmatvec_skinny(t, s, c->P_pad, c->K, c->Vb, c->Zin, nc);
+        else
+            launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, c->Vb, nc, c->Zin, nc);
+        launch_put_drive(t, s, c->jobs_dev, nb, drives, c->P_pad, c->Zin, nc, P);
+        run_chi0(c, s, nb, eps);
+        launch_post_jobs(t, s, c->jobs_dev, nb, c->slots, c->Yout, nc, P, c->status_dev);
+        if (any_arnoldi) launch_arnoldi(t, s, c->jobs_dev, nb, jmax, c->slots, P, c->status_dev);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(c->status_h, c->status_dev, sizeof(StepStatus) * nb, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        // (6) advance the slot state machines
+        for (int q = 0; q < nb; ++q) {
+            const Job &jb = c->jobs_h[q];
+            SlotState &ss = sl[jb.slot];
+            PointState &pt = ps[ss.point];
+            const StepStatus &st = c->status_h[q];
+            if (jb.type == JOB_RHS) {
+                ss.bnorm = st.value;
+                if (!(st.value > 0.0) || !std::isfinite(st.value)) {
+                    pt.rel = st.value == 0.0 ? 0.0 : NAN;
+                    pt.converged = st.value == 0.0;
+                    fin.push_back({jb.slot, 0, ss.point, 0});
+                    ss.state = S_FREE;
+                    ++done;
+                } else {
+                    ss.state = S_ARNOLDI;
+                    ss.j = 0;
+                }
+            } else if (jb.type == JOB_ARNOLDI) {
+                pt.iters += 1;
+                const bool conv_est = st.value <= o.tol * ss.bnorm;
+                const bool brk = st.hnext == 0.0;
+                if (brk) pt.breakdown = 1;
+                if (conv_est || brk || ss.j + 1 >= m || pt.iters >= o.max_iter || !std::isfinite(st.value)) {
+                    upd.push_back({jb.slot, 0, ss.j + 1, 0});
+                    ss.state = S_RESID;
+                } else {
+                    ss.j += 1;
+                }
+            } else {
+                pt.restarts += 1;
+                pt.rel = st.value / ss.bnorm;
+                if (pt.rel <= o.tol || pt.iters >= o.max_iter || !std::isfinite(pt.rel)) {
+                    pt.converged = pt.rel <= o.tol;
+                    fin.push_back({jb.slot, 0, ss.point, 0});
+                    ss.state = S_FREE;
+                    ++done;
+                } else {
+                    ss.state = S_ARNOLDI;
+                    ss.j = 0;
+                }
+            }
+        }
+    }
+    if (!fin.empty()) {
+        std::copy(fin.begin(), fin.end(), c->fin_h);
+        HIPCHK(c, hipMemcpyAsync(c->fin_dev, c->fin_h, sizeof(Job) * fin.size(), hipMemcpyHostToDevice, s));
+        launch_alpha(t, s, c->fin_dev, (int)fin.size(), c->slots, drives, n_drive, c->P_pad, P, nullptr, alpha_dev);
+        fin.clear();
+    }
+    std::vector<double> ah((size_t)npts * n_drive * 2);
+    HIPCHK(c, hipMemcpyAsync(ah.data(), alpha_dev, ah.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipGetLastError());
+    int not_conv = 0;
+    for (int w = 0; w < n_omega; ++w)
+        for (int i = 0; i < n_drive; ++i) {
+            const int p = w * n_drive + i;
+            for (int k = 0; k < n_drive; ++k) {
+                alpha[(((size_t)w * n_drive + k) * n_drive + i) * 2] = ah[((size_t)p * n_drive + k) * 2];
+                alpha[(((size_t)w * n_drive + k) * n_drive + i) * 2 + 1] = ah[((size_t)p * n_drive + k) * 2 + 1];
+            }
+            if (!ps[p].converged) ++not_conv;
+            if (stats) {
+                chi0_point_stats &r = stats[p];
+                r.iterations = ps[p].iters;
+                r.restarts = ps[p].restarts;
+                r.converged = ps[p].converged;
+                r.breakdown = ps[p].breakdown;
+                r.rel_residual = ps[p].rel;
+            }
+        }
+    c->err.clear();
+    if (not_conv) {
+        c->err = std::to_string(not_conv) + " point(s) did not reach the tolerance";
+        return CHI0_NOT_CONVERGED;
+    }
+    return CHI0_OK;
+}

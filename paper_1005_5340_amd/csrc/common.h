@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP translation units of libchi0.
+//
+// Device data layout (all FP64; "pad" sizes are multiples of the tile sizes
+// and the padding is kept at zero so no kernel needs edge checks along it):
+//   Xo   [N_pad][No_pad]   occupied columns of X, row = atomic orbital
+//   Xv   [N_pad][Nv_pad]   virtual columns of X
+//   Xvt  [Nv_pad][N_pad]   transpose of Xv
+//   Dlt  [No_pad][Nv_pad]  transition energies e_F - e_E (padding = 1)
+//   K    [P_pad][P_pad]    kernel matrix
+//   Vp   per atom-pair block k=(A,B): the sub-blocks V_mu[A-part][B-part] of
+//        every product mu whose support covers (A,B), each n_A x n_B row-major
+//
+// A batch of nb complex right-hand sides is carried as nc = 2*nb real
+// columns (column 2r = real part, 2r+1 = imaginary part of RHS r); ncp is nc
+// rounded up to the column tile (16).  Operator buffers are [rows][ncp].
+// The orbital-transform intermediates index their long dimension by
+// m = E*ncp + j (occupied state E, column j):
+//   dV, W [nnzB][ncp]            block-sparse, entry (k, a, b) -> row ent(k)+a*n_B+b
+//   Tt, Ut [N_pad][No_pad*ncp]   Tt[b][m] = (X_occ^T dV)[E][b] of column j
+//   at    [Nv_pad][No_pad*ncp]   at[F][m] = (X_occ^T dV X_virt)[E][F], then scaled
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chi0 {
+
+constexpr int TILE = 64;     // M/N tile of the dense GEMMs, E tile of the gathered ones
+constexpr int JT = 16;       // column tile of the gathered GEMMs and of ncp
+constexpr int NB_MAX = 16;   // maximum orbitals per atom supported by the gathered GEMMs
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ------------------------------------------------------------- kernel timing
+// Every launch goes through launch_begin/launch_end so that per-kernel
+// durations can be accumulated with HIP events when tracing is enabled.
+struct Tracer;
+void trace_begin(Tracer *t, const char *name, hipStream_t s);
+void trace_end(Tracer *t, hipStream_t s);
+
+// -------------------------------------------------------------- chi0 blocks
+struct BlockMapDev {
+    // per atom-pair block k (n_blk of them)
+    const int32_t *blk_nprod;     // products covering the block
+    const int64_t *blk_pstart;    // start of the block's entries in pidx / part
+    const int64_t *blk_vstart;    // start of the block's vertex panel in Vp (doubles)
+    const int64_t *blk_ent;       // first entry row of the block in dV / W
+    const int32_t *blk_na;        // n_A
+    const int32_t *blk_nb;        // n_B
+    const int32_t *pidx;          // [sum nprod] product of each (block, slot)
+    const double *Vp;             // vertex panels
+    // per column atom B: gathered rows (A, a) over the blocks (A, B)
+    const int32_t *col_gstart;    // [n_atoms+1] start of atom B's gathered rows
+    const int32_t *g_xrow;        // [n_g] global orbital a of the row
+    const int64_t *g_ent;         // [n_g] entry row of (k(A,B), a, b=0) in dV / W
+    const int32_t *atom_off;      // [n_atoms+1] orbital offsets
+    // per product: positions of its (block, slot) pairs in part
+    const int64_t *prod_pstart;   // [P+1]
+    const int64_t *prod_plist;    // [sum]
+};
+
+// ------------------------------------------------------------ launch wrappers
+// (a) dV = sum_mu z_mu V_mu, per block.
+void launch_vertex_gather(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk,
+                          const double *Z, double *dV, int nc, int ncp);
+// (d) n_mu = <V_mu, W>: per-block partial sums, then the sum over each product's blocks.
+void launch_vertex_contract(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk, int P,
+                            const double *W, double *part, double *Y, int nc, int ncp);
+// (b1) Tt = X_occ^T dV (gathered MFMA GEMM over the block pattern).
+void launch_occ_transform(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms,
+                          const double *Xo, int no_pad, const double *dV, double *Tt,
+                          int nc, int ncp);
+// (b4) W = X_occ Ut restricted to the block pattern.
+void launch_occ_back(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
+                     const double *Xo, int no_pad, const double *Ut, double *W, int nc, int ncp);
+// Dense FP64 MFMA GEMM C = A B (row-major, M%64 == K%16 == 0, N masked at n_valid).
+void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
+                  const double *A, int lda, const double *B, int ldb, double *C, int ldc);
+// (b2)+(c) at = Xvt Tt with the Lorentzian factor of column (E, j) and row F applied.
+void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K,
+                          const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                          const double *Dlt, int nv_pad, const double *omega, double eps,
+                          double occ, int ncp);
+// (e) skinny K z for a few columns (HBM-streaming GEMV).
+void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
+                           const double *Zin, double *Zout, int ncp);
+
+// ------------------------------------------------------------- Krylov support
+struct Job {
+    int32_t slot;
+    int32_t type;     // JOB_RHS, JOB_ARNOLDI, JOB_RESID
+    int32_t j;        // Arnoldi index (JOB_ARNOLDI) / cycle length for update_x
+    int32_t drive;    // drive index of the slot's point
+};
+enum { JOB_RHS = 0, JOB_ARNOLDI = 1, JOB_RESID = 2 };
+
+struct SlotsDev {
+    double *V;        // [n_slots][m+1][P_pad] complex (interleaved)
+    double *H;        // [n_slots][m(m+3)/2] complex, column j packed at j(j+3)/2, j+2 entries
+    double *cs;       // [n_slots][m] real
+    double *sn;       // [n_slots][m] complex
+    double *g;        // [n_slots][m+1] complex
+    double *x;        // [n_slots][P_pad] complex
+    double *b;        // [n_slots][P_pad] complex
+    double *hbuf;     // [n_slots][m+1] complex scratch for Gram-Schmidt coefficients
+    double *y;        // [n_slots][m] complex least-squares solution
+    int64_t vstride;  // doubles between slots in V  = (m+1)*P_pad*2
+    int64_t hstride;  // doubles between slots in H
+    int m;
+    int P_pad;
+};
+
+struct StepStatus {
+    double value;     // JOB_RHS: ||b||; JOB_ARNOLDI: |g_{j+1}|; JOB_RESID: ||r||
+    double hnext;     // JOB_ARNOLDI: h_{j+1,j}
+};
+
+void launch_gather_jobs(Tracer *t, hipStream_t s, const Job *jobs, int nb, const SlotsDev &sl,
+                        double *Vb, int ncp, int P);
+void launch_put_drive(Tracer *t, hipStream_t s, const Job *jobs, int nb, const double *drives,
+                      int P_pad, double *Zin, int ncp, int P);
+void launch_post_jobs(Tracer *t, hipStream_t s, const Job *jobs, int nb, const SlotsDev &sl,
+                      const double *Y, int ncp, int P, StepStatus *status);
+void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
+                    const SlotsDev &sl, int P, StepStatus *status);
+void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
+                     const SlotsDev &sl, int P);
+void launch_alpha(Tracer *t, hipStream_t s, const Job *jobs, int n, const SlotsDev &sl,
+                  const double *drives, int n_drive, int P_pad, int P, const int32_t *out_index,
+                  double *alpha_out);
+// apply: caller rows [r][P] complex <-> operator columns [P_pad][ncp]
+void launch_rows_to_cols(Tracer *t, hipStream_t s, const double *z, int nb, int P,
+                         double *Zin, int ncp);
+void launch_cols_to_rows(Tracer *t, hipStream_t s, const double *Y, int nb, int P, int ncp,
+                         double *out);
+void launch_zero(Tracer *t, hipStream_t s, double *p, int64_t n);
+
+}  // namespace chi0

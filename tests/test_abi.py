@@ -1,0 +1,104 @@
+"""The C-ABI library: loads, exports every declared symbol, validates inputs.
+
+CPU only: a host-only context (device -1) runs chi0_set_system's validation
+and block-map construction without touching a GPU.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1005_5340_amd import chi0, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chi0.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(chi0_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(chi0.LIB_PATH):
+        pytest.fail("libchi0.so not built (run __graft_entry__.build())")
+    return chi0.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in chi0.h but not exported"
+
+
+def test_host_only_context_validates_and_sizes(L):
+    s = synth.make_system("atoms4_orb4", seed=0)
+    with chi0.Context(-1) as ctx:
+        ctx.set_system_from(s)
+        assert ctx.sizes() == dict(n_orb=16, n_occ=8, n_prod=s.n_prod, n_atoms=4)
+        # computing needs a device
+        with pytest.raises(chi0.Chi0Error) as e:
+            ctx.solve_response([0.1], 0.02, s.drives("z"))
+        assert e.value.code == -2
+
+
+def _args(s):
+    return dict(n_atoms=s.n_atoms, positions=s.positions, n_orb=s.n_orb, n_occ=s.n_occ,
+                occ_factor=s.occ_factor, eigenvalues=s.eigenvalues.copy(), X=s.X.copy(),
+                atom_orb_offset=s.atom_orb_offset.copy(), n_prod=s.n_prod,
+                prod_atoms=s.prod_atoms.copy(), vblock_offset=s.vblock_offset.copy(),
+                vblock=s.vblock.copy(), K=s.K.copy())
+
+
+@pytest.mark.parametrize("case,code", [
+    ("nan_K", -5), ("inf_vertex", -5), ("asym_K", -6), ("asym_vertex", -6),
+    ("unshifted_energy", -1), ("bad_occ", -1), ("bad_offset", -1), ("bad_prod_atom", -1),
+    ("bad_vblock_offset", -1), ("occ_factor", -1), ("too_many_orbitals", -1),
+])
+def test_set_system_error_codes(L, case, code):
+    s = synth.make_system("atoms4_orb4", seed=0)
+    a = _args(s)
+    if case == "nan_K":
+        a["K"][1, 2] = np.nan
+    elif case == "inf_vertex":
+        a["vblock"][5] = np.inf
+    elif case == "asym_K":
+        a["K"][0, 3] += 1e-6
+    elif case == "asym_vertex":
+        a["vblock"][1] += 1e-3
+    elif case == "unshifted_energy":
+        a["eigenvalues"][0] = 0.1
+    elif case == "bad_occ":
+        a["n_occ"] = s.n_orb
+    elif case == "bad_offset":
+        a["atom_orb_offset"][2] = a["atom_orb_offset"][1]
+    elif case == "bad_prod_atom":
+        a["prod_atoms"][3, 1] = a["prod_atoms"][3, 0]
+    elif case == "bad_vblock_offset":
+        a["vblock_offset"][2] += 1
+    elif case == "occ_factor":
+        a["occ_factor"] = 0.0
+    elif case == "too_many_orbitals":
+        a["atom_orb_offset"] = np.array([0, 1, 2, 3, 16], np.int32)
+    with chi0.Context(-1) as ctx:
+        with pytest.raises(chi0.Chi0Error) as e:
+            ctx.set_system(**a)
+        assert e.value.code == code, str(e.value)
+        assert ctx.last_error
+
+
+def test_create_rejects_bad_device(L):
+    h = C.c_void_p()
+    assert L.chi0_create(C.byref(h), -7) == -1
+    assert b"device" in L.chi0_last_error(None)
+
+
+def test_default_options(L):
+    o = chi0.SolveOpts()
+    L.chi0_solve_opts_default(C.byref(o))
+    assert (o.restart, o.max_iter, o.tol, o.precision, o.batch) == (30, 10000, 1e-10, 0, 1)

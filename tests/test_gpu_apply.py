@@ -1,0 +1,96 @@
+"""chi0(w) z on the GPU (HIP path, through the C-ABI) against the FP64 oracle.
+
+Bar: FP64 arithmetic with different summation order, so the normwise
+relative difference per right-hand side must stay below 1e-12 (the factored
+sequence has ~4 dependent sums over <= a few thousand terms).
+"""
+import numpy as np
+import pytest
+
+import gpu_systems
+from oracle import chi0_oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a GPU"
+    return T
+
+
+def _ctx(sys):
+    from paper_1005_5340_amd import chi0
+    c = chi0.Context(0)
+    c.set_system_from(sys)
+    return c
+
+
+def _check(torch, ctx, sys, om, seed, tol=1e-12):
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((om.size, sys.n_prod)) + 1j * rng.standard_normal((om.size, sys.n_prod))
+    out = ctx.apply(om, sys.eps, torch.from_numpy(z).cuda())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    worst = 0.0
+    for k, w in enumerate(om):
+        ref = orc.chi0_apply(sys, float(w), z[k])
+        e = np.linalg.norm(got[k] - ref) / np.linalg.norm(ref)
+        worst = max(worst, e)
+    print(f"[apply] {sys.workload.name} n_rhs={om.size} worst rel err {worst:.2e}", flush=True)
+    assert worst < tol
+
+
+@pytest.mark.parametrize("name", ["atoms4_orb4", "tiny3", "atoms12_orb9", "atoms8_orb13"])
+@pytest.mark.parametrize("n_rhs", [1, 2, 5, 40])
+def test_apply_matches_oracle(torch, name, n_rhs):
+    sys = gpu_systems.get(name)
+    ctx = _ctx(sys)
+    om = np.linspace(-0.5, 1.6, n_rhs) if n_rhs > 1 else np.array([0.37])
+    if n_rhs >= 5:
+        om[1] = 0.0
+    _check(torch, ctx, sys, om, seed=n_rhs)
+    ctx.close()
+
+
+def test_apply_more_than_one_pass(torch):
+    """300 right-hand sides: more than one operator pass (256 per pass)."""
+    sys = gpu_systems.get("atoms4_orb4")
+    ctx = _ctx(sys)
+    om = np.linspace(0.0, 1.5, 300)
+    _check(torch, ctx, sys, om, seed=11)
+    ctx.close()
+
+
+def test_apply_reuses_workspace_across_sizes(torch):
+    """A large batch then a small one on the same context (stale workspace)."""
+    sys = gpu_systems.get("atoms12_orb9")
+    ctx = _ctx(sys)
+    _check(torch, ctx, sys, np.linspace(0.0, 1.5, 64), seed=1)
+    _check(torch, ctx, sys, np.array([0.8]), seed=2)
+    _check(torch, ctx, sys, np.linspace(0.1, 0.9, 3), seed=3)
+    ctx.close()
+
+
+def test_apply_full_size_atoms60(torch):
+    """Full 60-atom system (N=540, P~3.3k) at sampled frequencies."""
+    from paper_1005_5340_amd import synth
+    sys = synth.make_system("atoms60_orb9", 0)
+    ctx = _ctx(sys)
+    _check(torch, ctx, sys, np.array([0.0, 0.61, 1.37]), seed=5)
+    ctx.close()
+
+
+def test_apply_linearity_and_symmetry(torch):
+    """chi0(-w) z = conj(chi0(w) conj z) and chi0 is complex symmetric: u.chi0 v = v.chi0 u."""
+    sys = gpu_systems.get("atoms12_orb9")
+    ctx = _ctx(sys)
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal(sys.n_prod) + 1j * rng.standard_normal(sys.n_prod)
+    v = rng.standard_normal(sys.n_prod) + 1j * rng.standard_normal(sys.n_prod)
+    Z = torch.from_numpy(np.stack([u, v, np.conj(u)])).cuda()
+    out = ctx.apply(np.array([0.7, 0.7, -0.7]), sys.eps, Z).cpu().numpy()
+    assert abs(u @ out[1] - v @ out[0]) < 1e-12 * abs(u @ out[1])
+    assert np.linalg.norm(out[2] - np.conj(out[0])) < 1e-12 * np.linalg.norm(out[0])
+    ctx.close()

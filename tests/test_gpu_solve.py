@@ -1,0 +1,111 @@
+"""GMRES polarizability on the GPU against the oracle's dense LU solve.
+
+Error measure for Im alpha (per point): |Im a - Im a_ref| / max(|Im a_ref|,
+1e-3 max_w |Im a_ref|); at w = 0, Im alpha = 0 exactly, hence the floor.
+The parity bar is 1e-10 for the FP64 path; GMRES is run to a relative
+residual of 1e-13 here so that the stopping test, not arithmetic, would be
+the limit (Im alpha << |alpha| off resonance amplifies the solve error).
+"""
+import numpy as np
+import pytest
+
+import gpu_systems
+import pins
+from oracle import chi0_oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+
+def im_err(a, ref):
+    a, ref = np.asarray(a), np.asarray(ref)
+    floor = 1e-3 * np.max(np.abs(ref.imag))
+    return np.abs(a.imag - ref.imag) / np.maximum(np.abs(ref.imag), floor)
+
+
+def _ctx(sys):
+    from paper_1005_5340_amd import chi0
+    c = chi0.Context(0)
+    c.set_system_from(sys)
+    return c
+
+
+@pytest.mark.parametrize("batch", [1, 64])
+def test_full_grid_atoms4(batch):
+    from paper_1005_5340_amd import synth
+    sys = synth.make_system("atoms4_orb4", 0)
+    d = sys.drives("z")
+    ctx = _ctx(sys)
+    alpha, st, rc = ctx.solve_response(sys.omegas, sys.eps, d, restart=sys.n_prod, tol=1e-13, batch=batch)
+    ref = orc.polarizability(sys, sys.omegas, d)
+    e = im_err(alpha[:, 0, 0], ref[:, 0, 0])
+    print(f"[solve] atoms4 batch={batch} max Im err {e.max():.2e} iters {st['iterations'].max()}", flush=True)
+    assert rc == 0 and st["converged"].all()
+    assert e.max() < 1e-10
+    assert np.max(np.abs(alpha - ref)) < 1e-10 * np.max(np.abs(ref))
+    ctx.close()
+
+
+def test_batched_equals_plain_and_tensor():
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("xyz")
+    om = np.array([0.0, 0.21, 0.5, 0.93, 1.2])
+    ctx = _ctx(sys)
+    a1, s1, r1 = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-13, batch=1)
+    a2, s2, r2 = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-13, batch=7)
+    ref = orc.polarizability(sys, om, d)
+    print(f"[solve] atoms12 plain/batched iters {s1['iterations'].max()}/{s2['iterations'].max()}", flush=True)
+    assert r1 == 0 and r2 == 0
+    assert np.max(np.abs(a1 - ref)) < 1e-10 * np.max(np.abs(ref))
+    for i in range(3):
+        assert im_err(a1[:, i, i], ref[:, i, i]).max() < 1e-10
+    # same arithmetic per point regardless of batch composition
+    assert np.max(np.abs(a1 - a2)) < 1e-12 * np.max(np.abs(a1))
+    ctx.close()
+
+
+def test_restarted_gmres_atoms12():
+    """GMRES(m) with restarts reaches the same answer."""
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("z")
+    om = np.array([0.3, 1.1])
+    ctx = _ctx(sys)
+    a, st, rc = ctx.solve_response(om, sys.eps, d, restart=60, max_iter=20000, tol=1e-12, batch=2)
+    ref = orc.polarizability(sys, om, d)
+    print(f"[solve] GMRES(60) restarts {st['restarts'].ravel().tolist()}", flush=True)
+    assert rc == 0
+    assert np.max(np.abs(a - ref)) < 1e-9 * np.max(np.abs(ref))
+    ctx.close()
+
+
+def test_two_level_breakdown_exact():
+    """One product: the Krylov space is invariant after one step (happy breakdown)."""
+    sys = pins.two_level_system()
+    om = np.array([0.0, 0.5, 1.0, 1.118033988749895, 2.0, -1.0])
+    ctx = _ctx(sys)
+    a, st, rc = ctx.solve_response(om, sys.eps, np.array([[1.0]]), restart=5, tol=1e-14)
+    assert rc == 0
+    assert np.max(np.abs(a[:, 0, 0] - pins.two_level_alpha(om))) < 1e-13 * np.max(np.abs(a))
+    assert (st["iterations"] == 1).all()
+    ctx.close()
+
+
+def test_not_converged_is_reported():
+    sys = gpu_systems.get("atoms12_orb9")
+    ctx = _ctx(sys)
+    from paper_1005_5340_amd import chi0
+    a, st, rc = ctx.solve_response([0.4], sys.eps, sys.drives("z"), restart=2, max_iter=3, tol=1e-12)
+    assert rc == chi0.NOT_CONVERGED
+    assert st["converged"][0, 0] == 0 and st["iterations"][0, 0] == 3
+    assert np.isfinite(a).all()
+    ctx.close()
+
+
+def test_empty_grid_and_conjugate_frequency():
+    from paper_1005_5340_amd import synth
+    sys = synth.make_system("atoms4_orb4", 0)
+    ctx = _ctx(sys)
+    a, st, rc = ctx.solve_response([], sys.eps, sys.drives("z"))
+    assert rc == 0 and a.shape == (0, 1, 1)
+    a, st, rc = ctx.solve_response([0.7, -0.7], sys.eps, sys.drives("z"), restart=sys.n_prod, tol=1e-13, batch=2)
+    assert abs(a[1, 0, 0] - np.conj(a[0, 0, 0])) < 1e-11 * abs(a[0, 0, 0])
+    ctx.close()
