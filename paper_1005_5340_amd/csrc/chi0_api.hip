@@ -826,3 +826,41 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
     }
     return CHI0_OK;
 }
+
+// ============================================================= test hooks
+#include "chi0_debug.h"
+
+extern "C" int chi0_debug_dims(const chi0_ctx *c, int64_t *d) {
+    if (!c || !d) return CHI0_EINVAL;
+    if (!c->has_system) return CHI0_ENOSYS;
+    const int64_t v[10] = {c->N, c->No, c->Nv, c->P, c->N_pad, c->No_pad, c->Nv_pad, c->P_pad,
+                           c->n_blk, c->nnzB};
+    for (int i = 0; i < 10; ++i) d[i] = v[i];
+    return CHI0_OK;
+}
+
+extern "C" int chi0_debug_read(chi0_ctx *c, int32_t which, void *host, int64_t bytes) {
+    if (!c || !host || bytes < 0) return CHI0_EINVAL;
+    if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no device system");
+    const int64_t nc = c->nc_cap, mcol = (int64_t)c->No_pad * nc;
+    const void *src = nullptr;
+    int64_t cap = 0;
+    switch (which) {
+        case CHI0_DBG_ZIN: src = c->Zin; cap = (int64_t)c->P_pad * nc * 8; break;
+        case CHI0_DBG_DV: src = c->dV; cap = c->nnzB * nc * 8; break;
+        case CHI0_DBG_TT: src = c->Tt; cap = (int64_t)c->N_pad * mcol * 8; break;
+        case CHI0_DBG_AT: src = c->at; cap = (int64_t)c->Nv_pad * mcol * 8; break;
+        case CHI0_DBG_UT: src = c->Ut; cap = (int64_t)c->N_pad * mcol * 8; break;
+        case CHI0_DBG_W: src = c->W; cap = c->nnzB * nc * 8; break;
+        case CHI0_DBG_YOUT: src = c->Yout; cap = (int64_t)c->P_pad * nc * 8; break;
+        case CHI0_DBG_BLK_NA: src = c->bm.blk_na; cap = (int64_t)c->n_blk * 4; break;
+        case CHI0_DBG_BLK_NB: src = c->bm.blk_nb; cap = (int64_t)c->n_blk * 4; break;
+        case CHI0_DBG_BLK_ENT: src = c->bm.blk_ent; cap = (int64_t)c->n_blk * 8; break;
+        default: return fail(c, CHI0_EINVAL, "unknown buffer");
+    }
+    if (!src || bytes > cap) return fail(c, CHI0_EINVAL, "buffer not allocated or too small");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(host, src, (size_t)bytes, hipMemcpyDeviceToHost));
+    return CHI0_OK;
+}

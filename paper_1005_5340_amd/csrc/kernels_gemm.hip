@@ -5,7 +5,8 @@
 // Operand layout of one 16x16x4 step (lane l = 0..63):
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
 //   B (4 x 16):  lane l holds B[l / 16][l % 16]
-//   D (16 x 16): lane l holds D[4*(l/16) + r][l % 16] in element r = 0..3
+//   D (16 x 16): lane l holds D[4*r + l/16][l % 16] in element r = 0..3
+//                (rows interleaved by 4; checked on gfx950 with a lane probe)
 #include "common.h"
 
 namespace chi0 {
@@ -135,15 +136,16 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
         }
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
-            const int row0 = m0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4);
+            const int row0 = m0 + wm * (BM / WM) + i * 16 + (lane >> 4);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                const int row = row0 + 4 * r;
                 double v = acc[i][j][r];
                 if (LORENTZ) {
                     // L = n [1/(w - D + i eps) - 1/(w + D + i eps)], applied to
                     // the complex number held by this lane and its xor-1 partner.
                     const double other = __shfl_xor(v, 1);
-                    const double D = la.Dlt[(int64_t)E * la.nv_pad + row0 + r];
+                    const double D = la.Dlt[(int64_t)E * la.nv_pad + row];
                     const double d1 = w - D, d2 = w + D, e = la.eps;
                     const double s1 = 1.0 / (d1 * d1 + e * e), s2 = 1.0 / (d2 * d2 + e * e);
                     const double Lr = la.occ * (d1 * s1 - d2 * s2);
@@ -151,7 +153,7 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
                     const double re = par ? other : v, im = par ? v : other;
                     v = par ? (re * Li + im * Lr) : (re * Lr - im * Li);
                 }
-                if (ok) C[(int64_t)(row0 + r) * ldc + col] = v;
+                if (ok) C[(int64_t)row * ldc + col] = v;
             }
         }
     }
@@ -236,7 +238,7 @@ void k_occ_transform(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
             if (b < nB) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int E = e0 + wv * 16 + 4 * (lane >> 4) + r;
+                    const int E = e0 + wv * 16 + 4 * r + (lane >> 4);
                     Tt[(int64_t)(boff + b) * ldT + (int64_t)E * nc + j] = acc[b][r];
                 }
             }
@@ -304,7 +306,7 @@ void k_occ_back(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
     if (j < nc) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int g = g0 + wv * 16 + 4 * (lane >> 4) + r;
+            const int g = g0 + wv * 16 + 4 * r + (lane >> 4);
             if (g < g1) {
                 const int64_t base = bm.g_ent[g];
 #pragma unroll
