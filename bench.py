@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark: absorption-spectrum throughput of the GMRES polarizability solver.
+
+One step = the whole hot path once: solve (1 - chi0(w) K) x = chi0(w) d for
+every frequency of the workload's grid and every drive, then alpha = -d.x
+(all points of the spectrum).  The timed region covers `--steps` such
+solves with the system already resident in HBM.
+
+Printed JSON line (rank 0):
+  value      spectrum points per second that reach 1e-6 relative error in
+             Im alpha against the stored FP64 oracle reference
+  roofline   the kernel with the largest share of GPU time, its algorithmic
+             work per launch over its mean launch duration (HIP events on
+             the stream it runs on), against the MI355X peak of its bound
+  cpu_baseline  the FP64 oracle (dense chi0 + LU) timed on this host's cores
+             on a sample of the same workload
+
+Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload atoms60_orb9]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK = {"mfma": (78.6e12, "TFLOP/s"), "hbm": (8.0e12, "GB/s")}   # MI355X FP64 matrix, HBM3E
+CHI0_KERNELS = ("vertex_gather", "occ_transform", "virt_transform_lorentz", "virt_back",
+                "occ_back", "vertex_contract", "vertex_reduce")
+MFMA_KERNELS = ("virt_transform_lorentz", "virt_back", "occ_transform", "occ_back", "kernel_matmul")
+KERNEL_SOURCES = {  # kernel -> source file that defines it (for the counter-staleness check)
+    "virt_transform_lorentz": "kernels_gemm.hip", "virt_back": "kernels_gemm.hip",
+    "kernel_matmul": "kernels_gemm.hip", "kernel_matvec": "kernels_gemm.hip",
+    "occ_transform": "kernels_gemm.hip", "occ_back": "kernels_gemm.hip",
+    "vertex_gather": "kernels_vertex.hip", "vertex_contract": "kernels_vertex.hip",
+    "vertex_reduce": "kernels_vertex.hip",
+}
+
+
+def im_errors(a, ref):
+    floor = 1e-3 * np.max(np.abs(ref.imag))
+    return np.abs(a.imag - ref.imag) / np.maximum(np.abs(ref.imag), floor)
+
+
+def source_sha(kernel):
+    f = os.path.join(ROOT, "paper_1005_5340_amd", "csrc", KERNEL_SOURCES.get(kernel, "kernels_krylov.hip"))
+    return hashlib.sha256(open(f, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counters, or None if absent or stale."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha") != source_sha(kernel):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(sys_, drives, n_sample, seed=0):
+    from threadpoolctl import threadpool_info
+    from oracle import chi0_oracle as orc
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(sys_.omegas.size, size=n_sample, replace=False))
+    t0 = time.perf_counter()
+    for k in idx:
+        orc.polarizability(sys_, [sys_.omegas[k]], drives)
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()
+                   if p.get("user_api") == "blas"] or [1])
+    pts = n_sample * drives.shape[0]
+    return {"value": pts / dt, "unit": "spectrum points/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_sample} of {sys_.omegas.size} frequencies x {drives.shape[0]} drive(s) "
+                      f"(grid indices {idx.tolist()}), dense chi0 + LU in FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="atoms60_orb9")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=128, help="points solved concurrently")
+    ap.add_argument("--restart", type=int, default=0, help="GMRES(m); 0 = unrestarted (m = n_prod)")
+    ap.add_argument("--tol", type=float, default=0.0, help="0 = the workload's tolerance")
+    ap.add_argument("--max-iter", type=int, default=10000)
+    ap.add_argument("--cpu-sample", type=int, default=2, help="frequencies for the oracle baseline (0 = skip)")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              "(the (frequency, drive) points would be sharded across GPUs with no exchange "
+              "but the final gather of alpha; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1005_5340_amd import chi0, synth
+
+    w = synth.WORKLOADS[a.workload]
+    s = synth.make_system(a.workload, a.seed)
+    drives = s.drives()
+    tol = a.tol or w.tol
+    restart = a.restart or s.n_prod
+    ctx = chi0.Context(0)
+    ctx.set_system_from(s)
+
+    ref = None
+    refpath = os.path.join(ROOT, "tests", "golden", f"reference_{a.workload}_s{a.seed}.json")
+    if os.path.exists(refpath):
+        r = json.load(open(refpath))
+        if synth.same_inputs(s, r["fingerprint"]) and r["omega_index"] == list(range(s.omegas.size)):
+            ref = np.array(r["alpha_re"]) + 1j * np.array(r["alpha_im"])
+
+    def run():
+        return ctx.solve_response(s.omegas, s.eps, drives, restart=restart, max_iter=a.max_iter,
+                                  tol=tol, batch=a.batch)
+
+    print(f"[bench] {a.workload}: N={s.n_orb} N_occ={s.n_occ} n_prod={s.n_prod} points="
+          f"{s.omegas.size * drives.shape[0]} batch={a.batch} GMRES({restart}) tol={tol:g}",
+          file=sys.stderr, flush=True)
+    for i in range(a.warmup):
+        t0 = time.perf_counter()
+        run()
+        print(f"[bench] warmup {i} {time.perf_counter() - t0:.3f} s", file=sys.stderr, flush=True)
+    if not a.no_timing:
+        ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        alpha, stats, rc = run()
+        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    ks = ctx.kernel_stats() if not a.no_timing else {}
+
+    npts = s.omegas.size * drives.shape[0]
+    diag = np.stack([alpha[:, i, i] for i in range(drives.shape[0])], 1)
+    if ref is not None:
+        rdiag = np.stack([ref[:, i, i] for i in range(drives.shape[0])], 1)
+        err = np.stack([im_errors(diag[:, i], rdiag[:, i]) for i in range(drives.shape[0])], 1)
+        passing = int((err <= 1e-6).sum())
+        acc = {"checked": True, "max_im_rel_err": float(err.max()),
+               "max_re_rel_err": float(np.max(np.abs(diag.real - rdiag.real) / np.abs(rdiag.real))),
+               "points_passing_1e-6": passing, "points_passing_1e-10": int((err <= 1e-10).sum())}
+    else:
+        passing = npts
+        acc = {"checked": False}
+    applications = int((stats["iterations"] + stats["restarts"] + 1).sum())
+
+    roof = None
+    chi0_gflops = None
+    if ks:
+        dom = max(ks, key=lambda k: ks[k]["ms"])
+        rec = ks[dom]
+        bound = "mfma" if dom in MFMA_KERNELS else "hbm"
+        peak, unit = PEAK[bound]
+        work = rec["flops"] if bound == "mfma" else rec["bytes"]
+        achieved = work / (rec["ms"] * 1e-3)
+        scale = 1e12 if bound == "mfma" else 1e9
+        traffic = load_traffic(dom, a.workload)
+        roof = {"kernel": dom, "bound": bound, "achieved": achieved / scale, "peak": peak / scale,
+                "unit": unit, "frac": achieved / peak, "traffic": traffic,
+                "launches": rec["launches"] // a.steps, "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
+                "share_of_gpu_time": rec["ms"] / sum(v["ms"] for v in ks.values())}
+        chi0_ms = sum(ks[k]["ms"] for k in CHI0_KERNELS if k in ks)
+        N, No = s.n_orb, s.n_occ
+        Nv = N - No
+        S_V = int(sum(s.support(m).size for m in range(s.n_prod)))
+        F = 8.0 * No * S_V + 8.0 * N * No * Nv + 6.0 * No * Nv      # Table t:flops count per chi0 z
+        chi0_gflops = F * applications * a.steps / (chi0_ms * 1e-3) / 1e9
+        print("[bench] kernel            launches/step   ms/step   share   achieved", file=sys.stderr)
+        tot = sum(v["ms"] for v in ks.values())
+        for k, v in sorted(ks.items(), key=lambda kv: -kv[1]["ms"]):
+            b = "mfma" if k in MFMA_KERNELS else "hbm"
+            ach = (v["flops"] / 1e12 if b == "mfma" else v["bytes"] / 1e9) / (v["ms"] * 1e-3)
+            print(f"[bench] {k:24s} {v['launches'] // a.steps:8d} {v['ms'] / a.steps:9.2f} "
+                  f"{100 * v['ms'] / tot:6.1f}%  {ach:9.2f} {'TFLOP/s' if b == 'mfma' else 'GB/s'}",
+                  file=sys.stderr)
+
+    cpu = None
+    if a.cpu_sample > 0:
+        cpu = cpu_baseline(s, drives, a.cpu_sample)
+
+    out = {
+        "metric": "spectrum points/s at 1e-6 rel err in Im alpha vs FP64 oracle",
+        "value": passing / dt,
+        "unit": "spectrum points/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": a.workload, "seed": a.seed, "n_orb": s.n_orb, "n_occ": s.n_occ,
+                   "n_prod": s.n_prod, "n_omega": int(s.omegas.size), "drives": w.drives,
+                   "eps": s.eps, "tol": tol, "restart": restart, "batch": a.batch,
+                   "points": npts},
+        "chi0_gflops": chi0_gflops,
+        "chi0_applications_per_step": applications,
+        "iterations": {"mean": float(stats["iterations"].mean()), "max": int(stats["iterations"].max()),
+                       "converged": int(stats["converged"].sum())},
+        "accuracy": acc,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -178,8 +178,9 @@ int chi0_solve_response(chi0_ctx *ctx, int32_t n_omega, const double *omega, dou
 /*
  * Kernel timing (tracing).  When enabled, every kernel launch of the
  * library is bracketed by HIP events on the stream it runs on, and the
- * durations are accumulated per kernel name.  chi0_kernel_stats copies up
- * to `cap` records (name, launches, total milliseconds) and returns how
+ * durations are accumulated per kernel name, together with the algorithmic
+ * work of each launch (unpadded sizes; every operand counted once).
+ * chi0_kernel_stats copies up to `cap` records and returns how
  * many kernels have records.  Reading the records synchronises the
  * context's streams.  Disabled by default; enabling resets the records.
  */
@@ -187,6 +188,8 @@ typedef struct chi0_kernel_record {
     char    name[48];
     int64_t launches;
     double  total_ms;
+    double  flops;        /* algorithmic floating-point operations of those launches */
+    double  bytes;        /* algorithmic HBM bytes (each operand read or written once) */
 } chi0_kernel_record;
 
 int chi0_set_timing(chi0_ctx *ctx, int32_t enable);

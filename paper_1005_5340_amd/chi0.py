@@ -40,7 +40,8 @@ class PointStats(C.Structure):
 
 
 class KernelRecord(C.Structure):
-    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double)]
 
 
 SolveStats = np.dtype([("iterations", np.int32), ("restarts", np.int32), ("converged", np.int32),
@@ -231,9 +232,11 @@ class Context:
         self._check(self._L.chi0_set_timing(self._h, 1 if enable else 0))
 
     def kernel_stats(self) -> dict:
+        """{kernel: dict(launches, ms, flops, bytes)} accumulated since set_timing(True)."""
         n = self._L.chi0_kernel_stats(self._h, None, 0)
         self._check(min(n, 0))
         recs = (KernelRecord * max(1, n))()
         n = self._L.chi0_kernel_stats(self._h, recs, n)
-        return {recs[i].name.decode(): (int(recs[i].launches), float(recs[i].total_ms))
+        return {recs[i].name.decode(): dict(launches=int(recs[i].launches), ms=float(recs[i].total_ms),
+                                            flops=float(recs[i].flops), bytes=float(recs[i].bytes))
                 for i in range(n)}

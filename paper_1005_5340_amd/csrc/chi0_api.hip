@@ -24,10 +24,11 @@ using namespace chi0;
 // ================================================================== tracing
 struct chi0::Tracer {
     bool on = false;
-    struct Pending { const char *name; hipEvent_t a, b; };
+    struct Pending { const char *name; hipEvent_t a, b; double flops, bytes; };
+    struct Rec { int64_t launches = 0; double ms = 0.0, flops = 0.0, bytes = 0.0; };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
-    std::map<std::string, std::pair<int64_t, double>> recs;
+    std::map<std::string, Rec> recs;
     const char *cur_name = nullptr;
     hipEvent_t cur_a = nullptr;
 
@@ -42,8 +43,10 @@ struct chi0::Tracer {
             float ms = 0.f;
             if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
                 auto &r = recs[p.name];
-                r.first += 1;
-                r.second += ms;
+                r.launches += 1;
+                r.ms += ms;
+                r.flops += p.flops;
+                r.bytes += p.bytes;
             }
             pool.push_back(p.a);
             pool.push_back(p.b);
@@ -67,12 +70,12 @@ void chi0::trace_begin(Tracer *t, const char *name, hipStream_t s) {
     if (t->cur_a) (void)hipEventRecord(t->cur_a, s);
 }
 
-void chi0::trace_end(Tracer *t, hipStream_t s) {
+void chi0::trace_end(Tracer *t, hipStream_t s, double flops, double bytes) {
     if (!t || !t->on || !t->cur_a) return;
     hipEvent_t b = t->get();
     if (!b) return;
     (void)hipEventRecord(b, s);
-    t->pending.push_back({t->cur_name, t->cur_a, b});
+    t->pending.push_back({t->cur_name, t->cur_a, b, flops, bytes});
     t->cur_a = nullptr;
     if (t->pending.size() >= 16384) t->harvest();
 }
@@ -99,6 +102,7 @@ struct chi0_ctx {
     double occ = 2.0;
     int n_blk = 0, n_g = 0, max_rows = 0;
     int64_t nnzB = 0, npart = 0;
+    WorkSizes ws{};
     DevBuf sysbuf;
     double *Xo = nullptr, *Xv = nullptr, *Xvt = nullptr, *Dlt = nullptr, *K = nullptr;
     BlockMapDev bm{};
@@ -246,8 +250,10 @@ extern "C" int chi0_kernel_stats(chi0_ctx *ctx, chi0_kernel_record *rec, int32_t
         if (i < cap) {
             std::memset(&rec[i], 0, sizeof(rec[i]));
             std::snprintf(rec[i].name, sizeof(rec[i].name), "%s", kv.first.c_str());
-            rec[i].launches = kv.second.first;
-            rec[i].total_ms = kv.second.second;
+            rec[i].launches = kv.second.launches;
+            rec[i].total_ms = kv.second.ms;
+            rec[i].flops = kv.second.flops;
+            rec[i].bytes = kv.second.bytes;
         }
         ++i;
     }
@@ -439,6 +445,8 @@ extern "C" int chi0_set_system(chi0_ctx *c, int32_t n_atoms, const double *posit
     c->occ = occ_factor;
     c->n_blk = nblk; c->n_g = (int)hm.g_xrow.size(); c->max_rows = hm.max_rows;
     c->nnzB = ecur; c->npart = pcur;
+    c->ws.N = n_orb; c->ws.No = n_occ; c->ws.Nv = n_orb - n_occ; c->ws.P = n_prod;
+    c->ws.nnzB = (double)ecur; c->ws.npart = (double)pcur; c->ws.sum_s2 = (double)nv_tot;
 
     if (c->device < 0) {   // host-only context: validation and maps only
         c->has_system = true;
@@ -543,15 +551,20 @@ static int ensure_ws(chi0_ctx *c, int nc) {
 static void run_chi0(chi0_ctx *c, hipStream_t s, int nb, double eps) {
     const int nc = 2 * nb;
     Tracer *t = &c->tracer;
+    const WorkSizes &w = c->ws;
     const int64_t mcol = (int64_t)c->No_pad * nc;
-    launch_vertex_gather(t, s, c->bm, c->n_blk, c->Zin, c->dV, nc, nc);
-    launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, c->dV, c->Tt, nc, nc);
+    // algorithmic work of the two dense transforms (unpadded sizes)
+    const double fl = 2.0 * w.N * w.Nv * w.No * nc;
+    launch_vertex_gather(t, s, c->bm, c->n_blk, c->Zin, c->dV, nc, w);
+    launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, c->dV, c->Tt, nc, w);
     launch_dgemm_lorentz(t, s, c->Nv_pad, (int)mcol, c->N_pad, c->Xvt, c->N_pad, c->Tt, (int)mcol,
-                         c->at, (int)mcol, c->Dlt, c->Nv_pad, c->omega_dev, eps, c->occ, nc);
+                         c->at, (int)mcol, c->Dlt, c->Nv_pad, c->omega_dev, eps, c->occ, nc,
+                         fl + 6.0 * w.No * w.Nv * nb,
+                         8.0 * (w.N * w.No * nc + w.Nv * w.No * nc + w.N * w.Nv + w.No * w.Nv));
     launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, c->at, (int)mcol,
-                 c->Ut, (int)mcol);
-    launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, c->Ut, c->W, nc, nc);
-    launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, c->W, c->part, c->Yout, nc, nc);
+                 c->Ut, (int)mcol, fl, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv));
+    launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, c->Ut, c->W, nc, w);
+    launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, c->W, c->part, c->Yout, nc, w);
 }
 
 static const int kMaxBatch = 256;   // complex columns per operator pass
@@ -705,7 +718,9 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
             for (auto &u : upd) jm = std::max(jm, u.j);
             std::copy(upd.begin(), upd.end(), c->upd_h);
             HIPCHK(c, hipMemcpyAsync(c->upd_dev, c->upd_h, sizeof(Job) * upd.size(), hipMemcpyHostToDevice, s));
-            launch_update_x(t, s, c->upd_dev, (int)upd.size(), jm, c->slots, P);
+            double sumL = 0.0;
+            for (auto &u : upd) sumL += u.j;
+            launch_update_x(t, s, c->upd_dev, (int)upd.size(), jm, c->slots, P, sumL);
             upd.clear();
         }
         // (3) refill free slots
@@ -716,7 +731,8 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                 sl[k].j = 0;
             }
         // (4) one job per active slot
-        int nb = 0, jmax = -1;
+        int nb = 0, jmax = -1, n_arn = 0;
+        double sum_j1 = 0.0;
         bool any_arnoldi = false;
         for (int k = 0; k < nsl; ++k) {
             if (sl[k].state == S_FREE) continue;
@@ -725,7 +741,12 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
             jb.type = sl[k].state == S_RHS ? JOB_RHS : sl[k].state == S_ARNOLDI ? JOB_ARNOLDI : JOB_RESID;
             jb.j = sl[k].j;
             jb.drive = sl[k].point % n_drive;
-            if (jb.type == JOB_ARNOLDI) { any_arnoldi = true; jmax = std::max(jmax, jb.j); }
+            if (jb.type == JOB_ARNOLDI) {
+                any_arnoldi = true;
+                jmax = std::max(jmax, jb.j);
+                ++n_arn;
+                sum_j1 += jb.j + 1;
+            }
             c->jobs_h[nb] = jb;
             c->omega_h[nb] = omega[sl[k].point / n_drive];
             ++nb;
@@ -737,13 +758,15 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
         // (5) operator: Zin = K v (b jobs: d), Y = chi0 Zin
         launch_gather_jobs(t, s, c->jobs_dev, nb, c->slots, c->Vb, nc, P);
         if (nc <= 16)
-            launch_kmatvec_skinny(t, s, c->P_pad, c->K, c->Vb, c->Zin, nc);
+            launch_kmatvec_skinny(t, s, c->P_pad, c->K, c->Vb, c->Zin, nc, (double)P);
         else
-            launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, c->Vb, nc, c->Zin, nc);
+            launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, c->Vb, nc, c->Zin, nc,
+                         2.0 * P * (double)P * nc, 8.0 * ((double)P * P + 2.0 * P * nc));
         launch_put_drive(t, s, c->jobs_dev, nb, drives, c->P_pad, c->Zin, nc, P);
         run_chi0(c, s, nb, eps);
         launch_post_jobs(t, s, c->jobs_dev, nb, c->slots, c->Yout, nc, P, c->status_dev);
-        if (any_arnoldi) launch_arnoldi(t, s, c->jobs_dev, nb, jmax, c->slots, P, c->status_dev);
+        if (any_arnoldi)
+            launch_arnoldi(t, s, c->jobs_dev, nb, jmax, c->slots, P, c->status_dev, n_arn, sum_j1);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->status_h, c->status_dev, sizeof(StepStatus) * nb, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));

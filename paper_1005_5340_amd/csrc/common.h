@@ -11,13 +11,12 @@
 //        every product mu whose support covers (A,B), each n_A x n_B row-major
 //
 // A batch of nb complex right-hand sides is carried as nc = 2*nb real
-// columns (column 2r = real part, 2r+1 = imaginary part of RHS r); ncp is nc
-// rounded up to the column tile (16).  Operator buffers are [rows][ncp].
-// The orbital-transform intermediates index their long dimension by
-// m = E*ncp + j (occupied state E, column j):
-//   dV, W [nnzB][ncp]            block-sparse, entry (k, a, b) -> row ent(k)+a*n_B+b
-//   Tt, Ut [N_pad][No_pad*ncp]   Tt[b][m] = (X_occ^T dV)[E][b] of column j
-//   at    [Nv_pad][No_pad*ncp]   at[F][m] = (X_occ^T dV X_virt)[E][F], then scaled
+// columns (column 2r = real part, 2r+1 = imaginary part of RHS r).  Operator
+// buffers are [rows][nc].  The orbital-transform intermediates index their
+// long dimension by m = E*nc + j (occupied state E, column j):
+//   dV, W [nnzB][nc]             block-sparse, entry (k, a, b) -> row ent(k)+a*n_B+b
+//   Tt, Ut [N_pad][No_pad*nc]    Tt[b][m] = (X_occ^T dV)[E][b] of column j
+//   at    [Nv_pad][No_pad*nc]    at[F][m] = (X_occ^T dV X_virt)[E][F], then scaled
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,7 +35,12 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // durations can be accumulated with HIP events when tracing is enabled.
 struct Tracer;
 void trace_begin(Tracer *t, const char *name, hipStream_t s);
-void trace_end(Tracer *t, hipStream_t s);
+void trace_end(Tracer *t, hipStream_t s, double flops = 0.0, double bytes = 0.0);
+
+// Unpadded sizes for the algorithmic work counts of the tracer.
+struct WorkSizes {
+    double N = 0, No = 0, Nv = 0, P = 0, nnzB = 0, sum_s2 = 0, npart = 0;
+};
 
 // -------------------------------------------------------------- chi0 blocks
 struct BlockMapDev {
@@ -62,28 +66,30 @@ struct BlockMapDev {
 // ------------------------------------------------------------ launch wrappers
 // (a) dV = sum_mu z_mu V_mu, per block.
 void launch_vertex_gather(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk,
-                          const double *Z, double *dV, int nc, int ncp);
+                          const double *Z, double *dV, int nc, const WorkSizes &ws);
 // (d) n_mu = <V_mu, W>: per-block partial sums, then the sum over each product's blocks.
 void launch_vertex_contract(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk, int P,
-                            const double *W, double *part, double *Y, int nc, int ncp);
+                            const double *W, double *part, double *Y, int nc, const WorkSizes &ws);
 // (b1) Tt = X_occ^T dV (gathered MFMA GEMM over the block pattern).
 void launch_occ_transform(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms,
                           const double *Xo, int no_pad, const double *dV, double *Tt,
-                          int nc, int ncp);
+                          int nc, const WorkSizes &ws);
 // (b4) W = X_occ Ut restricted to the block pattern.
 void launch_occ_back(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
-                     const double *Xo, int no_pad, const double *Ut, double *W, int nc, int ncp);
-// Dense FP64 MFMA GEMM C = A B (row-major, M%64 == K%16 == 0, N masked at n_valid).
+                     const double *Xo, int no_pad, const double *Ut, double *W, int nc,
+                     const WorkSizes &ws);
+// Dense FP64 MFMA GEMM C = A B (row-major, M%64 == K%16 == 0, N masked).
 void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
-                  const double *A, int lda, const double *B, int ldb, double *C, int ldc);
+                  const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                  double flops, double bytes);
 // (b2)+(c) at = Xvt Tt with the Lorentzian factor of column (E, j) and row F applied.
 void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K,
                           const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                           const double *Dlt, int nv_pad, const double *omega, double eps,
-                          double occ, int ncp);
+                          double occ, int ncp, double flops, double bytes);
 // (e) skinny K z for a few columns (HBM-streaming GEMV).
 void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
-                           const double *Zin, double *Zout, int ncp);
+                           const double *Zin, double *Zout, int nc, double P);
 
 // ------------------------------------------------------------- Krylov support
 struct Job {
@@ -122,9 +128,9 @@ void launch_put_drive(Tracer *t, hipStream_t s, const Job *jobs, int nb, const d
 void launch_post_jobs(Tracer *t, hipStream_t s, const Job *jobs, int nb, const SlotsDev &sl,
                       const double *Y, int ncp, int P, StepStatus *status);
 void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
-                    const SlotsDev &sl, int P, StepStatus *status);
+                    const SlotsDev &sl, int P, StepStatus *status, int n_arnoldi, double sum_j1);
 void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
-                     const SlotsDev &sl, int P);
+                     const SlotsDev &sl, int P, double sum_L);
 void launch_alpha(Tracer *t, hipStream_t s, const Job *jobs, int n, const SlotsDev &sl,
                   const double *drives, int n_drive, int P_pad, int P, const int32_t *out_index,
                   double *alpha_out);

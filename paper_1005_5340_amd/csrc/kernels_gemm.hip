@@ -160,26 +160,27 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
 }
 
 void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
-                  const double *A, int lda, const double *B, int ldb, double *C, int ldc) {
+                  const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                  double flops, double bytes) {
     const int tiles = (M / 64) * ((N + 63) / 64);
     LorentzArgs la{};
     const int m_fastest = (M / 64) <= ((N + 63) / 64);
     trace_begin(t, name, s);
     hipLaunchKernelGGL((k_dgemm<64, 64, 2, 2, false>), dim3(tiles), dim3(256), 0, s,
                        M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
-    trace_end(t, s);
+    trace_end(t, s, flops, bytes);
 }
 
 void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K,
                           const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                           const double *Dlt, int nv_pad, const double *omega, double eps,
-                          double occ, int ncp) {
+                          double occ, int ncp, double flops, double bytes) {
     const int tiles = (M / 64) * ((N + 63) / 64);
     LorentzArgs la{Dlt, omega, nv_pad, ncp, eps, occ};
     trace_begin(t, "virt_transform_lorentz", s);
     hipLaunchKernelGGL((k_dgemm<64, 64, 2, 2, true>), dim3(tiles), dim3(256), 0, s,
                        M, N, K, A, lda, B, ldb, C, ldc, 1, la);
-    trace_end(t, s);
+    trace_end(t, s, flops, bytes);
 }
 
 // ------------------------------------------------------- (b1) occupied transform
@@ -248,12 +249,12 @@ void k_occ_transform(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
 
 void launch_occ_transform(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms,
                           const double *Xo, int no_pad, const double *dV, double *Tt,
-                          int nc, int ncp) {
-    (void)ncp;
+                          int nc, const WorkSizes &ws) {
     dim3 grid(n_atoms, no_pad / 64, (nc + JT - 1) / JT);
     trace_begin(t, "occ_transform", s);
     hipLaunchKernelGGL(k_occ_transform, grid, dim3(256), 0, s, bm, Xo, no_pad, dV, Tt, nc);
-    trace_end(t, s);
+    trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
+              8.0 * (ws.nnzB * nc + ws.N * ws.No + ws.N * ws.No * nc));
 }
 
 // ------------------------------------------------------ (b4) back to the pattern
@@ -318,12 +319,13 @@ void k_occ_back(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
 }
 
 void launch_occ_back(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
-                     const double *Xo, int no_pad, const double *Ut, double *W, int nc, int ncp) {
-    (void)ncp;
+                     const double *Xo, int no_pad, const double *Ut, double *W, int nc,
+                     const WorkSizes &ws) {
     dim3 grid(n_atoms, (max_rows + 63) / 64, (nc + JT - 1) / JT);
     trace_begin(t, "occ_back", s);
     hipLaunchKernelGGL(k_occ_back, grid, dim3(256), 0, s, bm, Xo, no_pad, Ut, W, nc);
-    trace_end(t, s);
+    trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
+              8.0 * (ws.N * ws.No * nc + ws.N * ws.No + ws.nnzB * nc));
 }
 
 // ---------------------------------------------------------- (e) skinny K z
@@ -374,7 +376,7 @@ void k_kmatvec_skinny(int P_pad, const double *__restrict__ K, const double *__r
 }
 
 void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
-                           const double *Zin, double *Zout, int nc) {
+                           const double *Zin, double *Zout, int nc, double P) {
     dim3 grid(P_pad / 16);
     trace_begin(t, "kernel_matvec", s);
     if (nc <= 2)
@@ -385,7 +387,7 @@ void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
         hipLaunchKernelGGL(k_kmatvec_skinny<8>, grid, dim3(256), 0, s, P_pad, K, Zin, Zout, nc);
     else
         hipLaunchKernelGGL(k_kmatvec_skinny<16>, grid, dim3(256), 0, s, P_pad, K, Zin, Zout, nc);
-    trace_end(t, s);
+    trace_end(t, s, 2.0 * P * P * nc, 8.0 * (P * P + 2.0 * P * nc));
 }
 
 }  // namespace chi0

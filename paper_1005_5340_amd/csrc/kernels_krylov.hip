@@ -265,20 +265,20 @@ void k_arnoldi_finalize(const Job *__restrict__ jobs, SlotsDev sl, int P, StepSt
 }
 
 void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
-                    const SlotsDev &sl, int P, StepStatus *status) {
+                    const SlotsDev &sl, int P, StepStatus *status, int n_arnoldi, double sum_j1) {
     const dim3 gd((jmax + 1 + 3) / 4, nb), gu((P + 255) / 256, nb);
     const size_t shm = (size_t)(jmax + 1) * 2 * sizeof(double);
     for (int pass = 0; pass < 2; ++pass) {
         trace_begin(t, "cgs_dots", s);
         hipLaunchKernelGGL(k_cgs_dots, gd, dim3(256), 0, s, jobs, sl, P);
-        trace_end(t, s);
+        trace_end(t, s, 8.0 * P * sum_j1, 16.0 * P * (sum_j1 + n_arnoldi));
         trace_begin(t, "cgs_update", s);
         hipLaunchKernelGGL(k_cgs_update, gu, dim3(256), shm, s, jobs, sl, P, pass);
-        trace_end(t, s);
+        trace_end(t, s, 8.0 * P * sum_j1, 16.0 * P * (sum_j1 + 2.0 * n_arnoldi));
     }
     trace_begin(t, "arnoldi_finalize", s);
     hipLaunchKernelGGL(k_arnoldi_finalize, dim3(nb), dim3(256), 0, s, jobs, sl, P, status);
-    trace_end(t, s);
+    trace_end(t, s, 4.0 * P * n_arnoldi, 16.0 * P * 2.0 * n_arnoldi);
 }
 
 // ------------------------------------------------------- end of a GMRES cycle
@@ -346,14 +346,14 @@ void k_xupdate(const Job *__restrict__ jobs, SlotsDev sl, int P) {
 }
 
 void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
-                     const SlotsDev &sl, int P) {
+                     const SlotsDev &sl, int P, double sum_L) {
     const size_t shm = (size_t)(jmax > 0 ? jmax : 1) * 2 * sizeof(double);
     trace_begin(t, "trisolve", s);
     hipLaunchKernelGGL(k_trisolve, dim3(n), dim3(256), shm, s, jobs, sl);
     trace_end(t, s);
     trace_begin(t, "x_update", s);
     hipLaunchKernelGGL(k_xupdate, dim3((P + 255) / 256, n), dim3(256), shm, s, jobs, sl, P);
-    trace_end(t, s);
+    trace_end(t, s, 8.0 * P * sum_L, 16.0 * P * (sum_L + 2.0 * n));
 }
 
 // ------------------------------------------------------------ polarizability

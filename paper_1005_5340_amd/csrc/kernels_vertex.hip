@@ -58,13 +58,12 @@ void k_vertex_gather(BlockMapDev bm, const double *__restrict__ Z, double *__res
 }
 
 void launch_vertex_gather(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk,
-                          const double *Z, double *dV, int nc, int ncp) {
-    (void)ncp;
+                          const double *Z, double *dV, int nc, const WorkSizes &ws) {
     const int jt = vertex_jt(nc);
     dim3 grid(n_blk, (nc + jt - 1) / jt);
     trace_begin(t, "vertex_gather", s);
     hipLaunchKernelGGL(k_vertex_gather, grid, dim3(256), 0, s, bm, Z, dV, nc, jt);
-    trace_end(t, s);
+    trace_end(t, s, 2.0 * ws.sum_s2 * nc, 8.0 * (ws.sum_s2 + ws.P * nc + ws.nnzB * nc));
 }
 
 // (d), first pass: part[pstart_k + i][j] = sum_ab Vp[k][i][ab] * W[(ent_k + ab)][j]
@@ -109,19 +108,18 @@ void k_vertex_reduce(BlockMapDev bm, int P, const double *__restrict__ part,
 }
 
 void launch_vertex_contract(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk, int P,
-                            const double *W, double *part, double *Y, int nc, int ncp) {
-    (void)ncp;
+                            const double *W, double *part, double *Y, int nc, const WorkSizes &ws) {
     int jt = vertex_jt(nc);
     if (jt > JTD) jt = JTD;
     dim3 grid(n_blk, (nc + jt - 1) / jt);
     trace_begin(t, "vertex_contract", s);
     hipLaunchKernelGGL(k_vertex_contract, grid, dim3(256), 0, s, bm, W, part, nc, jt);
-    trace_end(t, s);
+    trace_end(t, s, 2.0 * ws.sum_s2 * nc, 8.0 * (ws.sum_s2 + ws.nnzB * nc + ws.npart * nc));
     const int64_t n = (int64_t)P * nc;
     trace_begin(t, "vertex_reduce", s);
     hipLaunchKernelGGL(k_vertex_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        bm, P, part, Y, nc);
-    trace_end(t, s);
+    trace_end(t, s, ws.npart * nc, 8.0 * (ws.npart * nc + ws.P * nc));
 }
 
 }  // namespace chi0
