@@ -29,10 +29,29 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-PEAK = {"mfma": (78.6e12, "TFLOP/s"), "hbm": (8.0e12, "GB/s")}   # MI355X FP64 matrix, HBM3E
+# MI355X dense peaks: FP64 / FP32 / BF16 matrix cores, HBM3E
+PEAK = {"mfma": (78.6e12, "TFLOP/s"), "mfma_f32": (157.3e12, "TFLOP/s"),
+        "mfma_bf16": (2.5e15, "TFLOP/s"), "hbm": (8.0e12, "GB/s")}
+
 CHI0_KERNELS = ("vertex_gather", "occ_transform", "virt_transform_lorentz", "virt_back",
-                "occ_back", "vertex_contract", "vertex_reduce")
+                "occ_back", "vertex_contract", "vertex_reduce", "occ_transform_f32",
+                "virt_transform_lorentz_f32", "virt_back_f32", "occ_back_f32",
+                "virt_transform_lorentz_bf16x3", "virt_back_bf16x3")
 MFMA_KERNELS = ("virt_transform_lorentz", "virt_back", "occ_transform", "occ_back", "kernel_matmul")
+MFMA_F32 = ("virt_transform_lorentz_f32", "virt_back_f32", "occ_transform_f32", "occ_back_f32")
+MFMA_BF16 = ("virt_transform_lorentz_bf16x3", "virt_back_bf16x3")
+
+
+def bound_of(kernel):
+    if kernel in MFMA_KERNELS:
+        return "mfma"
+    if kernel in MFMA_F32:
+        return "mfma_f32"
+    if kernel in MFMA_BF16:
+        return "mfma_bf16"
+    return "hbm"
+
+
 KERNEL_SOURCES = {  # kernel -> source file that defines it (for the counter-staleness check)
     "virt_transform_lorentz": "kernels_gemm.hip", "virt_back": "kernels_gemm.hip",
     "kernel_matmul": "kernels_gemm.hip", "kernel_matvec": "kernels_gemm.hip",
@@ -91,6 +110,9 @@ def main():
     ap.add_argument("--restart", type=int, default=0, help="GMRES(m); 0 = unrestarted (m = n_prod)")
     ap.add_argument("--tol", type=float, default=0.0, help="0 = the workload's tolerance")
     ap.add_argument("--max-iter", type=int, default=10000)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="arithmetic of the Arnoldi-step transforms (IR keeps residuals in FP64)")
+    ap.add_argument("--inner-tol", type=float, default=0.0)
     ap.add_argument("--cpu-sample", type=int, default=2, help="frequencies for the oracle baseline (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
     a = ap.parse_args()
@@ -118,9 +140,11 @@ def main():
         if synth.same_inputs(s, r["fingerprint"]) and r["omega_index"] == list(range(s.omegas.size)):
             ref = np.array(r["alpha_re"]) + 1j * np.array(r["alpha_im"])
 
+    prec = {"fp64": chi0.PREC_FP64, "fp32": chi0.PREC_FP32, "bf16x3": chi0.PREC_BF16X3}[a.precision]
+
     def run():
         return ctx.solve_response(s.omegas, s.eps, drives, restart=restart, max_iter=a.max_iter,
-                                  tol=tol, batch=a.batch)
+                                  tol=tol, batch=a.batch, precision=prec, inner_tol=a.inner_tol)
 
     print(f"[bench] {a.workload}: N={s.n_orb} N_occ={s.n_occ} n_prod={s.n_prod} points="
           f"{s.omegas.size * drives.shape[0]} batch={a.batch} GMRES({restart}) tol={tol:g}",
@@ -159,13 +183,14 @@ def main():
     if ks:
         dom = max(ks, key=lambda k: ks[k]["ms"])
         rec = ks[dom]
-        bound = "mfma" if dom in MFMA_KERNELS else "hbm"
+        bound = bound_of(dom)
         peak, unit = PEAK[bound]
-        work = rec["flops"] if bound == "mfma" else rec["bytes"]
+        work = rec["bytes"] if bound == "hbm" else rec["flops"]
         achieved = work / (rec["ms"] * 1e-3)
-        scale = 1e12 if bound == "mfma" else 1e9
+        scale = 1e9 if bound == "hbm" else 1e12
         traffic = load_traffic(dom, a.workload)
-        roof = {"kernel": dom, "bound": bound, "achieved": achieved / scale, "peak": peak / scale,
+        roof = {"kernel": dom, "bound": "hbm" if bound == "hbm" else "mfma", "dtype": bound,
+                "achieved": achieved / scale, "peak": peak / scale,
                 "unit": unit, "frac": achieved / peak, "traffic": traffic,
                 "launches": rec["launches"] // a.steps, "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
                 "share_of_gpu_time": rec["ms"] / sum(v["ms"] for v in ks.values())}
@@ -178,10 +203,10 @@ def main():
         print("[bench] kernel            launches/step   ms/step   share   achieved", file=sys.stderr)
         tot = sum(v["ms"] for v in ks.values())
         for k, v in sorted(ks.items(), key=lambda kv: -kv[1]["ms"]):
-            b = "mfma" if k in MFMA_KERNELS else "hbm"
-            ach = (v["flops"] / 1e12 if b == "mfma" else v["bytes"] / 1e9) / (v["ms"] * 1e-3)
-            print(f"[bench] {k:24s} {v['launches'] // a.steps:8d} {v['ms'] / a.steps:9.2f} "
-                  f"{100 * v['ms'] / tot:6.1f}%  {ach:9.2f} {'TFLOP/s' if b == 'mfma' else 'GB/s'}",
+            b = bound_of(k)
+            ach = (v["bytes"] / 1e9 if b == "hbm" else v["flops"] / 1e12) / (v["ms"] * 1e-3)
+            print(f"[bench] {k:30s} {v['launches'] // a.steps:8d} {v['ms'] / a.steps:9.2f} "
+                  f"{100 * v['ms'] / tot:6.1f}%  {ach:9.2f} {'GB/s' if b == 'hbm' else 'TFLOP/s'}",
                   file=sys.stderr)
 
     cpu = None
@@ -195,15 +220,17 @@ def main():
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": dt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16x3": "f64+bf16x3"}[a.precision],
+        "data": "synthetic",
         "config": {"workload": a.workload, "seed": a.seed, "n_orb": s.n_orb, "n_occ": s.n_occ,
                    "n_prod": s.n_prod, "n_omega": int(s.omegas.size), "drives": w.drives,
                    "eps": s.eps, "tol": tol, "restart": restart, "batch": a.batch,
-                   "points": npts},
+                   "points": npts, "precision": a.precision},
         "chi0_gflops": chi0_gflops,
         "chi0_applications_per_step": applications,
         "iterations": {"mean": float(stats["iterations"].mean()), "max": int(stats["iterations"].max()),
-                       "converged": int(stats["converged"].sum())},
+                       "converged": int(stats["converged"].sum()),
+                       "fallbacks": int(stats["fallback"].sum())},
         "accuracy": acc,
         "roofline": roof,
         "cpu_baseline": cpu,

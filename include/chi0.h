@@ -48,8 +48,17 @@ extern "C" {
 #define CHI0_ENONFINITE      (-5) /* NaN or Inf in an input */
 #define CHI0_EASYM           (-6) /* vertex block or kernel matrix not symmetric */
 
-/* Arithmetic used for the orbital transforms inside chi0 (the rest is FP64). */
+/* Arithmetic of the orbital transforms inside chi0 (Table t:flops steps 2-5).
+ * The vertex contractions, the frequency factor, K, Gram-Schmidt, the
+ * Hessenberg problem and the true residual are always FP64.
+ *   FP64    every transform on FP64 matrix cores.
+ *   FP32    transforms on FP32 matrix cores, FP32 intermediates.
+ *   BF16X3  the two dense virtual-orbital transforms as split BF16 x 3 (each
+ *           operand x = bf16 hi + bf16 lo, three BF16 products, FP32
+ *           accumulation); the block-sparse occupied transforms in FP32. */
 #define CHI0_PREC_FP64        0
+#define CHI0_PREC_FP32        1
+#define CHI0_PREC_BF16X3      2
 
 typedef struct chi0_ctx chi0_ctx;      /* opaque */
 
@@ -129,7 +138,7 @@ int chi0_get_sizes(const chi0_ctx *ctx, int32_t *n_orb, int32_t *n_occ,
  *          default stream) and the call returns before it completes.  The
  *          context's workspace is shared by all calls on the context, so do
  *          not overlap two calls on one context on different streams.
- *  precision  CHI0_PREC_FP64.
+ *  precision  CHI0_PREC_FP64, CHI0_PREC_FP32 or CHI0_PREC_BF16X3.
  */
 int chi0_apply(chi0_ctx *ctx, int32_t n_rhs, const double *omega, double eps,
                const double *z, double *out, int32_t precision, void *stream);
@@ -137,20 +146,26 @@ int chi0_apply(chi0_ctx *ctx, int32_t n_rhs, const double *omega, double eps,
 /* Options of chi0_solve_response.  Zero-initialise, then set what you need;
  * chi0_solve_opts_default() fills the defaults. */
 typedef struct chi0_solve_opts {
-    int32_t restart;      /* GMRES(m) Krylov dimension per cycle, >= 1 (default 30) */
-    int32_t max_iter;     /* cap on matrix-vector products per point (default 10000) */
+    int32_t restart;      /* GMRES(m) Krylov dimension per cycle, 1..4000 (default 30) */
+    int32_t max_iter;     /* cap on Arnoldi steps per point (default 10000) */
     double  tol;          /* stop when ||chi0 d - A x||_2 <= tol ||chi0 d||_2 (default 1e-10) */
-    int32_t precision;    /* CHI0_PREC_* for chi0 inside the solve (default FP64) */
-    int32_t batch;        /* (omega, drive) points solved concurrently; 1 = one at a time (default 1) */
-    int32_t reserved[8];  /* must be zero */
+    int32_t precision;    /* CHI0_PREC_* of the Arnoldi steps (default FP64); b = chi0 d and
+                             every true residual are FP64 (iterative refinement) */
+    int32_t batch;        /* (omega, drive) points solved concurrently, 1..256; 1 = one at a time */
+    double  inner_tol;    /* low precision only: a cycle ends when the Arnoldi residual
+                             estimate falls by this factor (0 = 1e-6 for FP32, 1e-4 for BF16X3) */
+    int32_t reserved[6];  /* must be zero */
 } chi0_solve_opts;
 
 /* Per-point solver record (one per omega and drive). */
 typedef struct chi0_point_stats {
     int32_t iterations;   /* Arnoldi steps (operator applications, excluding b and residual checks) */
-    int32_t restarts;     /* completed GMRES cycles */
+    int32_t restarts;     /* completed GMRES cycles (each ends with an FP64 true residual) */
     int32_t converged;    /* 1 if the true relative residual met tol */
     int32_t breakdown;    /* 1 if the Krylov space became invariant (exact solution) */
+    int32_t fallback;     /* 1 if a low-precision point switched to FP64 steps after a cycle
+                             that did not halve the true residual */
+    int32_t reserved;
     double  rel_residual; /* true ||b - A x|| / ||b|| at exit */
 } chi0_point_stats;
 

@@ -16,11 +16,13 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Chi0Error", "Context", "lib", "LIB_PATH", "PREC_FP64", "SolveStats",
-           "NOT_CONVERGED"]
+__all__ = ["Chi0Error", "Context", "lib", "LIB_PATH", "PREC_FP64", "PREC_FP32", "PREC_BF16X3",
+           "SolveStats", "NOT_CONVERGED"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 PREC_FP64 = 0
+PREC_FP32 = 1
+PREC_BF16X3 = 2
 NOT_CONVERGED = 1
 _ERRORS = {-1: "EINVAL", -2: "ENOSYS", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EASYM"}
 
@@ -31,12 +33,14 @@ _i64p = C.POINTER(C.c_int64)
 
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
-                ("precision", C.c_int32), ("batch", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("precision", C.c_int32), ("batch", C.c_int32), ("inner_tol", C.c_double),
+                ("reserved", C.c_int32 * 6)]
 
 
 class PointStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
-                ("breakdown", C.c_int32), ("rel_residual", C.c_double)]
+                ("breakdown", C.c_int32), ("fallback", C.c_int32), ("reserved", C.c_int32),
+                ("rel_residual", C.c_double)]
 
 
 class KernelRecord(C.Structure):
@@ -45,7 +49,7 @@ class KernelRecord(C.Structure):
 
 
 SolveStats = np.dtype([("iterations", np.int32), ("restarts", np.int32), ("converged", np.int32),
-                       ("breakdown", np.int32), ("rel_residual", np.float64)])
+                       ("breakdown", np.int32), ("fallback", np.int32), ("rel_residual", np.float64)])
 
 _LIB = None
 
@@ -202,7 +206,8 @@ class Context:
 
     # ---------------------------------------------------------------- solve
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
-                       tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64):
+                       tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,
+                       inner_tol: float = 0.0):
         """GMRES polarizability over a frequency grid.
 
         Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
@@ -214,7 +219,7 @@ class Context:
         o = SolveOpts()
         self._L.chi0_solve_opts_default(C.byref(o))
         o.restart, o.max_iter, o.tol = int(restart), int(max_iter), float(tol)
-        o.batch, o.precision = int(batch), int(precision)
+        o.batch, o.precision, o.inner_tol = int(batch), int(precision), float(inner_tol)
         alpha = np.zeros((om.size, nd, nd, 2))
         st = (PointStats * max(1, om.size * nd))()
         rc = self._L.chi0_solve_response(self._h, int(om.size), _ptr(om), float(eps), int(nd),
@@ -224,7 +229,7 @@ class Context:
         flat = stats.reshape(-1)
         for i in range(om.size * nd):
             flat[i] = (st[i].iterations, st[i].restarts, st[i].converged, st[i].breakdown,
-                       st[i].rel_residual)
+                       st[i].fallback, st[i].rel_residual)
         return alpha[..., 0] + 1j * alpha[..., 1], stats, rc
 
     # --------------------------------------------------------------- tracing

@@ -100,7 +100,7 @@ struct chi0_ctx {
     int n_atoms = 0, N = 0, No = 0, Nv = 0, P = 0;
     int N_pad = 0, No_pad = 0, Nv_pad = 0, P_pad = 0;
     double occ = 2.0;
-    int n_blk = 0, n_g = 0, max_rows = 0;
+    int n_blk = 0, n_g = 0, max_rows = 0, max_nprod = 0;
     int64_t nnzB = 0, npart = 0;
     WorkSizes ws{};
     DevBuf sysbuf;
@@ -112,6 +112,14 @@ struct chi0_ctx {
     int nc_cap = 0;
     double *Vb = nullptr, *Zin = nullptr, *Yout = nullptr, *dV = nullptr, *W = nullptr;
     double *Tt = nullptr, *at = nullptr, *Ut = nullptr, *part = nullptr, *omega_dev = nullptr;
+    double *gemm_scratch = nullptr;
+    size_t gemm_scratch_n = 0;
+    // low-precision operator: operand copies (set_system) and FP32 intermediates (lazy)
+    float *Xo32 = nullptr, *Xv32 = nullptr, *Xvt32 = nullptr;
+    uint16_t *Xv_hi = nullptr, *Xv_lo = nullptr, *Xvt_hi = nullptr, *Xvt_lo = nullptr;
+    DevBuf lpbuf;
+    int lp_cap = 0;
+    float *Tt32 = nullptr, *at32 = nullptr, *Ut32 = nullptr;
 
     // solver workspace
     DevBuf slotbuf;
@@ -130,6 +138,7 @@ struct chi0_ctx {
             if (stream) (void)hipStreamSynchronize(stream);
         }
         slotbuf.release();
+        lpbuf.release();
         wsbuf.release();
         sysbuf.release();
         if (jobs_h) (void)hipHostFree(jobs_h);
@@ -285,6 +294,8 @@ static void drop_system(chi0_ctx *c) {
     }
     c->slotbuf.release();
     c->slot_n = c->slot_m = 0;
+    c->lpbuf.release();
+    c->lp_cap = 0;
     c->wsbuf.release();
     c->nc_cap = 0;
     c->sysbuf.release();
@@ -444,6 +455,7 @@ extern "C" int chi0_set_system(chi0_ctx *c, int32_t n_atoms, const double *posit
     c->P_pad = (int)round_up(n_prod, TILE);
     c->occ = occ_factor;
     c->n_blk = nblk; c->n_g = (int)hm.g_xrow.size(); c->max_rows = hm.max_rows;
+    c->max_nprod = *std::max_element(hm.blk_nprod.begin(), hm.blk_nprod.end());
     c->nnzB = ecur; c->npart = pcur;
     c->ws.N = n_orb; c->ws.No = n_occ; c->ws.Nv = n_orb - n_occ; c->ws.P = n_prod;
     c->ws.nnzB = (double)ecur; c->ws.npart = (double)pcur; c->ws.sum_s2 = (double)nv_tot;
@@ -478,6 +490,22 @@ extern "C" int chi0_set_system(chi0_ctx *c, int32_t n_atoms, const double *posit
         HIPCHK(c, hipMemcpy(c->Xv, xv.data(), xv.size() * 8, hipMemcpyHostToDevice));
         HIPCHK(c, hipMemcpy(c->Xvt, xvt.data(), xvt.size() * 8, hipMemcpyHostToDevice));
         HIPCHK(c, hipMemcpy(c->Dlt, dl.data(), dl.size() * 8, hipMemcpyHostToDevice));
+        // operand copies of the low-precision operator
+        CHK(dalloc(c, sb, &c->Xo32, (int64_t)xo.size()));
+        CHK(dalloc(c, sb, &c->Xv32, (int64_t)xv.size()));
+        CHK(dalloc(c, sb, &c->Xvt32, (int64_t)xvt.size()));
+        CHK(dalloc(c, sb, &c->Xv_hi, (int64_t)xv.size()));
+        CHK(dalloc(c, sb, &c->Xv_lo, (int64_t)xv.size()));
+        CHK(dalloc(c, sb, &c->Xvt_hi, (int64_t)xvt.size()));
+        CHK(dalloc(c, sb, &c->Xvt_lo, (int64_t)xvt.size()));
+        HIPCHK(c, hipDeviceSynchronize());
+        launch_to_f32(nullptr, c->Xo, c->Xo32, (int64_t)xo.size());
+        launch_to_f32(nullptr, c->Xv, c->Xv32, (int64_t)xv.size());
+        launch_to_f32(nullptr, c->Xvt, c->Xvt32, (int64_t)xvt.size());
+        launch_split_bf16(nullptr, c->Xv, c->Xv_hi, c->Xv_lo, (int64_t)xv.size());
+        launch_split_bf16(nullptr, c->Xvt, c->Xvt_hi, c->Xvt_lo, (int64_t)xvt.size());
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipDeviceSynchronize());
     }
     CHK(dalloc(c, sb, &c->K, (int64_t)c->P_pad * c->P_pad));
     HIPCHK(c, hipMemcpy2D(c->K, (size_t)c->P_pad * 8, K, (size_t)n_prod * 8, (size_t)n_prod * 8,
@@ -542,13 +570,33 @@ static int ensure_ws(chi0_ctx *c, int nc) {
     CHK(dalloc(c, w, &c->at, (int64_t)c->Nv_pad * mcol));
     CHK(dalloc(c, w, &c->part, c->npart * nc));
     CHK(dalloc(c, w, &c->omega_dev, nc / 2 + 1));
+    // split-K partials: splits are only used while tiles * splits < 2048, so
+    // the partial products never exceed 2048 64x64 tiles
+    c->gemm_scratch_n = (size_t)2048 * 64 * 64;
+    CHK(dalloc(c, w, &c->gemm_scratch, (int64_t)c->gemm_scratch_n));
     HIPCHK(c, hipDeviceSynchronize());
     c->nc_cap = nc;
     return CHI0_OK;
 }
 
-// Y = chi0(omega) Zin for nb column pairs already in Zin; omega_dev filled.
-static void run_chi0(chi0_ctx *c, hipStream_t s, int nb, double eps) {
+static int ensure_lp(chi0_ctx *c) {
+    if (c->lp_cap >= c->nc_cap && c->Tt32) return CHI0_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipDeviceSynchronize());
+    c->lpbuf.release();
+    c->lp_cap = 0;
+    const int64_t mcol = (int64_t)c->No_pad * c->nc_cap;
+    CHK(dalloc(c, c->lpbuf, &c->Tt32, (int64_t)c->N_pad * mcol));
+    CHK(dalloc(c, c->lpbuf, &c->Ut32, (int64_t)c->N_pad * mcol));
+    CHK(dalloc(c, c->lpbuf, &c->at32, (int64_t)c->Nv_pad * mcol));
+    HIPCHK(c, hipDeviceSynchronize());
+    c->lp_cap = c->nc_cap;
+    return CHI0_OK;
+}
+
+// Y = chi0(omega) Zin for nb column pairs already in Zin; omega: device [nb].
+// prec selects the arithmetic of the orbital transforms (ensure_lp first).
+static void run_chi0(chi0_ctx *c, hipStream_t s, int nb, double eps, int prec, const double *omega) {
     const int nc = 2 * nb;
     Tracer *t = &c->tracer;
     const WorkSizes &w = c->ws;
@@ -556,15 +604,40 @@ static void run_chi0(chi0_ctx *c, hipStream_t s, int nb, double eps) {
     // algorithmic work of the two dense transforms (unpadded sizes)
     const double fl = 2.0 * w.N * w.Nv * w.No * nc;
     launch_vertex_gather(t, s, c->bm, c->n_blk, c->Zin, c->dV, nc, w);
-    launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, c->dV, c->Tt, nc, w);
-    launch_dgemm_lorentz(t, s, c->Nv_pad, (int)mcol, c->N_pad, c->Xvt, c->N_pad, c->Tt, (int)mcol,
-                         c->at, (int)mcol, c->Dlt, c->Nv_pad, c->omega_dev, eps, c->occ, nc,
-                         fl + 6.0 * w.No * w.Nv * nb,
-                         8.0 * (w.N * w.No * nc + w.Nv * w.No * nc + w.N * w.Nv + w.No * w.Nv));
-    launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, c->at, (int)mcol,
-                 c->Ut, (int)mcol, fl, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv));
-    launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, c->Ut, c->W, nc, w);
-    launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, c->W, c->part, c->Yout, nc, w);
+    if (prec == CHI0_PREC_FP64) {
+        launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, c->dV, c->Tt, nc, w);
+        launch_dgemm_lorentz(t, s, c->Nv_pad, (int)mcol, c->N_pad, c->Xvt, c->N_pad, c->Tt, (int)mcol,
+                             c->at, (int)mcol, c->Dlt, c->Nv_pad, omega, eps, c->occ, nc,
+                             fl + 6.0 * w.No * w.Nv * nb,
+                             8.0 * (w.N * w.No * nc + w.Nv * w.No * nc + w.N * w.Nv + w.No * w.Nv),
+                             c->gemm_scratch, c->gemm_scratch_n);
+        launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, c->at, (int)mcol,
+                     c->Ut, (int)mcol, fl, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv),
+                     c->gemm_scratch, c->gemm_scratch_n);
+        launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, c->Ut, c->W, nc, w);
+    } else {
+        launch_occ_transform_f32(t, s, c->bm, c->n_atoms, c->Xo32, c->No_pad, c->dV, c->Tt32, nc, w);
+        LorentzArgs la{c->Dlt, omega, c->Nv_pad, nc, eps, c->occ};
+        const size_t sb = c->gemm_scratch_n * sizeof(double);
+        const double by = 4.0 * (w.N * w.No * nc + w.Nv * w.No * nc);
+        if (prec == CHI0_PREC_FP32) {
+            launch_sgemm(t, s, "virt_transform_lorentz_f32", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt32,
+                         c->N_pad, c->Tt32, (int)mcol, c->at32, (int)mcol, fl + 6.0 * w.No * w.Nv * nb,
+                         by + 4.0 * w.N * w.Nv, &la, c->gemm_scratch, sb);
+            launch_sgemm(t, s, "virt_back_f32", c->N_pad, (int)mcol, c->Nv_pad, c->Xv32, c->Nv_pad,
+                         c->at32, (int)mcol, c->Ut32, (int)mcol, fl, by + 4.0 * w.N * w.Nv, nullptr,
+                         c->gemm_scratch, sb);
+        } else {   // split BF16 x 3: three BF16 products per multiply-add
+            launch_bgemm3(t, s, "virt_transform_lorentz_bf16x3", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt_hi,
+                          c->Xvt_lo, c->N_pad, c->Tt32, (int)mcol, c->at32, (int)mcol, 3.0 * fl,
+                          by + 4.0 * w.N * w.Nv, &la, c->gemm_scratch, sb);
+            launch_bgemm3(t, s, "virt_back_bf16x3", c->N_pad, (int)mcol, c->Nv_pad, c->Xv_hi, c->Xv_lo,
+                          c->Nv_pad, c->at32, (int)mcol, c->Ut32, (int)mcol, 3.0 * fl,
+                          by + 4.0 * w.N * w.Nv, nullptr, c->gemm_scratch, sb);
+        }
+        launch_occ_back_f32(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo32, c->No_pad, c->Ut32, c->W, nc, w);
+    }
+    launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, c->W, c->part, c->Yout, nc, w, c->max_nprod);
 }
 
 static const int kMaxBatch = 256;   // complex columns per operator pass
@@ -577,17 +650,19 @@ extern "C" int chi0_apply(chi0_ctx *c, int32_t n_rhs, const double *omega, doubl
     if (n_rhs == 0) return CHI0_OK;
     if (!omega || !z || !out) return fail(c, CHI0_EINVAL, "NULL pointer");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
-    if (precision != CHI0_PREC_FP64) return fail(c, CHI0_EINVAL, "unsupported precision");
+    if (precision < CHI0_PREC_FP64 || precision > CHI0_PREC_BF16X3)
+        return fail(c, CHI0_EINVAL, "unknown precision");
     if (!all_finite(omega, n_rhs)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int cap = std::min(kMaxBatch, std::max(n_rhs, 1));
     CHK(ensure_ws(c, 2 * std::max(cap, c->nc_cap / 2)));
+    if (precision != CHI0_PREC_FP64) CHK(ensure_lp(c));
     for (int r0 = 0; r0 < n_rhs; r0 += cap) {
         const int nb = std::min(cap, n_rhs - r0), nc = 2 * nb;
         HIPCHK(c, hipMemcpyAsync(c->omega_dev, omega + r0, (size_t)nb * 8, hipMemcpyHostToDevice, s));
         launch_rows_to_cols(&c->tracer, s, z + (int64_t)r0 * c->P * 2, nb, c->P, c->Zin, nc);
-        run_chi0(c, s, nb, eps);
+        run_chi0(c, s, nb, eps, precision, c->omega_dev);
         launch_cols_to_rows(&c->tracer, s, c->Yout, nb, c->P, nc, out + (int64_t)r0 * c->P * 2);
     }
     HIPCHK(c, hipGetLastError());
@@ -648,10 +723,13 @@ struct SlotState {
     int state = S_FREE;
     int point = -1;
     int j = 0;
-    double bnorm = 0.0;
+    int prec = CHI0_PREC_FP64;   // arithmetic of this slot's Arnoldi steps
+    double bnorm = 0.0;          // ||b|| = ||chi0 d||
+    double cycle0 = 0.0;         // residual norm at the start of the current cycle
+    double rel_prev = 1.0;       // true relative residual after the previous cycle
 };
 struct PointState {
-    int iters = 0, restarts = 0, converged = 0, breakdown = 0;
+    int iters = 0, restarts = 0, converged = 0, breakdown = 0, fallback = 0;
     double rel = NAN;
 };
 }  // namespace
@@ -672,9 +750,14 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
     if (o.max_iter < 1) return fail(c, CHI0_EINVAL, "max_iter must be >= 1");
     if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(c, CHI0_EINVAL, "tol must be finite and > 0");
     if (o.batch < 1) return fail(c, CHI0_EINVAL, "batch must be >= 1");
-    if (o.precision != CHI0_PREC_FP64) return fail(c, CHI0_EINVAL, "unsupported precision");
-    for (int i = 0; i < 8; ++i)
+    if (o.batch > kMaxBatch) return fail(c, CHI0_EINVAL, "batch must be <= 256");
+    if (o.precision < CHI0_PREC_FP64 || o.precision > CHI0_PREC_BF16X3)
+        return fail(c, CHI0_EINVAL, "unknown precision");
+    if (!(o.inner_tol >= 0.0) || !(o.inner_tol < 1.0)) return fail(c, CHI0_EINVAL, "inner_tol must be in [0, 1)");
+    for (int i = 0; i < 6; ++i)
         if (o.reserved[i] != 0) return fail(c, CHI0_EINVAL, "reserved option fields must be zero");
+    const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol
+                             : (o.precision == CHI0_PREC_FP32 ? 1e-6 : 1e-4);
     if (!all_finite(omega, n_omega)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
     if (!all_finite(V_ext, (int64_t)n_drive * c->P)) return fail(c, CHI0_ENONFINITE, "non-finite V_ext");
     HIPCHK(c, hipSetDevice(c->device));
@@ -684,6 +767,7 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
     const int m = o.restart;
     const int P = c->P;
     CHK(ensure_ws(c, 2 * std::max(nsl, c->nc_cap / 2)));
+    if (o.precision != CHI0_PREC_FP64) CHK(ensure_lp(c));
     CHK(ensure_slots(c, nsl, m));
     hipStream_t s = c->stream;
     Tracer *t = &c->tracer;
@@ -730,42 +814,52 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                 sl[k].point = next_point++;
                 sl[k].j = 0;
             }
-        // (4) one job per active slot
-        int nb = 0, jmax = -1, n_arn = 0;
+        // (4) one job per active slot: FP64 jobs first (b, true residual, FP64
+        //     Arnoldi), then the low-precision Arnoldi steps, so each group is a
+        //     contiguous range processed by one operator pass
+        int nb = 0, nb64 = 0, jmax = -1, n_arn = 0;
         double sum_j1 = 0.0;
-        bool any_arnoldi = false;
-        for (int k = 0; k < nsl; ++k) {
-            if (sl[k].state == S_FREE) continue;
-            Job jb;
-            jb.slot = k;
-            jb.type = sl[k].state == S_RHS ? JOB_RHS : sl[k].state == S_ARNOLDI ? JOB_ARNOLDI : JOB_RESID;
-            jb.j = sl[k].j;
-            jb.drive = sl[k].point % n_drive;
-            if (jb.type == JOB_ARNOLDI) {
-                any_arnoldi = true;
-                jmax = std::max(jmax, jb.j);
-                ++n_arn;
-                sum_j1 += jb.j + 1;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int k = 0; k < nsl; ++k) {
+                if (sl[k].state == S_FREE) continue;
+                const bool lowp = sl[k].state == S_ARNOLDI && sl[k].prec != CHI0_PREC_FP64;
+                if (lowp != (pass == 1)) continue;
+                Job jb;
+                jb.slot = k;
+                jb.type = sl[k].state == S_RHS ? JOB_RHS : sl[k].state == S_ARNOLDI ? JOB_ARNOLDI : JOB_RESID;
+                jb.j = sl[k].j;
+                jb.drive = sl[k].point % n_drive;
+                if (jb.type == JOB_ARNOLDI) {
+                    jmax = std::max(jmax, jb.j);
+                    ++n_arn;
+                    sum_j1 += jb.j + 1;
+                }
+                c->jobs_h[nb] = jb;
+                c->omega_h[nb] = omega[sl[k].point / n_drive];
+                ++nb;
+                if (pass == 0) ++nb64;
             }
-            c->jobs_h[nb] = jb;
-            c->omega_h[nb] = omega[sl[k].point / n_drive];
-            ++nb;
-        }
         if (nb == 0) break;
-        const int nc = 2 * nb;
         HIPCHK(c, hipMemcpyAsync(c->jobs_dev, c->jobs_h, sizeof(Job) * nb, hipMemcpyHostToDevice, s));
         HIPCHK(c, hipMemcpyAsync(c->omega_dev, c->omega_h, sizeof(double) * nb, hipMemcpyHostToDevice, s));
-        // (5) operator: Zin = K v (b jobs: d), Y = chi0 Zin
-        launch_gather_jobs(t, s, c->jobs_dev, nb, c->slots, c->Vb, nc, P);
-        if (nc <= 16)
-            launch_kmatvec_skinny(t, s, c->P_pad, c->K, c->Vb, c->Zin, nc, (double)P);
-        else
-            launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, c->Vb, nc, c->Zin, nc,
-                         2.0 * P * (double)P * nc, 8.0 * ((double)P * P + 2.0 * P * nc));
-        launch_put_drive(t, s, c->jobs_dev, nb, drives, c->P_pad, c->Zin, nc, P);
-        run_chi0(c, s, nb, eps);
-        launch_post_jobs(t, s, c->jobs_dev, nb, c->slots, c->Yout, nc, P, c->status_dev);
-        if (any_arnoldi)
+        // (5) operator per group: Zin = K v (b jobs: d), Y = chi0 Zin, then post
+        auto run_group = [&](int g0, int gn, int prec) {
+            const int nc = 2 * gn;
+            const Job *jg = c->jobs_dev + g0;
+            launch_gather_jobs(t, s, jg, gn, c->slots, c->Vb, nc, P);
+            if (nc <= 16)
+                launch_kmatvec_skinny(t, s, c->P_pad, c->K, c->Vb, c->Zin, nc, (double)P);
+            else
+                launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, c->Vb, nc, c->Zin,
+                             nc, 2.0 * P * (double)P * nc, 8.0 * ((double)P * P + 2.0 * P * nc),
+                             c->gemm_scratch, c->gemm_scratch_n);
+            launch_put_drive(t, s, jg, gn, drives, c->P_pad, c->Zin, nc, P);
+            run_chi0(c, s, gn, eps, prec, c->omega_dev + g0);
+            launch_post_jobs(t, s, jg, gn, c->slots, c->Yout, nc, P, c->status_dev + g0);
+        };
+        if (nb64 > 0) run_group(0, nb64, CHI0_PREC_FP64);
+        if (nb > nb64) run_group(nb64, nb - nb64, o.precision);
+        if (n_arn > 0)
             launch_arnoldi(t, s, c->jobs_dev, nb, jmax, c->slots, P, c->status_dev, n_arn, sum_j1);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->status_h, c->status_dev, sizeof(StepStatus) * nb, hipMemcpyDeviceToHost, s));
@@ -778,6 +872,9 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
             const StepStatus &st = c->status_h[q];
             if (jb.type == JOB_RHS) {
                 ss.bnorm = st.value;
+                ss.cycle0 = st.value;
+                ss.rel_prev = 1.0;
+                ss.prec = o.precision;
                 if (!(st.value > 0.0) || !std::isfinite(st.value)) {
                     pt.rel = st.value == 0.0 ? 0.0 : NAN;
                     pt.converged = st.value == 0.0;
@@ -790,10 +887,12 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                 }
             } else if (jb.type == JOB_ARNOLDI) {
                 pt.iters += 1;
-                const bool conv_est = st.value <= o.tol * ss.bnorm;
+                double stop = o.tol * ss.bnorm;
+                if (ss.prec != CHI0_PREC_FP64) stop = std::max(stop, inner_tol * ss.cycle0);
                 const bool brk = st.hnext == 0.0;
                 if (brk) pt.breakdown = 1;
-                if (conv_est || brk || ss.j + 1 >= m || pt.iters >= o.max_iter || !std::isfinite(st.value)) {
+                if (st.value <= stop || brk || ss.j + 1 >= m || pt.iters >= o.max_iter ||
+                    !std::isfinite(st.value)) {
                     upd.push_back({jb.slot, 0, ss.j + 1, 0});
                     ss.state = S_RESID;
                 } else {
@@ -808,6 +907,14 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                     ss.state = S_FREE;
                     ++done;
                 } else {
+                    // iterative refinement: a low-precision cycle that did not halve the
+                    // true residual hands the point to FP64 Arnoldi steps
+                    if (ss.prec != CHI0_PREC_FP64 && pt.rel > 0.5 * ss.rel_prev) {
+                        ss.prec = CHI0_PREC_FP64;
+                        pt.fallback = 1;
+                    }
+                    ss.rel_prev = pt.rel;
+                    ss.cycle0 = st.value;
                     ss.state = S_ARNOLDI;
                     ss.j = 0;
                 }
@@ -839,6 +946,8 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                 r.restarts = ps[p].restarts;
                 r.converged = ps[p].converged;
                 r.breakdown = ps[p].breakdown;
+                r.fallback = ps[p].fallback;
+                r.reserved = 0;
                 r.rel_residual = ps[p].rel;
             }
         }

@@ -42,6 +42,17 @@ struct WorkSizes {
     double N = 0, No = 0, Nv = 0, P = 0, nnzB = 0, sum_s2 = 0, npart = 0;
 };
 
+// Frequency factor of (b2)+(c): GEMM column n <-> (E, j) with E = n / ncp,
+// j = n % ncp; columns 2r and 2r+1 hold Re and Im of RHS r; GEMM row = virtual F.
+struct LorentzArgs {
+    const double *Dlt;   // [No_pad][Nv_pad]
+    const double *omega; // [ncp/2]
+    int nv_pad;
+    int ncp;
+    double eps;
+    double occ;
+};
+
 // -------------------------------------------------------------- chi0 blocks
 struct BlockMapDev {
     // per atom-pair block k (n_blk of them)
@@ -68,8 +79,10 @@ struct BlockMapDev {
 void launch_vertex_gather(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk,
                           const double *Z, double *dV, int nc, const WorkSizes &ws);
 // (d) n_mu = <V_mu, W>: per-block partial sums, then the sum over each product's blocks.
+// max_nprod = largest number of products covering one block.
 void launch_vertex_contract(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk, int P,
-                            const double *W, double *part, double *Y, int nc, const WorkSizes &ws);
+                            const double *W, double *part, double *Y, int nc, const WorkSizes &ws,
+                            int max_nprod);
 // (b1) Tt = X_occ^T dV (gathered MFMA GEMM over the block pattern).
 void launch_occ_transform(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms,
                           const double *Xo, int no_pad, const double *dV, double *Tt,
@@ -79,14 +92,34 @@ void launch_occ_back(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atom
                      const double *Xo, int no_pad, const double *Ut, double *W, int nc,
                      const WorkSizes &ws);
 // Dense FP64 MFMA GEMM C = A B (row-major, M%64 == K%16 == 0, N masked).
+// scratch (may be NULL) holds split-K partial products when the tile count is low.
 void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                   const double *A, int lda, const double *B, int ldb, double *C, int ldc,
-                  double flops, double bytes);
+                  double flops, double bytes, double *scratch, size_t scratch_doubles);
 // (b2)+(c) at = Xvt Tt with the Lorentzian factor of column (E, j) and row F applied.
 void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K,
                           const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                           const double *Dlt, int nv_pad, const double *omega, double eps,
-                          double occ, int ncp, double flops, double bytes);
+                          double occ, int ncp, double flops, double bytes, double *scratch,
+                          size_t scratch_doubles);
+// Low-precision operator: FP32 gathered transforms, FP32 or split-BF16x3 dense transforms.
+void launch_occ_transform_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms,
+                              const float *Xo, int no_pad, const double *dV, float *Tt,
+                              int nc, const WorkSizes &ws);
+void launch_occ_back_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
+                         const float *Xo, int no_pad, const float *Ut, double *W, int nc,
+                         const WorkSizes &ws);
+void launch_sgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
+                  const float *A, int lda, const float *B, int ldb, float *C, int ldc,
+                  double flops, double bytes, const LorentzArgs *la, void *scratch,
+                  size_t scratch_bytes);
+void launch_bgemm3(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
+                   const uint16_t *Ahi, const uint16_t *Alo, int lda, const float *B, int ldb,
+                   float *C, int ldc, double flops, double bytes, const LorentzArgs *la,
+                   void *scratch, size_t scratch_bytes);
+void launch_to_f32(hipStream_t s, const double *x, float *y, int64_t n);
+void launch_split_bf16(hipStream_t s, const double *x, uint16_t *hi, uint16_t *lo, int64_t n);
+
 // (e) skinny K z for a few columns (HBM-streaming GEMV).
 void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
                            const double *Zin, double *Zout, int nc, double P);

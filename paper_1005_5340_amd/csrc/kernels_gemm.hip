@@ -1,20 +1,46 @@
-// FP64 MFMA kernels of the orbital transforms (Sec. 4.2, Table t:flops steps
-// 2-5) and the kernel matrix-vector product (Sec. 4.1).
+// Matrix-core kernels of the orbital transforms (Sec. 4.2, Table t:flops steps
+// 2-5) and the kernel matrix-vector product (Sec. 4.1), for FP64 and FP32.
 //
-// All matrix-core work uses v_mfma_f64_16x16x4f64 on 64-lane wavefronts.
-// Operand layout of one 16x16x4 step (lane l = 0..63):
+// 16x16x4 MFMA on 64-lane wavefronts, lane l = 0..63:
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
 //   B (4 x 16):  lane l holds B[l / 16][l % 16]
-//   D (16 x 16): lane l holds D[4*r + l/16][l % 16] in element r = 0..3
-//                (rows interleaved by 4; checked on gfx950 with a lane probe)
+//   D (16 x 16): element r of lane l holds D[row(l, r)][l % 16] with
+//                row = 4r + l/16     for v_mfma_f64_16x16x4f64 (interleaved)
+//                row = 4(l/16) + r   for v_mfma_f32_16x16x4f32 (contiguous)
+//   (both checked on gfx950 with lane probes)
 #include "common.h"
 
 namespace chi0 {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+template <class T> struct Mma;
+template <> struct Mma<double> {
+    typedef dbl4 acc;
+    static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ acc op(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mma<float> {
+    typedef flt4 acc;
+    static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+    static __device__ __forceinline__ acc op(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// four consecutive elements (16 B aligned for float, 2 x 16 B for double)
+__device__ __forceinline__ void load4(const double *p, double *v) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void load4(const float *p, float *v) {
+    const float4 a = reinterpret_cast<const float4 *>(p)[0];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
 // Workgroup id -> tile id such that each of the 8 XCDs (which receive
@@ -30,20 +56,17 @@ __device__ __forceinline__ int xcd_remap(int wid, int n) {
 // C[M x N] = A[M x K] B[K x N], row-major, M % BM == 0, K % 16 == 0, N masked.
 // Optional epilogue (b2)+(c): C column n <-> (E, j) with E = n / ncp,
 // j = n % ncp; columns 2r and 2r+1 hold Re and Im of RHS r; row = virtual F.
-struct LorentzArgs {
-    const double *Dlt;   // [No_pad][Nv_pad]
-    const double *omega; // [ncp/2]
-    int nv_pad;
-    int ncp;
-    double eps;
-    double occ;
-};
-
-template <int BM, int BN, int WM, int WN, bool LORENTZ>
+// Split-K: blockIdx.y selects a K range of length K (the per-split length);
+// A and B are advanced by it and each split writes raw partial sums to its
+// own C slice (C + split * M * ldc), summed later by k_splitk_reduce.
+template <class T, int BM, int BN, int WM, int WN, bool LORENTZ>
 __global__ __launch_bounds__(WM * WN * 64)
-void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
-             const double *__restrict__ B, int ldb, double *__restrict__ C, int ldc,
+void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
+             const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
              int m_fastest, LorentzArgs la) {
+    A += (int64_t)blockIdx.y * K;
+    B += (int64_t)blockIdx.y * K * ldb;
+    C += (int64_t)blockIdx.y * M * ldc;
     constexpr int BK = 16;
     constexpr int NT = WM * WN * 64;
     constexpr int TM = BM / WM / 16;
@@ -51,8 +74,8 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
     constexpr int APT = BM * BK / NT;   // A doubles per thread per tile
     constexpr int BPT = BK * BN / NT;   // B doubles per thread per tile
     static_assert(APT == 4 && BPT == 4, "tile shape must give 4 doubles per thread");
-    __shared__ double As[2][BK][BM + 1];
-    __shared__ double Bs[2][BK][BN];
+    __shared__ T As[2][BK][BM + 1];
+    __shared__ T Bs[2][BK][BN];
 
     const int ntm = M / BM, ntn = (N + BN - 1) / BN;
     const int tile = xcd_remap(blockIdx.x, ntm * ntn);
@@ -65,23 +88,19 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
     // global -> register mapping
     const int a_row = t / 4, a_k = (t % 4) * 4;        // BM rows x 16 k
     const int b_k = t / (BN / 4), b_n = (t % (BN / 4)) * 4;
-    const double *Ap = A + (int64_t)(m0 + a_row) * lda + a_k;
-    const double *Bp = B + (int64_t)b_k * ldb + n0 + b_n;
+    const T *Ap = A + (int64_t)(m0 + a_row) * lda + a_k;
+    const T *Bp = B + (int64_t)b_k * ldb + n0 + b_n;
     const bool b_full = (n0 + b_n + 3) < N;
 
-    double ra[4], rb[4];
+    T ra[4], rb[4];
     auto load = [&](int kt) {
-        const double2 *ap = reinterpret_cast<const double2 *>(Ap + kt * BK);
-        double2 x0 = ap[0], x1 = ap[1];
-        ra[0] = x0.x; ra[1] = x0.y; ra[2] = x1.x; ra[3] = x1.y;
-        const double *bp = Bp + (int64_t)kt * BK * ldb;
+        load4(Ap + kt * BK, ra);
+        const T *bp = Bp + (int64_t)kt * BK * ldb;
         if (b_full) {
-            const double2 *bq = reinterpret_cast<const double2 *>(bp);
-            double2 y0 = bq[0], y1 = bq[1];
-            rb[0] = y0.x; rb[1] = y0.y; rb[2] = y1.x; rb[3] = y1.y;
+            load4(bp, rb);
         } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) rb[c] = (n0 + b_n + c < N) ? bp[c] : 0.0;
+            for (int c = 0; c < 4; ++c) rb[c] = (n0 + b_n + c < N) ? bp[c] : T(0);
         }
     };
     auto store = [&](int buf) {
@@ -91,11 +110,11 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
         for (int c = 0; c < 4; ++c) Bs[buf][b_k][b_n + c] = rb[c];
     };
 
-    dbl4 acc[TM][TN];
+    typename Mma<T>::acc acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < TN; ++j) acc[i][j] = Mma<T>::zero();
 
     const int KT = K / BK;
     load(0);
@@ -107,7 +126,7 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             const int kk = ks * 4 + lane / 16;
-            double af[TM], bf[TN];
+            T af[TM], bf[TN];
 #pragma unroll
             for (int i = 0; i < TM; ++i) af[i] = As[cur][kk][wm * (BM / WM) + i * 16 + (lane & 15)];
 #pragma unroll
@@ -115,7 +134,7 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+                for (int j = 0; j < TN; ++j) acc[i][j] = Mma<T>::op(af[i], bf[j], acc[i][j]);
         }
         if (kt + 1 < KT) store(cur ^ 1);
         __syncthreads();
@@ -136,22 +155,22 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
         }
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
-            const int row0 = m0 + wm * (BM / WM) + i * 16 + (lane >> 4);
+            const int rbase = m0 + wm * (BM / WM) + i * 16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = row0 + 4 * r;
-                double v = acc[i][j][r];
+                const int row = rbase + Mma<T>::row(lane, r);
+                T v = acc[i][j][r];
                 if (LORENTZ) {
-                    // L = n [1/(w - D + i eps) - 1/(w + D + i eps)], applied to
-                    // the complex number held by this lane and its xor-1 partner.
-                    const double other = __shfl_xor(v, 1);
+                    // L = n [1/(w - D + i eps) - 1/(w + D + i eps)] (in FP64), applied
+                    // to the complex number held by this lane and its xor-1 partner.
+                    const T other = __shfl_xor(v, 1);
                     const double D = la.Dlt[(int64_t)E * la.nv_pad + row];
                     const double d1 = w - D, d2 = w + D, e = la.eps;
                     const double s1 = 1.0 / (d1 * d1 + e * e), s2 = 1.0 / (d2 * d2 + e * e);
                     const double Lr = la.occ * (d1 * s1 - d2 * s2);
                     const double Li = la.occ * (-e * s1 + e * s2);
-                    const double re = par ? other : v, im = par ? v : other;
-                    v = par ? (re * Li + im * Lr) : (re * Lr - im * Li);
+                    const double re = par ? (double)other : (double)v, im = par ? (double)v : (double)other;
+                    v = (T)(par ? (re * Li + im * Lr) : (re * Lr - im * Li));
                 }
                 if (ok) C[(int64_t)row * ldc + col] = v;
             }
@@ -159,75 +178,166 @@ void k_dgemm(int M, int N, int K, const double *__restrict__ A, int lda,
     }
 }
 
-void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
-                  const double *A, int lda, const double *B, int ldb, double *C, int ldc,
-                  double flops, double bytes) {
+// C = sum over splits of the partial products; optional Lorentzian epilogue.
+template <class T>
+__global__ __launch_bounds__(256)
+void k_splitk_reduce(int M, int N, int S, const T *__restrict__ part, int64_t slice,
+                     T *__restrict__ C, int ldc, int lorentz, LorentzArgs la) {
+    const int64_t npair = (int64_t)M * ((N + 1) / 2);
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < npair;
+         idx += (int64_t)gridDim.x * 256) {
+        const int row = (int)(idx / ((N + 1) / 2));
+        const int col = 2 * (int)(idx % ((N + 1) / 2));
+        const int64_t o = (int64_t)row * ldc + col;
+        const int64_t op = (int64_t)row * N + col;
+        const bool two = col + 1 < N;
+        double re = 0.0, im = 0.0;
+        for (int s2 = 0; s2 < S; ++s2) {
+            re += (double)part[s2 * slice + op];
+            if (two) im += (double)part[s2 * slice + op + 1];
+        }
+        if (lorentz) {
+            const int E = col / la.ncp, jj = col - E * la.ncp;
+            const double w = la.omega[jj >> 1];
+            const double D = la.Dlt[(int64_t)E * la.nv_pad + row];
+            const double d1 = w - D, d2 = w + D, e = la.eps;
+            const double s1 = 1.0 / (d1 * d1 + e * e), s2 = 1.0 / (d2 * d2 + e * e);
+            const double Lr = la.occ * (d1 * s1 - d2 * s2), Li = la.occ * (-e * s1 + e * s2);
+            const double r2 = re * Lr - im * Li, i2 = re * Li + im * Lr;
+            re = r2;
+            im = i2;
+        }
+        C[o] = (T)re;
+        if (two) C[o + 1] = (T)im;
+    }
+}
+
+// Number of K splits: enough workgroups to fill 256 CUs a few times over,
+// each split keeping >= 4 K tiles of `ktile`; limited by the scratch capacity.
+static int choose_splits(int M, int N, int K, int ktile, size_t scratch_elems) {
     const int tiles = (M / 64) * ((N + 63) / 64);
-    LorentzArgs la{};
+    const int KT = K / ktile;
+    int S = 1;
+    while (S < 16 && tiles * S < 1024 && KT % (2 * S) == 0 && KT / (2 * S) >= 4 &&
+           (size_t)(2 * S) * M * (size_t)N <= scratch_elems)
+        S *= 2;
+    return S;
+}
+
+template <class T>
+static void reduce_splits(Tracer *t, hipStream_t s, int M, int N, int S, const T *scratch, T *C,
+                          int ldc, bool lorentz, const LorentzArgs &la) {
+    const int64_t npair = (int64_t)M * ((N + 1) / 2);
+    int64_t blocks = (npair + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    trace_begin(t, "splitk_reduce", s);
+    hipLaunchKernelGGL(k_splitk_reduce<T>, dim3((unsigned)blocks), dim3(256), 0, s, M, N, S, scratch,
+                       (int64_t)M * N, C, ldc, lorentz ? 1 : 0, la);
+    trace_end(t, s, (double)S * M * N, (double)sizeof(T) * ((double)S + 1.0) * M * N);
+}
+
+template <class T>
+static void gemm_any(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
+                     const T *A, int lda, const T *B, int ldb, T *C, int ldc,
+                     double flops, double bytes, bool lorentz, const LorentzArgs &la,
+                     void *scratch, size_t scratch_bytes) {
+    const int tiles = (M / 64) * ((N + 63) / 64);
+    const int S = scratch ? choose_splits(M, N, K, 16, scratch_bytes / sizeof(T)) : 1;
     const int m_fastest = (M / 64) <= ((N + 63) / 64);
     trace_begin(t, name, s);
-    hipLaunchKernelGGL((k_dgemm<64, 64, 2, 2, false>), dim3(tiles), dim3(256), 0, s,
-                       M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+    if (S == 1) {
+        if (lorentz)
+            hipLaunchKernelGGL((k_dgemm<T, 64, 64, 2, 2, true>), dim3(tiles, 1), dim3(256), 0, s,
+                               M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        else
+            hipLaunchKernelGGL((k_dgemm<T, 64, 64, 2, 2, false>), dim3(tiles, 1), dim3(256), 0, s,
+                               M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        trace_end(t, s, flops, bytes);
+        return;
+    }
+    // partial products with ldc = N into scratch, then the reduction (+ epilogue)
+    T *part = static_cast<T *>(scratch);
+    hipLaunchKernelGGL((k_dgemm<T, 64, 64, 2, 2, false>), dim3(tiles, S), dim3(256), 0, s,
+                       M, N, K / S, A, lda, B, ldb, part, N, m_fastest, la);
     trace_end(t, s, flops, bytes);
+    reduce_splits<T>(t, s, M, N, S, part, C, ldc, lorentz, la);
+}
+
+void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
+                  const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                  double flops, double bytes, double *scratch, size_t scratch_doubles) {
+    LorentzArgs la{};
+    gemm_any<double>(t, s, name, M, N, K, A, lda, B, ldb, C, ldc, flops, bytes, false, la, scratch,
+                     scratch_doubles * sizeof(double));
 }
 
 void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K,
                           const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                           const double *Dlt, int nv_pad, const double *omega, double eps,
-                          double occ, int ncp, double flops, double bytes) {
-    const int tiles = (M / 64) * ((N + 63) / 64);
+                          double occ, int ncp, double flops, double bytes, double *scratch,
+                          size_t scratch_doubles) {
     LorentzArgs la{Dlt, omega, nv_pad, ncp, eps, occ};
-    trace_begin(t, "virt_transform_lorentz", s);
-    hipLaunchKernelGGL((k_dgemm<64, 64, 2, 2, true>), dim3(tiles), dim3(256), 0, s,
-                       M, N, K, A, lda, B, ldb, C, ldc, 1, la);
-    trace_end(t, s, flops, bytes);
+    gemm_any<double>(t, s, "virt_transform_lorentz", M, N, K, A, lda, B, ldb, C, ldc, flops, bytes,
+                     true, la, scratch, scratch_doubles * sizeof(double));
+}
+
+void launch_splitk_reduce_f32(Tracer *t, hipStream_t s, int M, int N, int S, const float *part,
+                              float *C, int ldc, const LorentzArgs *la) {
+    LorentzArgs none{};
+    reduce_splits<float>(t, s, M, N, S, part, C, ldc, la != nullptr, la ? *la : none);
+}
+
+void launch_sgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
+                  const float *A, int lda, const float *B, int ldb, float *C, int ldc,
+                  double flops, double bytes, const LorentzArgs *la, void *scratch,
+                  size_t scratch_bytes) {
+    LorentzArgs none{};
+    gemm_any<float>(t, s, name, M, N, K, A, lda, B, ldb, C, ldc, flops, bytes, la != nullptr,
+                    la ? *la : none, scratch, scratch_bytes);
 }
 
 // ------------------------------------------------------- (b1) occupied transform
 // Tt[b][E*nc + j] = sum_{A in nbr(B)} sum_{a in A} Xo[a][E] dV[(k(A,B), a, b)][j]
 // One workgroup: column atom B, 64 occupied states, 16 columns.  Wave w owns
 // states 16w..16w+15 and every orbital b of B (one accumulator per b).
+// T is the arithmetic type (FP64, or FP32 for the low-precision operator);
+// dV is always FP64 and is rounded to T when staged.
+template <class T>
 __global__ __launch_bounds__(256)
-void k_occ_transform(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
-                     const double *__restrict__ dV, double *__restrict__ Tt, int nc) {
+void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
+                     const double *__restrict__ dV, T *__restrict__ Tt, int nc) {
     const int B = blockIdx.x, e0 = blockIdx.y * 64, j0 = blockIdx.z * JT;
     const int g0 = bm.col_gstart[B], g1 = bm.col_gstart[B + 1];
     const int boff = bm.atom_off[B], nB = bm.atom_off[B + 1] - boff;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    __shared__ double Xs[16][64 + 1];
-    __shared__ double Ds[16][NB_MAX][JT];
+    __shared__ T Xs[16][64 + 1];
+    __shared__ T Ds[16][NB_MAX][JT];
 
-    dbl4 acc[NB_MAX];
+    typename Mma<T>::acc acc[NB_MAX];
 #pragma unroll
-    for (int b = 0; b < NB_MAX; ++b) acc[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NB_MAX; ++b) acc[b] = Mma<T>::zero();
 
     for (int gc = g0; gc < g1; gc += 16) {
         {   // Xs: 16 gathered rows x 64 states, 4 per thread
             const int r = t / 16, c = (t % 16) * 4, g = gc + r;
-            if (g < g1) {
-                const double *src = Xo + (int64_t)bm.g_xrow[g] * no_pad + e0 + c;
-                const double2 *p = reinterpret_cast<const double2 *>(src);
-                double2 x0 = p[0], x1 = p[1];
-                Xs[r][c] = x0.x; Xs[r][c + 1] = x0.y; Xs[r][c + 2] = x1.x; Xs[r][c + 3] = x1.y;
-            } else {
-                Xs[r][c] = 0.0; Xs[r][c + 1] = 0.0; Xs[r][c + 2] = 0.0; Xs[r][c + 3] = 0.0;
-            }
+            T v[4] = {T(0), T(0), T(0), T(0)};
+            if (g < g1) load4(Xo + (int64_t)bm.g_xrow[g] * no_pad + e0 + c, v);
+            Xs[r][c] = v[0]; Xs[r][c + 1] = v[1]; Xs[r][c + 2] = v[2]; Xs[r][c + 3] = v[3];
         }
-        for (int idx = t; idx < 16 * nB * JT; idx += 256) {
-            const int r = idx / (nB * JT), rem = idx % (nB * JT);
-            const int b = rem / JT, jj = rem % JT, g = gc + r, j = j0 + jj;
-            double v = 0.0;
-            if (g < g1 && j < nc) v = dV[(bm.g_ent[g] + b) * (int64_t)nc + j];
-            Ds[r][b][jj] = v;
+        {   // Ds: thread -> (gathered row r, column jj), looping over the orbitals b of B
+            const int r = t / JT, jj = t % JT, g = gc + r, j = j0 + jj;
+            const bool ok = g < g1 && j < nc;
+            const double *src = dV + (ok ? (bm.g_ent[g] * (int64_t)nc + j) : 0);
+            for (int b = 0; b < nB; ++b) Ds[r][b][jj] = ok ? (T)src[(int64_t)b * nc] : T(0);
         }
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            const double a = Xs[kk][wv * 16 + (lane & 15)];
+            const T a = Xs[kk][wv * 16 + (lane & 15)];
 #pragma unroll
             for (int b = 0; b < NB_MAX; ++b)
-                if (b < nB) acc[b] = mfma16(a, Ds[kk][b][lane & 15], acc[b]);
+                if (b < nB) acc[b] = Mma<T>::op(a, Ds[kk][b][lane & 15], acc[b]);
         }
         __syncthreads();
     }
@@ -239,7 +349,7 @@ void k_occ_transform(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
             if (b < nB) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int E = e0 + wv * 16 + 4 * r + (lane >> 4);
+                    const int E = e0 + wv * 16 + Mma<T>::row(lane, r);
                     Tt[(int64_t)(boff + b) * ldT + (int64_t)E * nc + j] = acc[b][r];
                 }
             }
@@ -247,22 +357,37 @@ void k_occ_transform(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
     }
 }
 
+template <class T>
+static void occ_transform_any(Tracer *t, hipStream_t s, const char *name, const BlockMapDev &bm,
+                              int n_atoms, const T *Xo, int no_pad, const double *dV, T *Tt, int nc,
+                              const WorkSizes &ws) {
+    dim3 grid(n_atoms, no_pad / 64, (nc + JT - 1) / JT);
+    trace_begin(t, name, s);
+    hipLaunchKernelGGL(k_occ_transform<T>, grid, dim3(256), 0, s, bm, Xo, no_pad, dV, Tt, nc);
+    trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
+              8.0 * ws.nnzB * nc + sizeof(T) * (ws.N * ws.No + ws.N * ws.No * nc));
+}
+
 void launch_occ_transform(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms,
                           const double *Xo, int no_pad, const double *dV, double *Tt,
                           int nc, const WorkSizes &ws) {
-    dim3 grid(n_atoms, no_pad / 64, (nc + JT - 1) / JT);
-    trace_begin(t, "occ_transform", s);
-    hipLaunchKernelGGL(k_occ_transform, grid, dim3(256), 0, s, bm, Xo, no_pad, dV, Tt, nc);
-    trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
-              8.0 * (ws.nnzB * nc + ws.N * ws.No + ws.N * ws.No * nc));
+    occ_transform_any<double>(t, s, "occ_transform", bm, n_atoms, Xo, no_pad, dV, Tt, nc, ws);
+}
+
+void launch_occ_transform_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms,
+                              const float *Xo, int no_pad, const double *dV, float *Tt,
+                              int nc, const WorkSizes &ws) {
+    occ_transform_any<float>(t, s, "occ_transform_f32", bm, n_atoms, Xo, no_pad, dV, Tt, nc, ws);
 }
 
 // ------------------------------------------------------ (b4) back to the pattern
 // W[(k(A,B), a, b)][j] = sum_E Xo[a][E] Ut[b][E*nc + j] for (A, B) in the pattern.
 // One workgroup: column atom B, 64 of its gathered rows (A, a), 16 columns.
+// Accumulation in T; W is written in FP64.
+template <class T>
 __global__ __launch_bounds__(256)
-void k_occ_back(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
-                const double *__restrict__ Ut, double *__restrict__ W, int nc) {
+void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
+                const T *__restrict__ Ut, double *__restrict__ W, int nc) {
     const int B = blockIdx.x, j0 = blockIdx.z * JT;
     const int g1 = bm.col_gstart[B + 1];
     const int g0 = bm.col_gstart[B] + blockIdx.y * 64;
@@ -270,36 +395,33 @@ void k_occ_back(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
     const int boff = bm.atom_off[B], nB = bm.atom_off[B + 1] - boff;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t ldT = (int64_t)no_pad * nc;
-    __shared__ double Xs[64][16 + 1];
-    __shared__ double Us[NB_MAX][16][JT];
+    __shared__ T Xs[64][16 + 1];
+    __shared__ T Us[NB_MAX][16][JT];
 
-    dbl4 acc[NB_MAX];
+    typename Mma<T>::acc acc[NB_MAX];
 #pragma unroll
-    for (int b = 0; b < NB_MAX; ++b) acc[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NB_MAX; ++b) acc[b] = Mma<T>::zero();
 
     const int xr = t / 4, xc = (t % 4) * 4, xg = g0 + xr;
-    const double *xsrc = (xg < g1) ? Xo + (int64_t)bm.g_xrow[xg] * no_pad + xc : nullptr;
+    const T *xsrc = (xg < g1) ? Xo + (int64_t)bm.g_xrow[xg] * no_pad + xc : nullptr;
     for (int E0 = 0; E0 < no_pad; E0 += 16) {
-        if (xsrc) {
-            const double2 *p = reinterpret_cast<const double2 *>(xsrc + E0);
-            double2 x0 = p[0], x1 = p[1];
-            Xs[xr][xc] = x0.x; Xs[xr][xc + 1] = x0.y; Xs[xr][xc + 2] = x1.x; Xs[xr][xc + 3] = x1.y;
-        } else {
-            Xs[xr][xc] = 0.0; Xs[xr][xc + 1] = 0.0; Xs[xr][xc + 2] = 0.0; Xs[xr][xc + 3] = 0.0;
-        }
-        for (int idx = t; idx < nB * 16 * JT; idx += 256) {
-            const int b = idx / (16 * JT), rem = idx % (16 * JT);
-            const int e = rem / JT, jj = rem % JT, j = j0 + jj;
-            Us[b][e][jj] = (j < nc) ? Ut[(int64_t)(boff + b) * ldT + (int64_t)(E0 + e) * nc + j] : 0.0;
+        T v[4] = {T(0), T(0), T(0), T(0)};
+        if (xsrc) load4(xsrc + E0, v);
+        Xs[xr][xc] = v[0]; Xs[xr][xc + 1] = v[1]; Xs[xr][xc + 2] = v[2]; Xs[xr][xc + 3] = v[3];
+        {   // Us: thread -> (state e, column jj), looping over the orbitals b of B
+            const int e = t / JT, jj = t % JT, j = j0 + jj;
+            const bool ok = j < nc;
+            const T *src = Ut + (int64_t)boff * ldT + (int64_t)(E0 + e) * nc + (ok ? j : 0);
+            for (int b = 0; b < nB; ++b) Us[b][e][jj] = ok ? src[(int64_t)b * ldT] : T(0);
         }
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            const double a = Xs[wv * 16 + (lane & 15)][kk];
+            const T a = Xs[wv * 16 + (lane & 15)][kk];
 #pragma unroll
             for (int b = 0; b < NB_MAX; ++b)
-                if (b < nB) acc[b] = mfma16(a, Us[b][kk][lane & 15], acc[b]);
+                if (b < nB) acc[b] = Mma<T>::op(a, Us[b][kk][lane & 15], acc[b]);
         }
         __syncthreads();
     }
@@ -307,25 +429,38 @@ void k_occ_back(BlockMapDev bm, const double *__restrict__ Xo, int no_pad,
     if (j < nc) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int g = g0 + wv * 16 + 4 * r + (lane >> 4);
+            const int g = g0 + wv * 16 + Mma<T>::row(lane, r);
             if (g < g1) {
                 const int64_t base = bm.g_ent[g];
 #pragma unroll
                 for (int b = 0; b < NB_MAX; ++b)
-                    if (b < nB) W[(base + b) * nc + j] = acc[b][r];
+                    if (b < nB) W[(base + b) * nc + j] = (double)acc[b][r];
             }
         }
     }
 }
 
+template <class T>
+static void occ_back_any(Tracer *t, hipStream_t s, const char *name, const BlockMapDev &bm,
+                         int n_atoms, int max_rows, const T *Xo, int no_pad, const T *Ut, double *W,
+                         int nc, const WorkSizes &ws) {
+    dim3 grid(n_atoms, (max_rows + 63) / 64, (nc + JT - 1) / JT);
+    trace_begin(t, name, s);
+    hipLaunchKernelGGL(k_occ_back<T>, grid, dim3(256), 0, s, bm, Xo, no_pad, Ut, W, nc);
+    trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
+              sizeof(T) * (ws.N * ws.No * nc + ws.N * ws.No) + 8.0 * ws.nnzB * nc);
+}
+
 void launch_occ_back(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
                      const double *Xo, int no_pad, const double *Ut, double *W, int nc,
                      const WorkSizes &ws) {
-    dim3 grid(n_atoms, (max_rows + 63) / 64, (nc + JT - 1) / JT);
-    trace_begin(t, "occ_back", s);
-    hipLaunchKernelGGL(k_occ_back, grid, dim3(256), 0, s, bm, Xo, no_pad, Ut, W, nc);
-    trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
-              8.0 * (ws.N * ws.No * nc + ws.N * ws.No + ws.nnzB * nc));
+    occ_back_any<double>(t, s, "occ_back", bm, n_atoms, max_rows, Xo, no_pad, Ut, W, nc, ws);
+}
+
+void launch_occ_back_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
+                         const float *Xo, int no_pad, const float *Ut, double *W, int nc,
+                         const WorkSizes &ws) {
+    occ_back_any<float>(t, s, "occ_back_f32", bm, n_atoms, max_rows, Xo, no_pad, Ut, W, nc, ws);
 }
 
 // ---------------------------------------------------------- (e) skinny K z

@@ -200,9 +200,23 @@ void k_cgs_update(const Job *__restrict__ jobs, SlotsDev sl, int P, int accumula
 }
 
 // ||w||, v_{j+1} = w / ||w||, then the Givens update of column j of H.
+//
+// Applying the earlier rotations G_i = [[c_i, s_i], [-conj(s_i), c_i]] to the
+// new column h is a first-order recurrence in the running entry u:
+//     r_i = c_i u_i + s_i h_{i+1},   u_{i+1} = a_i u_i + b_i,
+//     a_i = -conj(s_i),  b_i = c_i h_{i+1},  u_0 = h_0,
+// so the workgroup evaluates it with a parallel scan of the affine maps
+// u -> a u + b (each thread composes a contiguous chunk, a Hillis-Steele
+// scan combines the 256 chunk maps, then each thread replays its chunk).
+struct cpx { double r, i; };
+__device__ __forceinline__ cpx cmul(cpx a, cpx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cpx cadd(cpx a, cpx b) { return {a.r + b.r, a.i + b.i}; }
+
 __global__ __launch_bounds__(256)
 void k_arnoldi_finalize(const Job *__restrict__ jobs, SlotsDev sl, int P, StepStatus *__restrict__ st) {
     __shared__ double sh[4];
+    __shared__ cpx scanA[2][256], scanB[2][256];
+    __shared__ cpx ulast;
     const int q = blockIdx.x, t = threadIdx.x;
     const Job jb = jobs[q];
     if (jb.type != JOB_ARNOLDI) return;
@@ -220,25 +234,52 @@ void k_arnoldi_finalize(const Job *__restrict__ jobs, SlotsDev sl, int P, StepSt
         const double2 a = w[mu];
         w[mu] = make_double2(a.x * sc, a.y * sc);
     }
-    if (t != 0) return;
-    double *col = sl.H + jb.slot * sl.hstride + 2 * hoff(j);
-    double *cs = sl.cs + (int64_t)jb.slot * sl.m;
-    double *sn = sl.sn + (int64_t)jb.slot * sl.m * 2;
+    cpx *col = reinterpret_cast<cpx *>(sl.H + jb.slot * sl.hstride + 2 * hoff(j));
+    const double *cs = sl.cs + (int64_t)jb.slot * sl.m;
+    const cpx *sn = reinterpret_cast<const cpx *>(sl.sn + (int64_t)jb.slot * sl.m * 2);
+    cpx *tmp = reinterpret_cast<cpx *>(sl.hbuf + (int64_t)jb.slot * (sl.m + 1) * 2);
     double *g = sl.g + (int64_t)jb.slot * (sl.m + 1) * 2;
-    col[2 * (j + 1)] = hn;
-    col[2 * (j + 1) + 1] = 0.0;
-    // previous rotations G_i = [[c, s], [-conj(s), c]] on rows (i, i+1)
-    for (int i = 0; i < j; ++i) {
-        const double c = cs[i], sr = sn[2 * i], si = sn[2 * i + 1];
-        const double ar = col[2 * i], ai = col[2 * i + 1];
-        const double br = col[2 * i + 2], bi = col[2 * i + 3];
-        col[2 * i] = c * ar + (sr * br - si * bi);
-        col[2 * i + 1] = c * ai + (sr * bi + si * br);
-        col[2 * i + 2] = -(sr * ar + si * ai) + c * br;
-        col[2 * i + 3] = -(sr * ai - si * ar) + c * bi;
+
+    // chunk of rotations owned by this thread
+    const int chunk = (j + 255) / 256;
+    const int lo = min(j, t * chunk), hi = min(j, lo + chunk);
+    cpx A = {1.0, 0.0}, B = {0.0, 0.0};          // identity map
+    for (int i = lo; i < hi; ++i) {
+        const cpx a = {-sn[i].r, sn[i].i};        // -conj(s_i)
+        const cpx b = {cs[i] * col[i + 1].r, cs[i] * col[i + 1].i};
+        B = cadd(cmul(a, B), b);                  // (a, b) o (A, B)
+        A = cmul(a, A);
     }
-    // new rotation zeroing h_{j+1,j} (real, >= 0)
-    const double ar = col[2 * j], ai = col[2 * j + 1];
+    scanA[0][t] = A;
+    scanB[0][t] = B;
+    __syncthreads();
+    int cur = 0;
+    for (int o = 1; o < 256; o <<= 1) {
+        cpx nA = scanA[cur][t], nB = scanB[cur][t];
+        if (t >= o) {   // compose earlier prefix (t-o) first, then this element
+            const cpx pA = scanA[cur][t - o], pB = scanB[cur][t - o];
+            nB = cadd(cmul(nA, pB), nB);
+            nA = cmul(nA, pA);
+        }
+        scanA[cur ^ 1][t] = nA;
+        scanB[cur ^ 1][t] = nB;
+        cur ^= 1;
+        __syncthreads();
+    }
+    const cpx u0 = col[0];
+    cpx u = u0;
+    if (t > 0) u = cadd(cmul(scanA[cur][t - 1], u0), scanB[cur][t - 1]);
+    for (int i = lo; i < hi; ++i) {
+        const cpx si = sn[i], h1 = col[i + 1];
+        tmp[i] = cadd({cs[i] * u.r, cs[i] * u.i}, cmul(si, h1));
+        u = cadd(cmul({-si.r, si.i}, u), {cs[i] * h1.r, cs[i] * h1.i});
+    }
+    if (t == 255) ulast = cadd(cmul(scanA[cur][255], u0), scanB[cur][255]);
+    __syncthreads();
+    for (int i = t; i < j; i += 256) col[i] = tmp[i];
+    if (t != 0) return;
+    // new rotation zeroing h_{j+1,j} = hn (real, >= 0) against u_j
+    const double ar = ulast.r, ai = ulast.i;
     const double aa = sqrt(ar * ar + ai * ai);
     double c, sr, si, rr, ri;
     if (aa == 0.0) {
@@ -251,9 +292,11 @@ void k_arnoldi_finalize(const Job *__restrict__ jobs, SlotsDev sl, int P, StepSt
         rr = (ar / aa) * den;
         ri = (ai / aa) * den;
     }
-    cs[j] = c; sn[2 * j] = sr; sn[2 * j + 1] = si;
-    col[2 * j] = rr; col[2 * j + 1] = ri;
-    col[2 * (j + 1)] = 0.0; col[2 * (j + 1) + 1] = 0.0;
+    sl.cs[(int64_t)jb.slot * sl.m + j] = c;
+    sl.sn[((int64_t)jb.slot * sl.m + j) * 2] = sr;
+    sl.sn[((int64_t)jb.slot * sl.m + j) * 2 + 1] = si;
+    col[j] = {rr, ri};
+    col[j + 1] = {0.0, 0.0};
     const double gr = g[2 * j], gi = g[2 * j + 1];
     // g_{j+1} = -conj(s) g_j, g_j = c g_j
     g[2 * (j + 1)] = -(sr * gr + si * gi);
@@ -282,41 +325,70 @@ void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
 }
 
 // ------------------------------------------------------- end of a GMRES cycle
-// y = R^{-1} g over the cycle length L = jobs[q].j (R = rotated Hessenberg).
+// y = R^{-1} g over the cycle length L = jobs[q].j (R = rotated Hessenberg,
+// column i of R is column i of the packed H).  Blocked back substitution:
+// the 32 x 32 diagonal block is solved by wavefront 0 from registers (rows in
+// lanes, the pivot broadcast by shuffles), then all threads subtract the
+// block's contribution from the rows above it.
+__device__ __forceinline__ cpx cshfl(cpx v, int src) { return {__shfl(v.r, src), __shfl(v.i, src)}; }
+__device__ __forceinline__ cpx cdiv(cpx a, cpx b) {
+    const double d = b.r * b.r + b.i * b.i;
+    if (d == 0.0) return {0.0, 0.0};
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+
+constexpr int TSB = 32;
 __global__ __launch_bounds__(256)
 void k_trisolve(const Job *__restrict__ jobs, SlotsDev sl) {
-    extern __shared__ double gs[];
-    __shared__ double yi[2];
+    extern __shared__ double gsm[];
+    __shared__ cpx ys[TSB];
+    cpx *gs = reinterpret_cast<cpx *>(gsm);
     const int q = blockIdx.x, t = threadIdx.x;
     const Job jb = jobs[q];
     const int L = jb.j;
     const double *H = sl.H + jb.slot * sl.hstride;
-    const double *g = sl.g + (int64_t)jb.slot * (sl.m + 1) * 2;
-    double *y = sl.y + (int64_t)jb.slot * sl.m * 2;
-    for (int i = t; i < 2 * L; i += 256) gs[i] = g[i];
-    for (int i = L - 1; i >= 0; --i) {
-        __syncthreads();
-        if (t == 0) {
-            const double *col = H + 2 * hoff(i);
-            const double dr = col[2 * i], di = col[2 * i + 1];
-            const double den = dr * dr + di * di;
-            const double nr = gs[2 * i], ni = gs[2 * i + 1];
-            double vr = 0.0, vi = 0.0;
-            if (den > 0.0) {
-                vr = (nr * dr + ni * di) / den;
-                vi = (ni * dr - nr * di) / den;
+    const cpx *g = reinterpret_cast<const cpx *>(sl.g + (int64_t)jb.slot * (sl.m + 1) * 2);
+    cpx *y = reinterpret_cast<cpx *>(sl.y + (int64_t)jb.slot * sl.m * 2);
+    for (int i = t; i < L; i += 256) gs[i] = g[i];
+    __syncthreads();
+    for (int hi = L; hi > 0; hi -= TSB) {
+        const int lo = hi - TSB;          // may be negative for the top block
+        if (t < 64) {
+            const int r = lo + t;         // row held by this lane (lanes >= TSB idle)
+            const bool rv = t < TSB && r >= 0;
+            cpx v = rv ? gs[r] : cpx{0.0, 0.0};
+            cpx R[TSB];
+#pragma unroll
+            for (int s2 = 0; s2 < TSB; ++s2) {
+                const int i = lo + s2;
+                const cpx *coli = reinterpret_cast<const cpx *>(H + 2 * hoff(i < 0 ? 0 : i));
+                R[s2] = (rv && i >= 0 && r <= i) ? coli[r] : cpx{0.0, 0.0};
             }
-            yi[0] = vr; yi[1] = vi;
-            y[2 * i] = vr; y[2 * i + 1] = vi;
+#pragma unroll
+            for (int s2 = TSB - 1; s2 >= 0; --s2) {
+                if (lo + s2 < 0) continue;                 // uniform
+                const cpx vi = cshfl(v, s2), di = cshfl(R[s2], s2);
+                const cpx yi = cdiv(vi, di);
+                if (t < s2) {
+                    const cpx p = cmul(R[s2], yi);
+                    v = {v.r - p.r, v.i - p.i};
+                }
+                if (t == 0) ys[s2] = yi;
+            }
         }
         __syncthreads();
-        const double vr = yi[0], vi = yi[1];
-        const double *col = H + 2 * hoff(i);
-        for (int k = t; k < i; k += 256) {
-            const double rr = col[2 * k], ri = col[2 * k + 1];
-            gs[2 * k] -= rr * vr - ri * vi;
-            gs[2 * k + 1] -= rr * vi + ri * vr;
+        for (int s2 = t; s2 < TSB; s2 += 256)
+            if (lo + s2 >= 0) y[lo + s2] = ys[s2];
+        for (int k = t; k < lo; k += 256) {
+            cpx acc = gs[k];
+            for (int s2 = 0; s2 < TSB; ++s2) {
+                const cpx *coli = reinterpret_cast<const cpx *>(H + 2 * hoff(lo + s2));
+                const cpx p = cmul(coli[k], ys[s2]);
+                acc = {acc.r - p.r, acc.i - p.i};
+            }
+            gs[k] = acc;
         }
+        __syncthreads();
     }
 }
 

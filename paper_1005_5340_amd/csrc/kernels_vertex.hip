@@ -13,45 +13,80 @@
 
 namespace chi0 {
 
-// Column tile of the vertex kernels: a power of two <= 64 covering nc.
-static int vertex_jt(int nc) {
-    int jt = 1;
-    while (jt < nc && jt < 64) jt <<= 1;
-    return jt;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Both vertex kernels are small GEMMs per atom-pair block on the FP64 matrix
+// cores (16x16x4; lane l holds A[l%16][l/16], B[l/16][l%16] and returns
+// D[4r + l/16][l%16]).  A workgroup owns one block and 64 columns; wave w
+// owns the 16-row blocks w, w+4, w+8, w+12 of the block's output.
+constexpr int VCB = 4;     // 16-column MFMA blocks per workgroup
+constexpr int VRB = 4;     // 16-row MFMA blocks per wave (rows <= 256 = NB_MAX^2)
+constexpr int PCH = 256;   // product ids staged in LDS per chunk
+
 // (a) dV[(ent_k + ab)][j] = sum_i Vp[k][i][ab] * Z[pidx[k][i]][j]
+//     rows = ab (n_A n_B), K = the block's products, columns = j.
 __global__ __launch_bounds__(256)
-void k_vertex_gather(BlockMapDev bm, const double *__restrict__ Z, double *__restrict__ dV,
-                     int nc, int jt) {
-    constexpr int R = 4;
-    const int k = blockIdx.x;
-    const int t = threadIdx.x, jj = t % jt, grp = t / jt, G = 256 / jt;
-    const int j = blockIdx.y * jt + jj;
+void k_vertex_gather(BlockMapDev bm, const double *__restrict__ Z, double *__restrict__ dV, int nc) {
+    __shared__ int32_t ps[PCH];
+    const int k = blockIdx.x, j0 = blockIdx.y * 16 * VCB;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int nAB = bm.blk_na[k] * bm.blk_nb[k];
     const int np = bm.blk_nprod[k];
     const double *Vk = bm.Vp + bm.blk_vstart[k];
     const int32_t *pk = bm.pidx + bm.blk_pstart[k];
     const int64_t ent = bm.blk_ent[k];
-    const bool valid = j < nc;
-    for (int ab0 = grp; ab0 < nAB; ab0 += G * R) {
-        double acc[R];
+    const int nrb = (nAB + 15) / 16, ncb = min(VCB, (nc - j0 + 15) / 16);
+    const int lr = lane & 15, lk = lane >> 4;
+
+    dbl4 acc[VRB][VCB];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = 0.0;
-        for (int i = 0; i < np; ++i) {
-            const double zv = valid ? Z[(int64_t)pk[i] * nc + j] : 0.0;
-            const double *vi = Vk + (int64_t)i * nAB;
+    for (int r = 0; r < VRB; ++r)
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int ab = ab0 + r * G;
-                if (ab < nAB) acc[r] += vi[ab] * zv;
+        for (int c = 0; c < VCB; ++c) acc[r][c] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    for (int c0 = 0; c0 < np; c0 += PCH) {
+        const int cn = min(PCH, np - c0);
+        __syncthreads();
+        if (t < cn) ps[t] = pk[c0 + t];
+        __syncthreads();
+        for (int i0 = 0; i0 < cn; i0 += 4) {
+            const int kk = i0 + lk;
+            const bool kv = kk < cn;
+            const int64_t zrow = kv ? (int64_t)ps[kk] * nc : 0;
+            double a[VRB], b[VCB];
+#pragma unroll
+            for (int r = 0; r < VRB; ++r) {
+                const int row = (wv + 4 * r) * 16 + lr;
+                a[r] = (kv && row < nAB) ? Vk[(int64_t)(c0 + kk) * nAB + row] : 0.0;
             }
-        }
-        if (valid) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int ab = ab0 + r * G;
-                if (ab < nAB) dV[(ent + ab) * nc + j] = acc[r];
+            for (int c = 0; c < VCB; ++c) {
+                const int j = j0 + c * 16 + lr;
+                b[c] = (kv && j < nc) ? Z[zrow + j] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < VRB; ++r)
+                if (wv + 4 * r < nrb)
+#pragma unroll
+                    for (int c = 0; c < VCB; ++c)
+                        if (c < ncb) acc[r][c] = mfma16(a[r], b[c], acc[r][c]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < VRB; ++r) {
+        if (wv + 4 * r >= nrb) continue;
+#pragma unroll
+        for (int c = 0; c < VCB; ++c) {
+            const int j = j0 + c * 16 + lr;
+            if (c >= ncb || j >= nc) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = (wv + 4 * r) * 16 + 4 * e + lk;
+                if (row < nAB) dV[(ent + row) * nc + j] = acc[r][c][e];
             }
         }
     }
@@ -59,38 +94,68 @@ void k_vertex_gather(BlockMapDev bm, const double *__restrict__ Z, double *__res
 
 void launch_vertex_gather(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk,
                           const double *Z, double *dV, int nc, const WorkSizes &ws) {
-    const int jt = vertex_jt(nc);
-    dim3 grid(n_blk, (nc + jt - 1) / jt);
+    dim3 grid(n_blk, (nc + 16 * VCB - 1) / (16 * VCB));
     trace_begin(t, "vertex_gather", s);
-    hipLaunchKernelGGL(k_vertex_gather, grid, dim3(256), 0, s, bm, Z, dV, nc, jt);
+    hipLaunchKernelGGL(k_vertex_gather, grid, dim3(256), 0, s, bm, Z, dV, nc);
     trace_end(t, s, 2.0 * ws.sum_s2 * nc, 8.0 * (ws.sum_s2 + ws.P * nc + ws.nnzB * nc));
 }
 
 // (d), first pass: part[pstart_k + i][j] = sum_ab Vp[k][i][ab] * W[(ent_k + ab)][j]
-constexpr int JTD = 32;             // max columns per workgroup (LDS: NB_MAX^2 x JTD doubles)
+//     rows = the block's products, K = ab, columns = j.
 __global__ __launch_bounds__(256)
 void k_vertex_contract(BlockMapDev bm, const double *__restrict__ W, double *__restrict__ part,
-                       int nc, int jt) {
-    __shared__ double Ws[NB_MAX * NB_MAX * JTD];
-    const int k = blockIdx.x;
-    const int t = threadIdx.x, jj = t % jt, grp = t / jt, G = 256 / jt;
-    const int j0 = blockIdx.y * jt, j = j0 + jj;
+                       int nc) {
+    const int k = blockIdx.x, j0 = blockIdx.y * 16 * VCB, rb0 = blockIdx.z * 4 * VRB;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int nAB = bm.blk_na[k] * bm.blk_nb[k];
     const int np = bm.blk_nprod[k];
-    const int64_t ent = bm.blk_ent[k];
-    for (int idx = t; idx < nAB * jt; idx += 256) {
-        const int ab = idx / jt, c = idx % jt;
-        Ws[ab * jt + c] = (j0 + c < nc) ? W[(ent + ab) * nc + j0 + c] : 0.0;
-    }
-    __syncthreads();
-    if (j >= nc) return;
     const double *Vk = bm.Vp + bm.blk_vstart[k];
+    const int64_t ent = bm.blk_ent[k];
     const int64_t p0 = bm.blk_pstart[k];
-    for (int i = grp; i < np; i += G) {
-        const double *vi = Vk + (int64_t)i * nAB;
-        double acc = 0.0;
-        for (int ab = 0; ab < nAB; ++ab) acc += vi[ab] * Ws[ab * jt + jj];
-        part[(p0 + i) * nc + j] = acc;
+    const int nrb = (np + 15) / 16, ncb = min(VCB, (nc - j0 + 15) / 16);
+    if (rb0 >= nrb) return;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    dbl4 acc[VRB][VCB];
+#pragma unroll
+    for (int r = 0; r < VRB; ++r)
+#pragma unroll
+        for (int c = 0; c < VCB; ++c) acc[r][c] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    for (int a0 = 0; a0 < nAB; a0 += 4) {
+        const int kk = a0 + lk;
+        const bool kv = kk < nAB;
+        double a[VRB], b[VCB];
+#pragma unroll
+        for (int r = 0; r < VRB; ++r) {
+            const int i = (rb0 + wv + 4 * r) * 16 + lr;
+            a[r] = (kv && i < np) ? Vk[(int64_t)i * nAB + kk] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < VCB; ++c) {
+            const int j = j0 + c * 16 + lr;
+            b[c] = (kv && j < nc) ? W[(ent + kk) * nc + j] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < VRB; ++r)
+            if (rb0 + wv + 4 * r < nrb)
+#pragma unroll
+                for (int c = 0; c < VCB; ++c)
+                    if (c < ncb) acc[r][c] = mfma16(a[r], b[c], acc[r][c]);
+    }
+#pragma unroll
+    for (int r = 0; r < VRB; ++r) {
+        if (rb0 + wv + 4 * r >= nrb) continue;
+#pragma unroll
+        for (int c = 0; c < VCB; ++c) {
+            const int j = j0 + c * 16 + lr;
+            if (c >= ncb || j >= nc) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = (rb0 + wv + 4 * r) * 16 + 4 * e + lk;
+                if (i < np) part[(p0 + i) * nc + j] = acc[r][c][e];
+            }
+        }
     }
 }
 
@@ -108,12 +173,12 @@ void k_vertex_reduce(BlockMapDev bm, int P, const double *__restrict__ part,
 }
 
 void launch_vertex_contract(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_blk, int P,
-                            const double *W, double *part, double *Y, int nc, const WorkSizes &ws) {
-    int jt = vertex_jt(nc);
-    if (jt > JTD) jt = JTD;
-    dim3 grid(n_blk, (nc + jt - 1) / jt);
+                            const double *W, double *part, double *Y, int nc, const WorkSizes &ws,
+                            int max_nprod) {
+    const int rgroups = ((max_nprod + 15) / 16 + 4 * VRB - 1) / (4 * VRB);
+    dim3 grid(n_blk, (nc + 16 * VCB - 1) / (16 * VCB), rgroups);
     trace_begin(t, "vertex_contract", s);
-    hipLaunchKernelGGL(k_vertex_contract, grid, dim3(256), 0, s, bm, W, part, nc, jt);
+    hipLaunchKernelGGL(k_vertex_contract, grid, dim3(256), 0, s, bm, W, part, nc);
     trace_end(t, s, 2.0 * ws.sum_s2 * nc, 8.0 * (ws.sum_s2 + ws.nnzB * nc + ws.npart * nc));
     const int64_t n = (int64_t)P * nc;
     trace_begin(t, "vertex_reduce", s);

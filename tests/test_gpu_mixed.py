@@ -1,0 +1,75 @@
+"""Mixed precision: low-precision chi0 operators and FP64 iterative refinement.
+
+The operator error is bounded by the arithmetic of the orbital transforms
+(FP32: 24-bit, split BF16 x 3: ~16-bit operands with FP32 accumulation); the
+GMRES-IR solve must still reach the FP64 answer because every cycle ends
+with an FP64 true residual (the stopping test is unchanged).
+"""
+import numpy as np
+import pytest
+
+import gpu_systems
+from oracle import chi0_oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+# normwise relative error bounds of one chi0 application
+BOUND = {1: 2e-5, 2: 2e-3}
+
+
+def _ctx(sys):
+    from paper_1005_5340_amd import chi0
+    c = chi0.Context(0)
+    c.set_system_from(sys)
+    return c
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("name,n_rhs", [("atoms12_orb9", 5), ("atoms8_orb13", 40), ("tiny3", 2)])
+def test_low_precision_operator(prec, name, n_rhs):
+    import torch
+    sys = gpu_systems.get(name)
+    ctx = _ctx(sys)
+    rng = np.random.default_rng(prec)
+    om = np.linspace(0.0, 1.4, n_rhs)
+    z = rng.standard_normal((n_rhs, sys.n_prod)) + 1j * rng.standard_normal((n_rhs, sys.n_prod))
+    out = ctx.apply(om, sys.eps, torch.from_numpy(z).cuda(), precision=prec).cpu().numpy()
+    worst = max(np.linalg.norm(out[k] - orc.chi0_apply(sys, w, z[k])) / np.linalg.norm(orc.chi0_apply(sys, w, z[k]))
+                for k, w in enumerate(om))
+    print(f"[mixed] {name} prec={prec} worst operator rel err {worst:.2e}", flush=True)
+    assert worst < BOUND[prec]
+    assert worst > 1e-13    # really ran in reduced precision
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_iterative_refinement_reaches_fp64(prec):
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("z")
+    om = np.array([0.0, 0.25, 0.6, 1.05, 1.4])
+    ctx = _ctx(sys)
+    a, st, rc = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-12, batch=5, precision=prec)
+    a64, st64, rc64 = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-12, batch=5)
+    ref = orc.polarizability(sys, om, d)
+    err = np.max(np.abs(a - ref)) / np.max(np.abs(ref))
+    print(f"[mixed] IR prec={prec} err {err:.2e} iters {st['iterations'].ravel().tolist()} "
+          f"restarts {st['restarts'].ravel().tolist()} fallback {st['fallback'].ravel().tolist()} "
+          f"(fp64 iters {st64['iterations'].ravel().tolist()})", flush=True)
+    assert rc == 0 and st["converged"].all()
+    assert (st["restarts"] >= 1).all()
+    assert err < 1e-9
+    ctx.close()
+
+
+def test_fallback_to_fp64_is_counted_and_exact():
+    """A huge inner tolerance makes every low-precision cycle useless; the point
+    must fall back to FP64 steps and still converge."""
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("z")
+    ctx = _ctx(sys)
+    a, st, rc = ctx.solve_response([0.7], sys.eps, d, restart=sys.n_prod, tol=1e-12, precision=2,
+                                   inner_tol=0.9)
+    ref = orc.polarizability(sys, [0.7], d)
+    assert rc == 0 and st["converged"][0, 0] == 1
+    assert np.max(np.abs(a - ref)) < 1e-9 * np.max(np.abs(ref))
+    ctx.close()
