@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"],
                     help="arithmetic of the Arnoldi-step transforms (IR keeps residuals in FP64)")
     ap.add_argument("--inner-tol", type=float, default=0.0)
+    ap.add_argument("--warm", type=int, default=0,
+                    help="learned warm start fitted on this many seeded training frequencies (0 = off)")
     ap.add_argument("--cpu-sample", type=int, default=2, help="frequencies for the oracle baseline (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
     a = ap.parse_args()
@@ -141,10 +143,23 @@ def main():
             ref = np.array(r["alpha_re"]) + 1j * np.array(r["alpha_im"])
 
     prec = {"fp64": chi0.PREC_FP64, "fp32": chi0.PREC_FP32, "bf16x3": chi0.PREC_BF16X3}[a.precision]
+    ws, warm_info = None, None
+    if a.warm > 0:
+        rng = np.random.default_rng(1000)
+        om_train = np.sort(rng.uniform(0.0, w.omega_max, a.warm))
+        t0 = time.perf_counter()
+        ws = chi0.WarmStart(ctx, om_train, s.eps, drives[0], rank=min(64, a.warm), width=256,
+                            epochs=3000, restart=restart, batch=min(a.warm, a.batch), tol=tol)
+        h = ws.loss_history()
+        warm_info = {"n_train": a.warm, "fit_seconds": time.perf_counter() - t0,
+                     "loss_first": float(h[0]), "loss_last": float(h[-1])}
+        print(f"[bench] warm start fitted in {warm_info['fit_seconds']:.2f} s, loss {h[0]:.3e} -> {h[-1]:.3e}",
+              file=sys.stderr, flush=True)
 
     def run():
         return ctx.solve_response(s.omegas, s.eps, drives, restart=restart, max_iter=a.max_iter,
-                                  tol=tol, batch=a.batch, precision=prec, inner_tol=a.inner_tol)
+                                  tol=tol, batch=a.batch, precision=prec, inner_tol=a.inner_tol,
+                                  warm=ws)
 
     print(f"[bench] {a.workload}: N={s.n_orb} N_occ={s.n_occ} n_prod={s.n_prod} points="
           f"{s.omegas.size * drives.shape[0]} batch={a.batch} GMRES({restart}) tol={tol:g}",
@@ -225,17 +240,23 @@ def main():
         "config": {"workload": a.workload, "seed": a.seed, "n_orb": s.n_orb, "n_occ": s.n_occ,
                    "n_prod": s.n_prod, "n_omega": int(s.omegas.size), "drives": w.drives,
                    "eps": s.eps, "tol": tol, "restart": restart, "batch": a.batch,
-                   "points": npts, "precision": a.precision},
+                   "points": npts, "precision": a.precision, "warm_start_train": a.warm},
         "chi0_gflops": chi0_gflops,
         "chi0_applications_per_step": applications,
         "iterations": {"mean": float(stats["iterations"].mean()), "max": int(stats["iterations"].max()),
                        "converged": int(stats["converged"].sum()),
                        "fallbacks": int(stats["fallback"].sum())},
+        "warm_start": None if warm_info is None else {
+            **warm_info, "used": int((stats["warm_start"] == 1).sum()),
+            "rejected": int((stats["warm_start"] == 2).sum()),
+            "median_rel_residual_of_x0": float(np.median(stats["warm_rel0"]))},
         "accuracy": acc,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if ws is not None:
+        ws.close()
     ctx.close()
 
 

@@ -145,6 +145,8 @@ int chi0_apply(chi0_ctx *ctx, int32_t n_rhs, const double *omega, double eps,
 
 /* Options of chi0_solve_response.  Zero-initialise, then set what you need;
  * chi0_solve_opts_default() fills the defaults. */
+typedef struct chi0_ws chi0_ws;        /* learned warm start (see chi0_ws_fit) */
+
 typedef struct chi0_solve_opts {
     int32_t restart;      /* GMRES(m) Krylov dimension per cycle, 1..4000 (default 30) */
     int32_t max_iter;     /* cap on Arnoldi steps per point (default 10000) */
@@ -154,7 +156,10 @@ typedef struct chi0_solve_opts {
     int32_t batch;        /* (omega, drive) points solved concurrently, 1..256; 1 = one at a time */
     double  inner_tol;    /* low precision only: a cycle ends when the Arnoldi residual
                              estimate falls by this factor (0 = 1e-6 for FP32, 1e-4 for BF16X3) */
-    int32_t reserved[6];  /* must be zero */
+    const chi0_ws *warm;  /* NULL, or a warm start fitted on this context and system: every point
+                             starts from x0 = U c(omega) instead of 0, unless
+                             ||chi0 d - A x0|| >= ||chi0 d||, then from 0 */
+    int32_t reserved[4];  /* must be zero */
 } chi0_solve_opts;
 
 /* Per-point solver record (one per omega and drive). */
@@ -165,8 +170,9 @@ typedef struct chi0_point_stats {
     int32_t breakdown;    /* 1 if the Krylov space became invariant (exact solution) */
     int32_t fallback;     /* 1 if a low-precision point switched to FP64 steps after a cycle
                              that did not halve the true residual */
-    int32_t reserved;
+    int32_t warm_start;   /* 0 none, 1 started from the warm start, 2 warm start rejected */
     double  rel_residual; /* true ||b - A x|| / ||b|| at exit */
+    double  warm_rel0;    /* ||b - A x0|| / ||b|| of the warm start (0 if none) */
 } chi0_point_stats;
 
 void chi0_solve_opts_default(chi0_solve_opts *opts);
@@ -189,6 +195,50 @@ int chi0_solve_response(chi0_ctx *ctx, int32_t n_omega, const double *omega, dou
                         int32_t n_drive, const double *V_ext,
                         const chi0_solve_opts *opts,
                         double *alpha, chi0_point_stats *stats);
+
+/*
+ * Learned warm start.  The paper starts GMRES from 0 (Sec. 4.1); this adds an
+ * initial guess learned from solutions at training frequencies:
+ *   1. plain FP64 GMRES solves (1 - chi0 K) x = chi0 d at the n_train
+ *      frequencies omega_train (one drive d, host [n_prod]);
+ *   2. U = the `rank` leading left singular vectors of the solutions (from
+ *      the eigen-decomposition of their Gram matrix);
+ *   3. a 3-layer perceptron (tanh, `width` units) maps the Fourier features
+ *      sin/cos(k pi omega / w_scale), k = 1..n_freq, to the coordinates
+ *      c = U^H x of the training solutions; it is trained by full-batch Adam
+ *      with FP32 weights and BF16 matrix-core products;
+ *   4. x0(omega) = U c(omega).
+ * Everything runs on the context's device.  The warm start belongs to the
+ * context and system it was fitted on and must be freed before the context.
+ */
+typedef struct chi0_ws_cfg {
+    int32_t rank;         /* basis size r <= n_train (default 64) */
+    int32_t width;        /* hidden units, multiple of 32 (default 256) */
+    int32_t n_freq;       /* Fourier modes, 16 or 32 (default 16: 32 input features) */
+    int32_t epochs;       /* Adam steps (default 3000) */
+    double  w_scale;      /* feature period scale (0 = max |omega_train|) */
+    double  lr;           /* Adam learning rate (default 2e-3, cosine decay to 1e-2 of it) */
+    uint64_t seed;        /* weight initialisation */
+    int32_t restart;      /* training solves: GMRES(m) (0 = n_prod) */
+    int32_t batch;        /* training solves: concurrent points (default 64) */
+    double  tol;          /* training solves: tolerance (default 1e-10) */
+    int32_t reserved[4];  /* must be zero */
+} chi0_ws_cfg;
+
+void chi0_ws_cfg_default(chi0_ws_cfg *cfg);
+
+/* Fit a warm start (see above).  *out is NULL on failure. */
+int chi0_ws_fit(chi0_ctx *ctx, int32_t n_train, const double *omega_train, double eps,
+                const double *drive, const chi0_ws_cfg *cfg, chi0_ws **out);
+
+void chi0_ws_free(chi0_ws *ws);
+
+/* x0[i] = U c(omega[i]) into DEVICE memory x0 [n][n_prod] complex; synchronous. */
+int chi0_ws_predict(chi0_ws *ws, int32_t n, const double *omega, double *x0);
+
+/* Training loss (mean squared error of the normalised coordinates) after
+ * each Adam step; copies min(cap, epochs) values, returns epochs. */
+int chi0_ws_loss_history(const chi0_ws *ws, float *loss, int32_t cap);
 
 /*
  * Kernel timing (tracing).  When enabled, every kernel launch of the

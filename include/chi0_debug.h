@@ -40,6 +40,22 @@ int chi0_debug_dims(const chi0_ctx *ctx, int64_t *dims);
  * smaller or not allocated. */
 int chi0_debug_read(chi0_ctx *ctx, int32_t which, void *host, int64_t bytes);
 
+/* Warm-start network: dims[0..6] = r, n_features, width, n_outputs (2r rounded up
+ * to 32), n_params, n_freq, and w_scale as a double in *w_scale.  Parameters are
+ * one float vector [W1 (width x F) | b1 | W2 (width x width) | b2 | W3 (O x width) | b3],
+ * weight matrices row-major with one row per output unit. */
+int chi0_ws_debug_dims(const chi0_ws *ws, int64_t *dims, double *w_scale);
+/* Copy the parameters to host (set = 0) or from host (set = 1). */
+int chi0_ws_debug_params(chi0_ws *ws, float *host, int64_t n, int32_t set);
+/* Mean squared error of the network on n (<= 256) frequencies against host
+ * targets [n][n_outputs] (only the first 2r columns count) and its gradient
+ * with respect to every parameter, computed by the GPU kernels (no update). */
+int chi0_ws_debug_loss_grad(chi0_ws *ws, int32_t n, const double *omega, const float *target,
+                            float *loss, float *grads);
+/* Host eigen-decomposition of a Hermitian n x n matrix (row-major interleaved
+ * complex): eigenvalues descending in w[n], eigenvectors as columns of V. */
+int chi0_debug_eigh(int32_t n, const double *A, double *w, double *V);
+
 #ifdef __cplusplus
 }
 #endif

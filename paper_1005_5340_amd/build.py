@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchi0.so")
 SOURCES = ["chi0_api.hip", "kernels_gemm.hip", "kernels_vertex.hip", "kernels_krylov.hip",
-           "kernels_bf16.hip"]
+           "kernels_bf16.hip", "kernels_mlp.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -41,7 +41,7 @@ def _compile(src):
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         results = list(ex.map(_compile, SOURCES))
     objs = [o for o, _ in results]
     if verbose:

@@ -16,8 +16,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Chi0Error", "Context", "lib", "LIB_PATH", "PREC_FP64", "PREC_FP32", "PREC_BF16X3",
-           "SolveStats", "NOT_CONVERGED"]
+__all__ = ["Chi0Error", "Context", "WarmStart", "lib", "LIB_PATH", "PREC_FP64", "PREC_FP32",
+           "PREC_BF16X3", "SolveStats", "NOT_CONVERGED", "debug_eigh"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 PREC_FP64 = 0
@@ -34,13 +34,20 @@ _i64p = C.POINTER(C.c_int64)
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("batch", C.c_int32), ("inner_tol", C.c_double),
-                ("reserved", C.c_int32 * 6)]
+                ("warm", C.c_void_p), ("reserved", C.c_int32 * 4)]
+
+
+class WsCfg(C.Structure):
+    _fields_ = [("rank", C.c_int32), ("width", C.c_int32), ("n_freq", C.c_int32),
+                ("epochs", C.c_int32), ("w_scale", C.c_double), ("lr", C.c_double),
+                ("seed", C.c_uint64), ("restart", C.c_int32), ("batch", C.c_int32),
+                ("tol", C.c_double), ("reserved", C.c_int32 * 4)]
 
 
 class PointStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
-                ("breakdown", C.c_int32), ("fallback", C.c_int32), ("reserved", C.c_int32),
-                ("rel_residual", C.c_double)]
+                ("breakdown", C.c_int32), ("fallback", C.c_int32), ("warm_start", C.c_int32),
+                ("rel_residual", C.c_double), ("warm_rel0", C.c_double)]
 
 
 class KernelRecord(C.Structure):
@@ -49,7 +56,8 @@ class KernelRecord(C.Structure):
 
 
 SolveStats = np.dtype([("iterations", np.int32), ("restarts", np.int32), ("converged", np.int32),
-                       ("breakdown", np.int32), ("fallback", np.int32), ("rel_residual", np.float64)])
+                       ("breakdown", np.int32), ("fallback", np.int32), ("warm_start", np.int32),
+                       ("rel_residual", np.float64), ("warm_rel0", np.float64)])
 
 _LIB = None
 
@@ -61,6 +69,13 @@ def lib():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # PyTorch wheels ship their own libamdhip64.so.7.  Loading torch first makes
+    # the dynamic linker resolve this library's HIP runtime to the same copy,
+    # so one runtime owns the GPU and torch tensors can be passed to chi0_apply.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     L.chi0_create.argtypes = [C.POINTER(C.c_void_p), C.c_int]
     L.chi0_create.restype = C.c_int
@@ -85,6 +100,26 @@ def lib():
     L.chi0_set_timing.restype = C.c_int
     L.chi0_kernel_stats.argtypes = [C.c_void_p, C.POINTER(KernelRecord), C.c_int32]
     L.chi0_kernel_stats.restype = C.c_int
+    L.chi0_ws_cfg_default.argtypes = [C.POINTER(WsCfg)]
+    L.chi0_ws_cfg_default.restype = None
+    L.chi0_ws_fit.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_double, _dp, C.POINTER(WsCfg),
+                              C.POINTER(C.c_void_p)]
+    L.chi0_ws_fit.restype = C.c_int
+    L.chi0_ws_free.argtypes = [C.c_void_p]
+    L.chi0_ws_free.restype = None
+    L.chi0_ws_predict.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_void_p]
+    L.chi0_ws_predict.restype = C.c_int
+    L.chi0_ws_loss_history.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int32]
+    L.chi0_ws_loss_history.restype = C.c_int
+    L.chi0_ws_debug_dims.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    L.chi0_ws_debug_dims.restype = C.c_int
+    L.chi0_ws_debug_params.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int64, C.c_int32]
+    L.chi0_ws_debug_params.restype = C.c_int
+    L.chi0_ws_debug_loss_grad.argtypes = [C.c_void_p, C.c_int32, _dp, C.POINTER(C.c_float),
+                                          C.POINTER(C.c_float), C.POINTER(C.c_float)]
+    L.chi0_ws_debug_loss_grad.restype = C.c_int
+    L.chi0_debug_eigh.argtypes = [C.c_int32, _dp, _dp, _dp]
+    L.chi0_debug_eigh.restype = C.c_int
     _LIB = L
     return L
 
@@ -207,7 +242,7 @@ class Context:
     # ---------------------------------------------------------------- solve
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
                        tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,
-                       inner_tol: float = 0.0):
+                       inner_tol: float = 0.0, warm: "WarmStart" = None):
         """GMRES polarizability over a frequency grid.
 
         Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
@@ -220,6 +255,7 @@ class Context:
         self._L.chi0_solve_opts_default(C.byref(o))
         o.restart, o.max_iter, o.tol = int(restart), int(max_iter), float(tol)
         o.batch, o.precision, o.inner_tol = int(batch), int(precision), float(inner_tol)
+        o.warm = warm._h if warm is not None else None
         alpha = np.zeros((om.size, nd, nd, 2))
         st = (PointStats * max(1, om.size * nd))()
         rc = self._L.chi0_solve_response(self._h, int(om.size), _ptr(om), float(eps), int(nd),
@@ -229,7 +265,7 @@ class Context:
         flat = stats.reshape(-1)
         for i in range(om.size * nd):
             flat[i] = (st[i].iterations, st[i].restarts, st[i].converged, st[i].breakdown,
-                       st[i].fallback, st[i].rel_residual)
+                       st[i].fallback, st[i].warm_start, st[i].rel_residual, st[i].warm_rel0)
         return alpha[..., 0] + 1j * alpha[..., 1], stats, rc
 
     # --------------------------------------------------------------- tracing
@@ -245,3 +281,96 @@ class Context:
         return {recs[i].name.decode(): dict(launches=int(recs[i].launches), ms=float(recs[i].total_ms),
                                             flops=float(recs[i].flops), bytes=float(recs[i].bytes))
                 for i in range(n)}
+
+
+class WarmStart:
+    """Learned GMRES warm start (chi0_ws_fit): x0(omega) = U c(omega)."""
+
+    def __init__(self, ctx: Context, omega_train, eps: float, drive, rank: int = 64,
+                 width: int = 256, n_freq: int = 16, epochs: int = 3000, lr: float = 2e-3,
+                 seed: int = 1234, restart: int = 0, batch: int = 64, tol: float = 1e-10,
+                 w_scale: float = 0.0):
+        self._L = ctx._L
+        self.ctx = ctx
+        om = _f64(np.atleast_1d(omega_train))
+        d = _f64(drive)
+        cfg = WsCfg()
+        self._L.chi0_ws_cfg_default(C.byref(cfg))
+        cfg.rank, cfg.width, cfg.n_freq, cfg.epochs = int(rank), int(width), int(n_freq), int(epochs)
+        cfg.lr, cfg.seed, cfg.restart, cfg.batch = float(lr), int(seed), int(restart), int(batch)
+        cfg.tol, cfg.w_scale = float(tol), float(w_scale)
+        h = C.c_void_p()
+        rc = self._L.chi0_ws_fit(ctx._h, int(om.size), _ptr(om), float(eps), _ptr(d), C.byref(cfg),
+                                 C.byref(h))
+        ctx._check(rc, allow_warning=True)
+        self._h = h
+        self.fit_rc = rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.chi0_ws_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def predict(self, omega):
+        """x0 for each frequency as a torch complex128 CUDA tensor [n, n_prod]."""
+        import torch
+        om = _f64(np.atleast_1d(omega))
+        n_prod = self.ctx.sizes()["n_prod"]
+        out = torch.zeros((om.size, n_prod), dtype=torch.complex128, device="cuda")
+        self.ctx._check(self._L.chi0_ws_predict(self._h, int(om.size), _ptr(om), C.c_void_p(out.data_ptr())))
+        return out
+
+    def loss_history(self) -> np.ndarray:
+        n = self._L.chi0_ws_loss_history(self._h, None, 0)
+        buf = np.zeros(max(n, 1), np.float32)
+        self._L.chi0_ws_loss_history(self._h, buf.ctypes.data_as(C.POINTER(C.c_float)), n)
+        return buf[:n]
+
+    # ------------------------------------------------------------ test hooks
+    def dims(self) -> dict:
+        d = (C.c_int64 * 7)()
+        ws = C.c_double()
+        self.ctx._check(self._L.chi0_ws_debug_dims(self._h, d, C.byref(ws)))
+        return dict(r=d[0], F=d[1], W=d[2], O=d[3], n_params=d[4], n_freq=d[5], w_scale=ws.value)
+
+    def params(self, new=None) -> np.ndarray:
+        n = self.dims()["n_params"]
+        if new is not None:
+            buf = np.ascontiguousarray(new, dtype=np.float32)
+            assert buf.size == n
+            self.ctx._check(self._L.chi0_ws_debug_params(self._h, buf.ctypes.data_as(C.POINTER(C.c_float)), n, 1))
+            return buf
+        buf = np.zeros(n, np.float32)
+        self.ctx._check(self._L.chi0_ws_debug_params(self._h, buf.ctypes.data_as(C.POINTER(C.c_float)), n, 0))
+        return buf
+
+    def loss_grad(self, omega, target):
+        om = _f64(np.atleast_1d(omega))
+        tg = np.ascontiguousarray(target, dtype=np.float32)
+        n = self.dims()["n_params"]
+        loss = np.zeros(1, np.float32)
+        g = np.zeros(n, np.float32)
+        fp = C.POINTER(C.c_float)
+        self.ctx._check(self._L.chi0_ws_debug_loss_grad(self._h, int(om.size), _ptr(om), tg.ctypes.data_as(fp),
+                                                        loss.ctypes.data_as(fp), g.ctypes.data_as(fp)))
+        return float(loss[0]), g
+
+
+def debug_eigh(A):
+    """Host Jacobi eigen-decomposition of the library (test hook)."""
+    L = lib()
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n), np.complex128)
+    rc = L.chi0_debug_eigh(n, A.view(np.float64).ctypes.data_as(_dp), w.ctypes.data_as(_dp),
+                           V.view(np.float64).ctypes.data_as(_dp))
+    if rc != 0:
+        raise Chi0Error(rc, "debug_eigh")
+    return w, V

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -724,19 +725,85 @@ struct SlotState {
     int point = -1;
     int j = 0;
     int prec = CHI0_PREC_FP64;   // arithmetic of this slot's Arnoldi steps
+    bool warm_check = false;     // the pending residual job checks a warm start
     double bnorm = 0.0;          // ||b|| = ||chi0 d||
     double cycle0 = 0.0;         // residual norm at the start of the current cycle
     double rel_prev = 1.0;       // true relative residual after the previous cycle
 };
 struct PointState {
-    int iters = 0, restarts = 0, converged = 0, breakdown = 0, fallback = 0;
-    double rel = NAN;
+    int iters = 0, restarts = 0, converged = 0, breakdown = 0, fallback = 0, warm = 0;
+    double rel = NAN, warm_rel0 = 0.0;
 };
 }  // namespace
 
-extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *omega, double eps,
-                                   int32_t n_drive, const double *V_ext, const chi0_solve_opts *opts_in,
-                                   double *alpha, chi0_point_stats *stats) {
+// ============================================================ warm start
+struct chi0_ws {
+    chi0_ctx *ctx = nullptr;
+    int r = 0;            // basis size
+    int F = 0;            // input features (2 n_freq)
+    int W = 0;            // hidden width
+    int O = 0;            // network outputs (2 r rounded up to 32)
+    int nf = 0;
+    double w_scale = 1.0;
+    int epochs = 0;
+    DevBuf buf;
+    double *U = nullptr;  // [r][P_pad] complex
+    float *params = nullptr, *grads = nullptr, *am = nullptr, *av = nullptr;
+    int64_t n_params = 0, oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+    float *mean = nullptr, *sdev = nullptr;   // [O] output de-normalisation
+    // activations for batches of up to kMaxBatch rows
+    float *phi = nullptr, *H1 = nullptr, *H2 = nullptr, *out = nullptr, *dout = nullptr, *dH1 = nullptr,
+          *dH2 = nullptr, *tgt = nullptr, *loss = nullptr;
+    double *omega_dev = nullptr;
+    Job *jobs_dev = nullptr;
+    std::vector<float> loss_hist;
+    ~chi0_ws() { buf.release(); }
+};
+
+namespace {
+// Forward pass for `rows` (multiple of 32) feature rows already in ws->phi.
+void ws_forward(chi0_ws *w, hipStream_t s, int rows) {
+    float *P = w->params;
+    launch_mlp_gemm(s, rows, w->W, w->F, w->phi, w->F, 1, P + w->oW1, 1, w->F, w->H1, w->W);
+    launch_bias_act(s, rows, w->W, w->H1, P + w->ob1, 1);
+    launch_mlp_gemm(s, rows, w->W, w->W, w->H1, w->W, 1, P + w->oW2, 1, w->W, w->H2, w->W);
+    launch_bias_act(s, rows, w->W, w->H2, P + w->ob2, 1);
+    launch_mlp_gemm(s, rows, w->O, w->W, w->H2, w->W, 1, P + w->oW3, 1, w->W, w->out, w->O);
+    launch_bias_act(s, rows, w->O, w->out, P + w->ob3, 0);
+}
+
+// Loss of rows [0, n_rows) against ws->tgt and all parameter gradients into ws->grads.
+void ws_backward(chi0_ws *w, hipStream_t s, int rows, int n_rows, int n_cols, float *loss) {
+    float *P = w->params, *G = w->grads;
+    launch_mse(s, rows, w->O, n_rows, n_cols, w->out, w->tgt, w->dout, loss);
+    launch_mlp_gemm(s, w->O, w->W, rows, w->dout, 1, w->O, w->H2, w->W, 1, G + w->oW3, w->W);
+    launch_colsum(s, rows, w->O, w->dout, G + w->ob3);
+    launch_mlp_gemm(s, rows, w->W, w->O, w->dout, w->O, 1, P + w->oW3, w->W, 1, w->dH2, w->W);
+    launch_tanh_back(s, (int64_t)rows * w->W, w->H2, w->dH2);
+    launch_mlp_gemm(s, w->W, w->W, rows, w->dH2, 1, w->W, w->H1, w->W, 1, G + w->oW2, w->W);
+    launch_colsum(s, rows, w->W, w->dH2, G + w->ob2);
+    launch_mlp_gemm(s, rows, w->W, w->W, w->dH2, w->W, 1, P + w->oW2, w->W, 1, w->dH1, w->W);
+    launch_tanh_back(s, (int64_t)rows * w->W, w->H1, w->dH1);
+    launch_mlp_gemm(s, w->W, w->F, rows, w->dH1, 1, w->W, w->phi, w->F, 1, G + w->oW1, w->F);
+    launch_colsum(s, rows, w->W, w->dH1, G + w->ob1);
+}
+
+// Network forward for n frequencies (host array) -> ws->out rows [0, n).
+int ws_infer(chi0_ws *w, hipStream_t s, int n, const double *omega_host) {
+    chi0_ctx *c = w->ctx;
+    const int rows = (int)round_up(std::max(n, 1), 32);
+    HIPCHK(c, hipMemcpyAsync(w->omega_dev, omega_host, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    launch_features(s, n, rows, w->omega_dev, w->nf, w->w_scale, w->phi);
+    ws_forward(w, s, rows);
+    return CHI0_OK;
+}
+}  // namespace
+
+// ================================================================= solver
+// x_out: optional DEVICE [npts][P_pad] complex, the solution of each point.
+static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double eps, int32_t n_drive,
+                      const double *V_ext, const chi0_solve_opts *opts_in, double *alpha,
+                      chi0_point_stats *stats, double *x_out) {
     if (!c) return CHI0_EINVAL;
     if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no system on a device context");
     chi0_solve_opts o;
@@ -754,8 +821,10 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
     if (o.precision < CHI0_PREC_FP64 || o.precision > CHI0_PREC_BF16X3)
         return fail(c, CHI0_EINVAL, "unknown precision");
     if (!(o.inner_tol >= 0.0) || !(o.inner_tol < 1.0)) return fail(c, CHI0_EINVAL, "inner_tol must be in [0, 1)");
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 4; ++i)
         if (o.reserved[i] != 0) return fail(c, CHI0_EINVAL, "reserved option fields must be zero");
+    chi0_ws *ws = const_cast<chi0_ws *>(o.warm);
+    if (ws && ws->ctx != c) return fail(c, CHI0_EINVAL, "warm start belongs to another context");
     const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol
                              : (o.precision == CHI0_PREC_FP32 ? 1e-6 : 1e-4);
     if (!all_finite(omega, n_omega)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
@@ -785,15 +854,26 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
     std::vector<SlotState> sl(nsl);
     std::vector<PointState> ps(npts);
     int next_point = 0, done = 0;
-    std::vector<Job> fin, upd;
+    std::vector<Job> fin, upd, rst, wnew;
+    std::vector<double> wom;
 
     while (done < npts) {
-        // (1) polarizability of points that finished last step (before their slot is reused)
+        // (0) zero start for rejected warm starts (and x = 0 for points with b = 0)
+        if (!rst.empty()) {
+            std::copy(rst.begin(), rst.end(), c->upd_h);
+            HIPCHK(c, hipMemcpyAsync(c->upd_dev, c->upd_h, sizeof(Job) * rst.size(), hipMemcpyHostToDevice, s));
+            launch_reset_slots(s, c->upd_dev, (int)rst.size(), c->slots, P);
+            HIPCHK(c, hipStreamSynchronize(s));   // upd_h is reused below
+            rst.clear();
+        }
+        // (1) polarizability (and stored solution) of points that finished last step,
+        //     before their slot is reused
         if (!fin.empty()) {
             std::copy(fin.begin(), fin.end(), c->fin_h);
             HIPCHK(c, hipMemcpyAsync(c->fin_dev, c->fin_h, sizeof(Job) * fin.size(), hipMemcpyHostToDevice, s));
             launch_alpha(t, s, c->fin_dev, (int)fin.size(), c->slots, drives, n_drive, c->P_pad, P,
                          nullptr, alpha_dev);
+            if (x_out) launch_store_x(s, c->fin_dev, (int)fin.size(), c->slots, P, x_out);
             fin.clear();
         }
         // (2) x += V y for slots that ended a cycle
@@ -807,13 +887,29 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
             launch_update_x(t, s, c->upd_dev, (int)upd.size(), jm, c->slots, P, sumL);
             upd.clear();
         }
-        // (3) refill free slots
+        // (3) refill free slots; warm-started points get x0 = U c(omega) now
+        wnew.clear();
+        wom.clear();
         for (int k = 0; k < nsl; ++k)
             if (sl[k].state == S_FREE && next_point < npts) {
                 sl[k].state = S_RHS;
                 sl[k].point = next_point++;
                 sl[k].j = 0;
+                sl[k].warm_check = false;
+                if (ws) {
+                    wnew.push_back({k, 0, sl[k].point, 0});
+                    wom.push_back(omega[sl[k].point / n_drive]);
+                }
             }
+        if (!wnew.empty()) {
+            HIPCHK(c, hipStreamSynchronize(s));   // fin_h / upd_h copies done; reuse fin_h
+            std::copy(wnew.begin(), wnew.end(), c->fin_h);
+            HIPCHK(c, hipMemcpyAsync(ws->jobs_dev, c->fin_h, sizeof(Job) * wnew.size(), hipMemcpyHostToDevice, s));
+            CHK(ws_infer(ws, s, (int)wnew.size(), wom.data()));
+            launch_ws_apply(s, ws->jobs_dev, (int)wnew.size(), ws->out, ws->O, ws->mean, ws->sdev, ws->r, ws->U,
+                            (int64_t)c->P_pad * 2, c->slots.x, (int64_t)c->P_pad * 2, P);
+            HIPCHK(c, hipStreamSynchronize(s));
+        }
         // (4) one job per active slot: FP64 jobs first (b, true residual, FP64
         //     Arnoldi), then the low-precision Arnoldi steps, so each group is a
         //     contiguous range processed by one operator pass
@@ -827,7 +923,7 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                 Job jb;
                 jb.slot = k;
                 jb.type = sl[k].state == S_RHS ? JOB_RHS : sl[k].state == S_ARNOLDI ? JOB_ARNOLDI : JOB_RESID;
-                jb.j = sl[k].j;
+                jb.j = jb.type == JOB_RHS ? (ws ? 1 : 0) : sl[k].j;
                 jb.drive = sl[k].point % n_drive;
                 if (jb.type == JOB_ARNOLDI) {
                     jmax = std::max(jmax, jb.j);
@@ -878,9 +974,13 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                 if (!(st.value > 0.0) || !std::isfinite(st.value)) {
                     pt.rel = st.value == 0.0 ? 0.0 : NAN;
                     pt.converged = st.value == 0.0;
+                    if (ws) rst.push_back({jb.slot, 0, 0, 0});   // x = 0 is the answer
                     fin.push_back({jb.slot, 0, ss.point, 0});
                     ss.state = S_FREE;
                     ++done;
+                } else if (ws) {
+                    ss.state = S_RESID;       // r0 = b - A x0 decides on the warm start
+                    ss.warm_check = true;
                 } else {
                     ss.state = S_ARNOLDI;
                     ss.j = 0;
@@ -897,6 +997,31 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                     ss.state = S_RESID;
                 } else {
                     ss.j += 1;
+                }
+            } else if (ss.warm_check) {
+                ss.warm_check = false;
+                const double rel0 = st.value / ss.bnorm;
+                pt.rel = rel0;
+                pt.warm_rel0 = rel0;
+                if (rel0 <= o.tol) {                        // the warm start is already the answer
+                    pt.warm = 1;
+                    pt.converged = 1;
+                    fin.push_back({jb.slot, 0, ss.point, 0});
+                    ss.state = S_FREE;
+                    ++done;
+                } else if (!(rel0 < 1.0)) {                 // no better than x0 = 0: zero start
+                    pt.warm = 2;
+                    rst.push_back({jb.slot, 0, 0, 0});
+                    ss.cycle0 = ss.bnorm;
+                    ss.rel_prev = 1.0;
+                    ss.state = S_ARNOLDI;
+                    ss.j = 0;
+                } else {
+                    pt.warm = 1;
+                    ss.cycle0 = st.value;
+                    ss.rel_prev = rel0;
+                    ss.state = S_ARNOLDI;
+                    ss.j = 0;
                 }
             } else {
                 pt.restarts += 1;
@@ -921,10 +1046,18 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
             }
         }
     }
+    if (!rst.empty()) {   // finished points whose x must read 0 before alpha
+        std::copy(rst.begin(), rst.end(), c->upd_h);
+        HIPCHK(c, hipMemcpyAsync(c->upd_dev, c->upd_h, sizeof(Job) * rst.size(), hipMemcpyHostToDevice, s));
+        launch_reset_slots(s, c->upd_dev, (int)rst.size(), c->slots, P);
+        rst.clear();
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
     if (!fin.empty()) {
         std::copy(fin.begin(), fin.end(), c->fin_h);
         HIPCHK(c, hipMemcpyAsync(c->fin_dev, c->fin_h, sizeof(Job) * fin.size(), hipMemcpyHostToDevice, s));
         launch_alpha(t, s, c->fin_dev, (int)fin.size(), c->slots, drives, n_drive, c->P_pad, P, nullptr, alpha_dev);
+        if (x_out) launch_store_x(s, c->fin_dev, (int)fin.size(), c->slots, P, x_out);
         fin.clear();
     }
     std::vector<double> ah((size_t)npts * n_drive * 2);
@@ -947,8 +1080,9 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                 r.converged = ps[p].converged;
                 r.breakdown = ps[p].breakdown;
                 r.fallback = ps[p].fallback;
-                r.reserved = 0;
+                r.warm_start = ps[p].warm;
                 r.rel_residual = ps[p].rel;
+                r.warm_rel0 = ps[p].warm_rel0;
             }
         }
     c->err.clear();
@@ -957,6 +1091,325 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
         return CHI0_NOT_CONVERGED;
     }
     return CHI0_OK;
+}
+
+extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *omega, double eps,
+                                   int32_t n_drive, const double *V_ext, const chi0_solve_opts *opts,
+                                   double *alpha, chi0_point_stats *stats) {
+    return solve_impl(c, n_omega, omega, eps, n_drive, V_ext, opts, alpha, stats, nullptr);
+}
+
+// ----------------------------------------------------- warm-start fitting
+namespace {
+// Eigen-decomposition of a Hermitian n x n matrix (row-major, interleaved
+// complex) by cyclic Jacobi rotations: A = V diag(w) V^H, w descending.
+void jacobi_eigh(int n, std::vector<double> a, std::vector<double> &w, std::vector<double> &v) {
+    auto re = [&](std::vector<double> &m, int i, int j) -> double & { return m[2 * ((size_t)i * n + j)]; };
+    auto im = [&](std::vector<double> &m, int i, int j) -> double & { return m[2 * ((size_t)i * n + j) + 1]; };
+    v.assign((size_t)2 * n * n, 0.0);
+    for (int i = 0; i < n; ++i) re(v, i, i) = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double x = re(a, i, j) * re(a, i, j) + im(a, i, j) * im(a, i, j);
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double br = re(a, p, q), bi = im(a, p, q);
+                const double bb = std::sqrt(br * br + bi * bi);
+                if (bb <= 1e-300) continue;
+                const double er = br / bb, ei = bi / bb;      // e^{i phi}
+                const double app = re(a, p, p), aqq = re(a, q, q);
+                const double tau = (aqq - app) / (2.0 * bb);
+                const double tt = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double cc = 1.0 / std::sqrt(1.0 + tt * tt), ss = tt * cc;
+                // U = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] acting on columns p, q
+                for (int k = 0; k < n; ++k) {     // A <- A U
+                    const double xr = re(a, k, p), xi = im(a, k, p), yr = re(a, k, q), yi = im(a, k, q);
+                    const double ur = yr * er + yi * ei, ui = yi * er - yr * ei;   // y e^{-i phi}
+                    re(a, k, p) = cc * xr - ss * ur;
+                    im(a, k, p) = cc * xi - ss * ui;
+                    re(a, k, q) = ss * xr + cc * ur;
+                    im(a, k, q) = ss * xi + cc * ui;
+                }
+                for (int k = 0; k < n; ++k) {     // A <- U^H A
+                    const double xr = re(a, p, k), xi = im(a, p, k), yr = re(a, q, k), yi = im(a, q, k);
+                    const double ur = yr * er - yi * ei, ui = yi * er + yr * ei;   // y e^{+i phi}
+                    re(a, p, k) = cc * xr - ss * ur;
+                    im(a, p, k) = cc * xi - ss * ui;
+                    re(a, q, k) = ss * xr + cc * ur;
+                    im(a, q, k) = ss * xi + cc * ui;
+                }
+                for (int k = 0; k < n; ++k) {     // V <- V U
+                    const double xr = re(v, k, p), xi = im(v, k, p), yr = re(v, k, q), yi = im(v, k, q);
+                    const double ur = yr * er + yi * ei, ui = yi * er - yr * ei;
+                    re(v, k, p) = cc * xr - ss * ur;
+                    im(v, k, p) = cc * xi - ss * ui;
+                    re(v, k, q) = ss * xr + cc * ur;
+                    im(v, k, q) = ss * xi + cc * ui;
+                }
+                im(a, p, p) = 0.0;
+                im(a, q, q) = 0.0;
+            }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return re(a, x, x) > re(a, y, y); });
+    std::vector<double> vs((size_t)2 * n * n);
+    w.resize(n);
+    for (int k = 0; k < n; ++k) {
+        w[k] = re(a, idx[k], idx[k]);
+        for (int i = 0; i < n; ++i) {
+            vs[2 * ((size_t)i * n + k)] = re(v, i, idx[k]);
+            vs[2 * ((size_t)i * n + k) + 1] = im(v, i, idx[k]);
+        }
+    }
+    v.swap(vs);
+}
+
+uint64_t splitmix(uint64_t &x) {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+}  // namespace
+
+extern "C" void chi0_ws_cfg_default(chi0_ws_cfg *cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->rank = 64;
+    cfg->width = 256;
+    cfg->n_freq = 16;
+    cfg->epochs = 3000;
+    cfg->lr = 2e-3;
+    cfg->seed = 1234;
+    cfg->batch = 64;
+    cfg->tol = 1e-10;
+}
+
+extern "C" void chi0_ws_free(chi0_ws *ws) {
+    if (!ws) return;
+    if (ws->ctx && ws->ctx->device >= 0) {
+        (void)hipSetDevice(ws->ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    delete ws;
+}
+
+static int ws_alloc(chi0_ctx *c, chi0_ws *w, int r, int width, int nf) {
+    w->r = r;
+    w->W = width;
+    w->nf = nf;
+    w->F = 2 * nf;
+    w->O = (int)round_up(2 * r, 32);
+    w->oW1 = 0;
+    w->ob1 = w->oW1 + (int64_t)w->W * w->F;
+    w->oW2 = w->ob1 + w->W;
+    w->ob2 = w->oW2 + (int64_t)w->W * w->W;
+    w->oW3 = w->ob2 + w->W;
+    w->ob3 = w->oW3 + (int64_t)w->O * w->W;
+    w->n_params = w->ob3 + w->O;
+    DevBuf &b = w->buf;
+    const int R = kMaxBatch;
+    CHK(dalloc(c, b, &w->U, (int64_t)r * c->P_pad * 2));
+    CHK(dalloc(c, b, &w->params, w->n_params));
+    CHK(dalloc(c, b, &w->grads, w->n_params));
+    CHK(dalloc(c, b, &w->am, w->n_params));
+    CHK(dalloc(c, b, &w->av, w->n_params));
+    CHK(dalloc(c, b, &w->mean, w->O));
+    CHK(dalloc(c, b, &w->sdev, w->O));
+    CHK(dalloc(c, b, &w->phi, (int64_t)R * w->F));
+    CHK(dalloc(c, b, &w->H1, (int64_t)R * w->W));
+    CHK(dalloc(c, b, &w->H2, (int64_t)R * w->W));
+    CHK(dalloc(c, b, &w->dH1, (int64_t)R * w->W));
+    CHK(dalloc(c, b, &w->dH2, (int64_t)R * w->W));
+    CHK(dalloc(c, b, &w->out, (int64_t)R * w->O));
+    CHK(dalloc(c, b, &w->dout, (int64_t)R * w->O));
+    CHK(dalloc(c, b, &w->tgt, (int64_t)R * w->O));
+    CHK(dalloc(c, b, &w->loss, 1 + 100000));
+    CHK(dalloc(c, b, &w->omega_dev, R));
+    CHK(dalloc(c, b, &w->jobs_dev, R));
+    HIPCHK(c, hipDeviceSynchronize());
+    return CHI0_OK;
+}
+
+static void ws_init_params(chi0_ws *w, uint64_t seed, std::vector<float> &h) {
+    h.assign((size_t)w->n_params, 0.f);
+    uint64_t st = seed;
+    auto fill = [&](int64_t off, int rows, int cols) {   // Glorot uniform
+        const double a = std::sqrt(6.0 / (rows + cols));
+        for (int64_t i = 0; i < (int64_t)rows * cols; ++i) {
+            const double u = (double)(splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+            h[(size_t)(off + i)] = (float)((2.0 * u - 1.0) * a);
+        }
+    };
+    fill(w->oW1, w->W, w->F);
+    fill(w->oW2, w->W, w->W);
+    fill(w->oW3, w->O, w->W);
+}
+
+extern "C" int chi0_ws_fit(chi0_ctx *c, int32_t n_train, const double *omega_train, double eps,
+                           const double *drive, const chi0_ws_cfg *cfg_in, chi0_ws **out) {
+    if (!out) return fail(c, CHI0_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c) return CHI0_EINVAL;
+    if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no system on a device context");
+    chi0_ws_cfg cfg;
+    chi0_ws_cfg_default(&cfg);
+    if (cfg_in) cfg = *cfg_in;
+    if (n_train < 2 || n_train > kMaxBatch) return fail(c, CHI0_EINVAL, "n_train must be in [2, 256]");
+    if (!omega_train || !drive) return fail(c, CHI0_EINVAL, "NULL pointer");
+    if (cfg.rank < 1 || cfg.rank > n_train) return fail(c, CHI0_EINVAL, "rank must be in [1, n_train]");
+    if (cfg.width < 32 || cfg.width % 32 || cfg.width > 1024) return fail(c, CHI0_EINVAL, "width must be a multiple of 32 in [32, 1024]");
+    if (cfg.n_freq != 16 && cfg.n_freq != 32) return fail(c, CHI0_EINVAL, "n_freq must be 16 or 32");
+    if (cfg.epochs < 1 || cfg.epochs > 100000) return fail(c, CHI0_EINVAL, "epochs must be in [1, 100000]");
+    if (!(cfg.lr > 0.0)) return fail(c, CHI0_EINVAL, "lr must be > 0");
+    for (int i = 0; i < 4; ++i)
+        if (cfg.reserved[i] != 0) return fail(c, CHI0_EINVAL, "reserved fields must be zero");
+    if (!all_finite(omega_train, n_train)) return fail(c, CHI0_ENONFINITE, "non-finite omega_train");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int P = c->P;
+    const int64_t vlen = (int64_t)c->P_pad * 2;
+
+    // 1. training solutions by plain FP64 GMRES (zero start)
+    DevBuf tmp;
+    struct Guard { DevBuf *b; ~Guard() { b->release(); } } guard{&tmp};
+    double *S = nullptr, *G = nullptr, *Wc = nullptr;
+    CHK(dalloc(c, tmp, &S, (int64_t)n_train * vlen));
+    CHK(dalloc(c, tmp, &G, (int64_t)n_train * n_train * 2));
+    chi0_solve_opts so;
+    chi0_solve_opts_default(&so);
+    so.restart = cfg.restart > 0 ? cfg.restart : std::min(P, 4000);
+    so.tol = cfg.tol;
+    so.batch = std::max(1, std::min(cfg.batch, n_train));
+    so.max_iter = 20000;
+    std::vector<double> al((size_t)n_train * 2);
+    const int rc = solve_impl(c, n_train, omega_train, eps, 1, drive, &so, al.data(), nullptr, S);
+    if (rc < 0) return rc;
+
+    // 2. Gram matrix on the GPU, eigen-decomposition on the host (n_train <= 256)
+    launch_gram(c->stream, n_train, S, vlen, P, G);
+    std::vector<double> gh((size_t)n_train * n_train * 2);
+    HIPCHK(c, hipMemcpyAsync(gh.data(), G, gh.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> lam, V;
+    jacobi_eigh(n_train, gh, lam, V);
+    int r = 0;
+    while (r < cfg.rank && lam[r] > 1e-20 * lam[0] && lam[r] > 0.0) ++r;
+    if (r < 1) return fail(c, CHI0_EINVAL, "training solutions are zero");
+
+    chi0_ws *w = new (std::nothrow) chi0_ws();
+    if (!w) return fail(c, CHI0_ENOMEM, "host allocation failed");
+    std::unique_ptr<chi0_ws> hold(w);
+    w->ctx = c;
+    CHK(ws_alloc(c, w, r, cfg.width, cfg.n_freq));
+    double wmax = 0.0;
+    for (int i = 0; i < n_train; ++i) wmax = std::max(wmax, std::fabs(omega_train[i]));
+    w->w_scale = cfg.w_scale > 0.0 ? cfg.w_scale : (wmax > 0.0 ? wmax : 1.0);
+    w->epochs = cfg.epochs;
+
+    // 3. basis U = S V_r Sigma_r^-1 (GPU) and coordinates C = U^H S = Sigma^-1 V_r^H G (host)
+    std::vector<double> wc((size_t)n_train * r * 2);
+    for (int t2 = 0; t2 < n_train; ++t2)
+        for (int k = 0; k < r; ++k) {
+            const double sg = std::sqrt(lam[k]);
+            wc[2 * ((size_t)t2 * r + k)] = V[2 * ((size_t)t2 * n_train + k)] / sg;
+            wc[2 * ((size_t)t2 * r + k) + 1] = V[2 * ((size_t)t2 * n_train + k) + 1] / sg;
+        }
+    CHK(dalloc(c, tmp, &Wc, (int64_t)wc.size()));
+    HIPCHK(c, hipMemcpy(Wc, wc.data(), wc.size() * 8, hipMemcpyHostToDevice));
+    launch_basis(c->stream, n_train, r, S, vlen, P, Wc, w->U);
+    // C[t][k] = sum_s conj(Wc[s][k]) G[s][t]
+    const int O = w->O, rows = (int)round_up(n_train, 32);
+    std::vector<double> C((size_t)n_train * 2 * r);
+    for (int t2 = 0; t2 < n_train; ++t2)
+        for (int k = 0; k < r; ++k) {
+            double cr = 0.0, ci = 0.0;
+            for (int s2 = 0; s2 < n_train; ++s2) {
+                const double ar = wc[2 * ((size_t)s2 * r + k)], ai = -wc[2 * ((size_t)s2 * r + k) + 1];
+                const double gr = gh[2 * ((size_t)s2 * n_train + t2)], gi = gh[2 * ((size_t)s2 * n_train + t2) + 1];
+                cr += ar * gr - ai * gi;
+                ci += ar * gi + ai * gr;
+            }
+            C[(size_t)t2 * 2 * r + 2 * k] = cr;
+            C[(size_t)t2 * 2 * r + 2 * k + 1] = ci;
+        }
+    // normalised targets: (c - mean) / std per output
+    std::vector<float> mean(O, 0.f), sdev(O, 1.f), tg((size_t)kMaxBatch * O, 0.f);
+    for (int o2 = 0; o2 < 2 * r; ++o2) {
+        double mu = 0.0, sq = 0.0;
+        for (int t2 = 0; t2 < n_train; ++t2) mu += C[(size_t)t2 * 2 * r + o2];
+        mu /= n_train;
+        for (int t2 = 0; t2 < n_train; ++t2) {
+            const double d = C[(size_t)t2 * 2 * r + o2] - mu;
+            sq += d * d;
+        }
+        const double sd = std::sqrt(sq / n_train);
+        mean[o2] = (float)mu;
+        sdev[o2] = (float)(sd > 0.0 ? sd : 1.0);
+        for (int t2 = 0; t2 < n_train; ++t2)
+            tg[(size_t)t2 * O + o2] = (float)((C[(size_t)t2 * 2 * r + o2] - mu) / sdev[o2]);
+    }
+    HIPCHK(c, hipMemcpy(w->mean, mean.data(), O * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(w->sdev, sdev.data(), O * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(w->tgt, tg.data(), tg.size() * 4, hipMemcpyHostToDevice));
+    std::vector<float> p0;
+    ws_init_params(w, cfg.seed, p0);
+    HIPCHK(c, hipMemcpy(w->params, p0.data(), p0.size() * 4, hipMemcpyHostToDevice));
+
+    // 4. full-batch Adam, cosine-decayed learning rate
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(w->omega_dev, omega_train, sizeof(double) * n_train, hipMemcpyHostToDevice, s));
+    launch_features(s, n_train, rows, w->omega_dev, w->nf, w->w_scale, w->phi);
+    const int E = cfg.epochs;
+    DevBuf lbuf;
+    struct Guard2 { DevBuf *b; ~Guard2() { b->release(); } } guard2{&lbuf};
+    float *lh = nullptr;
+    CHK(dalloc(c, lbuf, &lh, E));
+    for (int ep = 1; ep <= E; ++ep) {
+        const double lr = cfg.lr * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(M_PI * (ep - 1) / E)));
+        ws_forward(w, s, rows);
+        ws_backward(w, s, rows, n_train, 2 * r, lh + (ep - 1));
+        launch_adam(s, w->n_params, w->params, w->grads, w->am, w->av, (float)lr, 0.9f, 0.999f, 1e-8f, ep);
+    }
+    w->loss_hist.resize(E);
+    HIPCHK(c, hipMemcpyAsync(w->loss_hist.data(), lh, (size_t)E * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipGetLastError());
+    *out = hold.release();
+    c->err.clear();
+    return rc;
+}
+
+extern "C" int chi0_ws_predict(chi0_ws *w, int32_t n, const double *omega, double *x0) {
+    if (!w || !w->ctx) return CHI0_EINVAL;
+    chi0_ctx *c = w->ctx;
+    if (n < 0 || n > kMaxBatch) return fail(c, CHI0_EINVAL, "n must be in [0, 256]");
+    if (n == 0) return CHI0_OK;
+    if (!omega || !x0) return fail(c, CHI0_EINVAL, "NULL pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    std::vector<Job> jl(n);
+    for (int i = 0; i < n; ++i) jl[i] = {i, 0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(w->jobs_dev, jl.data(), sizeof(Job) * n, hipMemcpyHostToDevice, s));
+    CHK(ws_infer(w, s, n, omega));
+    launch_ws_apply(s, w->jobs_dev, n, w->out, w->O, w->mean, w->sdev, w->r, w->U, (int64_t)c->P_pad * 2,
+                    x0, (int64_t)c->P * 2, c->P);
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipGetLastError());
+    return CHI0_OK;
+}
+
+extern "C" int chi0_ws_loss_history(const chi0_ws *w, float *loss, int32_t cap) {
+    if (!w || cap < 0 || (cap > 0 && !loss)) return CHI0_EINVAL;
+    const int n = std::min<int>(cap, (int)w->loss_hist.size());
+    for (int i = 0; i < n; ++i) loss[i] = w->loss_hist[i];
+    return (int)w->loss_hist.size();
 }
 
 // ============================================================= test hooks
@@ -994,5 +1447,55 @@ extern "C" int chi0_debug_read(chi0_ctx *c, int32_t which, void *host, int64_t b
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipDeviceSynchronize());
     HIPCHK(c, hipMemcpy(host, src, (size_t)bytes, hipMemcpyDeviceToHost));
+    return CHI0_OK;
+}
+
+extern "C" int chi0_ws_debug_dims(const chi0_ws *w, int64_t *d, double *w_scale) {
+    if (!w || !d) return CHI0_EINVAL;
+    const int64_t v[7] = {w->r, w->F, w->W, w->O, w->n_params, w->nf, 0};
+    for (int i = 0; i < 6; ++i) d[i] = v[i];
+    if (w_scale) *w_scale = w->w_scale;
+    return CHI0_OK;
+}
+
+extern "C" int chi0_ws_debug_params(chi0_ws *w, float *host, int64_t n, int32_t set) {
+    if (!w || !host || n != w->n_params) return CHI0_EINVAL;
+    chi0_ctx *c = w->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceSynchronize());
+    if (set)
+        HIPCHK(c, hipMemcpy(w->params, host, (size_t)n * 4, hipMemcpyHostToDevice));
+    else
+        HIPCHK(c, hipMemcpy(host, w->params, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return CHI0_OK;
+}
+
+extern "C" int chi0_ws_debug_loss_grad(chi0_ws *w, int32_t n, const double *omega, const float *target,
+                                       float *loss, float *grads) {
+    if (!w || !omega || !target || !loss || !grads || n < 1 || n > kMaxBatch) return CHI0_EINVAL;
+    chi0_ctx *c = w->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int rows = (int)round_up(n, 32);
+    std::vector<float> tg((size_t)rows * w->O, 0.f);
+    std::copy(target, target + (size_t)n * w->O, tg.begin());
+    HIPCHK(c, hipMemcpyAsync(w->tgt, tg.data(), tg.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(w->omega_dev, omega, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    launch_features(s, n, rows, w->omega_dev, w->nf, w->w_scale, w->phi);
+    ws_forward(w, s, rows);
+    ws_backward(w, s, rows, n, 2 * w->r, w->loss);
+    HIPCHK(c, hipMemcpyAsync(loss, w->loss, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(grads, w->grads, (size_t)w->n_params * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipGetLastError());
+    return CHI0_OK;
+}
+
+extern "C" int chi0_debug_eigh(int32_t n, const double *A, double *w, double *V) {
+    if (n < 1 || !A || !w || !V) return CHI0_EINVAL;
+    std::vector<double> a(A, A + (size_t)2 * n * n), lam, vec;
+    jacobi_eigh(n, a, lam, vec);
+    std::copy(lam.begin(), lam.end(), w);
+    std::copy(vec.begin(), vec.end(), V);
     return CHI0_OK;
 }

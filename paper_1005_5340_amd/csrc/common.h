@@ -128,7 +128,8 @@ void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
 struct Job {
     int32_t slot;
     int32_t type;     // JOB_RHS, JOB_ARNOLDI, JOB_RESID
-    int32_t j;        // Arnoldi index (JOB_ARNOLDI) / cycle length for update_x
+    int32_t j;        // Arnoldi index (JOB_ARNOLDI); 1 = keep the warm-start x (JOB_RHS);
+                      // cycle length (update_x); point index (alpha, store_x)
     int32_t drive;    // drive index of the slot's point
 };
 enum { JOB_RHS = 0, JOB_ARNOLDI = 1, JOB_RESID = 2 };
@@ -167,6 +168,27 @@ void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
 void launch_alpha(Tracer *t, hipStream_t s, const Job *jobs, int n, const SlotsDev &sl,
                   const double *drives, int n_drive, int P_pad, int P, const int32_t *out_index,
                   double *alpha_out);
+// learned warm start (kernels_mlp.hip)
+void launch_mlp_gemm(hipStream_t s, int M, int N, int K, const float *A, int sam, int sak,
+                     const float *B, int sbk, int sbn, float *C, int ldc);
+void launch_features(hipStream_t s, int n, int n_pad, const double *omega, int nf, double scale,
+                     float *phi);
+void launch_bias_act(hipStream_t s, int M, int N, float *Z, const float *bias, int act);
+void launch_mse(hipStream_t s, int M, int N, int n_rows, int n_cols, const float *out, const float *tgt,
+                float *dout, float *loss);
+void launch_tanh_back(hipStream_t s, int64_t n, const float *H, float *dH);
+void launch_colsum(hipStream_t s, int M, int N, const float *dZ, float *db);
+void launch_adam(hipStream_t s, int64_t n, float *p, const float *g, float *m, float *v, float lr,
+                 float b1, float b2, float eps, int t);
+void launch_gram(hipStream_t s, int n, const double *S, int64_t stride, int P, double *G);
+void launch_basis(hipStream_t s, int n, int r, const double *S, int64_t stride, int P, const double *Wc,
+                  double *U);
+void launch_ws_apply(hipStream_t s, const Job *jobs, int n, const float *out, int ldo, const float *mean,
+                     const float *sdev, int r, const double *U, int64_t ustride, double *x,
+                     int64_t xstride, int P);
+void launch_reset_slots(hipStream_t s, const Job *jobs, int n, const SlotsDev &sl, int P);
+void launch_store_x(hipStream_t s, const Job *jobs, int n, const SlotsDev &sl, int P, double *out);
+
 // apply: caller rows [r][P] complex <-> operator columns [P_pad][ncp]
 void launch_rows_to_cols(Tracer *t, hipStream_t s, const double *z, int nb, int P,
                          double *Zin, int ncp);

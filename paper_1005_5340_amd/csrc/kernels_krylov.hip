@@ -83,7 +83,7 @@ void launch_put_drive(Tracer *t, hipStream_t s, const Job *jobs, int nb, const d
 }
 
 // ----------------------------------------------------------------- post step
-// RHS:     b = Y, x = 0, r = b.            ARNOLDI: w = v_j - Y -> V[j+1].
+// RHS:     b = Y, x = 0 (kept if warm), r = b.   ARNOLDI: w = v_j - Y -> V[j+1].
 // RESID:   r = b - (x - Y).                RHS/RESID: V[0] = r/||r||, g0 = ||r||.
 __global__ __launch_bounds__(256)
 void k_post_jobs(const Job *__restrict__ jobs, SlotsDev sl, const double *__restrict__ Y, int nc,
@@ -111,7 +111,7 @@ void k_post_jobs(const Job *__restrict__ jobs, SlotsDev sl, const double *__rest
         double rr, ri;
         if (jb.type == JOB_RHS) {
             b[mu] = make_double2(yr, yi);
-            x[mu] = make_double2(0.0, 0.0);
+            if (jb.j == 0) x[mu] = make_double2(0.0, 0.0);   // else a warm start is in x
             rr = yr; ri = yi;
         } else {
             const double2 bb = b[mu], xx = x[mu];

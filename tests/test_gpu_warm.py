@@ -1,0 +1,125 @@
+"""Learned warm start on the GPU: gradients, training, predictions, solves.
+
+The network's loss and gradients from the GPU kernels are compared with the
+FP64 oracle (oracle/mlp_oracle.py) -- tightly when the oracle emulates the
+BF16 rounding of the matrix-product operands, loosely without it.  A warm
+start must never change the answer (GMRES still stops on the true FP64
+residual); what it changes is the number of iterations, printed here.
+"""
+import numpy as np
+import pytest
+
+import gpu_systems
+from oracle import chi0_oracle as orc
+from oracle import mlp_oracle as mo
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fitted():
+    from paper_1005_5340_amd import chi0
+    sys = gpu_systems.get("atoms12_orb9")
+    ctx = chi0.Context(0)
+    ctx.set_system_from(sys)
+    rng = np.random.default_rng(1000)
+    om_train = np.sort(rng.uniform(0.0, 1.5, 32))
+    d = sys.drives("z")[0]
+    ws = chi0.WarmStart(ctx, om_train, sys.eps, d, rank=32, width=128, epochs=2000,
+                        restart=sys.n_prod, batch=32, tol=1e-12)
+    yield sys, ctx, ws, om_train
+    ws.close()
+    ctx.close()
+
+
+def test_gradients_match_oracle(fitted):
+    sys, ctx, ws, _ = fitted
+    dm = ws.dims()
+    F, W, O, r = dm["F"], dm["W"], dm["O"], dm["r"]
+    keep = ws.params()
+    rng = np.random.default_rng(7)
+    p = (rng.standard_normal(dm["n_params"]) * 0.2).astype(np.float32)
+    ws.params(p)
+    om = rng.uniform(0.0, 1.5, 20)
+    tgt = rng.standard_normal((20, O)).astype(np.float32)
+    loss, g = ws.loss_grad(om, tgt)
+    phi = mo.features(om, dm["n_freq"], dm["w_scale"])
+    lr, gr = mo.loss_grad(p.astype(float), phi, tgt, 2 * r, F, W, O, round_bf16=True)
+    lu, gu = mo.loss_grad(p.astype(float), phi, tgt, 2 * r, F, W, O, round_bf16=False)
+    e_r = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    e_u = np.linalg.norm(g - gu) / np.linalg.norm(gu)
+    print(f"[warm] loss gpu {loss:.6e} oracle(bf16) {lr:.6e} oracle(fp64) {lu:.6e}; "
+          f"grad rel err vs bf16-emulating oracle {e_r:.2e}, vs fp64 oracle {e_u:.2e}", flush=True)
+    ws.params(keep)
+    assert abs(loss - lr) <= 1e-4 * lr
+    assert e_r < 2e-3
+    assert e_u < 5e-2
+
+
+def test_training_reduces_loss(fitted):
+    _, _, ws, _ = fitted
+    h = ws.loss_history()
+    print(f"[warm] loss first {h[0]:.3e} last {h[-1]:.3e} ({h.size} Adam steps)", flush=True)
+    assert h.size == 2000 and np.all(np.isfinite(h))
+    assert h[-1] < 1e-2 * h[0]
+
+
+def test_prediction_near_training_solutions(fitted):
+    sys, _, ws, om_train = fitted
+    d = sys.drives("z")
+    pick = om_train[[3, 17, 29]]
+    x0 = ws.predict(pick).cpu().numpy()
+    for k, w in enumerate(pick):
+        x = orc.solve_response(sys, float(w), d)[0]
+        e = np.linalg.norm(x0[k] - x) / np.linalg.norm(x)
+        print(f"[warm] omega {w:.4f} |x0 - x| / |x| = {e:.3e}", flush=True)
+        assert e < 0.3
+
+
+def test_warm_started_solves_are_exact(fitted):
+    sys, ctx, ws, _ = fitted
+    d = sys.drives("z")
+    om = np.linspace(0.05, 1.45, 16)
+    a0, s0, r0 = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-12, batch=16)
+    a1, s1, r1 = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-12, batch=16, warm=ws)
+    ref = orc.polarizability(sys, om, d)
+    print(f"[warm] tol 1e-12: iterations zero start {int(s0['iterations'].sum())} warm "
+          f"{int(s1['iterations'].sum())}; initial residual of x0 median "
+          f"{np.median(s1['warm_rel0']):.2e} max {s1['warm_rel0'].max():.2e}", flush=True)
+    assert r0 == 0 and r1 == 0
+    assert np.max(np.abs(a1 - ref)) < 1e-9 * np.max(np.abs(ref))
+    assert np.max(np.abs(a0 - ref)) < 1e-9 * np.max(np.abs(ref))
+    assert (s1["warm_start"] == 1).all() and (s0["warm_start"] == 0).all()
+    assert (s1["warm_rel0"] < 1.0).all()
+    assert s1["iterations"].sum() <= s0["iterations"].sum()
+
+
+def test_warm_start_gain_by_tolerance(fitted):
+    """The saving shrinks as the tolerance tightens: x0 removes the smooth part
+    of the error, while the GMRES work at tight tolerances goes into the
+    slowly resolved directions of the badly conditioned (1 - chi0 K)."""
+    sys, ctx, ws, _ = fitted
+    d = sys.drives("z")
+    om = np.linspace(0.05, 1.45, 16)
+    gains = {}
+    for tol in (1e-3, 1e-6, 1e-9):
+        _, s0, _ = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=tol, batch=16)
+        _, s1, _ = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=tol, batch=16, warm=ws)
+        i0, i1 = int(s0["iterations"].sum()), int(s1["iterations"].sum())
+        gains[tol] = 1.0 - i1 / i0
+        print(f"[warm] tol {tol:.0e}: iterations zero start {i0} warm {i1} (saved {100 * gains[tol]:.1f}%)",
+              flush=True)
+    assert gains[1e-3] > 0.0
+
+
+def test_rejected_warm_start_falls_back_to_zero(fitted):
+    sys, ctx, ws, _ = fitted
+    keep = ws.params()
+    ws.params(keep * 1e3)              # corrupt the network: absurd initial guesses
+    d = sys.drives("z")
+    om = np.array([0.33, 0.91])
+    a, st, rc = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-12, batch=2, warm=ws)
+    ws.params(keep)
+    ref = orc.polarizability(sys, om, d)
+    assert rc == 0 and (st["warm_start"] == 2).all()
+    assert np.max(np.abs(a - ref)) < 1e-9 * np.max(np.abs(ref))
