@@ -148,7 +148,7 @@ int chi0_apply(chi0_ctx *ctx, int32_t n_rhs, const double *omega, double eps,
 typedef struct chi0_ws chi0_ws;        /* learned warm start (see chi0_ws_fit) */
 
 typedef struct chi0_solve_opts {
-    int32_t restart;      /* GMRES(m) Krylov dimension per cycle, 1..4000 (default 30) */
+    int32_t restart;      /* GMRES(m) Krylov dimension per cycle, 1..3999 (default 30) */
     int32_t max_iter;     /* cap on Arnoldi steps per point (default 10000) */
     double  tol;          /* stop when ||chi0 d - A x||_2 <= tol ||chi0 d||_2 (default 1e-10) */
     int32_t precision;    /* CHI0_PREC_* of the Arnoldi steps (default FP64); b = chi0 d and
@@ -159,8 +159,21 @@ typedef struct chi0_solve_opts {
     const chi0_ws *warm;  /* NULL, or a warm start fitted on this context and system: every point
                              starts from x0 = U c(omega) instead of 0, unless
                              ||chi0 d - A x0|| >= ||chi0 d||, then from 0 */
-    int32_t reserved[4];  /* must be zero */
+    int32_t ortho;        /* CHI0_ORTHO_*: Gram-Schmidt variant of the Arnoldi step */
+    int32_t reserved[3];  /* must be zero */
 } chi0_solve_opts;
+
+/* Gram-Schmidt of the Arnoldi step (eq. orthogonal-krylov-basis, done twice).
+ *   CGS2   two classical passes per step: four reads of the basis.
+ *   DCGS2  the second pass of each vector is delayed into the next step and
+ *          fused with its projection: two reads of the basis per step; the
+ *          newest column is provisional until the next step, so the basis
+ *          holds one extra vector (m+2 per point) and the residual estimate
+ *          lags one step.
+ *   AUTO   DCGS2 when restart >= 8, else CGS2. */
+#define CHI0_ORTHO_AUTO       0
+#define CHI0_ORTHO_CGS2       1
+#define CHI0_ORTHO_DCGS2      2
 
 /* Per-point solver record (one per omega and drive). */
 typedef struct chi0_point_stats {

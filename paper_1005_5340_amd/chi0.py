@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so"
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16X3 = 2
+ORTHO_AUTO, ORTHO_CGS2, ORTHO_DCGS2 = 0, 1, 2
 NOT_CONVERGED = 1
 _ERRORS = {-1: "EINVAL", -2: "ENOSYS", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EASYM"}
 
@@ -34,7 +35,7 @@ _i64p = C.POINTER(C.c_int64)
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("batch", C.c_int32), ("inner_tol", C.c_double),
-                ("warm", C.c_void_p), ("reserved", C.c_int32 * 4)]
+                ("warm", C.c_void_p), ("ortho", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class WsCfg(C.Structure):
@@ -242,7 +243,7 @@ class Context:
     # ---------------------------------------------------------------- solve
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
                        tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,
-                       inner_tol: float = 0.0, warm: "WarmStart" = None):
+                       inner_tol: float = 0.0, warm: "WarmStart" = None, ortho: int = ORTHO_AUTO):
         """GMRES polarizability over a frequency grid.
 
         Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
@@ -256,6 +257,7 @@ class Context:
         o.restart, o.max_iter, o.tol = int(restart), int(max_iter), float(tol)
         o.batch, o.precision, o.inner_tol = int(batch), int(precision), float(inner_tol)
         o.warm = warm._h if warm is not None else None
+        o.ortho = int(ortho)
         alpha = np.zeros((om.size, nd, nd, 2))
         st = (PointStats * max(1, om.size * nd))()
         rc = self._L.chi0_solve_response(self._h, int(om.size), _ptr(om), float(eps), int(nd),

@@ -682,6 +682,7 @@ static int ensure_slots(chi0_ctx *c, int n, int m) {
     sl.P_pad = c->P_pad;
     sl.vstride = (int64_t)(m + 1) * c->P_pad * 2;
     sl.hstride = (int64_t)m * (m + 3) / 2 * 2;
+    sl.hbstride = (int64_t)(3 * m + 4) * 2;
     CHK(dalloc(c, b, &sl.V, n * sl.vstride));
     CHK(dalloc(c, b, &sl.H, n * sl.hstride));
     CHK(dalloc(c, b, &sl.cs, (int64_t)n * m));
@@ -689,7 +690,7 @@ static int ensure_slots(chi0_ctx *c, int n, int m) {
     CHK(dalloc(c, b, &sl.g, (int64_t)n * (m + 1) * 2));
     CHK(dalloc(c, b, &sl.x, (int64_t)n * c->P_pad * 2));
     CHK(dalloc(c, b, &sl.b, (int64_t)n * c->P_pad * 2));
-    CHK(dalloc(c, b, &sl.hbuf, (int64_t)n * (m + 1) * 2));
+    CHK(dalloc(c, b, &sl.hbuf, (int64_t)n * sl.hbstride));
     CHK(dalloc(c, b, &sl.y, (int64_t)n * m * 2));
     CHK(dalloc(c, b, &c->jobs_dev, n));
     CHK(dalloc(c, b, &c->fin_dev, n));
@@ -813,7 +814,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     if (n_omega == 0) return CHI0_OK;
     if (!omega || !V_ext || !alpha) return fail(c, CHI0_EINVAL, "NULL pointer");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
-    if (o.restart < 1 || o.restart > 4000) return fail(c, CHI0_EINVAL, "restart must be in [1, 4000]");
+    if (o.restart < 1 || o.restart > 3999) return fail(c, CHI0_EINVAL, "restart must be in [1, 3999]");
     if (o.max_iter < 1) return fail(c, CHI0_EINVAL, "max_iter must be >= 1");
     if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(c, CHI0_EINVAL, "tol must be finite and > 0");
     if (o.batch < 1) return fail(c, CHI0_EINVAL, "batch must be >= 1");
@@ -821,8 +822,12 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     if (o.precision < CHI0_PREC_FP64 || o.precision > CHI0_PREC_BF16X3)
         return fail(c, CHI0_EINVAL, "unknown precision");
     if (!(o.inner_tol >= 0.0) || !(o.inner_tol < 1.0)) return fail(c, CHI0_EINVAL, "inner_tol must be in [0, 1)");
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (o.reserved[i] != 0) return fail(c, CHI0_EINVAL, "reserved option fields must be zero");
+    if (o.ortho < CHI0_ORTHO_AUTO || o.ortho > CHI0_ORTHO_DCGS2) return fail(c, CHI0_EINVAL, "unknown ortho");
+    // delayed reorthogonalisation needs a few columns per cycle (one is always provisional)
+    const bool dcgs = o.ortho == CHI0_ORTHO_DCGS2 || (o.ortho == CHI0_ORTHO_AUTO && o.restart >= 8);
+    if (dcgs && o.restart < 3) return fail(c, CHI0_EINVAL, "DCGS2 needs restart >= 3");
     chi0_ws *ws = const_cast<chi0_ws *>(o.warm);
     if (ws && ws->ctx != c) return fail(c, CHI0_EINVAL, "warm start belongs to another context");
     const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol
@@ -833,7 +838,9 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
 
     const int npts = n_omega * n_drive;
     const int nsl = std::min(std::min(o.batch, npts), kMaxBatch);
-    const int m = o.restart;
+    // storage for m columns per cycle; the delayed scheme keeps one extra
+    // provisional column, so it gets one more basis vector
+    const int m = o.restart + (dcgs ? 1 : 0);
     const int P = c->P;
     CHK(ensure_ws(c, 2 * std::max(nsl, c->nc_cap / 2)));
     if (o.precision != CHI0_PREC_FP64) CHK(ensure_lp(c));
@@ -955,8 +962,12 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
         };
         if (nb64 > 0) run_group(0, nb64, CHI0_PREC_FP64);
         if (nb > nb64) run_group(nb64, nb - nb64, o.precision);
-        if (n_arn > 0)
-            launch_arnoldi(t, s, c->jobs_dev, nb, jmax, c->slots, P, c->status_dev, n_arn, sum_j1);
+        if (n_arn > 0) {
+            if (dcgs)
+                launch_dcgs(t, s, c->jobs_dev, nb, jmax, c->slots, P, c->status_dev, n_arn, sum_j1);
+            else
+                launch_arnoldi(t, s, c->jobs_dev, nb, jmax, c->slots, P, c->status_dev, n_arn, sum_j1);
+        }
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(c->status_h, c->status_dev, sizeof(StepStatus) * nb, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
@@ -991,9 +1002,13 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 if (ss.prec != CHI0_PREC_FP64) stop = std::max(stop, inner_tol * ss.cycle0);
                 const bool brk = st.hnext == 0.0;
                 if (brk) pt.breakdown = 1;
-                if (st.value <= stop || brk || ss.j + 1 >= m || pt.iters >= o.max_iter ||
-                    !std::isfinite(st.value)) {
-                    upd.push_back({jb.slot, 0, ss.j + 1, 0});
+                // CGS2: the step completes column j (dimension j+1).  Delayed
+                // reorthogonalisation: it completes column j-1 (dimension j) and
+                // leaves column j provisional, so a cycle uses the first j columns.
+                const int L = dcgs ? ss.j : ss.j + 1;
+                const bool est_ok = L >= 1 && st.value <= stop;
+                if (est_ok || brk || ss.j + 1 >= m || pt.iters >= o.max_iter || !std::isfinite(st.value)) {
+                    if (L >= 1) upd.push_back({jb.slot, 0, L, 0});
                     ss.state = S_RESID;
                 } else {
                     ss.j += 1;

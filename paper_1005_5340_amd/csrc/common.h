@@ -142,10 +142,11 @@ struct SlotsDev {
     double *g;        // [n_slots][m+1] complex
     double *x;        // [n_slots][P_pad] complex
     double *b;        // [n_slots][P_pad] complex
-    double *hbuf;     // [n_slots][m+1] complex scratch for Gram-Schmidt coefficients
+    double *hbuf;     // [n_slots][hbstride] scratch for Gram-Schmidt coefficients (>= 3m+4 complex)
     double *y;        // [n_slots][m] complex least-squares solution
     int64_t vstride;  // doubles between slots in V  = (m+1)*P_pad*2
     int64_t hstride;  // doubles between slots in H
+    int64_t hbstride; // doubles between slots in hbuf
     int m;
     int P_pad;
 };
@@ -163,6 +164,9 @@ void launch_post_jobs(Tracer *t, hipStream_t s, const Job *jobs, int nb, const S
                       const double *Y, int ncp, int P, StepStatus *status);
 void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
                     const SlotsDev &sl, int P, StepStatus *status, int n_arnoldi, double sum_j1);
+// Arnoldi step with delayed reorthogonalisation (two passes over the basis).
+void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, const SlotsDev &sl, int P,
+                 StepStatus *status, int n_arnoldi, double sum_j1);
 void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
                      const SlotsDev &sl, int P, double sum_L);
 void launch_alpha(Tracer *t, hipStream_t s, const Job *jobs, int n, const SlotsDev &sl,

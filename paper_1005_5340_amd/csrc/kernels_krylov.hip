@@ -163,7 +163,7 @@ void k_cgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P) {
     re = wave_sum(re);
     im = wave_sum(im);
     if (lane == 0) {
-        double *h = sl.hbuf + (int64_t)jb.slot * (sl.m + 1) * 2;
+        double *h = sl.hbuf + (int64_t)jb.slot * sl.hbstride;
         h[2 * i] = re;
         h[2 * i + 1] = im;
     }
@@ -177,7 +177,7 @@ void k_cgs_update(const Job *__restrict__ jobs, SlotsDev sl, int P, int accumula
     const Job jb = jobs[q];
     if (jb.type != JOB_ARNOLDI) return;
     const int n = jb.j + 1;
-    const double *h = sl.hbuf + (int64_t)jb.slot * (sl.m + 1) * 2;
+    const double *h = sl.hbuf + (int64_t)jb.slot * sl.hbstride;
     for (int i = t; i < 2 * n; i += 256) hs[i] = h[i];
     __syncthreads();
     if (blockIdx.x == 0) {
@@ -212,11 +212,96 @@ struct cpx { double r, i; };
 __device__ __forceinline__ cpx cmul(cpx a, cpx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 __device__ __forceinline__ cpx cadd(cpx a, cpx b) { return {a.r + b.r, a.i + b.i}; }
 
+struct GivensShared {
+    cpx A[2][256], B[2][256];
+    cpx ulast;
+};
+
+// Givens update of Hessenberg column j (col[0..j] from Gram-Schmidt, col[j+1]
+// = hn = h_{j+1,j} >= 0): applies rotations 0..j-1, forms rotation j that
+// zeroes h_{j+1,j}, updates g and returns |g_{j+1}| (valid in thread 0).
+// Called by all 256 threads; tmp is scratch of >= j complex.
+__device__ double givens_column(cpx *col, int j, double hn, double *cs, cpx *sn, double *g, cpx *tmp,
+                                GivensShared &gs) {
+    const int t = threadIdx.x;
+    const int chunk = (j + 255) / 256;
+    const int lo = min(j, t * chunk), hi = min(j, lo + chunk);
+    cpx A = {1.0, 0.0}, B = {0.0, 0.0};          // identity map
+    for (int i = lo; i < hi; ++i) {
+        const cpx a = {-sn[i].r, sn[i].i};        // -conj(s_i)
+        const cpx b = {cs[i] * col[i + 1].r, cs[i] * col[i + 1].i};
+        B = cadd(cmul(a, B), b);                  // (a, b) o (A, B)
+        A = cmul(a, A);
+    }
+    gs.A[0][t] = A;
+    gs.B[0][t] = B;
+    __syncthreads();
+    int cur = 0;
+    for (int o = 1; o < 256; o <<= 1) {
+        cpx nA = gs.A[cur][t], nB = gs.B[cur][t];
+        if (t >= o) {   // compose the earlier prefix (t-o) first, then this element
+            const cpx pA = gs.A[cur][t - o], pB = gs.B[cur][t - o];
+            nB = cadd(cmul(nA, pB), nB);
+            nA = cmul(nA, pA);
+        }
+        gs.A[cur ^ 1][t] = nA;
+        gs.B[cur ^ 1][t] = nB;
+        cur ^= 1;
+        __syncthreads();
+    }
+    const cpx u0 = col[0];
+    cpx u = u0;
+    if (t > 0) u = cadd(cmul(gs.A[cur][t - 1], u0), gs.B[cur][t - 1]);
+    for (int i = lo; i < hi; ++i) {
+        const cpx si = sn[i], h1 = col[i + 1];
+        tmp[i] = cadd({cs[i] * u.r, cs[i] * u.i}, cmul(si, h1));
+        u = cadd(cmul({-si.r, si.i}, u), {cs[i] * h1.r, cs[i] * h1.i});
+    }
+    if (t == 255) gs.ulast = cadd(cmul(gs.A[cur][255], u0), gs.B[cur][255]);
+    __syncthreads();
+    for (int i = t; i < j; i += 256) col[i] = tmp[i];
+    __syncthreads();
+    if (t != 0) return 0.0;
+    // new rotation zeroing h_{j+1,j} = hn (real, >= 0) against u_j
+    const double ar = gs.ulast.r, ai = gs.ulast.i;
+    const double aa = sqrt(ar * ar + ai * ai);
+    double c, sr, si, rr, ri;
+    if (aa == 0.0) {
+        c = 0.0; sr = 1.0; si = 0.0; rr = hn; ri = 0.0;
+    } else {
+        const double den = sqrt(aa * aa + hn * hn);
+        c = aa / den;
+        sr = (ar / aa) * hn / den;
+        si = (ai / aa) * hn / den;
+        rr = (ar / aa) * den;
+        ri = (ai / aa) * den;
+    }
+    cs[j] = c;
+    sn[j] = {sr, si};
+    col[j] = {rr, ri};
+    col[j + 1] = {0.0, 0.0};
+    const double gr = g[2 * j], gi = g[2 * j + 1];
+    // g_{j+1} = -conj(s) g_j, g_j = c g_j
+    g[2 * (j + 1)] = -(sr * gr + si * gi);
+    g[2 * (j + 1) + 1] = -(sr * gi - si * gr);
+    g[2 * j] = c * gr;
+    g[2 * j + 1] = c * gi;
+    return sqrt(g[2 * (j + 1)] * g[2 * (j + 1)] + g[2 * (j + 1) + 1] * g[2 * (j + 1) + 1]);
+}
+
+// ||w||, v_{j+1} = w / ||w||, then the Givens update of column j of H.
+//
+// Applying the earlier rotations G_i = [[c_i, s_i], [-conj(s_i), c_i]] to the
+// new column h is a first-order recurrence in the running entry u:
+//     r_i = c_i u_i + s_i h_{i+1},   u_{i+1} = a_i u_i + b_i,
+//     a_i = -conj(s_i),  b_i = c_i h_{i+1},  u_0 = h_0,
+// so the workgroup evaluates it with a parallel scan of the affine maps
+// u -> a u + b (each thread composes a contiguous chunk, a Hillis-Steele
+// scan combines the 256 chunk maps, then each thread replays its chunk).
 __global__ __launch_bounds__(256)
 void k_arnoldi_finalize(const Job *__restrict__ jobs, SlotsDev sl, int P, StepStatus *__restrict__ st) {
     __shared__ double sh[4];
-    __shared__ cpx scanA[2][256], scanB[2][256];
-    __shared__ cpx ulast;
+    __shared__ GivensShared gsh;
     const int q = blockIdx.x, t = threadIdx.x;
     const Job jb = jobs[q];
     if (jb.type != JOB_ARNOLDI) return;
@@ -235,76 +320,241 @@ void k_arnoldi_finalize(const Job *__restrict__ jobs, SlotsDev sl, int P, StepSt
         w[mu] = make_double2(a.x * sc, a.y * sc);
     }
     cpx *col = reinterpret_cast<cpx *>(sl.H + jb.slot * sl.hstride + 2 * hoff(j));
-    const double *cs = sl.cs + (int64_t)jb.slot * sl.m;
-    const cpx *sn = reinterpret_cast<const cpx *>(sl.sn + (int64_t)jb.slot * sl.m * 2);
-    cpx *tmp = reinterpret_cast<cpx *>(sl.hbuf + (int64_t)jb.slot * (sl.m + 1) * 2);
-    double *g = sl.g + (int64_t)jb.slot * (sl.m + 1) * 2;
+    if (t == 0) col[j + 1] = {hn, 0.0};
+    __syncthreads();
+    const double est = givens_column(col, j, hn, sl.cs + (int64_t)jb.slot * sl.m,
+                                     reinterpret_cast<cpx *>(sl.sn + (int64_t)jb.slot * sl.m * 2),
+                                     sl.g + (int64_t)jb.slot * (sl.m + 1) * 2,
+                                     reinterpret_cast<cpx *>(sl.hbuf + (int64_t)jb.slot * sl.hbstride), gsh);
+    if (t == 0) {
+        st[q].value = est;
+        st[q].hnext = hn;
+    }
+}
 
-    // chunk of rotations owned by this thread
-    const int chunk = (j + 255) / 256;
-    const int lo = min(j, t * chunk), hi = min(j, lo + chunk);
-    cpx A = {1.0, 0.0}, B = {0.0, 0.0};          // identity map
-    for (int i = lo; i < hi; ++i) {
-        const cpx a = {-sn[i].r, sn[i].i};        // -conj(s_i)
-        const cpx b = {cs[i] * col[i + 1].r, cs[i] * col[i + 1].i};
-        B = cadd(cmul(a, B), b);                  // (a, b) o (A, B)
-        A = cmul(a, A);
-    }
-    scanA[0][t] = A;
-    scanB[0][t] = B;
-    __syncthreads();
-    int cur = 0;
-    for (int o = 1; o < 256; o <<= 1) {
-        cpx nA = scanA[cur][t], nB = scanB[cur][t];
-        if (t >= o) {   // compose earlier prefix (t-o) first, then this element
-            const cpx pA = scanA[cur][t - o], pB = scanB[cur][t - o];
-            nB = cadd(cmul(nA, pB), nB);
-            nA = cmul(nA, pA);
+// ------------------------------------------------ delayed reorthogonalisation
+// One Arnoldi step with a single fused projection pass and a single fused
+// update pass over the basis (classical Gram-Schmidt whose second pass is
+// delayed by one step).  On entry V[j] holds the candidate v~_j (one pass of
+// Gram-Schmidt against V_j = [v_0..v_{j-1}], unit norm) and V[j+1] holds
+// z = A v~_j.  With s = V_j^H v~_j, rho^2 = |v~_j|^2 - |s|^2:
+//   v_j = (v~_j - V_j s) / rho                  (finishes v_j's second pass)
+//   column j-1 of H += beta~ s, h_{j,j-1} = beta~ rho   (beta~ = its provisional h_{j,j-1})
+//   w' = (z - V_{j+1} V_{j+1}^H z) / rho = A v_j - V_{j+1} c,
+//   c = [V_j^H z ; v_j^H z] / rho = [t / rho ; (v~_j^H z - s^H t) / rho^2]
+// because A V_j s lies in span(V_{j+1}) and so drops out of the projection.
+// Column j of H is set to c (exact up to the term H s / rho, of the size of
+// the loss of orthogonality), and h_{j+1,j} = |w'| provisionally.  Column j-1
+// is final after this step, so its Givens rotation (and the residual
+// estimate for dimension j) is formed now.
+//
+// hbuf per slot (complex entries): s at [0, j); t at [j, 2j), overwritten by
+// c_0..c_{j-1}; sigma at 2j, overwritten by c_j; tau at 2j+1, overwritten by
+// rho; scratch of the Givens scan from 2j+2 (j-1 entries): 3m+4 in all.
+
+// s_i = <v_i | v~_j>, t_i = <v_i | z> for i < j; for i = j: sigma = <v~_j|v~_j>,
+// tau = <v~_j|z>.  Each wavefront takes 4 consecutive i, so v~_j and z are
+// loaded once per 4 basis vectors.
+constexpr int DPW = 4;
+__global__ __launch_bounds__(256)
+void k_dcgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P) {
+    const int q = blockIdx.y, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const Job jb = jobs[q];
+    const int i0 = (blockIdx.x * 4 + wv) * DPW;
+    const int j = jb.j;
+    if (jb.type != JOB_ARNOLDI || i0 > j) return;
+    const int nv = min(DPW, j + 1 - i0);
+    const int64_t vlen = (int64_t)sl.P_pad * 2;
+    const double *V = sl.V + jb.slot * sl.vstride;
+    const double2 *vi = reinterpret_cast<const double2 *>(V + (int64_t)i0 * vlen);
+    const double2 *vt = reinterpret_cast<const double2 *>(V + (int64_t)j * vlen);
+    const double2 *z = reinterpret_cast<const double2 *>(V + (int64_t)(j + 1) * vlen);
+    const int64_t vst = vlen / 2;
+    double sr[DPW], si[DPW], tr[DPW], ti[DPW];
+#pragma unroll
+    for (int k = 0; k < DPW; ++k) sr[k] = si[k] = tr[k] = ti[k] = 0.0;
+    for (int mu = lane; mu < P; mu += 64) {
+        const double2 b = vt[mu], c = z[mu];
+#pragma unroll
+        for (int k = 0; k < DPW; ++k) {
+            if (k < nv) {
+                const double2 a = vi[(int64_t)k * vst + mu];
+                sr[k] += a.x * b.x + a.y * b.y;
+                si[k] += a.x * b.y - a.y * b.x;
+                tr[k] += a.x * c.x + a.y * c.y;
+                ti[k] += a.x * c.y - a.y * c.x;
+            }
         }
-        scanA[cur ^ 1][t] = nA;
-        scanB[cur ^ 1][t] = nB;
-        cur ^= 1;
+    }
+#pragma unroll
+    for (int k = 0; k < DPW; ++k) {
+        if (k >= nv) break;
+        const double a0 = wave_sum(sr[k]), a1 = wave_sum(si[k]), a2 = wave_sum(tr[k]), a3 = wave_sum(ti[k]);
+        if (lane == 0) {
+            const int i = i0 + k;
+            double *h = sl.hbuf + (int64_t)jb.slot * sl.hbstride;
+            if (i < j) {
+                h[2 * i] = a0; h[2 * i + 1] = a1;               // s_i
+                h[2 * (j + i)] = a2; h[2 * (j + i) + 1] = a3;   // t_i
+            } else {
+                h[4 * j] = a0; h[4 * j + 1] = 0.0;              // sigma at 2j
+                h[4 * j + 2] = a2; h[4 * j + 3] = a3;           // tau at 2j+1
+            }
+        }
+    }
+}
+
+// rho, correction and Givens of column j-1, coefficients c and provisional column j.
+__global__ __launch_bounds__(256)
+void k_dcgs_coef(const Job *__restrict__ jobs, SlotsDev sl, StepStatus *__restrict__ st) {
+    __shared__ double sh[4];
+    __shared__ GivensShared gsh;
+    const int q = blockIdx.x, t = threadIdx.x;
+    const Job jb = jobs[q];
+    if (jb.type != JOB_ARNOLDI) return;
+    const int j = jb.j;
+    cpx *h = reinterpret_cast<cpx *>(sl.hbuf + (int64_t)jb.slot * sl.hbstride);
+    // |s|^2 and s^H t
+    double a2 = 0.0, str = 0.0, sti = 0.0;
+    for (int i = t; i < j; i += 256) {
+        const cpx sv = h[i], tv = h[j + i];
+        a2 += sv.r * sv.r + sv.i * sv.i;
+        str += sv.r * tv.r + sv.i * tv.i;
+        sti += sv.r * tv.i - sv.i * tv.r;
+    }
+    a2 = block_sum(a2, sh);
+    str = block_sum(str, sh);
+    sti = block_sum(sti, sh);
+    const double sigma = h[2 * j].r;
+    const cpx tau = h[2 * j + 1];
+    const double r2 = sigma - a2;
+    const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+    const double ir = rho > 0.0 ? 1.0 / rho : 0.0;
+    double *g = sl.g + (int64_t)jb.slot * (sl.m + 1) * 2;
+    double est = sqrt(g[0] * g[0] + g[1] * g[1]);
+    if (j >= 1) {
+        cpx *colp = reinterpret_cast<cpx *>(sl.H + jb.slot * sl.hstride + 2 * hoff(j - 1));
+        const double bt = colp[j].r;                  // provisional h_{j,j-1}
+        for (int i = t; i < j; i += 256) colp[i] = cadd(colp[i], {bt * h[i].r, bt * h[i].i});
         __syncthreads();
+        if (t == 0) colp[j] = {bt * rho, 0.0};
+        __syncthreads();
+        // scratch for the scan: entries beyond 2j+1 of hbuf
+        est = givens_column(colp, j - 1, bt * rho, sl.cs + (int64_t)jb.slot * sl.m,
+                            reinterpret_cast<cpx *>(sl.sn + (int64_t)jb.slot * sl.m * 2), g, h + 2 * j + 2, gsh);
     }
-    const cpx u0 = col[0];
-    cpx u = u0;
-    if (t > 0) u = cadd(cmul(scanA[cur][t - 1], u0), scanB[cur][t - 1]);
-    for (int i = lo; i < hi; ++i) {
-        const cpx si = sn[i], h1 = col[i + 1];
-        tmp[i] = cadd({cs[i] * u.r, cs[i] * u.i}, cmul(si, h1));
-        u = cadd(cmul({-si.r, si.i}, u), {cs[i] * h1.r, cs[i] * h1.i});
-    }
-    if (t == 255) ulast = cadd(cmul(scanA[cur][255], u0), scanB[cur][255]);
+    // c_i = t_i / rho (i < j), c_j = (tau - s^H t) / rho^2 ; stored over t, rho after it
     __syncthreads();
-    for (int i = t; i < j; i += 256) col[i] = tmp[i];
-    if (t != 0) return;
-    // new rotation zeroing h_{j+1,j} = hn (real, >= 0) against u_j
-    const double ar = ulast.r, ai = ulast.i;
-    const double aa = sqrt(ar * ar + ai * ai);
-    double c, sr, si, rr, ri;
-    if (aa == 0.0) {
-        c = 0.0; sr = 1.0; si = 0.0; rr = hn; ri = 0.0;
-    } else {
-        const double den = sqrt(aa * aa + hn * hn);
-        c = aa / den;
-        sr = (ar / aa) * hn / den;
-        si = (ai / aa) * hn / den;
-        rr = (ar / aa) * den;
-        ri = (ai / aa) * den;
+    cpx *colj = reinterpret_cast<cpx *>(sl.H + jb.slot * sl.hstride + 2 * hoff(j));
+    for (int i = t; i < j; i += 256) {
+        const cpx c = {h[j + i].r * ir, h[j + i].i * ir};
+        h[j + i] = c;
+        colj[i] = c;
     }
-    sl.cs[(int64_t)jb.slot * sl.m + j] = c;
-    sl.sn[((int64_t)jb.slot * sl.m + j) * 2] = sr;
-    sl.sn[((int64_t)jb.slot * sl.m + j) * 2 + 1] = si;
-    col[j] = {rr, ri};
-    col[j + 1] = {0.0, 0.0};
-    const double gr = g[2 * j], gi = g[2 * j + 1];
-    // g_{j+1} = -conj(s) g_j, g_j = c g_j
-    g[2 * (j + 1)] = -(sr * gr + si * gi);
-    g[2 * (j + 1) + 1] = -(sr * gi - si * gr);
-    g[2 * j] = c * gr;
-    g[2 * j + 1] = c * gi;
-    st[q].value = sqrt(g[2 * (j + 1)] * g[2 * (j + 1)] + g[2 * (j + 1) + 1] * g[2 * (j + 1) + 1]);
-    st[q].hnext = hn;
+    if (t == 0) {
+        const cpx cj = {(tau.r - str) * ir * ir, (tau.i - sti) * ir * ir};
+        h[2 * j] = cj;
+        colj[j] = cj;
+        h[2 * j + 1] = {rho, 0.0};
+        st[q].value = est;
+    }
+}
+
+// v_j = (v~_j - V_j s) / rho and w' = z / rho - V_j c_top - v_j c_j in one pass.
+// The coefficients are staged through LDS in chunks (s and c of up to 4000
+// vectors do not fit at once).
+constexpr int DCH = 512;
+__global__ __launch_bounds__(256)
+void k_dcgs_update(const Job *__restrict__ jobs, SlotsDev sl, int P) {
+    __shared__ cpx shs[DCH], shc[DCH];
+    const int q = blockIdx.y, t = threadIdx.x;
+    const Job jb = jobs[q];
+    if (jb.type != JOB_ARNOLDI) return;
+    const int mu = blockIdx.x * 256 + t;
+    const bool act = mu < P;
+    const int j = jb.j;
+    const cpx *h = reinterpret_cast<const cpx *>(sl.hbuf + (int64_t)jb.slot * sl.hbstride);
+    const int64_t vlen = (int64_t)sl.P_pad * 2;
+    double *V = sl.V + jb.slot * sl.vstride;
+    const double2 *vb = reinterpret_cast<const double2 *>(V) + (act ? mu : 0);
+    const int64_t vst = vlen / 2;   // double2 stride between basis vectors
+    double2 as = make_double2(0.0, 0.0), ac = make_double2(0.0, 0.0);
+    for (int i0 = 0; i0 < j; i0 += DCH) {
+        const int n = min(DCH, j - i0);
+        __syncthreads();
+        for (int k = t; k < n; k += 256) {
+            shs[k] = h[i0 + k];
+            shc[k] = h[j + i0 + k];
+        }
+        __syncthreads();
+        if (act) {
+            const double2 *vp = vb + (int64_t)i0 * vst;
+#pragma unroll 4
+            for (int k = 0; k < n; ++k) {
+                const double2 v = vp[(int64_t)k * vst];
+                const cpx sv = shs[k], cv = shc[k];
+                as.x += v.x * sv.r - v.y * sv.i;
+                as.y += v.x * sv.i + v.y * sv.r;
+                ac.x += v.x * cv.r - v.y * cv.i;
+                ac.y += v.x * cv.i + v.y * cv.r;
+            }
+        }
+    }
+    if (!act) return;
+    const double rho = h[2 * j + 1].r, ir = rho > 0.0 ? 1.0 / rho : 0.0;
+    const cpx cj = h[2 * j];
+    double2 *pv = reinterpret_cast<double2 *>(V + (int64_t)j * vlen) + mu;
+    double2 *pz = reinterpret_cast<double2 *>(V + (int64_t)(j + 1) * vlen) + mu;
+    const double2 vt = *pv, z = *pz;
+    const double2 v = make_double2((vt.x - as.x) * ir, (vt.y - as.y) * ir);
+    *pv = v;
+    *pz = make_double2(z.x * ir - ac.x - (v.x * cj.r - v.y * cj.i),
+                       z.y * ir - ac.y - (v.x * cj.i + v.y * cj.r));
+}
+
+// beta~ = |w'|, v~_{j+1} = w' / beta~, provisional h_{j+1,j} = beta~.
+__global__ __launch_bounds__(256)
+void k_dcgs_norm(const Job *__restrict__ jobs, SlotsDev sl, int P, StepStatus *__restrict__ st) {
+    __shared__ double sh[4];
+    const int q = blockIdx.x, t = threadIdx.x;
+    const Job jb = jobs[q];
+    if (jb.type != JOB_ARNOLDI) return;
+    const int j = jb.j;
+    const int64_t vlen = (int64_t)sl.P_pad * 2;
+    double2 *w = reinterpret_cast<double2 *>(sl.V + jb.slot * sl.vstride + (int64_t)(j + 1) * vlen);
+    double ss = 0.0;
+    for (int mu = t; mu < P; mu += 256) {
+        const double2 a = w[mu];
+        ss += a.x * a.x + a.y * a.y;
+    }
+    const double hn = sqrt(block_sum(ss, sh));
+    const double sc = hn > 0.0 ? 1.0 / hn : 0.0;
+    for (int mu = t; mu < P; mu += 256) {
+        const double2 a = w[mu];
+        w[mu] = make_double2(a.x * sc, a.y * sc);
+    }
+    if (t == 0) {
+        cpx *colj = reinterpret_cast<cpx *>(sl.H + jb.slot * sl.hstride + 2 * hoff(j));
+        colj[j + 1] = {hn, 0.0};
+        st[q].hnext = hn;
+    }
+}
+
+void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, const SlotsDev &sl, int P,
+                 StepStatus *status, int n_arnoldi, double sum_j1) {
+    const dim3 gd((jmax + 1 + 4 * DPW - 1) / (4 * DPW), nb), gu((P + 255) / 256, nb);
+    trace_begin(t, "dcgs_dots", s);
+    hipLaunchKernelGGL(k_dcgs_dots, gd, dim3(256), 0, s, jobs, sl, P);
+    trace_end(t, s, 16.0 * P * sum_j1, 16.0 * P * (sum_j1 + 2.0 * n_arnoldi));
+    trace_begin(t, "dcgs_coef", s);
+    hipLaunchKernelGGL(k_dcgs_coef, dim3(nb), dim3(256), 0, s, jobs, sl, status);
+    trace_end(t, s, 0.0, 16.0 * 4.0 * sum_j1);
+    trace_begin(t, "dcgs_update", s);
+    hipLaunchKernelGGL(k_dcgs_update, gu, dim3(256), 0, s, jobs, sl, P);
+    trace_end(t, s, 16.0 * P * sum_j1, 16.0 * P * (sum_j1 + 3.0 * n_arnoldi));
+    trace_begin(t, "dcgs_norm", s);
+    hipLaunchKernelGGL(k_dcgs_norm, dim3(nb), dim3(256), 0, s, jobs, sl, P, status);
+    trace_end(t, s, 4.0 * P * n_arnoldi, 16.0 * P * 2.0 * n_arnoldi);
 }
 
 void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
