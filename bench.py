@@ -117,7 +117,19 @@ def main():
                     help="learned warm start fitted on this many seeded training frequencies (0 = off)")
     ap.add_argument("--cpu-sample", type=int, default=2, help="frequencies for the oracle baseline (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 3 device copies of MIB MiB (reference for HBM traffic counters)")
     a = ap.parse_args()
+    if a.calibrate_copy:
+        import torch
+        n = a.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 3}))
+        return
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
               "(the (frequency, drive) points would be sharded across GPUs with no exchange "
@@ -207,6 +219,8 @@ def main():
         roof = {"kernel": dom, "bound": "hbm" if bound == "hbm" else "mfma", "dtype": bound,
                 "achieved": achieved / scale, "peak": peak / scale,
                 "unit": unit, "frac": achieved / peak, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+                "traffic_over_algorithmic": (traffic / (work / rec["launches"])) if traffic else None,
                 "launches": rec["launches"] // a.steps, "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
                 "share_of_gpu_time": rec["ms"] / sum(v["ms"] for v in ks.values())}
         chi0_ms = sum(ks[k]["ms"] for k in CHI0_KERNELS if k in ks)
