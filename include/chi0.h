@@ -273,6 +273,14 @@ typedef struct chi0_kernel_record {
 int chi0_set_timing(chi0_ctx *ctx, int32_t enable);
 int chi0_kernel_stats(chi0_ctx *ctx, chi0_kernel_record *records, int32_t cap);
 
+/* Restrict timing to the kernels named in `names` (comma-separated record
+ * names as reported by chi0_kernel_stats, e.g. "dcgs_update,dcgs_dots");
+ * NULL or "" times every kernel.  Each timed launch adds two HIP events on
+ * the stream, so timing only the kernels of interest keeps the overhead of
+ * the events out of a measured run.  Resets the records; returns CHI0_OK,
+ * or CHI0_EINVAL for a NULL context.  Valid on host-only contexts. */
+int chi0_set_timing_filter(chi0_ctx *ctx, const char *names);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,6 +99,8 @@ def lib():
     L.chi0_solve_response.restype = C.c_int
     L.chi0_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.chi0_set_timing.restype = C.c_int
+    L.chi0_set_timing_filter.argtypes = [C.c_void_p, C.c_char_p]
+    L.chi0_set_timing_filter.restype = C.c_int
     L.chi0_kernel_stats.argtypes = [C.c_void_p, C.POINTER(KernelRecord), C.c_int32]
     L.chi0_kernel_stats.restype = C.c_int
     L.chi0_ws_cfg_default.argtypes = [C.POINTER(WsCfg)]
@@ -271,7 +273,10 @@ class Context:
         return alpha[..., 0] + 1j * alpha[..., 1], stats, rc
 
     # --------------------------------------------------------------- tracing
-    def set_timing(self, enable: bool):
+    def set_timing(self, enable: bool, only=None):
+        """Enable per-kernel HIP-event timing; `only` restricts it to the named kernels."""
+        names = ",".join(only).encode() if only else None
+        self._check(self._L.chi0_set_timing_filter(self._h, names))
         self._check(self._L.chi0_set_timing(self._h, 1 if enable else 0))
 
     def kernel_stats(self) -> dict:

@@ -30,8 +30,16 @@ struct chi0::Tracer {
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
     std::map<std::string, Rec> recs;
+    std::vector<std::string> only;   // kernels to time; empty = all
     const char *cur_name = nullptr;
     hipEvent_t cur_a = nullptr;
+
+    bool wanted(const char *name) const {
+        if (only.empty()) return true;
+        for (const auto &n : only)
+            if (n == name) return true;
+        return false;
+    }
 
     hipEvent_t get() {
         if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -66,6 +74,10 @@ struct chi0::Tracer {
 
 void chi0::trace_begin(Tracer *t, const char *name, hipStream_t s) {
     if (!t || !t->on) return;
+    if (!t->wanted(name)) {
+        t->cur_a = nullptr;
+        return;
+    }
     t->cur_name = name;
     t->cur_a = t->get();
     if (t->cur_a) (void)hipEventRecord(t->cur_a, s);
@@ -126,12 +138,21 @@ struct chi0_ctx {
     DevBuf slotbuf;
     int slot_n = 0, slot_m = 0;
     SlotsDev slots{};
-    Job *jobs_dev = nullptr, *fin_dev = nullptr, *upd_dev = nullptr;
+    // Two sets of step buffers (the solver keeps two steps in flight).  Set q
+    // of the job arena holds [Job x slot_n][double omega x slot_n], so one copy
+    // moves a step's jobs and frequencies; fin/upd/status are [2][slot_n].
+    char *arena_dev = nullptr, *arena_h = nullptr;
+    Job *fin_dev = nullptr, *upd_dev = nullptr;
     StepStatus *status_dev = nullptr;
-    Job *jobs_h = nullptr, *fin_h = nullptr, *upd_h = nullptr;
+    Job *fin_h = nullptr, *upd_h = nullptr;
     StepStatus *status_h = nullptr;
-    double *omega_h = nullptr;
     int host_cap = 0;
+    hipEvent_t step_ev[2] = {nullptr, nullptr};
+    size_t arena_bytes() const { return (size_t)slot_n * (sizeof(Job) + sizeof(double)); }
+    Job *jobs_dev(int q) { return reinterpret_cast<Job *>(arena_dev + q * arena_bytes()); }
+    double *somega_dev(int q) { return reinterpret_cast<double *>(arena_dev + q * arena_bytes() + slot_n * sizeof(Job)); }
+    Job *jobs_h(int q) { return reinterpret_cast<Job *>(arena_h + q * arena_bytes()); }
+    double *omega_h(int q) { return reinterpret_cast<double *>(arena_h + q * arena_bytes() + slot_n * sizeof(Job)); }
 
     ~chi0_ctx() {
         if (device >= 0) {
@@ -142,11 +163,12 @@ struct chi0_ctx {
         lpbuf.release();
         wsbuf.release();
         sysbuf.release();
-        if (jobs_h) (void)hipHostFree(jobs_h);
+        if (arena_h) (void)hipHostFree(arena_h);
         if (fin_h) (void)hipHostFree(fin_h);
         if (upd_h) (void)hipHostFree(upd_h);
         if (status_h) (void)hipHostFree(status_h);
-        if (omega_h) (void)hipHostFree(omega_h);
+        for (hipEvent_t &e : step_ev)
+            if (e) (void)hipEventDestroy(e);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -248,6 +270,26 @@ extern "C" int chi0_set_timing(chi0_ctx *ctx, int32_t enable) {
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
     ctx->tracer.clear();
     ctx->tracer.on = enable != 0;
+    return CHI0_OK;
+}
+
+extern "C" int chi0_set_timing_filter(chi0_ctx *ctx, const char *names) {
+    if (!ctx) return CHI0_EINVAL;
+    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+    ctx->tracer.clear();
+    ctx->tracer.only.clear();
+    if (names) {
+        std::string cur;
+        for (const char *p = names;; ++p) {
+            if (*p == ',' || *p == '\0') {
+                if (!cur.empty()) ctx->tracer.only.push_back(cur);
+                cur.clear();
+                if (*p == '\0') break;
+            } else if (*p != ' ') {
+                cur.push_back(*p);
+            }
+        }
+    }
     return CHI0_OK;
 }
 
@@ -692,27 +734,30 @@ static int ensure_slots(chi0_ctx *c, int n, int m) {
     CHK(dalloc(c, b, &sl.b, (int64_t)n * c->P_pad * 2));
     CHK(dalloc(c, b, &sl.hbuf, (int64_t)n * sl.hbstride));
     CHK(dalloc(c, b, &sl.y, (int64_t)n * m * 2));
-    CHK(dalloc(c, b, &c->jobs_dev, n));
-    CHK(dalloc(c, b, &c->fin_dev, n));
-    CHK(dalloc(c, b, &c->upd_dev, n));
-    CHK(dalloc(c, b, &c->status_dev, n));
-    if (c->host_cap < n) {
-        if (c->jobs_h) (void)hipHostFree(c->jobs_h);
+    const int64_t ab = (int64_t)n * (sizeof(Job) + sizeof(double));
+    double *arena = nullptr;
+    CHK(dalloc(c, b, &arena, 2 * ab / 8));
+    c->arena_dev = reinterpret_cast<char *>(arena);
+    CHK(dalloc(c, b, &c->fin_dev, 2 * n));
+    CHK(dalloc(c, b, &c->upd_dev, 2 * n));
+    CHK(dalloc(c, b, &c->status_dev, 2 * n));
+    if (c->host_cap != n) {   // the host arena's layout depends on n
+        if (c->arena_h) (void)hipHostFree(c->arena_h);
         if (c->fin_h) (void)hipHostFree(c->fin_h);
         if (c->upd_h) (void)hipHostFree(c->upd_h);
         if (c->status_h) (void)hipHostFree(c->status_h);
-        if (c->omega_h) (void)hipHostFree(c->omega_h);
-        c->jobs_h = c->fin_h = c->upd_h = nullptr;
+        c->arena_h = nullptr;
+        c->fin_h = c->upd_h = nullptr;
         c->status_h = nullptr;
-        c->omega_h = nullptr;
         c->host_cap = 0;
-        HIPCHK(c, hipHostMalloc((void **)&c->jobs_h, sizeof(Job) * n, hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc((void **)&c->fin_h, sizeof(Job) * n, hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc((void **)&c->upd_h, sizeof(Job) * n, hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc((void **)&c->status_h, sizeof(StepStatus) * n, hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc((void **)&c->omega_h, sizeof(double) * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->arena_h, 2 * ab, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->fin_h, sizeof(Job) * 2 * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->upd_h, sizeof(Job) * 2 * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->status_h, sizeof(StepStatus) * 2 * n, hipHostMallocDefault));
         c->host_cap = n;
     }
+    for (hipEvent_t &e : c->step_ev)
+        if (!e) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(c, hipDeviceSynchronize());
     c->slot_n = n;
     c->slot_m = m;
@@ -724,7 +769,10 @@ enum { S_FREE = 0, S_RHS, S_ARNOLDI, S_RESID };
 struct SlotState {
     int state = S_FREE;
     int point = -1;
-    int j = 0;
+    int j = 0;                   // next Arnoldi index to launch in the current cycle
+    int pend = 0;                // launched Arnoldi steps of this cycle not yet seen by the host
+    int epoch = 0;               // bumped when a cycle ends: steps launched before are void
+    bool busy = false;           // a b or residual job of this slot is in flight
     int prec = CHI0_PREC_FP64;   // arithmetic of this slot's Arnoldi steps
     bool warm_check = false;     // the pending residual job checks a warm start
     double bnorm = 0.0;          // ||b|| = ||chi0 d||
@@ -850,7 +898,15 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
 
     // per-call device buffers: drives and alpha
     DevBuf callbuf;
-    struct Guard { DevBuf *b; ~Guard() { b->release(); } } guard{&callbuf};
+    // on every exit (also an error with steps in flight) drain the stream first
+    struct Guard {
+        DevBuf *b;
+        hipStream_t s;
+        ~Guard() {
+            (void)hipStreamSynchronize(s);
+            b->release();
+        }
+    } guard{&callbuf, c->stream};
     double *drives = nullptr, *alpha_dev = nullptr;
     CHK(dalloc(c, callbuf, &drives, (int64_t)n_drive * c->P_pad));
     CHK(dalloc(c, callbuf, &alpha_dev, (int64_t)npts * n_drive * 2));
@@ -864,91 +920,66 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     std::vector<Job> fin, upd, rst, wnew;
     std::vector<double> wom;
 
-    while (done < npts) {
-        // (0) zero start for rejected warm starts (and x = 0 for points with b = 0)
-        if (!rst.empty()) {
-            std::copy(rst.begin(), rst.end(), c->upd_h);
-            HIPCHK(c, hipMemcpyAsync(c->upd_dev, c->upd_h, sizeof(Job) * rst.size(), hipMemcpyHostToDevice, s));
-            launch_reset_slots(s, c->upd_dev, (int)rst.size(), c->slots, P);
-            HIPCHK(c, hipStreamSynchronize(s));   // upd_h is reused below
-            rst.clear();
-        }
-        // (1) polarizability (and stored solution) of points that finished last step,
-        //     before their slot is reused
-        if (!fin.empty()) {
-            std::copy(fin.begin(), fin.end(), c->fin_h);
-            HIPCHK(c, hipMemcpyAsync(c->fin_dev, c->fin_h, sizeof(Job) * fin.size(), hipMemcpyHostToDevice, s));
-            launch_alpha(t, s, c->fin_dev, (int)fin.size(), c->slots, drives, n_drive, c->P_pad, P,
-                         nullptr, alpha_dev);
-            if (x_out) launch_store_x(s, c->fin_dev, (int)fin.size(), c->slots, P, x_out);
-            fin.clear();
-        }
-        // (2) x += V y for slots that ended a cycle
-        if (!upd.empty()) {
-            int jm = 0;
-            for (auto &u : upd) jm = std::max(jm, u.j);
-            std::copy(upd.begin(), upd.end(), c->upd_h);
-            HIPCHK(c, hipMemcpyAsync(c->upd_dev, c->upd_h, sizeof(Job) * upd.size(), hipMemcpyHostToDevice, s));
-            double sumL = 0.0;
-            for (auto &u : upd) sumL += u.j;
-            launch_update_x(t, s, c->upd_dev, (int)upd.size(), jm, c->slots, P, sumL);
-            upd.clear();
-        }
-        // (3) refill free slots; warm-started points get x0 = U c(omega) now
-        wnew.clear();
-        wom.clear();
-        for (int k = 0; k < nsl; ++k)
-            if (sl[k].state == S_FREE && next_point < npts) {
-                sl[k].state = S_RHS;
-                sl[k].point = next_point++;
-                sl[k].j = 0;
-                sl[k].warm_check = false;
-                if (ws) {
-                    wnew.push_back({k, 0, sl[k].point, 0});
-                    wom.push_back(omega[sl[k].point / n_drive]);
-                }
-            }
-        if (!wnew.empty()) {
-            HIPCHK(c, hipStreamSynchronize(s));   // fin_h / upd_h copies done; reuse fin_h
-            std::copy(wnew.begin(), wnew.end(), c->fin_h);
-            HIPCHK(c, hipMemcpyAsync(ws->jobs_dev, c->fin_h, sizeof(Job) * wnew.size(), hipMemcpyHostToDevice, s));
-            CHK(ws_infer(ws, s, (int)wnew.size(), wom.data()));
-            launch_ws_apply(s, ws->jobs_dev, (int)wnew.size(), ws->out, ws->O, ws->mean, ws->sdev, ws->r, ws->U,
-                            (int64_t)c->P_pad * 2, c->slots.x, (int64_t)c->P_pad * 2, P);
-            HIPCHK(c, hipStreamSynchronize(s));
-        }
-        // (4) one job per active slot: FP64 jobs first (b, true residual, FP64
-        //     Arnoldi), then the low-precision Arnoldi steps, so each group is a
-        //     contiguous range processed by one operator pass
+    // Two steps are kept in flight.  While the GPU runs step s+1 the host reads
+    // the status of step s and decides what step s+2 does.  A slot in its
+    // Arnoldi phase is launched again before the host has seen its previous
+    // step; if that previous step ends the cycle, the extra step is void (its
+    // epoch no longer matches).  It only wrote basis vectors, Hessenberg
+    // columns and rotations beyond the cycle's length L, which the update of x
+    // never reads.  b and residual jobs are never launched ahead.
+    struct InFlight {
+        int nb = 0;
+        std::vector<int> epoch;
+    } fl[2];
+    int q_launch = 0, n_inflight = 0, q_oldest = 0;
+
+    auto plan_and_launch = [&](int q) -> int {
+        Job *jobs_h = c->jobs_h(q);
+        double *om_h = c->omega_h(q);
+        InFlight &f = fl[q];
+        f.epoch.clear();
         int nb = 0, nb64 = 0, jmax = -1, n_arn = 0;
         double sum_j1 = 0.0;
+        // FP64 jobs first (b, true residual, FP64 Arnoldi), then the
+        // low-precision Arnoldi steps: each group is one operator pass
         for (int pass = 0; pass < 2; ++pass)
             for (int k = 0; k < nsl; ++k) {
-                if (sl[k].state == S_FREE) continue;
-                const bool lowp = sl[k].state == S_ARNOLDI && sl[k].prec != CHI0_PREC_FP64;
+                SlotState &ss = sl[k];
+                if (ss.state == S_FREE || ss.busy) continue;
+                const bool lowp = ss.state == S_ARNOLDI && ss.prec != CHI0_PREC_FP64;
                 if (lowp != (pass == 1)) continue;
                 Job jb;
                 jb.slot = k;
-                jb.type = sl[k].state == S_RHS ? JOB_RHS : sl[k].state == S_ARNOLDI ? JOB_ARNOLDI : JOB_RESID;
-                jb.j = jb.type == JOB_RHS ? (ws ? 1 : 0) : sl[k].j;
-                jb.drive = sl[k].point % n_drive;
-                if (jb.type == JOB_ARNOLDI) {
+                jb.drive = ss.point % n_drive;
+                if (ss.state == S_ARNOLDI) {
+                    if (ss.j >= m || ps[ss.point].iters + ss.pend >= o.max_iter) continue;
+                    jb.type = JOB_ARNOLDI;
+                    jb.j = ss.j++;
+                    ss.pend += 1;
                     jmax = std::max(jmax, jb.j);
                     ++n_arn;
                     sum_j1 += jb.j + 1;
+                } else {
+                    jb.type = ss.state == S_RHS ? JOB_RHS : JOB_RESID;
+                    jb.j = jb.type == JOB_RHS ? (ws ? 1 : 0) : 0;
+                    ss.busy = true;
                 }
-                c->jobs_h[nb] = jb;
-                c->omega_h[nb] = omega[sl[k].point / n_drive];
+                jobs_h[nb] = jb;
+                om_h[nb] = omega[ss.point / n_drive];
+                f.epoch.push_back(ss.epoch);
                 ++nb;
                 if (pass == 0) ++nb64;
             }
-        if (nb == 0) break;
-        HIPCHK(c, hipMemcpyAsync(c->jobs_dev, c->jobs_h, sizeof(Job) * nb, hipMemcpyHostToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(c->omega_dev, c->omega_h, sizeof(double) * nb, hipMemcpyHostToDevice, s));
-        // (5) operator per group: Zin = K v (b jobs: d), Y = chi0 Zin, then post
+        f.nb = nb;
+        if (nb == 0) return CHI0_OK;
+        Job *jobs_d = c->jobs_dev(q);
+        double *om_d = c->somega_dev(q);
+        HIPCHK(c, hipMemcpyAsync(c->jobs_dev(q), jobs_h, c->slot_n * sizeof(Job) + nb * sizeof(double),
+                                 hipMemcpyHostToDevice, s));
+        // operator per group: Zin = K v (b jobs: d), Y = chi0 Zin, then post
         auto run_group = [&](int g0, int gn, int prec) {
             const int nc = 2 * gn;
-            const Job *jg = c->jobs_dev + g0;
+            const Job *jg = jobs_d + g0;
             launch_gather_jobs(t, s, jg, gn, c->slots, c->Vb, nc, P);
             if (nc <= 16)
                 launch_kmatvec_skinny(t, s, c->P_pad, c->K, c->Vb, c->Zin, nc, (double)P);
@@ -957,26 +988,57 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                              nc, 2.0 * P * (double)P * nc, 8.0 * ((double)P * P + 2.0 * P * nc),
                              c->gemm_scratch, c->gemm_scratch_n);
             launch_put_drive(t, s, jg, gn, drives, c->P_pad, c->Zin, nc, P);
-            run_chi0(c, s, gn, eps, prec, c->omega_dev + g0);
-            launch_post_jobs(t, s, jg, gn, c->slots, c->Yout, nc, P, c->status_dev + g0);
+            run_chi0(c, s, gn, eps, prec, om_d + g0);
+            launch_post_jobs(t, s, jg, gn, c->slots, c->Yout, nc, P, c->status_dev + q * nsl + g0);
         };
         if (nb64 > 0) run_group(0, nb64, CHI0_PREC_FP64);
         if (nb > nb64) run_group(nb64, nb - nb64, o.precision);
         if (n_arn > 0) {
             if (dcgs)
-                launch_dcgs(t, s, c->jobs_dev, nb, jmax, c->slots, P, c->status_dev, n_arn, sum_j1);
+                launch_dcgs(t, s, jobs_d, nb, jmax, c->slots, P, c->status_dev + q * nsl, n_arn, sum_j1);
             else
-                launch_arnoldi(t, s, c->jobs_dev, nb, jmax, c->slots, P, c->status_dev, n_arn, sum_j1);
+                launch_arnoldi(t, s, jobs_d, nb, jmax, c->slots, P, c->status_dev + q * nsl, n_arn, sum_j1);
         }
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipMemcpyAsync(c->status_h, c->status_dev, sizeof(StepStatus) * nb, hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        // (6) advance the slot state machines
-        for (int q = 0; q < nb; ++q) {
-            const Job &jb = c->jobs_h[q];
+        HIPCHK(c, hipMemcpyAsync(c->status_h + q * nsl, c->status_dev + q * nsl, sizeof(StepStatus) * nb,
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipEventRecord(c->step_ev[q], s));
+        return CHI0_OK;
+    };
+
+    // Advance the slot state machines with the status of the step in set q.
+    auto process = [&](int q) {
+        const InFlight &f = fl[q];
+        const Job *jobs_h = c->jobs_h(q);
+        const StepStatus *sts = c->status_h + q * nsl;
+        for (int r = 0; r < f.nb; ++r) {
+            const Job &jb = jobs_h[r];
             SlotState &ss = sl[jb.slot];
+            const StepStatus &st = sts[r];
+            if (jb.type == JOB_ARNOLDI) {
+                if (f.epoch[r] != ss.epoch || ss.state != S_ARNOLDI) continue;   // void step
+                PointState &pt = ps[ss.point];
+                ss.pend -= 1;
+                pt.iters += 1;
+                double stop = o.tol * ss.bnorm;
+                if (ss.prec != CHI0_PREC_FP64) stop = std::max(stop, inner_tol * ss.cycle0);
+                const bool brk = st.hnext == 0.0;
+                if (brk) pt.breakdown = 1;
+                // CGS2: the step completes column j (dimension j+1).  Delayed
+                // reorthogonalisation: it completes column j-1 (dimension j) and
+                // leaves column j provisional, so a cycle uses the first j columns.
+                const int L = dcgs ? jb.j : jb.j + 1;
+                const bool est_ok = L >= 1 && st.value <= stop;
+                if (est_ok || brk || jb.j + 1 >= m || pt.iters >= o.max_iter || !std::isfinite(st.value)) {
+                    if (L >= 1) upd.push_back({jb.slot, 0, L, 0});
+                    ss.state = S_RESID;
+                    ss.epoch += 1;
+                    ss.pend = 0;
+                }
+                continue;
+            }
             PointState &pt = ps[ss.point];
-            const StepStatus &st = c->status_h[q];
+            ss.busy = false;
             if (jb.type == JOB_RHS) {
                 ss.bnorm = st.value;
                 ss.cycle0 = st.value;
@@ -995,23 +1057,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 } else {
                     ss.state = S_ARNOLDI;
                     ss.j = 0;
-                }
-            } else if (jb.type == JOB_ARNOLDI) {
-                pt.iters += 1;
-                double stop = o.tol * ss.bnorm;
-                if (ss.prec != CHI0_PREC_FP64) stop = std::max(stop, inner_tol * ss.cycle0);
-                const bool brk = st.hnext == 0.0;
-                if (brk) pt.breakdown = 1;
-                // CGS2: the step completes column j (dimension j+1).  Delayed
-                // reorthogonalisation: it completes column j-1 (dimension j) and
-                // leaves column j provisional, so a cycle uses the first j columns.
-                const int L = dcgs ? ss.j : ss.j + 1;
-                const bool est_ok = L >= 1 && st.value <= stop;
-                if (est_ok || brk || ss.j + 1 >= m || pt.iters >= o.max_iter || !std::isfinite(st.value)) {
-                    if (L >= 1) upd.push_back({jb.slot, 0, L, 0});
-                    ss.state = S_RESID;
-                } else {
-                    ss.j += 1;
+                    ss.pend = 0;
                 }
             } else if (ss.warm_check) {
                 ss.warm_check = false;
@@ -1031,12 +1077,14 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                     ss.rel_prev = 1.0;
                     ss.state = S_ARNOLDI;
                     ss.j = 0;
+                    ss.pend = 0;
                 } else {
                     pt.warm = 1;
                     ss.cycle0 = st.value;
                     ss.rel_prev = rel0;
                     ss.state = S_ARNOLDI;
                     ss.j = 0;
+                    ss.pend = 0;
                 }
             } else {
                 pt.restarts += 1;
@@ -1057,24 +1105,98 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                     ss.cycle0 = st.value;
                     ss.state = S_ARNOLDI;
                     ss.j = 0;
+                    ss.pend = 0;
                 }
             }
         }
+    };
+
+    // Work decided by the last processed status, issued in stream order
+    // before the next step.  Each list uses the host set of that status's
+    // step: it is rewritten only after the host has waited for that set's
+    // next step, which follows these copies on the stream.
+    auto issue_pending = [&](int q) -> int {
+        Job *fin_h = c->fin_h + q * nsl, *upd_h = c->upd_h + q * nsl;
+        Job *fin_d = c->fin_dev + q * nsl, *upd_d = c->upd_dev + q * nsl;
+        if (!rst.empty()) {   // zero start for rejected warm starts (and x = 0 where b = 0)
+            HIPCHK(c, hipStreamSynchronize(s));   // upd_h is reused below
+            std::copy(rst.begin(), rst.end(), upd_h);
+            HIPCHK(c, hipMemcpyAsync(upd_d, upd_h, sizeof(Job) * rst.size(), hipMemcpyHostToDevice, s));
+            launch_reset_slots(s, upd_d, (int)rst.size(), c->slots, P);
+            HIPCHK(c, hipStreamSynchronize(s));
+            rst.clear();
+        }
+        // polarizability (and stored solution) of finished points, before the slot is reused
+        if (!fin.empty()) {
+            std::copy(fin.begin(), fin.end(), fin_h);
+            HIPCHK(c, hipMemcpyAsync(fin_d, fin_h, sizeof(Job) * fin.size(), hipMemcpyHostToDevice, s));
+            launch_alpha(t, s, fin_d, (int)fin.size(), c->slots, drives, n_drive, c->P_pad, P, nullptr,
+                         alpha_dev);
+            if (x_out) launch_store_x(s, fin_d, (int)fin.size(), c->slots, P, x_out);
+            fin.clear();
+        }
+        // x += V y for slots that ended a cycle
+        if (!upd.empty()) {
+            int jm = 0;
+            double sumL = 0.0;
+            for (auto &u : upd) {
+                jm = std::max(jm, u.j);
+                sumL += u.j;
+            }
+            std::copy(upd.begin(), upd.end(), upd_h);
+            HIPCHK(c, hipMemcpyAsync(upd_d, upd_h, sizeof(Job) * upd.size(), hipMemcpyHostToDevice, s));
+            launch_update_x(t, s, upd_d, (int)upd.size(), jm, c->slots, P, sumL);
+            upd.clear();
+        }
+        // refill free slots; warm-started points get x0 = U c(omega) now
+        wnew.clear();
+        wom.clear();
+        for (int k = 0; k < nsl; ++k)
+            if (sl[k].state == S_FREE && !sl[k].busy && next_point < npts) {
+                sl[k].state = S_RHS;
+                sl[k].point = next_point++;
+                sl[k].j = 0;
+                sl[k].pend = 0;
+                sl[k].epoch += 1;
+                sl[k].warm_check = false;
+                if (ws) {
+                    wnew.push_back({k, 0, sl[k].point, 0});
+                    wom.push_back(omega[sl[k].point / n_drive]);
+                }
+            }
+        if (!wnew.empty()) {
+            HIPCHK(c, hipStreamSynchronize(s));   // fin_h copies done; reuse fin_h
+            std::copy(wnew.begin(), wnew.end(), fin_h);
+            HIPCHK(c, hipMemcpyAsync(ws->jobs_dev, fin_h, sizeof(Job) * wnew.size(), hipMemcpyHostToDevice, s));
+            CHK(ws_infer(ws, s, (int)wnew.size(), wom.data()));
+            launch_ws_apply(s, ws->jobs_dev, (int)wnew.size(), ws->out, ws->O, ws->mean, ws->sdev, ws->r, ws->U,
+                            (int64_t)c->P_pad * 2, c->slots.x, (int64_t)c->P_pad * 2, P);
+            HIPCHK(c, hipStreamSynchronize(s));
+        }
+        return CHI0_OK;
+    };
+
+    int last_q = 0;
+    for (;;) {
+        CHK(issue_pending(last_q));
+        while (n_inflight < 2) {
+            CHK(plan_and_launch(q_launch));
+            if (fl[q_launch].nb == 0) break;
+            if (n_inflight == 0) q_oldest = q_launch;
+            ++n_inflight;
+            q_launch ^= 1;
+        }
+        if (n_inflight == 0) {
+            if (done < npts) return fail(c, CHI0_EHIP, "solver stalled with unfinished points");
+            break;
+        }
+        HIPCHK(c, hipEventSynchronize(c->step_ev[q_oldest]));
+        process(q_oldest);
+        last_q = q_oldest;
+        q_oldest ^= 1;
+        --n_inflight;
     }
-    if (!rst.empty()) {   // finished points whose x must read 0 before alpha
-        std::copy(rst.begin(), rst.end(), c->upd_h);
-        HIPCHK(c, hipMemcpyAsync(c->upd_dev, c->upd_h, sizeof(Job) * rst.size(), hipMemcpyHostToDevice, s));
-        launch_reset_slots(s, c->upd_dev, (int)rst.size(), c->slots, P);
-        rst.clear();
-        HIPCHK(c, hipStreamSynchronize(s));
-    }
-    if (!fin.empty()) {
-        std::copy(fin.begin(), fin.end(), c->fin_h);
-        HIPCHK(c, hipMemcpyAsync(c->fin_dev, c->fin_h, sizeof(Job) * fin.size(), hipMemcpyHostToDevice, s));
-        launch_alpha(t, s, c->fin_dev, (int)fin.size(), c->slots, drives, n_drive, c->P_pad, P, nullptr, alpha_dev);
-        if (x_out) launch_store_x(s, c->fin_dev, (int)fin.size(), c->slots, P, x_out);
-        fin.clear();
-    }
+    CHK(issue_pending(last_q));   // finished points still waiting for their alpha
     std::vector<double> ah((size_t)npts * n_drive * 2);
     HIPCHK(c, hipMemcpyAsync(ah.data(), alpha_dev, ah.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));

@@ -102,3 +102,11 @@ def test_default_options(L):
     o = chi0.SolveOpts()
     L.chi0_solve_opts_default(C.byref(o))
     assert (o.restart, o.max_iter, o.tol, o.precision, o.batch) == (30, 10000, 1e-10, 0, 1)
+
+
+def test_timing_filter_on_host_context(L):
+    with chi0.Context(-1) as ctx:
+        ctx.set_timing(True, only=["dcgs_update", "dcgs_dots"])
+        assert ctx.kernel_stats() == {}
+        ctx.set_timing(False)
+    assert L.chi0_set_timing_filter(None, b"x") == -1
