@@ -580,6 +580,9 @@ extern "C" int chi0_set_system(chi0_ctx *c, int32_t n_atoms, const double *posit
     CHK(up32(hm.g_xrow, &bm.g_xrow));
     CHK(up64(hm.g_ent, &bm.g_ent));
     CHK(up32(hm.atom_off, &bm.atom_off));
+    bm.nb_max = 0;
+    for (size_t A = 0; A + 1 < hm.atom_off.size(); ++A)
+        bm.nb_max = std::max(bm.nb_max, hm.atom_off[A + 1] - hm.atom_off[A]);
     CHK(up64(hm.prod_pstart, &bm.prod_pstart));
     CHK(up64(hm.prod_plist, &bm.prod_plist));
     {

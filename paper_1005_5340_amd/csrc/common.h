@@ -72,6 +72,7 @@ struct BlockMapDev {
     // per product: positions of its (block, slot) pairs in part
     const int64_t *prod_pstart;   // [P+1]
     const int64_t *prod_plist;    // [sum]
+    int nb_max;                   // largest number of orbitals on one atom
 };
 
 // ------------------------------------------------------------ launch wrappers

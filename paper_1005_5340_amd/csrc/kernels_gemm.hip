@@ -299,10 +299,13 @@ void launch_sgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int 
 // ------------------------------------------------------- (b1) occupied transform
 // Tt[b][E*nc + j] = sum_{A in nbr(B)} sum_{a in A} Xo[a][E] dV[(k(A,B), a, b)][j]
 // One workgroup: column atom B, 64 occupied states, 16 columns.  Wave w owns
-// states 16w..16w+15 and every orbital b of B (one accumulator per b).
+// states 16w..16w+15 and every orbital b of B (one accumulator per b; NBT is
+// the system's largest atom rounded up to a multiple of 4).  The gathered rows
+// come in chunks of 16; the next chunk's global loads are issued before the
+// current chunk's MFMAs so their latency overlaps the arithmetic.
 // T is the arithmetic type (FP64, or FP32 for the low-precision operator);
 // dV is always FP64 and is rounded to T when staged.
-template <class T>
+template <class T, int NBT>
 __global__ __launch_bounds__(256)
 void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
                      const double *__restrict__ dV, T *__restrict__ Tt, int nc) {
@@ -311,32 +314,39 @@ void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
     const int boff = bm.atom_off[B], nB = bm.atom_off[B + 1] - boff;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     __shared__ T Xs[16][64 + 1];
-    __shared__ T Ds[16][NB_MAX][JT];
+    __shared__ T Ds[16][NBT][JT];
 
-    typename Mma<T>::acc acc[NB_MAX];
+    typename Mma<T>::acc acc[NBT];
 #pragma unroll
-    for (int b = 0; b < NB_MAX; ++b) acc[b] = Mma<T>::zero();
+    for (int b = 0; b < NBT; ++b) acc[b] = Mma<T>::zero();
 
+    // register staging of one chunk: 4 X values and the nB dV values of (row, column)
+    const int xr = t / 16, xc = (t % 16) * 4;
+    const int dr = t / JT, djj = t % JT, dj = j0 + djj;
+    T xv[4], dv[NBT];
+    auto fetch = [&](int gc) {
+        const int gx = gc + xr;
+        xv[0] = xv[1] = xv[2] = xv[3] = T(0);
+        if (gx < g1) load4(Xo + (int64_t)bm.g_xrow[gx] * no_pad + e0 + xc, xv);
+        const int gd = gc + dr;
+        const bool ok = gd < g1 && dj < nc;
+        const double *src = dV + (ok ? (bm.g_ent[gd] * (int64_t)nc + dj) : 0);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) dv[b] = (ok && b < nB) ? (T)src[(int64_t)b * nc] : T(0);
+    };
+    fetch(g0);
     for (int gc = g0; gc < g1; gc += 16) {
-        {   // Xs: 16 gathered rows x 64 states, 4 per thread
-            const int r = t / 16, c = (t % 16) * 4, g = gc + r;
-            T v[4] = {T(0), T(0), T(0), T(0)};
-            if (g < g1) load4(Xo + (int64_t)bm.g_xrow[g] * no_pad + e0 + c, v);
-            Xs[r][c] = v[0]; Xs[r][c + 1] = v[1]; Xs[r][c + 2] = v[2]; Xs[r][c + 3] = v[3];
-        }
-        {   // Ds: thread -> (gathered row r, column jj), looping over the orbitals b of B
-            const int r = t / JT, jj = t % JT, g = gc + r, j = j0 + jj;
-            const bool ok = g < g1 && j < nc;
-            const double *src = dV + (ok ? (bm.g_ent[g] * (int64_t)nc + j) : 0);
-            for (int b = 0; b < nB; ++b) Ds[r][b][jj] = ok ? (T)src[(int64_t)b * nc] : T(0);
-        }
+        Xs[xr][xc] = xv[0]; Xs[xr][xc + 1] = xv[1]; Xs[xr][xc + 2] = xv[2]; Xs[xr][xc + 3] = xv[3];
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) Ds[dr][b][djj] = dv[b];
         __syncthreads();
+        if (gc + 16 < g1) fetch(gc + 16);
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
             const T a = Xs[kk][wv * 16 + (lane & 15)];
 #pragma unroll
-            for (int b = 0; b < NB_MAX; ++b)
+            for (int b = 0; b < NBT; ++b)
                 if (b < nB) acc[b] = Mma<T>::op(a, Ds[kk][b][lane & 15], acc[b]);
         }
         __syncthreads();
@@ -345,7 +355,7 @@ void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
     const int j = j0 + (lane & 15);
     if (j < nc) {
 #pragma unroll
-        for (int b = 0; b < NB_MAX; ++b) {
+        for (int b = 0; b < NBT; ++b) {
             if (b < nB) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -357,13 +367,26 @@ void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
     }
 }
 
+template <class T, int NBT>
+static void occ_transform_nbt(hipStream_t s, dim3 grid, const BlockMapDev &bm, const T *Xo, int no_pad,
+                              const double *dV, T *Tt, int nc) {
+    hipLaunchKernelGGL((k_occ_transform<T, NBT>), grid, dim3(256), 0, s, bm, Xo, no_pad, dV, Tt, nc);
+}
+
 template <class T>
 static void occ_transform_any(Tracer *t, hipStream_t s, const char *name, const BlockMapDev &bm,
                               int n_atoms, const T *Xo, int no_pad, const double *dV, T *Tt, int nc,
                               const WorkSizes &ws) {
     dim3 grid(n_atoms, no_pad / 64, (nc + JT - 1) / JT);
     trace_begin(t, name, s);
-    hipLaunchKernelGGL(k_occ_transform<T>, grid, dim3(256), 0, s, bm, Xo, no_pad, dV, Tt, nc);
+    if (bm.nb_max <= 4)
+        occ_transform_nbt<T, 4>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
+    else if (bm.nb_max <= 8)
+        occ_transform_nbt<T, 8>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
+    else if (bm.nb_max <= 12)
+        occ_transform_nbt<T, 12>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
+    else
+        occ_transform_nbt<T, 16>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
     trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
               8.0 * ws.nnzB * nc + sizeof(T) * (ws.N * ws.No + ws.N * ws.No * nc));
 }
@@ -382,9 +405,10 @@ void launch_occ_transform_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, i
 
 // ------------------------------------------------------ (b4) back to the pattern
 // W[(k(A,B), a, b)][j] = sum_E Xo[a][E] Ut[b][E*nc + j] for (A, B) in the pattern.
-// One workgroup: column atom B, 64 of its gathered rows (A, a), 16 columns.
-// Accumulation in T; W is written in FP64.
-template <class T>
+// One workgroup: column atom B, 64 of its gathered rows (A, a), 16 columns;
+// the occupied states come in chunks of 16 with the next chunk's global loads
+// issued before the current chunk's MFMAs.  Accumulation in T; W is FP64.
+template <class T, int NBT>
 __global__ __launch_bounds__(256)
 void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
                 const T *__restrict__ Ut, double *__restrict__ W, int nc) {
@@ -396,31 +420,38 @@ void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t ldT = (int64_t)no_pad * nc;
     __shared__ T Xs[64][16 + 1];
-    __shared__ T Us[NB_MAX][16][JT];
+    __shared__ T Us[NBT][16][JT];
 
-    typename Mma<T>::acc acc[NB_MAX];
+    typename Mma<T>::acc acc[NBT];
 #pragma unroll
-    for (int b = 0; b < NB_MAX; ++b) acc[b] = Mma<T>::zero();
+    for (int b = 0; b < NBT; ++b) acc[b] = Mma<T>::zero();
 
     const int xr = t / 4, xc = (t % 4) * 4, xg = g0 + xr;
     const T *xsrc = (xg < g1) ? Xo + (int64_t)bm.g_xrow[xg] * no_pad + xc : nullptr;
+    const int ue = t / JT, ujj = t % JT, uj = j0 + ujj;
+    const bool uok = uj < nc;
+    const T *usrc = Ut + (int64_t)boff * ldT + (int64_t)ue * nc + (uok ? uj : 0);
+    T xv[4], uv[NBT];
+    auto fetch = [&](int E0) {
+        xv[0] = xv[1] = xv[2] = xv[3] = T(0);
+        if (xsrc) load4(xsrc + E0, xv);
+#pragma unroll
+        for (int b = 0; b < NBT; ++b)
+            uv[b] = (uok && b < nB) ? usrc[(int64_t)b * ldT + (int64_t)E0 * nc] : T(0);
+    };
+    fetch(0);
     for (int E0 = 0; E0 < no_pad; E0 += 16) {
-        T v[4] = {T(0), T(0), T(0), T(0)};
-        if (xsrc) load4(xsrc + E0, v);
-        Xs[xr][xc] = v[0]; Xs[xr][xc + 1] = v[1]; Xs[xr][xc + 2] = v[2]; Xs[xr][xc + 3] = v[3];
-        {   // Us: thread -> (state e, column jj), looping over the orbitals b of B
-            const int e = t / JT, jj = t % JT, j = j0 + jj;
-            const bool ok = j < nc;
-            const T *src = Ut + (int64_t)boff * ldT + (int64_t)(E0 + e) * nc + (ok ? j : 0);
-            for (int b = 0; b < nB; ++b) Us[b][e][jj] = ok ? src[(int64_t)b * ldT] : T(0);
-        }
+        Xs[xr][xc] = xv[0]; Xs[xr][xc + 1] = xv[1]; Xs[xr][xc + 2] = xv[2]; Xs[xr][xc + 3] = xv[3];
+#pragma unroll
+        for (int b = 0; b < NBT; ++b) Us[b][ue][ujj] = uv[b];
         __syncthreads();
+        if (E0 + 16 < no_pad) fetch(E0 + 16);
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
             const T a = Xs[wv * 16 + (lane & 15)][kk];
 #pragma unroll
-            for (int b = 0; b < NB_MAX; ++b)
+            for (int b = 0; b < NBT; ++b)
                 if (b < nB) acc[b] = Mma<T>::op(a, Us[b][kk][lane & 15], acc[b]);
         }
         __syncthreads();
@@ -433,11 +464,17 @@ void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
             if (g < g1) {
                 const int64_t base = bm.g_ent[g];
 #pragma unroll
-                for (int b = 0; b < NB_MAX; ++b)
+                for (int b = 0; b < NBT; ++b)
                     if (b < nB) W[(base + b) * nc + j] = (double)acc[b][r];
             }
         }
     }
+}
+
+template <class T, int NBT>
+static void occ_back_nbt(hipStream_t s, dim3 grid, const BlockMapDev &bm, const T *Xo, int no_pad,
+                         const T *Ut, double *W, int nc) {
+    hipLaunchKernelGGL((k_occ_back<T, NBT>), grid, dim3(256), 0, s, bm, Xo, no_pad, Ut, W, nc);
 }
 
 template <class T>
@@ -446,7 +483,14 @@ static void occ_back_any(Tracer *t, hipStream_t s, const char *name, const Block
                          int nc, const WorkSizes &ws) {
     dim3 grid(n_atoms, (max_rows + 63) / 64, (nc + JT - 1) / JT);
     trace_begin(t, name, s);
-    hipLaunchKernelGGL(k_occ_back<T>, grid, dim3(256), 0, s, bm, Xo, no_pad, Ut, W, nc);
+    if (bm.nb_max <= 4)
+        occ_back_nbt<T, 4>(s, grid, bm, Xo, no_pad, Ut, W, nc);
+    else if (bm.nb_max <= 8)
+        occ_back_nbt<T, 8>(s, grid, bm, Xo, no_pad, Ut, W, nc);
+    else if (bm.nb_max <= 12)
+        occ_back_nbt<T, 12>(s, grid, bm, Xo, no_pad, Ut, W, nc);
+    else
+        occ_back_nbt<T, 16>(s, grid, bm, Xo, no_pad, Ut, W, nc);
     trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
               sizeof(T) * (ws.N * ws.No * nc + ws.N * ws.No) + 8.0 * ws.nnzB * nc);
 }
