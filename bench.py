@@ -259,6 +259,12 @@ def main():
                   f"{100 * v['ms'] / tot_all:6.1f}%  {ach:9.2f} {'GB/s' if b == 'hbm' else 'TFLOP/s'}",
                   file=sys.stderr)
 
+    tuned = ctx.autotune_table()
+    for k, v in sorted(tuned.items()):
+        us = ", ".join(f"{x:.0f}" if x > 0 else "-" for x in v["us"])
+        print(f"[bench] autotune {k:58s} -> {v['tile']:8s} (us per variant 64x64,64x128,128x64,128x128: {us})",
+              file=sys.stderr)
+
     cpu = None
     if a.cpu_sample > 0:
         cpu = cpu_baseline(s, drives, a.cpu_sample)
@@ -277,6 +283,7 @@ def main():
                    "eps": s.eps, "tol": tol, "restart": restart, "batch": a.batch,
                    "points": npts, "precision": a.precision, "warm_start_train": a.warm},
         "chi0_gflops": chi0_gflops,
+        "autotune": {k: v["tile"] for k, v in sorted(tuned.items())},
         "chi0_applications_per_step": applications,
         "iterations": {"mean": float(stats["iterations"].mean()), "max": int(stats["iterations"].max()),
                        "converged": int(stats["converged"].sum()),

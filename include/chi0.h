@@ -281,6 +281,29 @@ int chi0_kernel_stats(chi0_ctx *ctx, chi0_kernel_record *records, int32_t cap);
  * or CHI0_EINVAL for a NULL context.  Valid on host-only contexts. */
 int chi0_set_timing_filter(chi0_ctx *ctx, const char *names);
 
+/*
+ * Tile-shape autotuning of the dense matrix-core GEMMs (the virtual-orbital
+ * transforms and the batched kernel product K V).  Enabled by default: the
+ * first GEMM of a new shape class (kernel, M, K, split count, N within a half
+ * octave) on a context times each valid tile variant (64x64, 64x128, 128x64,
+ * 128x128 outputs per workgroup) once after a warm launch, on the call's
+ * stream, and keeps the fastest for that class.  All variants accumulate each
+ * output element in the same order, so tuning never changes a result, only
+ * the time; it does add a synchronisation of the stream on each new class.
+ * chi0_set_autotune(ctx, 0) uses the 64x64 variant everywhere.
+ * chi0_autotune_table copies up to `cap` entries of the context's table and
+ * returns the number of entries (or a negative error code).
+ */
+typedef struct chi0_tune_record {
+    char    key[96];      /* shape class */
+    char    tile[16];     /* chosen variant, e.g. "64x128" */
+    int32_t variant;      /* its index 0..3 */
+    float   us[4];        /* timed launch of each variant in microseconds; 0 = not valid for the shape */
+} chi0_tune_record;
+
+int chi0_set_autotune(chi0_ctx *ctx, int32_t enable);
+int chi0_autotune_table(chi0_ctx *ctx, chi0_tune_record *records, int32_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,11 @@ class PointStats(C.Structure):
                 ("rel_residual", C.c_double), ("warm_rel0", C.c_double)]
 
 
+class TuneRecord(C.Structure):
+    _fields_ = [("key", C.c_char * 96), ("tile", C.c_char * 16), ("variant", C.c_int32),
+                ("us", C.c_float * 4)]
+
+
 class KernelRecord(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
                 ("flops", C.c_double), ("bytes", C.c_double)]
@@ -99,6 +104,10 @@ def lib():
     L.chi0_solve_response.restype = C.c_int
     L.chi0_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.chi0_set_timing.restype = C.c_int
+    L.chi0_set_autotune.argtypes = [C.c_void_p, C.c_int32]
+    L.chi0_set_autotune.restype = C.c_int
+    L.chi0_autotune_table.argtypes = [C.c_void_p, C.POINTER(TuneRecord), C.c_int32]
+    L.chi0_autotune_table.restype = C.c_int
     L.chi0_set_timing_filter.argtypes = [C.c_void_p, C.c_char_p]
     L.chi0_set_timing_filter.restype = C.c_int
     L.chi0_kernel_stats.argtypes = [C.c_void_p, C.POINTER(KernelRecord), C.c_int32]
@@ -278,6 +287,19 @@ class Context:
         names = ",".join(only).encode() if only else None
         self._check(self._L.chi0_set_timing_filter(self._h, names))
         self._check(self._L.chi0_set_timing(self._h, 1 if enable else 0))
+
+    def set_autotune(self, enable: bool):
+        self._check(self._L.chi0_set_autotune(self._h, 1 if enable else 0))
+
+    def autotune_table(self) -> dict:
+        """{shape class: dict(tile, variant, us=[per-variant microseconds, 0 = not valid])}."""
+        n = self._L.chi0_autotune_table(self._h, None, 0)
+        self._check(min(n, 0))
+        recs = (TuneRecord * max(1, n))()
+        n = self._L.chi0_autotune_table(self._h, recs, n)
+        return {recs[i].key.decode(): dict(tile=recs[i].tile.decode(), variant=int(recs[i].variant),
+                                           us=[float(x) for x in recs[i].us])
+                for i in range(n)}
 
     def kernel_stats(self) -> dict:
         """{kernel: dict(launches, ms, flops, bytes)} accumulated since set_timing(True)."""

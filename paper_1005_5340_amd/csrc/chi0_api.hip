@@ -107,6 +107,7 @@ struct chi0_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     Tracer tracer;
+    GemmTuner tuner;
 
     // system
     bool has_system = false;
@@ -291,6 +292,28 @@ extern "C" int chi0_set_timing_filter(chi0_ctx *ctx, const char *names) {
         }
     }
     return CHI0_OK;
+}
+
+extern "C" int chi0_set_autotune(chi0_ctx *ctx, int32_t enable) {
+    if (!ctx) return CHI0_EINVAL;
+    ctx->tuner.enabled = enable != 0;
+    return CHI0_OK;
+}
+
+extern "C" int chi0_autotune_table(chi0_ctx *ctx, chi0_tune_record *rec, int32_t cap) {
+    if (!ctx || cap < 0 || (cap > 0 && !rec)) return fail(ctx, CHI0_EINVAL, "bad arguments");
+    int i = 0;
+    for (auto &kv : ctx->tuner.table) {
+        if (i < cap) {
+            std::memset(&rec[i], 0, sizeof(rec[i]));
+            std::snprintf(rec[i].key, sizeof(rec[i].key), "%s", kv.first.c_str());
+            rec[i].variant = kv.second.variant;
+            std::snprintf(rec[i].tile, sizeof(rec[i].tile), "%s", kGemmVariantNames[kv.second.variant]);
+            for (int v = 0; v < GEMM_VARIANTS && v < 4; ++v) rec[i].us[v] = kv.second.us[v];
+        }
+        ++i;
+    }
+    return i;
 }
 
 extern "C" int chi0_kernel_stats(chi0_ctx *ctx, chi0_kernel_record *rec, int32_t cap) {
@@ -656,10 +679,10 @@ static void run_chi0(chi0_ctx *c, hipStream_t s, int nb, double eps, int prec, c
                              c->at, (int)mcol, c->Dlt, c->Nv_pad, omega, eps, c->occ, nc,
                              fl + 6.0 * w.No * w.Nv * nb,
                              8.0 * (w.N * w.No * nc + w.Nv * w.No * nc + w.N * w.Nv + w.No * w.Nv),
-                             c->gemm_scratch, c->gemm_scratch_n);
+                             c->gemm_scratch, c->gemm_scratch_n, &c->tuner);
         launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, c->at, (int)mcol,
                      c->Ut, (int)mcol, fl, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv),
-                     c->gemm_scratch, c->gemm_scratch_n);
+                     c->gemm_scratch, c->gemm_scratch_n, &c->tuner);
         launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, c->Ut, c->W, nc, w);
     } else {
         launch_occ_transform_f32(t, s, c->bm, c->n_atoms, c->Xo32, c->No_pad, c->dV, c->Tt32, nc, w);
@@ -669,10 +692,10 @@ static void run_chi0(chi0_ctx *c, hipStream_t s, int nb, double eps, int prec, c
         if (prec == CHI0_PREC_FP32) {
             launch_sgemm(t, s, "virt_transform_lorentz_f32", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt32,
                          c->N_pad, c->Tt32, (int)mcol, c->at32, (int)mcol, fl + 6.0 * w.No * w.Nv * nb,
-                         by + 4.0 * w.N * w.Nv, &la, c->gemm_scratch, sb);
+                         by + 4.0 * w.N * w.Nv, &la, c->gemm_scratch, sb, &c->tuner);
             launch_sgemm(t, s, "virt_back_f32", c->N_pad, (int)mcol, c->Nv_pad, c->Xv32, c->Nv_pad,
                          c->at32, (int)mcol, c->Ut32, (int)mcol, fl, by + 4.0 * w.N * w.Nv, nullptr,
-                         c->gemm_scratch, sb);
+                         c->gemm_scratch, sb, &c->tuner);
         } else {   // split BF16 x 3: three BF16 products per multiply-add
             launch_bgemm3(t, s, "virt_transform_lorentz_bf16x3", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt_hi,
                           c->Xvt_lo, c->N_pad, c->Tt32, (int)mcol, c->at32, (int)mcol, 3.0 * fl,
@@ -989,7 +1012,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
             else
                 launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, c->Vb, nc, c->Zin,
                              nc, 2.0 * P * (double)P * nc, 8.0 * ((double)P * P + 2.0 * P * nc),
-                             c->gemm_scratch, c->gemm_scratch_n);
+                             c->gemm_scratch, c->gemm_scratch_n, &c->tuner);
             launch_put_drive(t, s, jg, gn, drives, c->P_pad, c->Zin, nc, P);
             run_chi0(c, s, gn, eps, prec, om_d + g0);
             launch_post_jobs(t, s, jg, gn, c->slots, c->Yout, nc, P, c->status_dev + q * nsl + g0);

@@ -22,11 +22,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <string>
+
 namespace chi0 {
 
 constexpr int TILE = 64;     // M/N tile of the dense GEMMs, E tile of the gathered ones
 constexpr int JT = 16;       // column tile of the gathered GEMMs and of ncp
 constexpr int NB_MAX = 16;   // maximum orbitals per atom supported by the gathered GEMMs
+constexpr int GEMM_VARIANTS = 4;   // tile shapes of the dense GEMM (see GemmTuner)
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -92,17 +96,36 @@ void launch_occ_transform(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n
 void launch_occ_back(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
                      const double *Xo, int no_pad, const double *Ut, double *W, int nc,
                      const WorkSizes &ws);
+// Tile-shape autotuner of the dense GEMMs (one per context).  The first call
+// of a GEMM whose (name, M, K, split count, N within a half octave) has not
+// been seen times every tile variant valid for it (HIP events, one warm and
+// one timed launch each, outside the tracer) and keeps the fastest for the
+// key.  Tile variants give bit-identical results, so the choice never changes
+// a number, only the time.
+struct GemmTuner {
+    struct Entry {
+        int variant = 0;
+        float us[GEMM_VARIANTS] = {};   // timed launch per variant (0: not valid for the shape)
+    };
+    bool enabled = true;
+    std::map<std::string, Entry> table;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~GemmTuner();
+};
+extern const char *const kGemmVariantNames[GEMM_VARIANTS];
+
 // Dense FP64 MFMA GEMM C = A B (row-major, M%64 == K%16 == 0, N masked).
 // scratch (may be NULL) holds split-K partial products when the tile count is low.
 void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                   const double *A, int lda, const double *B, int ldb, double *C, int ldc,
-                  double flops, double bytes, double *scratch, size_t scratch_doubles);
+                  double flops, double bytes, double *scratch, size_t scratch_doubles,
+                  GemmTuner *tu = nullptr);
 // (b2)+(c) at = Xvt Tt with the Lorentzian factor of column (E, j) and row F applied.
 void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K,
                           const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                           const double *Dlt, int nv_pad, const double *omega, double eps,
                           double occ, int ncp, double flops, double bytes, double *scratch,
-                          size_t scratch_doubles);
+                          size_t scratch_doubles, GemmTuner *tu = nullptr);
 // Low-precision operator: FP32 gathered transforms, FP32 or split-BF16x3 dense transforms.
 void launch_occ_transform_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms,
                               const float *Xo, int no_pad, const double *dV, float *Tt,
@@ -113,7 +136,7 @@ void launch_occ_back_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_
 void launch_sgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                   const float *A, int lda, const float *B, int ldb, float *C, int ldc,
                   double flops, double bytes, const LorentzArgs *la, void *scratch,
-                  size_t scratch_bytes);
+                  size_t scratch_bytes, GemmTuner *tu = nullptr);
 void launch_bgemm3(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                    const uint16_t *Ahi, const uint16_t *Alo, int lda, const float *B, int ldb,
                    float *C, int ldc, double flops, double bytes, const LorentzArgs *la,

@@ -10,6 +10,9 @@
 //   (both checked on gfx950 with lane probes)
 #include "common.h"
 
+#include <algorithm>
+#include <cmath>
+
 namespace chi0 {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -59,6 +62,9 @@ __device__ __forceinline__ int xcd_remap(int wid, int n) {
 // Split-K: blockIdx.y selects a K range of length K (the per-split length);
 // A and B are advanced by it and each split writes raw partial sums to its
 // own C slice (C + split * M * ldc), summed later by k_splitk_reduce.
+// The tile shape (BM x BN, WM x WN wavefronts) changes only which workgroup
+// computes an element, never the order of its k accumulation, so every tile
+// variant gives bit-identical results and the autotuner may pick any of them.
 template <class T, int BM, int BN, int WM, int WN, bool LORENTZ>
 __global__ __launch_bounds__(WM * WN * 64)
 void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
@@ -71,9 +77,10 @@ void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
     constexpr int NT = WM * WN * 64;
     constexpr int TM = BM / WM / 16;
     constexpr int TN = BN / WN / 16;
-    constexpr int APT = BM * BK / NT;   // A doubles per thread per tile
-    constexpr int BPT = BK * BN / NT;   // B doubles per thread per tile
-    static_assert(APT == 4 && BPT == 4, "tile shape must give 4 doubles per thread");
+    constexpr int CA = BM * (BK / 4) / NT;   // 4-element A chunks per thread per tile
+    constexpr int CB = BK * (BN / 4) / NT;   // 4-element B chunks per thread per tile
+    static_assert(CA >= 1 && CB >= 1 && CA * NT == BM * (BK / 4) && CB * NT == BK * (BN / 4),
+                  "tile shape must split into whole 4-element chunks per thread");
     __shared__ T As[2][BK][BM + 1];
     __shared__ T Bs[2][BK][BN];
 
@@ -85,29 +92,45 @@ void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wm = wv % WM, wn = wv / WM;
 
-    // global -> register mapping
-    const int a_row = t / 4, a_k = (t % 4) * 4;        // BM rows x 16 k
-    const int b_k = t / (BN / 4), b_n = (t % (BN / 4)) * 4;
-    const T *Ap = A + (int64_t)(m0 + a_row) * lda + a_k;
-    const T *Bp = B + (int64_t)b_k * ldb + n0 + b_n;
-    const bool b_full = (n0 + b_n + 3) < N;
-
-    T ra[4], rb[4];
-    auto load = [&](int kt) {
-        load4(Ap + kt * BK, ra);
-        const T *bp = Bp + (int64_t)kt * BK * ldb;
-        if (b_full) {
-            load4(bp, rb);
-        } else {
+    // global -> register mapping: chunk q of a thread is chunk t + q NT of the tile
+    int a_row[CA], a_k[CA], b_k[CB], b_n[CB];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) rb[c] = (n0 + b_n + c < N) ? bp[c] : T(0);
+    for (int q = 0; q < CA; ++q) {
+        const int ch = t + q * NT;
+        a_row[q] = ch / 4;
+        a_k[q] = (ch % 4) * 4;
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+        const int ch = t + q * NT;
+        b_k[q] = ch / (BN / 4);
+        b_n[q] = (ch % (BN / 4)) * 4;
+    }
+
+    T ra[CA][4], rb[CB][4];
+    auto load = [&](int kt) {
+#pragma unroll
+        for (int q = 0; q < CA; ++q) load4(A + (int64_t)(m0 + a_row[q]) * lda + kt * BK + a_k[q], ra[q]);
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+            const T *bp = B + (int64_t)(kt * BK + b_k[q]) * ldb + n0 + b_n[q];
+            if (n0 + b_n[q] + 3 < N) {
+                load4(bp, rb[q]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) rb[q][c] = (n0 + b_n[q] + c < N) ? bp[c] : T(0);
+            }
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) As[buf][a_k + c][a_row] = ra[c];
+        for (int q = 0; q < CA; ++q)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) Bs[buf][b_k][b_n + c] = rb[c];
+            for (int c = 0; c < 4; ++c) As[buf][a_k[q] + c][a_row[q]] = ra[q][c];
+#pragma unroll
+        for (int q = 0; q < CB; ++q)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Bs[buf][b_k[q]][b_n[q] + c] = rb[q][c];
     };
 
     typename Mma<T>::acc acc[TM][TN];
@@ -236,49 +259,120 @@ static void reduce_splits(Tracer *t, hipStream_t s, int M, int N, int S, const T
     trace_end(t, s, (double)S * M * N, (double)sizeof(T) * ((double)S + 1.0) * M * N);
 }
 
+const char *const kGemmVariantNames[GEMM_VARIANTS] = {"64x64", "64x128", "128x64", "128x128"};
+static const int kVarBM[GEMM_VARIANTS] = {64, 64, 128, 128};
+
+GemmTuner::~GemmTuner() {
+    for (hipEvent_t &e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+template <class T, bool LZ>
+static void launch_variant(int v, hipStream_t s, dim3 grid_s, int M, int N, int K, const T *A, int lda,
+                           const T *B, int ldb, T *C, int ldc, int m_fastest, const LorentzArgs &la) {
+    const int S = grid_s.y;
+    auto tiles = [&](int bm, int bn) { return (unsigned)((M / bm) * ((N + bn - 1) / bn)); };
+    switch (v) {
+    case 1:
+        hipLaunchKernelGGL((k_dgemm<T, 64, 128, 2, 2, LZ>), dim3(tiles(64, 128), S), dim3(256), 0, s,
+                           M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_dgemm<T, 128, 64, 2, 2, LZ>), dim3(tiles(128, 64), S), dim3(256), 0, s,
+                           M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        break;
+    case 3:
+        hipLaunchKernelGGL((k_dgemm<T, 128, 128, 2, 2, LZ>), dim3(tiles(128, 128), S), dim3(256), 0, s,
+                           M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        break;
+    default:
+        hipLaunchKernelGGL((k_dgemm<T, 64, 64, 2, 2, LZ>), dim3(tiles(64, 64), S), dim3(256), 0, s,
+                           M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        break;
+    }
+}
+
+// Variant for this call: the tuned one for its key, tuning first if the key is new.
+template <class T, bool LZ>
+static int pick_variant(GemmTuner *tu, hipStream_t s, const char *name, int S, int M, int N, int K,
+                        const T *A, int lda, const T *B, int ldb, T *C, int ldc, int m_fastest,
+                        const LorentzArgs &la) {
+    if (!tu || !tu->enabled) return 0;
+    const int nb = (int)std::floor(2.0 * std::log2((double)std::max(N, 1)));
+    const std::string key = std::string(name) + (sizeof(T) == 8 ? "" : "_f32") + " M=" + std::to_string(M) +
+                            " K=" + std::to_string(K * S) + " S=" + std::to_string(S) + " N~2^" +
+                            std::to_string(nb / 2) + (nb % 2 ? ".5" : "");
+    auto it = tu->table.find(key);
+    if (it != tu->table.end()) return it->second.variant;
+    GemmTuner::Entry e;
+    for (hipEvent_t &ev : tu->ev)
+        if (!ev && hipEventCreate(&ev) != hipSuccess) return 0;
+    float best = 0.f;
+    for (int v = 0; v < GEMM_VARIANTS; ++v) {
+        if (M % kVarBM[v] != 0) continue;
+        launch_variant<T, LZ>(v, s, dim3(1, S), M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        (void)hipEventRecord(tu->ev[0], s);
+        launch_variant<T, LZ>(v, s, dim3(1, S), M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        (void)hipEventRecord(tu->ev[1], s);
+        float ms = 0.f;
+        if (hipEventSynchronize(tu->ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, tu->ev[0], tu->ev[1]) != hipSuccess)
+            return 0;
+        e.us[v] = 1e3f * ms;
+        if (best == 0.f || e.us[v] < best) {
+            best = e.us[v];
+            e.variant = v;
+        }
+    }
+    tu->table.emplace(key, e);
+    return e.variant;
+}
+
 template <class T>
 static void gemm_any(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                      const T *A, int lda, const T *B, int ldb, T *C, int ldc,
                      double flops, double bytes, bool lorentz, const LorentzArgs &la,
-                     void *scratch, size_t scratch_bytes) {
-    const int tiles = (M / 64) * ((N + 63) / 64);
+                     void *scratch, size_t scratch_bytes, GemmTuner *tu) {
     const int S = scratch ? choose_splits(M, N, K, 16, scratch_bytes / sizeof(T)) : 1;
     const int m_fastest = (M / 64) <= ((N + 63) / 64);
-    trace_begin(t, name, s);
     if (S == 1) {
-        if (lorentz)
-            hipLaunchKernelGGL((k_dgemm<T, 64, 64, 2, 2, true>), dim3(tiles, 1), dim3(256), 0, s,
-                               M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
-        else
-            hipLaunchKernelGGL((k_dgemm<T, 64, 64, 2, 2, false>), dim3(tiles, 1), dim3(256), 0, s,
-                               M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        if (lorentz) {
+            const int v = pick_variant<T, true>(tu, s, name, 1, M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+            trace_begin(t, name, s);
+            launch_variant<T, true>(v, s, dim3(1, 1), M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        } else {
+            const int v = pick_variant<T, false>(tu, s, name, 1, M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+            trace_begin(t, name, s);
+            launch_variant<T, false>(v, s, dim3(1, 1), M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        }
         trace_end(t, s, flops, bytes);
         return;
     }
     // partial products with ldc = N into scratch, then the reduction (+ epilogue)
     T *part = static_cast<T *>(scratch);
-    hipLaunchKernelGGL((k_dgemm<T, 64, 64, 2, 2, false>), dim3(tiles, S), dim3(256), 0, s,
-                       M, N, K / S, A, lda, B, ldb, part, N, m_fastest, la);
+    const int v = pick_variant<T, false>(tu, s, name, S, M, N, K / S, A, lda, B, ldb, part, N, m_fastest, la);
+    trace_begin(t, name, s);
+    launch_variant<T, false>(v, s, dim3(1, S), M, N, K / S, A, lda, B, ldb, part, N, m_fastest, la);
     trace_end(t, s, flops, bytes);
     reduce_splits<T>(t, s, M, N, S, part, C, ldc, lorentz, la);
 }
 
 void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                   const double *A, int lda, const double *B, int ldb, double *C, int ldc,
-                  double flops, double bytes, double *scratch, size_t scratch_doubles) {
+                  double flops, double bytes, double *scratch, size_t scratch_doubles, GemmTuner *tu) {
     LorentzArgs la{};
     gemm_any<double>(t, s, name, M, N, K, A, lda, B, ldb, C, ldc, flops, bytes, false, la, scratch,
-                     scratch_doubles * sizeof(double));
+                     scratch_doubles * sizeof(double), tu);
 }
 
 void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K,
                           const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                           const double *Dlt, int nv_pad, const double *omega, double eps,
                           double occ, int ncp, double flops, double bytes, double *scratch,
-                          size_t scratch_doubles) {
+                          size_t scratch_doubles, GemmTuner *tu) {
     LorentzArgs la{Dlt, omega, nv_pad, ncp, eps, occ};
     gemm_any<double>(t, s, "virt_transform_lorentz", M, N, K, A, lda, B, ldb, C, ldc, flops, bytes,
-                     true, la, scratch, scratch_doubles * sizeof(double));
+                     true, la, scratch, scratch_doubles * sizeof(double), tu);
 }
 
 void launch_splitk_reduce_f32(Tracer *t, hipStream_t s, int M, int N, int S, const float *part,
@@ -290,10 +384,10 @@ void launch_splitk_reduce_f32(Tracer *t, hipStream_t s, int M, int N, int S, con
 void launch_sgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                   const float *A, int lda, const float *B, int ldb, float *C, int ldc,
                   double flops, double bytes, const LorentzArgs *la, void *scratch,
-                  size_t scratch_bytes) {
+                  size_t scratch_bytes, GemmTuner *tu) {
     LorentzArgs none{};
     gemm_any<float>(t, s, name, M, N, K, A, lda, B, ldb, C, ldc, flops, bytes, la != nullptr,
-                    la ? *la : none, scratch, scratch_bytes);
+                    la ? *la : none, scratch, scratch_bytes, tu);
 }
 
 // ------------------------------------------------------- (b1) occupied transform

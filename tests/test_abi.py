@@ -110,3 +110,11 @@ def test_timing_filter_on_host_context(L):
         assert ctx.kernel_stats() == {}
         ctx.set_timing(False)
     assert L.chi0_set_timing_filter(None, b"x") == -1
+
+
+def test_autotune_switch_on_host_context(L):
+    with chi0.Context(-1) as ctx:
+        ctx.set_autotune(False)
+        assert ctx.autotune_table() == {}
+        ctx.set_autotune(True)
+    assert L.chi0_set_autotune(None, 1) == -1

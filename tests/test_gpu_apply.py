@@ -94,3 +94,36 @@ def test_apply_linearity_and_symmetry(torch):
     assert abs(u @ out[1] - v @ out[0]) < 1e-12 * abs(u @ out[1])
     assert np.linalg.norm(out[2] - np.conj(out[0])) < 1e-12 * np.linalg.norm(out[0])
     ctx.close()
+
+
+def test_autotuned_tiles_are_bit_identical(torch):
+    """Every GEMM tile variant accumulates in the same order: the tuned operator
+    equals the untuned (64x64) one bit for bit, also with a variant forced per
+    shape by tuning on a size where several are valid (M = P_pad, 128 | M)."""
+    from paper_1005_5340_amd import synth
+    sys = synth.make_system("atoms60_orb9", 0)
+    rng = np.random.default_rng(21)
+    om = np.linspace(0.05, 1.4, 48)
+    z = rng.standard_normal((om.size, sys.n_prod)) + 1j * rng.standard_normal((om.size, sys.n_prod))
+    zt = torch.from_numpy(z).cuda()
+    outs = []
+    for tune in (False, True, True):
+        ctx = _ctx(sys)
+        ctx.set_autotune(tune)
+        outs.append(ctx.apply(om, sys.eps, zt).cpu().numpy())
+        table = ctx.autotune_table()
+        if tune:
+            print("[autotune]", {k: v["tile"] for k, v in table.items()}, flush=True)
+            assert len(table) >= 2 and all(v["us"][v["variant"]] > 0 for v in table.values())
+        else:
+            assert table == {}
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+    ctx = _ctx(sys)
+    d = sys.drives("z")
+    a1, s1, r1 = ctx.solve_response(om[:8], sys.eps, d, restart=sys.n_prod, tol=1e-8, batch=8)
+    ctx.set_autotune(False)
+    a2, s2, r2 = ctx.solve_response(om[:8], sys.eps, d, restart=sys.n_prod, tol=1e-8, batch=8)
+    ctx.close()
+    assert r1 == 0 and r2 == 0
+    assert np.array_equal(a1, a2) and np.array_equal(s1["iterations"], s2["iterations"])
