@@ -210,6 +210,20 @@ int chi0_solve_response(chi0_ctx *ctx, int32_t n_omega, const double *omega, dou
                         double *alpha, chi0_point_stats *stats);
 
 /*
+ * chi0_solve_response that also returns the solutions: the induced density
+ * response x = delta n(omega) of eq. sle in the product basis, for every
+ * point.
+ *
+ *  x   host [n_omega][n_drive][n_prod] complex (interleaved doubles), written;
+ *      x[w][i] solves (1 - chi0(omega[w]) K) x = chi0(omega[w]) d_i.
+ * The call needs n_omega * n_drive * n_prod * 16 bytes of extra device
+ * memory for the duration of the call.  Everything else as chi0_solve_response.
+ */
+int chi0_solve_response_x(chi0_ctx *ctx, int32_t n_omega, const double *omega, double eps,
+                          int32_t n_drive, const double *V_ext, const chi0_solve_opts *opts,
+                          double *alpha, chi0_point_stats *stats, double *x);
+
+/*
  * Learned warm start.  The paper starts GMRES from 0 (Sec. 4.1); this adds an
  * initial guess learned from solutions at training frequencies:
  *   1. plain FP64 GMRES solves (1 - chi0 K) x = chi0 d at the n_train

@@ -102,6 +102,8 @@ def lib():
     L.chi0_solve_response.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_double, C.c_int32, _dp,
                                       C.POINTER(SolveOpts), _dp, C.POINTER(PointStats)]
     L.chi0_solve_response.restype = C.c_int
+    L.chi0_solve_response_x.argtypes = list(L.chi0_solve_response.argtypes) + [_dp]
+    L.chi0_solve_response_x.restype = C.c_int
     L.chi0_set_timing.argtypes = [C.c_void_p, C.c_int32]
     L.chi0_set_timing.restype = C.c_int
     L.chi0_set_autotune.argtypes = [C.c_void_p, C.c_int32]
@@ -254,11 +256,13 @@ class Context:
     # ---------------------------------------------------------------- solve
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
                        tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,
-                       inner_tol: float = 0.0, warm: "WarmStart" = None, ortho: int = ORTHO_AUTO):
+                       inner_tol: float = 0.0, warm: "WarmStart" = None, ortho: int = ORTHO_AUTO,
+                       return_x: bool = False):
         """GMRES polarizability over a frequency grid.
 
         Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
-        where rc is 0 or NOT_CONVERGED.
+        where rc is 0 or NOT_CONVERGED; with return_x also the solutions
+        x [n_omega, n_drive, n_prod] complex (chi0_solve_response_x).
         """
         om = _f64(np.atleast_1d(omega))
         D = _f64(np.atleast_2d(V_ext))
@@ -271,15 +275,24 @@ class Context:
         o.ortho = int(ortho)
         alpha = np.zeros((om.size, nd, nd, 2))
         st = (PointStats * max(1, om.size * nd))()
-        rc = self._L.chi0_solve_response(self._h, int(om.size), _ptr(om), float(eps), int(nd),
-                                         _ptr(D), C.byref(o), _ptr(alpha), st)
+        if return_x:
+            n_prod = self.sizes()["n_prod"]
+            x = np.zeros((om.size, nd, n_prod, 2))
+            rc = self._L.chi0_solve_response_x(self._h, int(om.size), _ptr(om), float(eps), int(nd),
+                                               _ptr(D), C.byref(o), _ptr(alpha), st, _ptr(x))
+        else:
+            rc = self._L.chi0_solve_response(self._h, int(om.size), _ptr(om), float(eps), int(nd),
+                                             _ptr(D), C.byref(o), _ptr(alpha), st)
         self._check(rc, allow_warning=True)
         stats = np.zeros((om.size, nd), dtype=SolveStats)
         flat = stats.reshape(-1)
         for i in range(om.size * nd):
             flat[i] = (st[i].iterations, st[i].restarts, st[i].converged, st[i].breakdown,
                        st[i].fallback, st[i].warm_start, st[i].rel_residual, st[i].warm_rel0)
-        return alpha[..., 0] + 1j * alpha[..., 1], stats, rc
+        a = alpha[..., 0] + 1j * alpha[..., 1]
+        if return_x:
+            return a, stats, rc, x[..., 0] + 1j * x[..., 1]
+        return a, stats, rc
 
     # --------------------------------------------------------------- tracing
     def set_timing(self, enable: bool, only=None):

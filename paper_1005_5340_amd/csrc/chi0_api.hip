@@ -1021,7 +1021,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
         if (nb > nb64) run_group(nb64, nb - nb64, o.precision);
         if (n_arn > 0) {
             if (dcgs)
-                launch_dcgs(t, s, jobs_d, nb, jmax, c->slots, P, c->status_dev + q * nsl, n_arn, sum_j1);
+                launch_dcgs(t, s, jobs_d, nb, jmax, c->slots, P, c->status_dev + q * nsl, n_arn, sum_j1,
+                            c->gemm_scratch, c->gemm_scratch_n);
             else
                 launch_arnoldi(t, s, jobs_d, nb, jmax, c->slots, P, c->status_dev + q * nsl, n_arn, sum_j1);
         }
@@ -1260,6 +1261,27 @@ extern "C" int chi0_solve_response(chi0_ctx *c, int32_t n_omega, const double *o
                                    int32_t n_drive, const double *V_ext, const chi0_solve_opts *opts,
                                    double *alpha, chi0_point_stats *stats) {
     return solve_impl(c, n_omega, omega, eps, n_drive, V_ext, opts, alpha, stats, nullptr);
+}
+
+extern "C" int chi0_solve_response_x(chi0_ctx *c, int32_t n_omega, const double *omega, double eps,
+                                     int32_t n_drive, const double *V_ext, const chi0_solve_opts *opts,
+                                     double *alpha, chi0_point_stats *stats, double *x) {
+    if (!c) return CHI0_EINVAL;
+    if (!x) return fail(c, CHI0_EINVAL, "NULL x");
+    if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no system on a device context");
+    if (n_omega <= 0 || n_drive < 1 || n_drive > 3)
+        return solve_impl(c, n_omega, omega, eps, n_drive, V_ext, opts, alpha, stats, nullptr);
+    HIPCHK(c, hipSetDevice(c->device));
+    const int64_t npts = (int64_t)n_omega * n_drive;
+    DevBuf xb;
+    struct Guard { DevBuf *b; ~Guard() { b->release(); } } guard{&xb};
+    double *xd = nullptr;
+    CHK(dalloc(c, xb, &xd, npts * c->P_pad * 2));
+    const int rc = solve_impl(c, n_omega, omega, eps, n_drive, V_ext, opts, alpha, stats, xd);
+    if (rc < 0) return rc;
+    HIPCHK(c, hipMemcpy2D(x, (size_t)c->P * 16, xd, (size_t)c->P_pad * 16, (size_t)c->P * 16, (size_t)npts,
+                          hipMemcpyDeviceToHost));
+    return rc;
 }
 
 // ----------------------------------------------------- warm-start fitting

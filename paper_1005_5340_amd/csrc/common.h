@@ -189,8 +189,10 @@ void launch_post_jobs(Tracer *t, hipStream_t s, const Job *jobs, int nb, const S
 void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
                     const SlotsDev &sl, int P, StepStatus *status, int n_arnoldi, double sum_j1);
 // Arnoldi step with delayed reorthogonalisation (two passes over the basis).
+// scratch (may be NULL) holds the partial sums of the split update (few jobs).
 void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, const SlotsDev &sl, int P,
-                 StepStatus *status, int n_arnoldi, double sum_j1);
+                 StepStatus *status, int n_arnoldi, double sum_j1, double *scratch = nullptr,
+                 size_t scratch_doubles = 0);
 void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
                      const SlotsDev &sl, int P, double sum_L);
 void launch_alpha(Tracer *t, hipStream_t s, const Job *jobs, int n, const SlotsDev &sl,

@@ -185,11 +185,14 @@ void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
                 T v = acc[i][j][r];
                 if (LORENTZ) {
                     // L = n [1/(w - D + i eps) - 1/(w + D + i eps)] (in FP64), applied
-                    // to the complex number held by this lane and its xor-1 partner.
+                    // to the complex number held by this lane and its xor-1 partner;
+                    // the pair shares the two reciprocals (one computed by each lane).
                     const T other = __shfl_xor(v, 1);
                     const double D = la.Dlt[(int64_t)E * la.nv_pad + row];
                     const double d1 = w - D, d2 = w + D, e = la.eps;
-                    const double s1 = 1.0 / (d1 * d1 + e * e), s2 = 1.0 / (d2 * d2 + e * e);
+                    const double dm = par ? d2 : d1;
+                    const double sm = 1.0 / (dm * dm + e * e), so = __shfl_xor(sm, 1);
+                    const double s1 = par ? so : sm, s2 = par ? sm : so;
                     const double Lr = la.occ * (d1 * s1 - d2 * s2);
                     const double Li = la.occ * (-e * s1 + e * s2);
                     const double re = par ? (double)other : (double)v, im = par ? (double)v : (double)other;

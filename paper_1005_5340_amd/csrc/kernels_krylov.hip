@@ -464,6 +464,48 @@ void k_dcgs_coef(const Job *__restrict__ jobs, SlotsDev sl, StepStatus *__restri
 // The coefficients are staged through LDS in chunks (s and c of up to 4000
 // vectors do not fit at once).
 constexpr int DCH = 512;
+
+// Sums V_[i0,i1) s and V_[i0,i1) c for row mu (all threads join the LDS staging).
+__device__ __forceinline__ void dcgs_sums(const cpx *h, int j, const double2 *vb, int64_t vst, bool act,
+                                          int i0, int i1, cpx *shs, cpx *shc, double2 &as, double2 &ac) {
+    const int t = threadIdx.x;
+    for (int c0 = i0; c0 < i1; c0 += DCH) {
+        const int n = min(DCH, i1 - c0);
+        __syncthreads();
+        for (int k = t; k < n; k += 256) {
+            shs[k] = h[c0 + k];
+            shc[k] = h[j + c0 + k];
+        }
+        __syncthreads();
+        if (act) {
+            const double2 *vp = vb + (int64_t)c0 * vst;
+#pragma unroll 4
+            for (int k = 0; k < n; ++k) {
+                const double2 v = vp[(int64_t)k * vst];
+                const cpx sv = shs[k], cv = shc[k];
+                as.x += v.x * sv.r - v.y * sv.i;
+                as.y += v.x * sv.i + v.y * sv.r;
+                ac.x += v.x * cv.r - v.y * cv.i;
+                ac.y += v.x * cv.i + v.y * cv.r;
+            }
+        }
+    }
+}
+
+// Final formula for row mu given the sums over the whole basis V_j.
+__device__ __forceinline__ void dcgs_finish(const cpx *h, int j, double *V, int64_t vlen, int mu,
+                                            double2 as, double2 ac) {
+    const double rho = h[2 * j + 1].r, ir = rho > 0.0 ? 1.0 / rho : 0.0;
+    const cpx cj = h[2 * j];
+    double2 *pv = reinterpret_cast<double2 *>(V + (int64_t)j * vlen) + mu;
+    double2 *pz = reinterpret_cast<double2 *>(V + (int64_t)(j + 1) * vlen) + mu;
+    const double2 vt = *pv, z = *pz;
+    const double2 v = make_double2((vt.x - as.x) * ir, (vt.y - as.y) * ir);
+    *pv = v;
+    *pz = make_double2(z.x * ir - ac.x - (v.x * cj.r - v.y * cj.i),
+                       z.y * ir - ac.y - (v.x * cj.i + v.y * cj.r));
+}
+
 __global__ __launch_bounds__(256)
 void k_dcgs_update(const Job *__restrict__ jobs, SlotsDev sl, int P) {
     __shared__ cpx shs[DCH], shc[DCH];
@@ -477,39 +519,53 @@ void k_dcgs_update(const Job *__restrict__ jobs, SlotsDev sl, int P) {
     const int64_t vlen = (int64_t)sl.P_pad * 2;
     double *V = sl.V + jb.slot * sl.vstride;
     const double2 *vb = reinterpret_cast<const double2 *>(V) + (act ? mu : 0);
-    const int64_t vst = vlen / 2;   // double2 stride between basis vectors
     double2 as = make_double2(0.0, 0.0), ac = make_double2(0.0, 0.0);
-    for (int i0 = 0; i0 < j; i0 += DCH) {
-        const int n = min(DCH, j - i0);
-        __syncthreads();
-        for (int k = t; k < n; k += 256) {
-            shs[k] = h[i0 + k];
-            shc[k] = h[j + i0 + k];
-        }
-        __syncthreads();
-        if (act) {
-            const double2 *vp = vb + (int64_t)i0 * vst;
-#pragma unroll 4
-            for (int k = 0; k < n; ++k) {
-                const double2 v = vp[(int64_t)k * vst];
-                const cpx sv = shs[k], cv = shc[k];
-                as.x += v.x * sv.r - v.y * sv.i;
-                as.y += v.x * sv.i + v.y * sv.r;
-                ac.x += v.x * cv.r - v.y * cv.i;
-                ac.y += v.x * cv.i + v.y * cv.r;
-            }
-        }
+    dcgs_sums(h, j, vb, vlen / 2, act, 0, j, shs, shc, as, ac);
+    if (act) dcgs_finish(h, j, V, vlen, mu, as, ac);
+}
+
+// Split form for steps with few Arnoldi jobs: workgroup (x, q, g) sums basis
+// vectors [g jc, (g+1) jc) of job q into part[(q G + g) P_pad + mu] (as, ac),
+// then k_dcgs_update_fin adds the G partial sums in order and finishes.
+__global__ __launch_bounds__(256)
+void k_dcgs_update_part(const Job *__restrict__ jobs, SlotsDev sl, int P, int jc,
+                        double *__restrict__ part) {
+    __shared__ cpx shs[DCH], shc[DCH];
+    const int q = blockIdx.y, g = blockIdx.z, G = gridDim.z, t = threadIdx.x;
+    const Job jb = jobs[q];
+    if (jb.type != JOB_ARNOLDI) return;
+    const int mu = blockIdx.x * 256 + t;
+    const bool act = mu < P;
+    const int j = jb.j;
+    const cpx *h = reinterpret_cast<const cpx *>(sl.hbuf + (int64_t)jb.slot * sl.hbstride);
+    const int64_t vlen = (int64_t)sl.P_pad * 2;
+    const double2 *vb = reinterpret_cast<const double2 *>(sl.V + jb.slot * sl.vstride) + (act ? mu : 0);
+    double2 as = make_double2(0.0, 0.0), ac = make_double2(0.0, 0.0);
+    const int i0 = min(j, g * jc), i1 = min(j, (g + 1) * jc);
+    dcgs_sums(h, j, vb, vlen / 2, act, i0, i1, shs, shc, as, ac);
+    if (act) {
+        double2 *o = reinterpret_cast<double2 *>(part) + ((int64_t)(q * G + g) * sl.P_pad + mu) * 2;
+        o[0] = as;
+        o[1] = ac;
     }
-    if (!act) return;
-    const double rho = h[2 * j + 1].r, ir = rho > 0.0 ? 1.0 / rho : 0.0;
-    const cpx cj = h[2 * j];
-    double2 *pv = reinterpret_cast<double2 *>(V + (int64_t)j * vlen) + mu;
-    double2 *pz = reinterpret_cast<double2 *>(V + (int64_t)(j + 1) * vlen) + mu;
-    const double2 vt = *pv, z = *pz;
-    const double2 v = make_double2((vt.x - as.x) * ir, (vt.y - as.y) * ir);
-    *pv = v;
-    *pz = make_double2(z.x * ir - ac.x - (v.x * cj.r - v.y * cj.i),
-                       z.y * ir - ac.y - (v.x * cj.i + v.y * cj.r));
+}
+
+__global__ __launch_bounds__(256)
+void k_dcgs_update_fin(const Job *__restrict__ jobs, SlotsDev sl, int P, int G, const double *__restrict__ part) {
+    const int q = blockIdx.y, t = threadIdx.x;
+    const Job jb = jobs[q];
+    if (jb.type != JOB_ARNOLDI) return;
+    const int mu = blockIdx.x * 256 + t;
+    if (mu >= P) return;
+    const cpx *h = reinterpret_cast<const cpx *>(sl.hbuf + (int64_t)jb.slot * sl.hbstride);
+    const double2 *o = reinterpret_cast<const double2 *>(part) + ((int64_t)q * G * sl.P_pad + mu) * 2;
+    double2 as = make_double2(0.0, 0.0), ac = make_double2(0.0, 0.0);
+    for (int g = 0; g < G; ++g) {
+        const double2 a = o[(int64_t)g * sl.P_pad * 2], c = o[(int64_t)g * sl.P_pad * 2 + 1];
+        as.x += a.x; as.y += a.y;
+        ac.x += c.x; ac.y += c.y;
+    }
+    dcgs_finish(h, jb.j, sl.V + jb.slot * sl.vstride, (int64_t)sl.P_pad * 2, mu, as, ac);
 }
 
 // beta~ = |w'|, v~_{j+1} = w' / beta~, provisional h_{j+1,j} = beta~.
@@ -540,8 +596,20 @@ void k_dcgs_norm(const Job *__restrict__ jobs, SlotsDev sl, int P, StepStatus *_
     }
 }
 
+// Basis groups of the split update: enough workgroups to fill the chip a few
+// times over, at least 256 basis vectors per group, at most 16 groups, and the
+// partial sums within the scratch buffer.  A function of the step's shape only.
+static int update_groups(int P, int nb, int jmax, int64_t P_pad, size_t scratch_doubles) {
+    const int base = ((P + 255) / 256) * nb;
+    int G = 1;
+    while (G < 16 && base * G < 2048 && jmax / (2 * G) >= 256 &&
+           (size_t)(2 * G) * nb * P_pad * 4 <= scratch_doubles)
+        G *= 2;
+    return G;
+}
+
 void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, const SlotsDev &sl, int P,
-                 StepStatus *status, int n_arnoldi, double sum_j1) {
+                 StepStatus *status, int n_arnoldi, double sum_j1, double *scratch, size_t scratch_doubles) {
     const dim3 gd((jmax + 1 + 4 * DPW - 1) / (4 * DPW), nb), gu((P + 255) / 256, nb);
     trace_begin(t, "dcgs_dots", s);
     hipLaunchKernelGGL(k_dcgs_dots, gd, dim3(256), 0, s, jobs, sl, P);
@@ -549,8 +617,15 @@ void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, co
     trace_begin(t, "dcgs_coef", s);
     hipLaunchKernelGGL(k_dcgs_coef, dim3(nb), dim3(256), 0, s, jobs, sl, status);
     trace_end(t, s, 0.0, 16.0 * 4.0 * sum_j1);
+    const int G = scratch ? update_groups(P, nb, jmax, sl.P_pad, scratch_doubles) : 1;
     trace_begin(t, "dcgs_update", s);
-    hipLaunchKernelGGL(k_dcgs_update, gu, dim3(256), 0, s, jobs, sl, P);
+    if (G == 1) {
+        hipLaunchKernelGGL(k_dcgs_update, gu, dim3(256), 0, s, jobs, sl, P);
+    } else {
+        const int jc = (jmax + G - 1) / G;
+        hipLaunchKernelGGL(k_dcgs_update_part, dim3(gu.x, nb, G), dim3(256), 0, s, jobs, sl, P, jc, scratch);
+        hipLaunchKernelGGL(k_dcgs_update_fin, gu, dim3(256), 0, s, jobs, sl, P, G, scratch);
+    }
     trace_end(t, s, 16.0 * P * sum_j1, 16.0 * P * (sum_j1 + 3.0 * n_arnoldi));
     trace_begin(t, "dcgs_norm", s);
     hipLaunchKernelGGL(k_dcgs_norm, dim3(nb), dim3(256), 0, s, jobs, sl, P, status);

@@ -26,6 +26,7 @@ __device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c) {
 constexpr int VCB = 4;     // 16-column MFMA blocks per workgroup
 constexpr int VRB = 4;     // 16-row MFMA blocks per wave (rows <= 256 = NB_MAX^2)
 constexpr int PCH = 256;   // product ids staged in LDS per chunk
+constexpr int KU = 4;      // k-steps whose operand loads are issued together
 
 // (a) dV[(ent_k + ab)][j] = sum_i Vp[k][i][ab] * Z[pidx[k][i]][j]
 //     rows = ab (n_A n_B), K = the block's products, columns = j.
@@ -53,27 +54,34 @@ void k_vertex_gather(BlockMapDev bm, const double *__restrict__ Z, double *__res
         __syncthreads();
         if (t < cn) ps[t] = pk[c0 + t];
         __syncthreads();
-        for (int i0 = 0; i0 < cn; i0 += 4) {
-            const int kk = i0 + lk;
-            const bool kv = kk < cn;
-            const int64_t zrow = kv ? (int64_t)ps[kk] * nc : 0;
-            double a[VRB], b[VCB];
+        // KU k-steps of 4 products per round: all their loads are issued
+        // before their MFMAs, so KU loads per lane and operand are in flight
+        for (int i0 = 0; i0 < cn; i0 += 4 * KU) {
+            double a[KU][VRB], b[KU][VCB];
 #pragma unroll
-            for (int r = 0; r < VRB; ++r) {
-                const int row = (wv + 4 * r) * 16 + lr;
-                a[r] = (kv && row < nAB) ? Vk[(int64_t)(c0 + kk) * nAB + row] : 0.0;
+            for (int u = 0; u < KU; ++u) {
+                const int kk = i0 + 4 * u + lk;
+                const bool kv = kk < cn;
+                const int64_t zrow = kv ? (int64_t)ps[kk] * nc : 0;
+#pragma unroll
+                for (int r = 0; r < VRB; ++r) {
+                    const int row = (wv + 4 * r) * 16 + lr;
+                    a[u][r] = (kv && row < nAB) ? Vk[(int64_t)(c0 + kk) * nAB + row] : 0.0;
+                }
+#pragma unroll
+                for (int c = 0; c < VCB; ++c) {
+                    const int j = j0 + c * 16 + lr;
+                    b[u][c] = (kv && j < nc) ? Z[zrow + j] : 0.0;
+                }
             }
 #pragma unroll
-            for (int c = 0; c < VCB; ++c) {
-                const int j = j0 + c * 16 + lr;
-                b[c] = (kv && j < nc) ? Z[zrow + j] : 0.0;
-            }
+            for (int u = 0; u < KU; ++u)
 #pragma unroll
-            for (int r = 0; r < VRB; ++r)
-                if (wv + 4 * r < nrb)
+                for (int r = 0; r < VRB; ++r)
+                    if (wv + 4 * r < nrb)
 #pragma unroll
-                    for (int c = 0; c < VCB; ++c)
-                        if (c < ncb) acc[r][c] = mfma16(a[r], b[c], acc[r][c]);
+                        for (int c = 0; c < VCB; ++c)
+                            if (c < ncb) acc[r][c] = mfma16(a[u][r], b[u][c], acc[r][c]);
         }
     }
 #pragma unroll
@@ -122,26 +130,31 @@ void k_vertex_contract(BlockMapDev bm, const double *__restrict__ W, double *__r
 #pragma unroll
         for (int c = 0; c < VCB; ++c) acc[r][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    for (int a0 = 0; a0 < nAB; a0 += 4) {
-        const int kk = a0 + lk;
-        const bool kv = kk < nAB;
-        double a[VRB], b[VCB];
+    for (int a0 = 0; a0 < nAB; a0 += 4 * KU) {
+        double a[KU][VRB], b[KU][VCB];
 #pragma unroll
-        for (int r = 0; r < VRB; ++r) {
-            const int i = (rb0 + wv + 4 * r) * 16 + lr;
-            a[r] = (kv && i < np) ? Vk[(int64_t)i * nAB + kk] : 0.0;
+        for (int u = 0; u < KU; ++u) {
+            const int kk = a0 + 4 * u + lk;
+            const bool kv = kk < nAB;
+#pragma unroll
+            for (int r = 0; r < VRB; ++r) {
+                const int i = (rb0 + wv + 4 * r) * 16 + lr;
+                a[u][r] = (kv && i < np) ? Vk[(int64_t)i * nAB + kk] : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < VCB; ++c) {
+                const int j = j0 + c * 16 + lr;
+                b[u][c] = (kv && j < nc) ? W[(ent + kk) * nc + j] : 0.0;
+            }
         }
 #pragma unroll
-        for (int c = 0; c < VCB; ++c) {
-            const int j = j0 + c * 16 + lr;
-            b[c] = (kv && j < nc) ? W[(ent + kk) * nc + j] : 0.0;
-        }
+        for (int u = 0; u < KU; ++u)
 #pragma unroll
-        for (int r = 0; r < VRB; ++r)
-            if (rb0 + wv + 4 * r < nrb)
+            for (int r = 0; r < VRB; ++r)
+                if (rb0 + wv + 4 * r < nrb)
 #pragma unroll
-                for (int c = 0; c < VCB; ++c)
-                    if (c < ncb) acc[r][c] = mfma16(a[r], b[c], acc[r][c]);
+                    for (int c = 0; c < VCB; ++c)
+                        if (c < ncb) acc[r][c] = mfma16(a[u][r], b[u][c], acc[r][c]);
     }
 #pragma unroll
     for (int r = 0; r < VRB; ++r) {

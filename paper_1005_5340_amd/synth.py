@@ -296,3 +296,9 @@ def same_inputs(sys: System, fp: dict, xtol: float = 1e-12) -> bool:
         return False
     x = sys.X.ravel()[np.asarray(fp["x_index"], dtype=np.int64)]
     return bool(np.max(np.abs(x - np.asarray(fp["x_value"]))) <= xtol)
+
+
+def seeded_complex(shape, seed: int) -> np.ndarray:
+    """Seeded complex test vectors with N(0,1) real and imaginary parts."""
+    r = np.random.default_rng(seed)
+    return r.standard_normal(shape) + 1j * r.standard_normal(shape)

@@ -157,3 +157,38 @@ def test_delayed_reorthogonalisation_matches_cgs2(name):
         assert np.max(np.abs(a1 - a2)) < 1e-9 * np.max(np.abs(ref))
         assert np.all(np.abs(s2["iterations"] - s1["iterations"]) <= 0.05 * s1["iterations"] + 3)
         ctx.close()
+
+
+def test_split_update_on_long_bases():
+    """Few points with long Krylov bases: the DCGS2 update then splits the basis
+    over workgroups (partial sums added in a fixed order).  Three points of the
+    60-atom workload, unrestarted, against CGS2 (no split) and the oracle's
+    stored spectrum (tests/golden/reference_atoms60_orb9_s0.json)."""
+    import json
+    import os
+    from paper_1005_5340_amd import chi0, synth
+    sys = synth.make_system("atoms60_orb9", 0)
+    rec = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "reference_atoms60_orb9_s0.json")))
+    assert synth.same_inputs(sys, rec["fingerprint"])
+    ref_all = np.array(rec["alpha_re"])[:, 0, 0] + 1j * np.array(rec["alpha_im"])[:, 0, 0]
+    floor = 1e-3 * np.max(np.abs(ref_all.imag))
+    idx = [10, 64, 120]
+    om = sys.omegas[idx]
+    d = sys.drives("z")
+    ctx = _ctx(sys)
+    a1, s1, r1 = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-11, batch=3,
+                                    ortho=chi0.ORTHO_DCGS2)
+    a2, s2, r2 = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-11, batch=3,
+                                    ortho=chi0.ORTHO_CGS2)
+    ctx.close()
+    print(f"[split] iterations DCGS2 {s1['iterations'].ravel().tolist()} CGS2 {s2['iterations'].ravel().tolist()}",
+          flush=True)
+    assert r1 == 0 and r2 == 0
+    assert s1["iterations"].max() > 600          # bases long enough for the split form
+    ref = ref_all[idx]
+    for a in (a1, a2):
+        e = np.abs(a[:, 0, 0].imag - ref.imag) / np.maximum(np.abs(ref.imag), floor)
+        print(f"[split]   Im alpha error vs oracle {e.max():.2e}", flush=True)
+        assert e.max() < 1e-6
+    assert np.max(np.abs(a1 - a2)) < 1e-8 * np.max(np.abs(a2))
