@@ -117,6 +117,7 @@ def main():
                     help="learned warm start fitted on this many seeded training frequencies (0 = off)")
     ap.add_argument("--cpu-sample", type=int, default=2, help="frequencies for the oracle baseline (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
+    ap.add_argument("--lanes", type=int, default=0, help="solver lanes (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 device copies of MIB MiB (reference for HBM traffic counters)")
     a = ap.parse_args()
@@ -168,27 +169,34 @@ def main():
         print(f"[bench] warm start fitted in {warm_info['fit_seconds']:.2f} s, loss {h[0]:.3e} -> {h[-1]:.3e}",
               file=sys.stderr, flush=True)
 
-    def run():
+    def run(lanes=None):
         return ctx.solve_response(s.omegas, s.eps, drives, restart=restart, max_iter=a.max_iter,
                                   tol=tol, batch=a.batch, precision=prec, inner_tol=a.inner_tol,
-                                  warm=ws)
+                                  warm=ws, lanes=a.lanes if lanes is None else lanes)
 
     print(f"[bench] {a.workload}: N={s.n_orb} N_occ={s.n_occ} n_prod={s.n_prod} points="
           f"{s.omegas.size * drives.shape[0]} batch={a.batch} GMRES({restart}) tol={tol:g}",
           file=sys.stderr, flush=True)
-    # The untimed warmup steps time every kernel (the per-kernel breakdown);
-    # the timed steps time only the dominant kernel, so the two HIP events per
-    # timed launch stay off the other ~20 launches of each Arnoldi step.
+    # One untimed solve on a single lane times every kernel (the per-kernel
+    # breakdown, each kernel alone on the GPU); the warmup and timed steps use
+    # the requested lanes, and the timed steps time only the dominant kernel,
+    # so the two HIP events per timed launch stay off the other ~20 launches
+    # of each Arnoldi step.
     ks_all = {}
+    if not a.no_timing and a.warmup > 0:
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        run(lanes=1)
+        ks_all = ctx.kernel_stats()
+        print(f"[bench] breakdown run (one lane, all kernels timed) {time.perf_counter() - t0:.3f} s",
+              file=sys.stderr, flush=True)
+        ctx.set_timing(False)
     for i in range(a.warmup):
-        if not a.no_timing and i == a.warmup - 1:
-            ctx.set_timing(True)
         t0 = time.perf_counter()
         run()
         print(f"[bench] warmup {i} {time.perf_counter() - t0:.3f} s", file=sys.stderr, flush=True)
     if not a.no_timing:
-        if a.warmup > 0:
-            ks_all = ctx.kernel_stats()
+        if ks_all:
             dom0 = max(ks_all, key=lambda k: ks_all[k]["ms"])
             ctx.set_timing(True, only=[dom0])
         else:
@@ -240,9 +248,12 @@ def main():
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
                 "traffic_over_algorithmic": (traffic / (work / rec["launches"])) if traffic else None,
                 "launches": rec["launches"] // a.steps, "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
-                "share_of_gpu_time": (ks_all[dom]["ms"] / tot_all) if dom in ks_all else None}
-        # chi0 rate and the per-kernel breakdown: every kernel timed (the last
-        # warmup step, or the timed steps when there is no warmup)
+                "share_of_gpu_time": (ks_all[dom]["ms"] / tot_all) if dom in ks_all else None,
+                "lanes": a.lanes or ("auto: 2" if a.batch >= 16 else "auto: 1"),
+                "note": "per-launch rate of the timed steps; with 2 lanes a launch shares the GPU "
+                        "with the other lane's kernels (single-lane rates: stderr breakdown, chi0_gflops)"}
+        # chi0 rate and the per-kernel breakdown: every kernel timed (the
+        # single-lane breakdown run, or the timed steps when there is no warmup)
         chi0_ms = sum(ks_all[k]["ms"] for k in CHI0_KERNELS if k in ks_all)
         N, No = s.n_orb, s.n_occ
         Nv = N - No
@@ -250,7 +261,7 @@ def main():
         F = 8.0 * No * S_V + 8.0 * N * No * Nv + 6.0 * No * Nv      # Table t:flops count per chi0 z
         if chi0_ms > 0:
             chi0_gflops = F * applications / (chi0_ms * 1e-3) / 1e9
-        print("[bench] per-step breakdown (all kernels timed)", file=sys.stderr)
+        print("[bench] per-step breakdown (one lane, all kernels timed)", file=sys.stderr)
         print("[bench] kernel            launches/step   ms/step   share   achieved", file=sys.stderr)
         for k, v in sorted(ks_all.items(), key=lambda kv: -kv[1]["ms"]):
             b = bound_of(k)
@@ -281,7 +292,8 @@ def main():
         "config": {"workload": a.workload, "seed": a.seed, "n_orb": s.n_orb, "n_occ": s.n_occ,
                    "n_prod": s.n_prod, "n_omega": int(s.omegas.size), "drives": w.drives,
                    "eps": s.eps, "tol": tol, "restart": restart, "batch": a.batch,
-                   "points": npts, "precision": a.precision, "warm_start_train": a.warm},
+                   "points": npts, "precision": a.precision, "warm_start_train": a.warm,
+                   "lanes": a.lanes},
         "chi0_gflops": chi0_gflops,
         "autotune": {k: v["tile"] for k, v in sorted(tuned.items())},
         "chi0_applications_per_step": applications,

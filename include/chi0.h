@@ -160,7 +160,11 @@ typedef struct chi0_solve_opts {
                              starts from x0 = U c(omega) instead of 0, unless
                              ||chi0 d - A x0|| >= ||chi0 d||, then from 0 */
     int32_t ortho;        /* CHI0_ORTHO_*: Gram-Schmidt variant of the Arnoldi step */
-    int32_t reserved[3];  /* must be zero */
+    int32_t lanes;        /* 0 = auto (2 when batch >= 16, else 1), or 1 or 2: the concurrent
+                             slots are dealt to this many lanes, each with its own stream and
+                             operator workspace, so that one lane's memory-bound Gram-Schmidt
+                             passes overlap the other's matrix-core transforms */
+    int32_t reserved[2];  /* must be zero */
 } chi0_solve_opts;
 
 /* Gram-Schmidt of the Arnoldi step (eq. orthogonal-krylov-basis, done twice).

@@ -35,7 +35,8 @@ _i64p = C.POINTER(C.c_int64)
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("batch", C.c_int32), ("inner_tol", C.c_double),
-                ("warm", C.c_void_p), ("ortho", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("warm", C.c_void_p), ("ortho", C.c_int32), ("lanes", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class WsCfg(C.Structure):
@@ -257,7 +258,7 @@ class Context:
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
                        tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,
                        inner_tol: float = 0.0, warm: "WarmStart" = None, ortho: int = ORTHO_AUTO,
-                       return_x: bool = False):
+                       return_x: bool = False, lanes: int = 0):
         """GMRES polarizability over a frequency grid.
 
         Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
@@ -273,6 +274,7 @@ class Context:
         o.batch, o.precision, o.inner_tol = int(batch), int(precision), float(inner_tol)
         o.warm = warm._h if warm is not None else None
         o.ortho = int(ortho)
+        o.lanes = int(lanes)
         alpha = np.zeros((om.size, nd, nd, 2))
         st = (PointStats * max(1, om.size * nd))()
         if return_x:

@@ -102,6 +102,28 @@ struct DevBuf {
     }
 };
 
+// Buffers of one chi0 pass over up to nc_cap real columns (and its FP32
+// intermediates for the low-precision operator, allocated on first use).
+// chi0_apply uses op[0]; the solver gives each lane of slots its own.
+struct OpWork {
+    DevBuf buf, lpbuf;
+    int nc_cap = 0, lp_cap = 0;
+    double *Vb = nullptr, *Zin = nullptr, *Yout = nullptr, *dV = nullptr, *W = nullptr;
+    double *Tt = nullptr, *at = nullptr, *Ut = nullptr, *part = nullptr, *omega_dev = nullptr;
+    double *gemm_scratch = nullptr;
+    size_t gemm_scratch_n = 0;
+    float *Tt32 = nullptr, *at32 = nullptr, *Ut32 = nullptr;
+    void release() {
+        lpbuf.release();
+        buf.release();
+        nc_cap = lp_cap = 0;
+        Tt32 = at32 = Ut32 = nullptr;
+    }
+};
+constexpr int kLanes = 2;            // slot lanes of the solver, one stream each
+constexpr int kSets = 2 * kLanes;    // step buffer sets: two steps in flight per lane
+
+
 struct chi0_ctx {
     int device = -1;
     hipStream_t stream = nullptr;
@@ -121,34 +143,27 @@ struct chi0_ctx {
     double *Xo = nullptr, *Xv = nullptr, *Xvt = nullptr, *Dlt = nullptr, *K = nullptr;
     BlockMapDev bm{};
 
-    // operator workspace, sized for nc_cap real columns
-    DevBuf wsbuf;
-    int nc_cap = 0;
-    double *Vb = nullptr, *Zin = nullptr, *Yout = nullptr, *dV = nullptr, *W = nullptr;
-    double *Tt = nullptr, *at = nullptr, *Ut = nullptr, *part = nullptr, *omega_dev = nullptr;
-    double *gemm_scratch = nullptr;
-    size_t gemm_scratch_n = 0;
-    // low-precision operator: operand copies (set_system) and FP32 intermediates (lazy)
+    // operator workspaces (lane 0 also serves chi0_apply) and the lanes' streams
+    OpWork op[kLanes];
+    hipStream_t lane_stream[kLanes] = {nullptr, nullptr};   // [0] is `stream`
+    // low-precision operator: operand copies (set_system)
     float *Xo32 = nullptr, *Xv32 = nullptr, *Xvt32 = nullptr;
     uint16_t *Xv_hi = nullptr, *Xv_lo = nullptr, *Xvt_hi = nullptr, *Xvt_lo = nullptr;
-    DevBuf lpbuf;
-    int lp_cap = 0;
-    float *Tt32 = nullptr, *at32 = nullptr, *Ut32 = nullptr;
 
     // solver workspace
     DevBuf slotbuf;
     int slot_n = 0, slot_m = 0;
     SlotsDev slots{};
-    // Two sets of step buffers (the solver keeps two steps in flight).  Set q
-    // of the job arena holds [Job x slot_n][double omega x slot_n], so one copy
-    // moves a step's jobs and frequencies; fin/upd/status are [2][slot_n].
+    // kSets sets of step buffers (two steps in flight per lane).  Set q of the
+    // job arena holds [Job x slot_n][double omega x slot_n], so one copy moves
+    // a step's jobs and frequencies; fin/upd/status are [kSets][slot_n].
     char *arena_dev = nullptr, *arena_h = nullptr;
     Job *fin_dev = nullptr, *upd_dev = nullptr;
     StepStatus *status_dev = nullptr;
     Job *fin_h = nullptr, *upd_h = nullptr;
     StepStatus *status_h = nullptr;
     int host_cap = 0;
-    hipEvent_t step_ev[2] = {nullptr, nullptr};
+    hipEvent_t step_ev[kSets] = {};
     size_t arena_bytes() const { return (size_t)slot_n * (sizeof(Job) + sizeof(double)); }
     Job *jobs_dev(int q) { return reinterpret_cast<Job *>(arena_dev + q * arena_bytes()); }
     double *somega_dev(int q) { return reinterpret_cast<double *>(arena_dev + q * arena_bytes() + slot_n * sizeof(Job)); }
@@ -160,9 +175,11 @@ struct chi0_ctx {
             (void)hipSetDevice(device);
             if (stream) (void)hipStreamSynchronize(stream);
         }
+        if (device >= 0)
+            for (hipStream_t ls : lane_stream)
+                if (ls) (void)hipStreamSynchronize(ls);
         slotbuf.release();
-        lpbuf.release();
-        wsbuf.release();
+        for (OpWork &o : op) o.release();
         sysbuf.release();
         if (arena_h) (void)hipHostFree(arena_h);
         if (fin_h) (void)hipHostFree(fin_h);
@@ -170,6 +187,7 @@ struct chi0_ctx {
         if (status_h) (void)hipHostFree(status_h);
         for (hipEvent_t &e : step_ev)
             if (e) (void)hipEventDestroy(e);
+        if (lane_stream[1]) (void)hipStreamDestroy(lane_stream[1]);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -228,6 +246,8 @@ extern "C" int chi0_create(chi0_ctx **out, int device) {
         }
         e = hipSetDevice(device);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->lane_stream[1], hipStreamNonBlocking);
+        c->lane_stream[0] = c->stream;
         if (e != hipSuccess) {
             g_create_error = std::string("HIP setup failed: ") + hipGetErrorString(e);
             delete c;
@@ -358,12 +378,11 @@ static void drop_system(chi0_ctx *c) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
     }
+    for (hipStream_t ls : c->lane_stream)
+        if (c->device >= 0 && ls) (void)hipStreamSynchronize(ls);
     c->slotbuf.release();
     c->slot_n = c->slot_m = 0;
-    c->lpbuf.release();
-    c->lp_cap = 0;
-    c->wsbuf.release();
-    c->nc_cap = 0;
+    for (OpWork &o : c->op) o.release();
     c->sysbuf.release();
     c->has_system = false;
 }
@@ -621,92 +640,94 @@ extern "C" int chi0_set_system(chi0_ctx *c, int32_t n_atoms, const double *posit
 }
 
 // ================================================================ operator
-static int ensure_ws(chi0_ctx *c, int nc) {
-    if (nc <= c->nc_cap) return CHI0_OK;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+static int ensure_ws(chi0_ctx *c, OpWork &o, int nc) {
+    if (nc <= o.nc_cap) return CHI0_OK;
+    for (hipStream_t ls : c->lane_stream)
+        if (ls) HIPCHK(c, hipStreamSynchronize(ls));
     HIPCHK(c, hipDeviceSynchronize());
-    c->wsbuf.release();
-    c->nc_cap = 0;
-    DevBuf &w = c->wsbuf;
+    o.release();
+    DevBuf &w = o.buf;
     const int64_t mcol = (int64_t)c->No_pad * nc;
-    CHK(dalloc(c, w, &c->Vb, (int64_t)c->P_pad * nc));
-    CHK(dalloc(c, w, &c->Zin, (int64_t)c->P_pad * nc));
-    CHK(dalloc(c, w, &c->Yout, (int64_t)c->P_pad * nc));
-    CHK(dalloc(c, w, &c->dV, c->nnzB * nc));
-    CHK(dalloc(c, w, &c->W, c->nnzB * nc));
-    CHK(dalloc(c, w, &c->Tt, (int64_t)c->N_pad * mcol));
-    CHK(dalloc(c, w, &c->Ut, (int64_t)c->N_pad * mcol));
-    CHK(dalloc(c, w, &c->at, (int64_t)c->Nv_pad * mcol));
-    CHK(dalloc(c, w, &c->part, c->npart * nc));
-    CHK(dalloc(c, w, &c->omega_dev, nc / 2 + 1));
+    CHK(dalloc(c, w, &o.Vb, (int64_t)c->P_pad * nc));
+    CHK(dalloc(c, w, &o.Zin, (int64_t)c->P_pad * nc));
+    CHK(dalloc(c, w, &o.Yout, (int64_t)c->P_pad * nc));
+    CHK(dalloc(c, w, &o.dV, c->nnzB * nc));
+    CHK(dalloc(c, w, &o.W, c->nnzB * nc));
+    CHK(dalloc(c, w, &o.Tt, (int64_t)c->N_pad * mcol));
+    CHK(dalloc(c, w, &o.Ut, (int64_t)c->N_pad * mcol));
+    CHK(dalloc(c, w, &o.at, (int64_t)c->Nv_pad * mcol));
+    CHK(dalloc(c, w, &o.part, c->npart * nc));
+    CHK(dalloc(c, w, &o.omega_dev, nc / 2 + 1));
     // split-K partials: splits are only used while tiles * splits < 2048, so
     // the partial products never exceed 2048 64x64 tiles
-    c->gemm_scratch_n = (size_t)2048 * 64 * 64;
-    CHK(dalloc(c, w, &c->gemm_scratch, (int64_t)c->gemm_scratch_n));
+    o.gemm_scratch_n = (size_t)2048 * 64 * 64;
+    CHK(dalloc(c, w, &o.gemm_scratch, (int64_t)o.gemm_scratch_n));
     HIPCHK(c, hipDeviceSynchronize());
-    c->nc_cap = nc;
+    o.nc_cap = nc;
     return CHI0_OK;
 }
 
-static int ensure_lp(chi0_ctx *c) {
-    if (c->lp_cap >= c->nc_cap && c->Tt32) return CHI0_OK;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+static int ensure_lp(chi0_ctx *c, OpWork &o) {
+    if (o.lp_cap >= o.nc_cap && o.Tt32) return CHI0_OK;
+    for (hipStream_t ls : c->lane_stream)
+        if (ls) HIPCHK(c, hipStreamSynchronize(ls));
     HIPCHK(c, hipDeviceSynchronize());
-    c->lpbuf.release();
-    c->lp_cap = 0;
-    const int64_t mcol = (int64_t)c->No_pad * c->nc_cap;
-    CHK(dalloc(c, c->lpbuf, &c->Tt32, (int64_t)c->N_pad * mcol));
-    CHK(dalloc(c, c->lpbuf, &c->Ut32, (int64_t)c->N_pad * mcol));
-    CHK(dalloc(c, c->lpbuf, &c->at32, (int64_t)c->Nv_pad * mcol));
+    o.lpbuf.release();
+    o.lp_cap = 0;
+    const int64_t mcol = (int64_t)c->No_pad * o.nc_cap;
+    CHK(dalloc(c, o.lpbuf, &o.Tt32, (int64_t)c->N_pad * mcol));
+    CHK(dalloc(c, o.lpbuf, &o.Ut32, (int64_t)c->N_pad * mcol));
+    CHK(dalloc(c, o.lpbuf, &o.at32, (int64_t)c->Nv_pad * mcol));
     HIPCHK(c, hipDeviceSynchronize());
-    c->lp_cap = c->nc_cap;
+    o.lp_cap = o.nc_cap;
     return CHI0_OK;
 }
 
 // Y = chi0(omega) Zin for nb column pairs already in Zin; omega: device [nb].
 // prec selects the arithmetic of the orbital transforms (ensure_lp first).
-static void run_chi0(chi0_ctx *c, hipStream_t s, int nb, double eps, int prec, const double *omega) {
+static void run_chi0(chi0_ctx *c, OpWork &o, hipStream_t s, int nb, double eps, int prec,
+                     const double *omega) {
     const int nc = 2 * nb;
     Tracer *t = &c->tracer;
     const WorkSizes &w = c->ws;
     const int64_t mcol = (int64_t)c->No_pad * nc;
     // algorithmic work of the two dense transforms (unpadded sizes)
     const double fl = 2.0 * w.N * w.Nv * w.No * nc;
-    launch_vertex_gather(t, s, c->bm, c->n_blk, c->Zin, c->dV, nc, w);
+    launch_vertex_gather(t, s, c->bm, c->n_blk, o.Zin, o.dV, nc, w);
     if (prec == CHI0_PREC_FP64) {
-        launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, c->dV, c->Tt, nc, w);
-        launch_dgemm_lorentz(t, s, c->Nv_pad, (int)mcol, c->N_pad, c->Xvt, c->N_pad, c->Tt, (int)mcol,
-                             c->at, (int)mcol, c->Dlt, c->Nv_pad, omega, eps, c->occ, nc,
+        launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, o.dV, o.Tt, nc, w);
+        launch_dgemm_lorentz(t, s, c->Nv_pad, (int)mcol, c->N_pad, c->Xvt, c->N_pad, o.Tt, (int)mcol,
+                             o.at, (int)mcol, c->Dlt, c->Nv_pad, omega, eps, c->occ, nc,
                              fl + 6.0 * w.No * w.Nv * nb,
                              8.0 * (w.N * w.No * nc + w.Nv * w.No * nc + w.N * w.Nv + w.No * w.Nv),
-                             c->gemm_scratch, c->gemm_scratch_n, &c->tuner);
-        launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, c->at, (int)mcol,
-                     c->Ut, (int)mcol, fl, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv),
-                     c->gemm_scratch, c->gemm_scratch_n, &c->tuner);
-        launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, c->Ut, c->W, nc, w);
+                             o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
+        launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, o.at, (int)mcol,
+                     o.Ut, (int)mcol, fl, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv),
+                     o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
+        launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, o.Ut, o.W, nc, w);
     } else {
-        launch_occ_transform_f32(t, s, c->bm, c->n_atoms, c->Xo32, c->No_pad, c->dV, c->Tt32, nc, w);
+        launch_occ_transform_f32(t, s, c->bm, c->n_atoms, c->Xo32, c->No_pad, o.dV, o.Tt32, nc, w);
         LorentzArgs la{c->Dlt, omega, c->Nv_pad, nc, eps, c->occ};
-        const size_t sb = c->gemm_scratch_n * sizeof(double);
+        const size_t sb = o.gemm_scratch_n * sizeof(double);
         const double by = 4.0 * (w.N * w.No * nc + w.Nv * w.No * nc);
         if (prec == CHI0_PREC_FP32) {
             launch_sgemm(t, s, "virt_transform_lorentz_f32", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt32,
-                         c->N_pad, c->Tt32, (int)mcol, c->at32, (int)mcol, fl + 6.0 * w.No * w.Nv * nb,
-                         by + 4.0 * w.N * w.Nv, &la, c->gemm_scratch, sb, &c->tuner);
+                         c->N_pad, o.Tt32, (int)mcol, o.at32, (int)mcol, fl + 6.0 * w.No * w.Nv * nb,
+                         by + 4.0 * w.N * w.Nv, &la, o.gemm_scratch, sb, &c->tuner);
             launch_sgemm(t, s, "virt_back_f32", c->N_pad, (int)mcol, c->Nv_pad, c->Xv32, c->Nv_pad,
-                         c->at32, (int)mcol, c->Ut32, (int)mcol, fl, by + 4.0 * w.N * w.Nv, nullptr,
-                         c->gemm_scratch, sb, &c->tuner);
+                         o.at32, (int)mcol, o.Ut32, (int)mcol, fl, by + 4.0 * w.N * w.Nv, nullptr,
+                         o.gemm_scratch, sb, &c->tuner);
         } else {   // split BF16 x 3: three BF16 products per multiply-add
             launch_bgemm3(t, s, "virt_transform_lorentz_bf16x3", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt_hi,
-                          c->Xvt_lo, c->N_pad, c->Tt32, (int)mcol, c->at32, (int)mcol, 3.0 * fl,
-                          by + 4.0 * w.N * w.Nv, &la, c->gemm_scratch, sb);
+                          c->Xvt_lo, c->N_pad, o.Tt32, (int)mcol, o.at32, (int)mcol, 3.0 * fl,
+                          by + 4.0 * w.N * w.Nv, &la, o.gemm_scratch, sb);
             launch_bgemm3(t, s, "virt_back_bf16x3", c->N_pad, (int)mcol, c->Nv_pad, c->Xv_hi, c->Xv_lo,
-                          c->Nv_pad, c->at32, (int)mcol, c->Ut32, (int)mcol, 3.0 * fl,
-                          by + 4.0 * w.N * w.Nv, nullptr, c->gemm_scratch, sb);
+                          c->Nv_pad, o.at32, (int)mcol, o.Ut32, (int)mcol, 3.0 * fl,
+                          by + 4.0 * w.N * w.Nv, nullptr, o.gemm_scratch, sb);
         }
-        launch_occ_back_f32(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo32, c->No_pad, c->Ut32, c->W, nc, w);
+        launch_occ_back_f32(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo32, c->No_pad, o.Ut32, o.W, nc, w);
     }
-    launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, c->W, c->part, c->Yout, nc, w, c->max_nprod);
+    launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, o.W, o.part, o.Yout, nc, w, c->max_nprod);
 }
 
 static const int kMaxBatch = 256;   // complex columns per operator pass
@@ -725,14 +746,15 @@ extern "C" int chi0_apply(chi0_ctx *c, int32_t n_rhs, const double *omega, doubl
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int cap = std::min(kMaxBatch, std::max(n_rhs, 1));
-    CHK(ensure_ws(c, 2 * std::max(cap, c->nc_cap / 2)));
-    if (precision != CHI0_PREC_FP64) CHK(ensure_lp(c));
+    OpWork &ow = c->op[0];
+    CHK(ensure_ws(c, ow, 2 * std::max(cap, ow.nc_cap / 2)));
+    if (precision != CHI0_PREC_FP64) CHK(ensure_lp(c, ow));
     for (int r0 = 0; r0 < n_rhs; r0 += cap) {
         const int nb = std::min(cap, n_rhs - r0), nc = 2 * nb;
-        HIPCHK(c, hipMemcpyAsync(c->omega_dev, omega + r0, (size_t)nb * 8, hipMemcpyHostToDevice, s));
-        launch_rows_to_cols(&c->tracer, s, z + (int64_t)r0 * c->P * 2, nb, c->P, c->Zin, nc);
-        run_chi0(c, s, nb, eps, precision, c->omega_dev);
-        launch_cols_to_rows(&c->tracer, s, c->Yout, nb, c->P, nc, out + (int64_t)r0 * c->P * 2);
+        HIPCHK(c, hipMemcpyAsync(ow.omega_dev, omega + r0, (size_t)nb * 8, hipMemcpyHostToDevice, s));
+        launch_rows_to_cols(&c->tracer, s, z + (int64_t)r0 * c->P * 2, nb, c->P, ow.Zin, nc);
+        run_chi0(c, ow, s, nb, eps, precision, ow.omega_dev);
+        launch_cols_to_rows(&c->tracer, s, ow.Yout, nb, c->P, nc, out + (int64_t)r0 * c->P * 2);
     }
     HIPCHK(c, hipGetLastError());
     return CHI0_OK;
@@ -741,7 +763,8 @@ extern "C" int chi0_apply(chi0_ctx *c, int32_t n_rhs, const double *omega, doubl
 // ================================================================== solver
 static int ensure_slots(chi0_ctx *c, int n, int m) {
     if (n <= c->slot_n && m == c->slot_m) return CHI0_OK;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (hipStream_t ls : c->lane_stream)
+        if (ls) HIPCHK(c, hipStreamSynchronize(ls));
     c->slotbuf.release();
     c->slot_n = c->slot_m = 0;
     DevBuf &b = c->slotbuf;
@@ -762,11 +785,11 @@ static int ensure_slots(chi0_ctx *c, int n, int m) {
     CHK(dalloc(c, b, &sl.y, (int64_t)n * m * 2));
     const int64_t ab = (int64_t)n * (sizeof(Job) + sizeof(double));
     double *arena = nullptr;
-    CHK(dalloc(c, b, &arena, 2 * ab / 8));
+    CHK(dalloc(c, b, &arena, kSets * ab / 8));
     c->arena_dev = reinterpret_cast<char *>(arena);
-    CHK(dalloc(c, b, &c->fin_dev, 2 * n));
-    CHK(dalloc(c, b, &c->upd_dev, 2 * n));
-    CHK(dalloc(c, b, &c->status_dev, 2 * n));
+    CHK(dalloc(c, b, &c->fin_dev, kSets * n));
+    CHK(dalloc(c, b, &c->upd_dev, kSets * n));
+    CHK(dalloc(c, b, &c->status_dev, kSets * n));
     if (c->host_cap != n) {   // the host arena's layout depends on n
         if (c->arena_h) (void)hipHostFree(c->arena_h);
         if (c->fin_h) (void)hipHostFree(c->fin_h);
@@ -776,10 +799,10 @@ static int ensure_slots(chi0_ctx *c, int n, int m) {
         c->fin_h = c->upd_h = nullptr;
         c->status_h = nullptr;
         c->host_cap = 0;
-        HIPCHK(c, hipHostMalloc((void **)&c->arena_h, 2 * ab, hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc((void **)&c->fin_h, sizeof(Job) * 2 * n, hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc((void **)&c->upd_h, sizeof(Job) * 2 * n, hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc((void **)&c->status_h, sizeof(StepStatus) * 2 * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->arena_h, kSets * ab, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->fin_h, sizeof(Job) * kSets * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->upd_h, sizeof(Job) * kSets * n, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->status_h, sizeof(StepStatus) * kSets * n, hipHostMallocDefault));
         c->host_cap = n;
     }
     for (hipEvent_t &e : c->step_ev)
@@ -896,8 +919,9 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     if (o.precision < CHI0_PREC_FP64 || o.precision > CHI0_PREC_BF16X3)
         return fail(c, CHI0_EINVAL, "unknown precision");
     if (!(o.inner_tol >= 0.0) || !(o.inner_tol < 1.0)) return fail(c, CHI0_EINVAL, "inner_tol must be in [0, 1)");
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (o.reserved[i] != 0) return fail(c, CHI0_EINVAL, "reserved option fields must be zero");
+    if (o.lanes < 0 || o.lanes > kLanes) return fail(c, CHI0_EINVAL, "lanes must be 0 (auto), 1 or 2");
     if (o.ortho < CHI0_ORTHO_AUTO || o.ortho > CHI0_ORTHO_DCGS2) return fail(c, CHI0_EINVAL, "unknown ortho");
     // delayed reorthogonalisation needs a few columns per cycle (one is always provisional)
     const bool dcgs = o.ortho == CHI0_ORTHO_DCGS2 || (o.ortho == CHI0_ORTHO_AUTO && o.restart >= 8);
@@ -916,23 +940,33 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     // provisional column, so it gets one more basis vector
     const int m = o.restart + (dcgs ? 1 : 0);
     const int P = c->P;
-    CHK(ensure_ws(c, 2 * std::max(nsl, c->nc_cap / 2)));
-    if (o.precision != CHI0_PREC_FP64) CHK(ensure_lp(c));
+    // Slots are dealt to lanes (slot k to lane k mod nl), each lane with its own
+    // stream, operator workspace and step buffers, so that one lane's
+    // memory-bound Gram-Schmidt passes can run beside the other lane's
+    // matrix-core transforms.  Dealing the slots mixes the frequencies, whose
+    // iteration counts differ by up to 5x, over both lanes.  Small batches use
+    // one lane.
+    const int nl = std::min(nsl, o.lanes > 0 ? o.lanes : (nsl >= 16 ? kLanes : 1));
+    for (int L = 0; L < nl; ++L) {
+        const int ln = (nsl - L + nl - 1) / nl;
+        CHK(ensure_ws(c, c->op[L], 2 * std::max(ln, c->op[L].nc_cap / 2)));
+        if (o.precision != CHI0_PREC_FP64) CHK(ensure_lp(c, c->op[L]));
+    }
     CHK(ensure_slots(c, nsl, m));
-    hipStream_t s = c->stream;
     Tracer *t = &c->tracer;
 
     // per-call device buffers: drives and alpha
     DevBuf callbuf;
-    // on every exit (also an error with steps in flight) drain the stream first
+    // on every exit (also an error with steps in flight) drain the lanes first
     struct Guard {
         DevBuf *b;
-        hipStream_t s;
+        chi0_ctx *c;
         ~Guard() {
-            (void)hipStreamSynchronize(s);
+            for (hipStream_t ls : c->lane_stream)
+                if (ls) (void)hipStreamSynchronize(ls);
             b->release();
         }
-    } guard{&callbuf, c->stream};
+    } guard{&callbuf, c};
     double *drives = nullptr, *alpha_dev = nullptr;
     CHK(dalloc(c, callbuf, &drives, (int64_t)n_drive * c->P_pad));
     CHK(dalloc(c, callbuf, &alpha_dev, (int64_t)npts * n_drive * 2));
@@ -943,23 +977,30 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     std::vector<SlotState> sl(nsl);
     std::vector<PointState> ps(npts);
     int next_point = 0, done = 0;
-    std::vector<Job> fin, upd, rst, wnew;
-    std::vector<double> wom;
 
-    // Two steps are kept in flight.  While the GPU runs step s+1 the host reads
-    // the status of step s and decides what step s+2 does.  A slot in its
-    // Arnoldi phase is launched again before the host has seen its previous
-    // step; if that previous step ends the cycle, the extra step is void (its
-    // epoch no longer matches).  It only wrote basis vectors, Hessenberg
-    // columns and rotations beyond the cycle's length L, which the update of x
-    // never reads.  b and residual jobs are never launched ahead.
+    // Each lane keeps two steps in flight.  While the GPU runs step s+1 the
+    // host reads the status of step s and decides what step s+2 does.  A slot
+    // in its Arnoldi phase is launched again before the host has seen its
+    // previous step; if that previous step ends the cycle, the extra step is
+    // void (its epoch no longer matches).  It only wrote basis vectors,
+    // Hessenberg columns and rotations beyond the cycle's length L, which the
+    // update of x never reads.  b and residual jobs are never launched ahead.
     struct InFlight {
         int nb = 0;
+        int64_t seq = 0;
         std::vector<int> epoch;
-    } fl[2];
-    int q_launch = 0, n_inflight = 0, q_oldest = 0;
+    } fl[kSets];
+    struct LaneState {
+        int q_launch = 0, n_inflight = 0, q_oldest = 0, last_q = 0;
+        std::vector<Job> fin, upd, rst, wnew;
+        std::vector<double> wom;
+    } lanes[kLanes];
+    for (int L = 0; L < nl; ++L) lanes[L].q_launch = lanes[L].q_oldest = lanes[L].last_q = 2 * L;
+    int64_t seq = 0;
 
-    auto plan_and_launch = [&](int q) -> int {
+    auto plan_and_launch = [&](int L, int q) -> int {
+        hipStream_t s = c->lane_stream[L];
+        OpWork &ow = c->op[L];
         Job *jobs_h = c->jobs_h(q);
         double *om_h = c->omega_h(q);
         InFlight &f = fl[q];
@@ -969,7 +1010,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
         // FP64 jobs first (b, true residual, FP64 Arnoldi), then the
         // low-precision Arnoldi steps: each group is one operator pass
         for (int pass = 0; pass < 2; ++pass)
-            for (int k = 0; k < nsl; ++k) {
+            for (int k = L; k < nsl; k += nl) {
                 SlotState &ss = sl[k];
                 if (ss.state == S_FREE || ss.busy) continue;
                 const bool lowp = ss.state == S_ARNOLDI && ss.prec != CHI0_PREC_FP64;
@@ -997,44 +1038,46 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 if (pass == 0) ++nb64;
             }
         f.nb = nb;
+        f.seq = seq++;
         if (nb == 0) return CHI0_OK;
         Job *jobs_d = c->jobs_dev(q);
         double *om_d = c->somega_dev(q);
-        HIPCHK(c, hipMemcpyAsync(c->jobs_dev(q), jobs_h, c->slot_n * sizeof(Job) + nb * sizeof(double),
+        StepStatus *st_d = c->status_dev + q * nsl;
+        HIPCHK(c, hipMemcpyAsync(jobs_d, jobs_h, c->slot_n * sizeof(Job) + nb * sizeof(double),
                                  hipMemcpyHostToDevice, s));
         // operator per group: Zin = K v (b jobs: d), Y = chi0 Zin, then post
         auto run_group = [&](int g0, int gn, int prec) {
             const int nc = 2 * gn;
             const Job *jg = jobs_d + g0;
-            launch_gather_jobs(t, s, jg, gn, c->slots, c->Vb, nc, P);
+            launch_gather_jobs(t, s, jg, gn, c->slots, ow.Vb, nc, P);
             if (nc <= 16)
-                launch_kmatvec_skinny(t, s, c->P_pad, c->K, c->Vb, c->Zin, nc, (double)P);
+                launch_kmatvec_skinny(t, s, c->P_pad, c->K, ow.Vb, ow.Zin, nc, (double)P);
             else
-                launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, c->Vb, nc, c->Zin,
+                launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, ow.Vb, nc, ow.Zin,
                              nc, 2.0 * P * (double)P * nc, 8.0 * ((double)P * P + 2.0 * P * nc),
-                             c->gemm_scratch, c->gemm_scratch_n, &c->tuner);
-            launch_put_drive(t, s, jg, gn, drives, c->P_pad, c->Zin, nc, P);
-            run_chi0(c, s, gn, eps, prec, om_d + g0);
-            launch_post_jobs(t, s, jg, gn, c->slots, c->Yout, nc, P, c->status_dev + q * nsl + g0);
+                             ow.gemm_scratch, ow.gemm_scratch_n, &c->tuner);
+            launch_put_drive(t, s, jg, gn, drives, c->P_pad, ow.Zin, nc, P);
+            run_chi0(c, ow, s, gn, eps, prec, om_d + g0);
+            launch_post_jobs(t, s, jg, gn, c->slots, ow.Yout, nc, P, st_d + g0);
         };
         if (nb64 > 0) run_group(0, nb64, CHI0_PREC_FP64);
         if (nb > nb64) run_group(nb64, nb - nb64, o.precision);
         if (n_arn > 0) {
             if (dcgs)
-                launch_dcgs(t, s, jobs_d, nb, jmax, c->slots, P, c->status_dev + q * nsl, n_arn, sum_j1,
-                            c->gemm_scratch, c->gemm_scratch_n);
+                launch_dcgs(t, s, jobs_d, nb, jmax, c->slots, P, st_d, n_arn, sum_j1, ow.gemm_scratch,
+                            ow.gemm_scratch_n);
             else
-                launch_arnoldi(t, s, jobs_d, nb, jmax, c->slots, P, c->status_dev + q * nsl, n_arn, sum_j1);
+                launch_arnoldi(t, s, jobs_d, nb, jmax, c->slots, P, st_d, n_arn, sum_j1);
         }
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipMemcpyAsync(c->status_h + q * nsl, c->status_dev + q * nsl, sizeof(StepStatus) * nb,
-                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(c->status_h + q * nsl, st_d, sizeof(StepStatus) * nb, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipEventRecord(c->step_ev[q], s));
         return CHI0_OK;
     };
 
-    // Advance the slot state machines with the status of the step in set q.
-    auto process = [&](int q) {
+    // Advance the slot state machines of lane L with the status of its step in set q.
+    auto process = [&](int L, int q) {
+        LaneState &ln = lanes[L];
         const InFlight &f = fl[q];
         const Job *jobs_h = c->jobs_h(q);
         const StepStatus *sts = c->status_h + q * nsl;
@@ -1054,10 +1097,10 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 // CGS2: the step completes column j (dimension j+1).  Delayed
                 // reorthogonalisation: it completes column j-1 (dimension j) and
                 // leaves column j provisional, so a cycle uses the first j columns.
-                const int L = dcgs ? jb.j : jb.j + 1;
-                const bool est_ok = L >= 1 && st.value <= stop;
+                const int Lc = dcgs ? jb.j : jb.j + 1;
+                const bool est_ok = Lc >= 1 && st.value <= stop;
                 if (est_ok || brk || jb.j + 1 >= m || pt.iters >= o.max_iter || !std::isfinite(st.value)) {
-                    if (L >= 1) upd.push_back({jb.slot, 0, L, 0});
+                    if (Lc >= 1) ln.upd.push_back({jb.slot, 0, Lc, 0});
                     ss.state = S_RESID;
                     ss.epoch += 1;
                     ss.pend = 0;
@@ -1074,8 +1117,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 if (!(st.value > 0.0) || !std::isfinite(st.value)) {
                     pt.rel = st.value == 0.0 ? 0.0 : NAN;
                     pt.converged = st.value == 0.0;
-                    if (ws) rst.push_back({jb.slot, 0, 0, 0});   // x = 0 is the answer
-                    fin.push_back({jb.slot, 0, ss.point, 0});
+                    if (ws) ln.rst.push_back({jb.slot, 0, 0, 0});   // x = 0 is the answer
+                    ln.fin.push_back({jb.slot, 0, ss.point, 0});
                     ss.state = S_FREE;
                     ++done;
                 } else if (ws) {
@@ -1094,12 +1137,12 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 if (rel0 <= o.tol) {                        // the warm start is already the answer
                     pt.warm = 1;
                     pt.converged = 1;
-                    fin.push_back({jb.slot, 0, ss.point, 0});
+                    ln.fin.push_back({jb.slot, 0, ss.point, 0});
                     ss.state = S_FREE;
                     ++done;
                 } else if (!(rel0 < 1.0)) {                 // no better than x0 = 0: zero start
                     pt.warm = 2;
-                    rst.push_back({jb.slot, 0, 0, 0});
+                    ln.rst.push_back({jb.slot, 0, 0, 0});
                     ss.cycle0 = ss.bnorm;
                     ss.rel_prev = 1.0;
                     ss.state = S_ARNOLDI;
@@ -1118,7 +1161,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 pt.rel = st.value / ss.bnorm;
                 if (pt.rel <= o.tol || pt.iters >= o.max_iter || !std::isfinite(pt.rel)) {
                     pt.converged = pt.rel <= o.tol;
-                    fin.push_back({jb.slot, 0, ss.point, 0});
+                    ln.fin.push_back({jb.slot, 0, ss.point, 0});
                     ss.state = S_FREE;
                     ++done;
                 } else {
@@ -1138,46 +1181,65 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
         }
     };
 
-    // Work decided by the last processed status, issued in stream order
-    // before the next step.  Each list uses the host set of that status's
-    // step: it is rewritten only after the host has waited for that set's
-    // next step, which follows these copies on the stream.
-    auto issue_pending = [&](int q) -> int {
+    // Work of lane L decided by its last processed status, issued on its
+    // stream before its next step.  Each list uses the host set q of that
+    // status's step: the set is rewritten only after the host has waited for
+    // the set's next step, which follows these copies on the stream.
+    auto issue_pending = [&](int L, int q) -> int {
+        LaneState &ln = lanes[L];
+        hipStream_t s = c->lane_stream[L];
         Job *fin_h = c->fin_h + q * nsl, *upd_h = c->upd_h + q * nsl;
         Job *fin_d = c->fin_dev + q * nsl, *upd_d = c->upd_dev + q * nsl;
-        if (!rst.empty()) {   // zero start for rejected warm starts (and x = 0 where b = 0)
+        if (!ln.rst.empty()) {   // zero start for rejected warm starts (and x = 0 where b = 0)
             HIPCHK(c, hipStreamSynchronize(s));   // upd_h is reused below
-            std::copy(rst.begin(), rst.end(), upd_h);
-            HIPCHK(c, hipMemcpyAsync(upd_d, upd_h, sizeof(Job) * rst.size(), hipMemcpyHostToDevice, s));
-            launch_reset_slots(s, upd_d, (int)rst.size(), c->slots, P);
+            std::copy(ln.rst.begin(), ln.rst.end(), upd_h);
+            HIPCHK(c, hipMemcpyAsync(upd_d, upd_h, sizeof(Job) * ln.rst.size(), hipMemcpyHostToDevice, s));
+            launch_reset_slots(s, upd_d, (int)ln.rst.size(), c->slots, P);
             HIPCHK(c, hipStreamSynchronize(s));
-            rst.clear();
+            ln.rst.clear();
         }
         // polarizability (and stored solution) of finished points, before the slot is reused
-        if (!fin.empty()) {
-            std::copy(fin.begin(), fin.end(), fin_h);
-            HIPCHK(c, hipMemcpyAsync(fin_d, fin_h, sizeof(Job) * fin.size(), hipMemcpyHostToDevice, s));
-            launch_alpha(t, s, fin_d, (int)fin.size(), c->slots, drives, n_drive, c->P_pad, P, nullptr,
+        if (!ln.fin.empty()) {
+            std::copy(ln.fin.begin(), ln.fin.end(), fin_h);
+            HIPCHK(c, hipMemcpyAsync(fin_d, fin_h, sizeof(Job) * ln.fin.size(), hipMemcpyHostToDevice, s));
+            launch_alpha(t, s, fin_d, (int)ln.fin.size(), c->slots, drives, n_drive, c->P_pad, P, nullptr,
                          alpha_dev);
-            if (x_out) launch_store_x(s, fin_d, (int)fin.size(), c->slots, P, x_out);
-            fin.clear();
+            if (x_out) launch_store_x(s, fin_d, (int)ln.fin.size(), c->slots, P, x_out);
+            ln.fin.clear();
         }
         // x += V y for slots that ended a cycle
-        if (!upd.empty()) {
+        if (!ln.upd.empty()) {
             int jm = 0;
             double sumL = 0.0;
-            for (auto &u : upd) {
+            for (auto &u : ln.upd) {
                 jm = std::max(jm, u.j);
                 sumL += u.j;
             }
-            std::copy(upd.begin(), upd.end(), upd_h);
-            HIPCHK(c, hipMemcpyAsync(upd_d, upd_h, sizeof(Job) * upd.size(), hipMemcpyHostToDevice, s));
-            launch_update_x(t, s, upd_d, (int)upd.size(), jm, c->slots, P, sumL);
-            upd.clear();
+            std::copy(ln.upd.begin(), ln.upd.end(), upd_h);
+            HIPCHK(c, hipMemcpyAsync(upd_d, upd_h, sizeof(Job) * ln.upd.size(), hipMemcpyHostToDevice, s));
+            launch_update_x(t, s, upd_d, (int)ln.upd.size(), jm, c->slots, P, sumL);
+            ln.upd.clear();
         }
-        // refill free slots; warm-started points get x0 = U c(omega) now
-        wnew.clear();
-        wom.clear();
+        // warm-started points new in this lane's slots get x0 = U c(omega) now
+        if (!ln.wnew.empty()) {
+            // the network's buffers are shared by the lanes: this stream finishes
+            // its inference before the host moves on
+            HIPCHK(c, hipStreamSynchronize(s));   // fin_h copies done; reuse fin_h
+            std::copy(ln.wnew.begin(), ln.wnew.end(), fin_h);
+            HIPCHK(c, hipMemcpyAsync(ws->jobs_dev, fin_h, sizeof(Job) * ln.wnew.size(), hipMemcpyHostToDevice, s));
+            CHK(ws_infer(ws, s, (int)ln.wnew.size(), ln.wom.data()));
+            launch_ws_apply(s, ws->jobs_dev, (int)ln.wnew.size(), ws->out, ws->O, ws->mean, ws->sdev, ws->r,
+                            ws->U, (int64_t)c->P_pad * 2, c->slots.x, (int64_t)c->P_pad * 2, P);
+            HIPCHK(c, hipStreamSynchronize(s));
+            ln.wnew.clear();
+            ln.wom.clear();
+        }
+        return CHI0_OK;
+    };
+
+    // Free slots take the next points in slot order, so consecutive points
+    // (neighbouring frequencies, alike in cost) alternate between the lanes.
+    auto refill = [&]() {
         for (int k = 0; k < nsl; ++k)
             if (sl[k].state == S_FREE && !sl[k].busy && next_point < npts) {
                 sl[k].state = S_RHS;
@@ -1187,43 +1249,45 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 sl[k].epoch += 1;
                 sl[k].warm_check = false;
                 if (ws) {
-                    wnew.push_back({k, 0, sl[k].point, 0});
-                    wom.push_back(omega[sl[k].point / n_drive]);
+                    LaneState &ln = lanes[k % nl];
+                    ln.wnew.push_back({k, 0, sl[k].point, 0});
+                    ln.wom.push_back(omega[sl[k].point / n_drive]);
                 }
             }
-        if (!wnew.empty()) {
-            HIPCHK(c, hipStreamSynchronize(s));   // fin_h copies done; reuse fin_h
-            std::copy(wnew.begin(), wnew.end(), fin_h);
-            HIPCHK(c, hipMemcpyAsync(ws->jobs_dev, fin_h, sizeof(Job) * wnew.size(), hipMemcpyHostToDevice, s));
-            CHK(ws_infer(ws, s, (int)wnew.size(), wom.data()));
-            launch_ws_apply(s, ws->jobs_dev, (int)wnew.size(), ws->out, ws->O, ws->mean, ws->sdev, ws->r, ws->U,
-                            (int64_t)c->P_pad * 2, c->slots.x, (int64_t)c->P_pad * 2, P);
-            HIPCHK(c, hipStreamSynchronize(s));
-        }
-        return CHI0_OK;
     };
 
-    int last_q = 0;
     for (;;) {
-        CHK(issue_pending(last_q));
-        while (n_inflight < 2) {
-            CHK(plan_and_launch(q_launch));
-            if (fl[q_launch].nb == 0) break;
-            if (n_inflight == 0) q_oldest = q_launch;
-            ++n_inflight;
-            q_launch ^= 1;
+        refill();
+        for (int L = 0; L < nl; ++L) {
+            LaneState &ln = lanes[L];
+            CHK(issue_pending(L, ln.last_q));
+            while (ln.n_inflight < 2) {
+                CHK(plan_and_launch(L, ln.q_launch));
+                if (fl[ln.q_launch].nb == 0) break;
+                if (ln.n_inflight == 0) ln.q_oldest = ln.q_launch;
+                ++ln.n_inflight;
+                ln.q_launch ^= 1;   // sets 2L and 2L+1
+            }
         }
-        if (n_inflight == 0) {
+        // process the oldest step over all lanes
+        int Lw = -1;
+        for (int L = 0; L < nl; ++L)
+            if (lanes[L].n_inflight > 0 && (Lw < 0 || fl[lanes[L].q_oldest].seq < fl[lanes[Lw].q_oldest].seq))
+                Lw = L;
+        if (Lw < 0) {
             if (done < npts) return fail(c, CHI0_EHIP, "solver stalled with unfinished points");
             break;
         }
-        HIPCHK(c, hipEventSynchronize(c->step_ev[q_oldest]));
-        process(q_oldest);
-        last_q = q_oldest;
-        q_oldest ^= 1;
-        --n_inflight;
+        LaneState &ln = lanes[Lw];
+        HIPCHK(c, hipEventSynchronize(c->step_ev[ln.q_oldest]));
+        process(Lw, ln.q_oldest);
+        ln.last_q = ln.q_oldest;
+        ln.q_oldest ^= 1;
+        --ln.n_inflight;
     }
-    CHK(issue_pending(last_q));   // finished points still waiting for their alpha
+    for (int L = 0; L < nl; ++L) CHK(issue_pending(L, lanes[L].last_q));   // alpha of the last points
+    for (int L = 0; L < nl; ++L) HIPCHK(c, hipStreamSynchronize(c->lane_stream[L]));
+    hipStream_t s = c->stream;
     std::vector<double> ah((size_t)npts * n_drive * 2);
     HIPCHK(c, hipMemcpyAsync(ah.data(), alpha_dev, ah.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
@@ -1612,17 +1676,18 @@ extern "C" int chi0_debug_dims(const chi0_ctx *c, int64_t *d) {
 extern "C" int chi0_debug_read(chi0_ctx *c, int32_t which, void *host, int64_t bytes) {
     if (!c || !host || bytes < 0) return CHI0_EINVAL;
     if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no device system");
-    const int64_t nc = c->nc_cap, mcol = (int64_t)c->No_pad * nc;
+    const OpWork &o = c->op[0];
+    const int64_t nc = o.nc_cap, mcol = (int64_t)c->No_pad * nc;
     const void *src = nullptr;
     int64_t cap = 0;
     switch (which) {
-        case CHI0_DBG_ZIN: src = c->Zin; cap = (int64_t)c->P_pad * nc * 8; break;
-        case CHI0_DBG_DV: src = c->dV; cap = c->nnzB * nc * 8; break;
-        case CHI0_DBG_TT: src = c->Tt; cap = (int64_t)c->N_pad * mcol * 8; break;
-        case CHI0_DBG_AT: src = c->at; cap = (int64_t)c->Nv_pad * mcol * 8; break;
-        case CHI0_DBG_UT: src = c->Ut; cap = (int64_t)c->N_pad * mcol * 8; break;
-        case CHI0_DBG_W: src = c->W; cap = c->nnzB * nc * 8; break;
-        case CHI0_DBG_YOUT: src = c->Yout; cap = (int64_t)c->P_pad * nc * 8; break;
+        case CHI0_DBG_ZIN: src = o.Zin; cap = (int64_t)c->P_pad * nc * 8; break;
+        case CHI0_DBG_DV: src = o.dV; cap = c->nnzB * nc * 8; break;
+        case CHI0_DBG_TT: src = o.Tt; cap = (int64_t)c->N_pad * mcol * 8; break;
+        case CHI0_DBG_AT: src = o.at; cap = (int64_t)c->Nv_pad * mcol * 8; break;
+        case CHI0_DBG_UT: src = o.Ut; cap = (int64_t)c->N_pad * mcol * 8; break;
+        case CHI0_DBG_W: src = o.W; cap = c->nnzB * nc * 8; break;
+        case CHI0_DBG_YOUT: src = o.Yout; cap = (int64_t)c->P_pad * nc * 8; break;
         case CHI0_DBG_BLK_NA: src = c->bm.blk_na; cap = (int64_t)c->n_blk * 4; break;
         case CHI0_DBG_BLK_NB: src = c->bm.blk_nb; cap = (int64_t)c->n_blk * 4; break;
         case CHI0_DBG_BLK_ENT: src = c->bm.blk_ent; cap = (int64_t)c->n_blk * 8; break;
