@@ -353,8 +353,9 @@ void k_arnoldi_finalize(const Job *__restrict__ jobs, SlotsDev sl, int P, StepSt
 // rho; scratch of the Givens scan from 2j+2 (j-1 entries): 3m+4 in all.
 
 // s_i = <v_i | v~_j>, t_i = <v_i | z> for i < j; for i = j: sigma = <v~_j|v~_j>,
-// tau = <v~_j|z>.  Each wavefront takes 4 consecutive i, so v~_j and z are
-// loaded once per 4 basis vectors.
+// tau = <v~_j|z>.  Each wavefront takes DPW consecutive i, so v~_j and z are
+// loaded once per DPW basis vectors (DPW = 4 measured fastest: 2 re-reads more
+// of v~_j and z, 8 gives too few wavefronts).
 constexpr int DPW = 4;
 __global__ __launch_bounds__(256)
 void k_dcgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P) {
@@ -373,17 +374,20 @@ void k_dcgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P) {
     double sr[DPW], si[DPW], tr[DPW], ti[DPW];
 #pragma unroll
     for (int k = 0; k < DPW; ++k) sr[k] = si[k] = tr[k] = ti[k] = 0.0;
+    // a group shorter than DPW repeats its last vector (its sums are not stored),
+    // so the loop has no branch and its loads can be issued ahead
+    int64_t off[DPW];
+#pragma unroll
+    for (int k = 0; k < DPW; ++k) off[k] = (int64_t)min(k, nv - 1) * vst;
     for (int mu = lane; mu < P; mu += 64) {
         const double2 b = vt[mu], c = z[mu];
 #pragma unroll
         for (int k = 0; k < DPW; ++k) {
-            if (k < nv) {
-                const double2 a = vi[(int64_t)k * vst + mu];
-                sr[k] += a.x * b.x + a.y * b.y;
-                si[k] += a.x * b.y - a.y * b.x;
-                tr[k] += a.x * c.x + a.y * c.y;
-                ti[k] += a.x * c.y - a.y * c.x;
-            }
+            const double2 a = vi[off[k] + mu];
+            sr[k] += a.x * b.x + a.y * b.y;
+            si[k] += a.x * b.y - a.y * b.x;
+            tr[k] += a.x * c.x + a.y * c.y;
+            ti[k] += a.x * c.y - a.y * c.x;
         }
     }
 #pragma unroll
