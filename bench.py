@@ -272,9 +272,9 @@ def main():
 
     tuned = ctx.autotune_table()
     for k, v in sorted(tuned.items()):
-        us = ", ".join(f"{x:.0f}" if x > 0 else "-" for x in v["us"])
-        print(f"[bench] autotune {k:58s} -> {v['tile']:8s} (us per variant 64x64,64x128,128x64,128x128: {us})",
-              file=sys.stderr)
+        us = ", ".join(f"{x:.0f}" if x > 0 else "-" for x in v["us"][:6])
+        print(f"[bench] autotune {k:58s} -> {v['tile']:10s} (us per variant 64x64, 64x128, 128x64, "
+              f"128x128, 64x64/k32, 64x128/k32: {us})", file=sys.stderr)
 
     cpu = None
     if a.cpu_sample > 0:

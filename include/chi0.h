@@ -304,22 +304,26 @@ int chi0_set_timing_filter(chi0_ctx *ctx, const char *names);
  * transforms and the batched kernel product K V).  Enabled by default: the
  * first GEMM of a new shape class (kernel, M, K, split count, N within a half
  * octave) on a context times each valid tile variant (64x64, 64x128, 128x64,
- * 128x128 outputs per workgroup) once after a warm launch, on the call's
+ * 128x128 outputs per workgroup with k tiles of 16; 64x64 and 64x128 with k
+ * tiles of 32) once after a warm launch, on the call's
  * stream, and keeps the fastest for that class.  All variants accumulate each
  * output element in the same order, so tuning never changes a result, only
  * the time; it does add a synchronisation of the stream on each new class.
- * chi0_set_autotune(ctx, 0) uses the 64x64 variant everywhere.
+ * chi0_set_autotune(ctx, mode): 1 tunes (default), 0 uses the 64x64 variant
+ * everywhere, 100 + v forces variant v wherever it is valid for the shape
+ * (64x64 elsewhere) without timing, for tests; other values: CHI0_EINVAL.
  * chi0_autotune_table copies up to `cap` entries of the context's table and
  * returns the number of entries (or a negative error code).
  */
 typedef struct chi0_tune_record {
     char    key[96];      /* shape class */
     char    tile[16];     /* chosen variant, e.g. "64x128" */
-    int32_t variant;      /* its index 0..3 */
-    float   us[4];        /* timed launch of each variant in microseconds; 0 = not valid for the shape */
+    int32_t variant;      /* its index 0..5 */
+    float   us[8];        /* timed launch of each variant in microseconds; 0 = not valid for the
+                             shape (or beyond the variants of this build) */
 } chi0_tune_record;
 
-int chi0_set_autotune(chi0_ctx *ctx, int32_t enable);
+int chi0_set_autotune(chi0_ctx *ctx, int32_t mode);
 int chi0_autotune_table(chi0_ctx *ctx, chi0_tune_record *records, int32_t cap);
 
 #ifdef __cplusplus

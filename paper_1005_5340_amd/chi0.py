@@ -54,7 +54,7 @@ class PointStats(C.Structure):
 
 class TuneRecord(C.Structure):
     _fields_ = [("key", C.c_char * 96), ("tile", C.c_char * 16), ("variant", C.c_int32),
-                ("us", C.c_float * 4)]
+                ("us", C.c_float * 8)]
 
 
 class KernelRecord(C.Structure):
@@ -303,8 +303,10 @@ class Context:
         self._check(self._L.chi0_set_timing_filter(self._h, names))
         self._check(self._L.chi0_set_timing(self._h, 1 if enable else 0))
 
-    def set_autotune(self, enable: bool):
-        self._check(self._L.chi0_set_autotune(self._h, 1 if enable else 0))
+    def set_autotune(self, enable: bool, force_variant: int = -1):
+        """Tile autotuning on/off; force_variant >= 0 forces that tile variant (tests)."""
+        mode = 100 + force_variant if force_variant >= 0 else (1 if enable else 0)
+        self._check(self._L.chi0_set_autotune(self._h, mode))
 
     def autotune_table(self) -> dict:
         """{shape class: dict(tile, variant, us=[per-variant microseconds, 0 = not valid])}."""

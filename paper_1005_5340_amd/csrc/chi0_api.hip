@@ -314,9 +314,15 @@ extern "C" int chi0_set_timing_filter(chi0_ctx *ctx, const char *names) {
     return CHI0_OK;
 }
 
-extern "C" int chi0_set_autotune(chi0_ctx *ctx, int32_t enable) {
+extern "C" int chi0_set_autotune(chi0_ctx *ctx, int32_t mode) {
     if (!ctx) return CHI0_EINVAL;
-    ctx->tuner.enabled = enable != 0;
+    if (mode >= 100 && mode < 100 + GEMM_VARIANTS) {
+        ctx->tuner.force = mode - 100;
+        return CHI0_OK;
+    }
+    if (mode != 0 && mode != 1) return fail(ctx, CHI0_EINVAL, "autotune mode must be 0, 1 or 100 + variant");
+    ctx->tuner.force = -1;
+    ctx->tuner.enabled = mode != 0;
     return CHI0_OK;
 }
 
@@ -329,7 +335,7 @@ extern "C" int chi0_autotune_table(chi0_ctx *ctx, chi0_tune_record *rec, int32_t
             std::snprintf(rec[i].key, sizeof(rec[i].key), "%s", kv.first.c_str());
             rec[i].variant = kv.second.variant;
             std::snprintf(rec[i].tile, sizeof(rec[i].tile), "%s", kGemmVariantNames[kv.second.variant]);
-            for (int v = 0; v < GEMM_VARIANTS && v < 4; ++v) rec[i].us[v] = kv.second.us[v];
+            for (int v = 0; v < GEMM_VARIANTS && v < 8; ++v) rec[i].us[v] = kv.second.us[v];
         }
         ++i;
     }

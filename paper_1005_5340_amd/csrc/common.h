@@ -30,7 +30,7 @@ namespace chi0 {
 constexpr int TILE = 64;     // M/N tile of the dense GEMMs, E tile of the gathered ones
 constexpr int JT = 16;       // column tile of the gathered GEMMs and of ncp
 constexpr int NB_MAX = 16;   // maximum orbitals per atom supported by the gathered GEMMs
-constexpr int GEMM_VARIANTS = 4;   // tile shapes of the dense GEMM (see GemmTuner)
+constexpr int GEMM_VARIANTS = 6;   // tile shapes of the dense GEMM (see GemmTuner)
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -108,6 +108,7 @@ struct GemmTuner {
         float us[GEMM_VARIANTS] = {};   // timed launch per variant (0: not valid for the shape)
     };
     bool enabled = true;
+    int force = -1;   // >= 0: use this variant wherever it is valid (tests), no timing
     std::map<std::string, Entry> table;
     hipEvent_t ev[2] = {nullptr, nullptr};
     ~GemmTuner();

@@ -65,7 +65,7 @@ __device__ __forceinline__ int xcd_remap(int wid, int n) {
 // The tile shape (BM x BN, WM x WN wavefronts) changes only which workgroup
 // computes an element, never the order of its k accumulation, so every tile
 // variant gives bit-identical results and the autotuner may pick any of them.
-template <class T, int BM, int BN, int WM, int WN, bool LORENTZ>
+template <class T, int BM, int BN, int WM, int WN, bool LORENTZ, int BK = 16>
 __global__ __launch_bounds__(WM * WN * 64)
 void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
              const T *__restrict__ B, int ldb, T *__restrict__ C, int ldc,
@@ -73,7 +73,6 @@ void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
     A += (int64_t)blockIdx.y * K;
     B += (int64_t)blockIdx.y * K * ldb;
     C += (int64_t)blockIdx.y * M * ldc;
-    constexpr int BK = 16;
     constexpr int NT = WM * WN * 64;
     constexpr int TM = BM / WM / 16;
     constexpr int TN = BN / WN / 16;
@@ -97,8 +96,8 @@ void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
 #pragma unroll
     for (int q = 0; q < CA; ++q) {
         const int ch = t + q * NT;
-        a_row[q] = ch / 4;
-        a_k[q] = (ch % 4) * 4;
+        a_row[q] = ch / (BK / 4);
+        a_k[q] = (ch % (BK / 4)) * 4;
     }
 #pragma unroll
     for (int q = 0; q < CB; ++q) {
@@ -262,8 +261,10 @@ static void reduce_splits(Tracer *t, hipStream_t s, int M, int N, int S, const T
     trace_end(t, s, (double)S * M * N, (double)sizeof(T) * ((double)S + 1.0) * M * N);
 }
 
-const char *const kGemmVariantNames[GEMM_VARIANTS] = {"64x64", "64x128", "128x64", "128x128"};
-static const int kVarBM[GEMM_VARIANTS] = {64, 64, 128, 128};
+const char *const kGemmVariantNames[GEMM_VARIANTS] = {"64x64", "64x128", "128x64", "128x128",
+                                                      "64x64/k32", "64x128/k32"};
+static const int kVarBM[GEMM_VARIANTS] = {64, 64, 128, 128, 64, 64};
+static const int kVarBK[GEMM_VARIANTS] = {16, 16, 16, 16, 32, 32};
 
 GemmTuner::~GemmTuner() {
     for (hipEvent_t &e : ev)
@@ -288,6 +289,14 @@ static void launch_variant(int v, hipStream_t s, dim3 grid_s, int M, int N, int 
         hipLaunchKernelGGL((k_dgemm<T, 128, 128, 2, 2, LZ>), dim3(tiles(128, 128), S), dim3(256), 0, s,
                            M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
         break;
+    case 4:
+        hipLaunchKernelGGL((k_dgemm<T, 64, 64, 2, 2, LZ, 32>), dim3(tiles(64, 64), S), dim3(256), 0, s,
+                           M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        break;
+    case 5:
+        hipLaunchKernelGGL((k_dgemm<T, 64, 128, 2, 2, LZ, 32>), dim3(tiles(64, 128), S), dim3(256), 0, s,
+                           M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+        break;
     default:
         hipLaunchKernelGGL((k_dgemm<T, 64, 64, 2, 2, LZ>), dim3(tiles(64, 64), S), dim3(256), 0, s,
                            M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
@@ -300,7 +309,10 @@ template <class T, bool LZ>
 static int pick_variant(GemmTuner *tu, hipStream_t s, const char *name, int S, int M, int N, int K,
                         const T *A, int lda, const T *B, int ldb, T *C, int ldc, int m_fastest,
                         const LorentzArgs &la) {
-    if (!tu || !tu->enabled) return 0;
+    if (!tu) return 0;
+    if (tu->force >= 0 && tu->force < GEMM_VARIANTS)
+        return (M % kVarBM[tu->force] == 0 && K % kVarBK[tu->force] == 0) ? tu->force : 0;
+    if (!tu->enabled) return 0;
     const int nb = (int)std::floor(2.0 * std::log2((double)std::max(N, 1)));
     const std::string key = std::string(name) + (sizeof(T) == 8 ? "" : "_f32") + " M=" + std::to_string(M) +
                             " K=" + std::to_string(K * S) + " S=" + std::to_string(S) + " N~2^" +
@@ -312,7 +324,7 @@ static int pick_variant(GemmTuner *tu, hipStream_t s, const char *name, int S, i
         if (!ev && hipEventCreate(&ev) != hipSuccess) return 0;
     float best = 0.f;
     for (int v = 0; v < GEMM_VARIANTS; ++v) {
-        if (M % kVarBM[v] != 0) continue;
+        if (M % kVarBM[v] != 0 || K % kVarBK[v] != 0) continue;
         launch_variant<T, LZ>(v, s, dim3(1, S), M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
         (void)hipEventRecord(tu->ev[0], s);
         launch_variant<T, LZ>(v, s, dim3(1, S), M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
