@@ -148,7 +148,8 @@ int chi0_apply(chi0_ctx *ctx, int32_t n_rhs, const double *omega, double eps,
 typedef struct chi0_ws chi0_ws;        /* learned warm start (see chi0_ws_fit) */
 
 typedef struct chi0_solve_opts {
-    int32_t restart;      /* GMRES(m) Krylov dimension per cycle, 1..3999 (default 30) */
+    int32_t restart;      /* GMRES(m) Krylov dimension per cycle, 1..32767 (4095 with CGS2;
+                             default 30); the basis needs (m+2) n_prod 16 bytes per slot */
     int32_t max_iter;     /* cap on Arnoldi steps per point (default 10000) */
     double  tol;          /* stop when ||chi0 d - A x||_2 <= tol ||chi0 d||_2 (default 1e-10) */
     int32_t precision;    /* CHI0_PREC_* of the Arnoldi steps (default FP64); b = chi0 d and

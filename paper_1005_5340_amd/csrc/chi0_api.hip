@@ -917,7 +917,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     if (n_omega == 0) return CHI0_OK;
     if (!omega || !V_ext || !alpha) return fail(c, CHI0_EINVAL, "NULL pointer");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
-    if (o.restart < 1 || o.restart > 3999) return fail(c, CHI0_EINVAL, "restart must be in [1, 3999]");
+    if (o.restart < 1 || o.restart > 32767) return fail(c, CHI0_EINVAL, "restart must be in [1, 32767]");
     if (o.max_iter < 1) return fail(c, CHI0_EINVAL, "max_iter must be >= 1");
     if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(c, CHI0_EINVAL, "tol must be finite and > 0");
     if (o.batch < 1) return fail(c, CHI0_EINVAL, "batch must be >= 1");
@@ -932,6 +932,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     // delayed reorthogonalisation needs a few columns per cycle (one is always provisional)
     const bool dcgs = o.ortho == CHI0_ORTHO_DCGS2 || (o.ortho == CHI0_ORTHO_AUTO && o.restart >= 8);
     if (dcgs && o.restart < 3) return fail(c, CHI0_EINVAL, "DCGS2 needs restart >= 3");
+    // CGS2 stages a step's coefficients in LDS (64 KB: 4095 complex)
+    if (!dcgs && o.restart > 4095) return fail(c, CHI0_EINVAL, "CGS2 needs restart <= 4095");
     chi0_ws *ws = const_cast<chi0_ws *>(o.warm);
     if (ws && ws->ctx != c) return fail(c, CHI0_EINVAL, "warm start belongs to another context");
     const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol

@@ -666,94 +666,150 @@ __device__ __forceinline__ cpx cdiv(cpx a, cpx b) {
     return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
 }
 
-constexpr int TSB = 32;
+constexpr int TSB = 32;    // rows of a diagonal block solved by one wavefront
+constexpr int TPW = 256;   // rows of a panel (one launch pair per panel)
+
+// y[0, L) = g[0, L): the working right-hand side of the back substitution.
 __global__ __launch_bounds__(256)
-void k_trisolve(const Job *__restrict__ jobs, SlotsDev sl) {
-    extern __shared__ double gsm[];
-    __shared__ cpx ys[TSB];
-    cpx *gs = reinterpret_cast<cpx *>(gsm);
+void k_tri_init(const Job *__restrict__ jobs, SlotsDev sl) {
+    const int q = blockIdx.y, i = blockIdx.x * 256 + threadIdx.x;
+    const Job jb = jobs[q];
+    if (i >= jb.j) return;
+    const cpx *g = reinterpret_cast<const cpx *>(sl.g + (int64_t)jb.slot * (sl.m + 1) * 2);
+    reinterpret_cast<cpx *>(sl.y + (int64_t)jb.slot * sl.m * 2)[i] = g[i];
+}
+
+// Panel p (from the bottom) of y = R^{-1} y: rows [lo, hi), hi = L - p TPW.
+// The rows below hi are solved and already subtracted from these rows, so
+// the panel is a triangular solve with its own diagonal block: 32 x 32
+// blocks from the bottom, each solved by wavefront 0 from registers (rows in
+// lanes, the pivot broadcast by shuffles), then subtracted by all threads
+// from the panel's rows above it.
+__global__ __launch_bounds__(256)
+void k_tri_diag(const Job *__restrict__ jobs, SlotsDev sl, int p) {
+    __shared__ cpx ys[TPW];
+    __shared__ cpx yb[TSB];
     const int q = blockIdx.x, t = threadIdx.x;
     const Job jb = jobs[q];
-    const int L = jb.j;
+    const int hi = jb.j - p * TPW;
+    if (hi <= 0) return;
+    const int lo = hi > TPW ? hi - TPW : 0;
     const double *H = sl.H + jb.slot * sl.hstride;
-    const cpx *g = reinterpret_cast<const cpx *>(sl.g + (int64_t)jb.slot * (sl.m + 1) * 2);
     cpx *y = reinterpret_cast<cpx *>(sl.y + (int64_t)jb.slot * sl.m * 2);
-    for (int i = t; i < L; i += 256) gs[i] = g[i];
+    for (int i = lo + t; i < hi; i += 256) ys[i - lo] = y[i];
     __syncthreads();
-    for (int hi = L; hi > 0; hi -= TSB) {
-        const int lo = hi - TSB;          // may be negative for the top block
+    for (int bh = hi; bh > lo; bh -= TSB) {
+        const int bl = bh - TSB > lo ? bh - TSB : lo;   // block rows [bl, bh)
+        const int b0 = bh - TSB;                        // lane t holds row b0 + t
         if (t < 64) {
-            const int r = lo + t;         // row held by this lane (lanes >= TSB idle)
-            const bool rv = t < TSB && r >= 0;
-            cpx v = rv ? gs[r] : cpx{0.0, 0.0};
+            const int r = b0 + t;
+            const bool rv = t < TSB && r >= bl;
+            cpx v = rv ? ys[r - lo] : cpx{0.0, 0.0};
             cpx R[TSB];
 #pragma unroll
             for (int s2 = 0; s2 < TSB; ++s2) {
-                const int i = lo + s2;
-                const cpx *coli = reinterpret_cast<const cpx *>(H + 2 * hoff(i < 0 ? 0 : i));
-                R[s2] = (rv && i >= 0 && r <= i) ? coli[r] : cpx{0.0, 0.0};
+                const int i = b0 + s2;
+                const cpx *coli = reinterpret_cast<const cpx *>(H + 2 * hoff(i < bl ? bl : i));
+                R[s2] = (rv && i >= bl && r <= i) ? coli[r] : cpx{0.0, 0.0};
             }
 #pragma unroll
             for (int s2 = TSB - 1; s2 >= 0; --s2) {
-                if (lo + s2 < 0) continue;                 // uniform
+                if (b0 + s2 < bl) continue;                // uniform
                 const cpx vi = cshfl(v, s2), di = cshfl(R[s2], s2);
                 const cpx yi = cdiv(vi, di);
                 if (t < s2) {
-                    const cpx p = cmul(R[s2], yi);
-                    v = {v.r - p.r, v.i - p.i};
+                    const cpx pr = cmul(R[s2], yi);
+                    v = {v.r - pr.r, v.i - pr.i};
                 }
-                if (t == 0) ys[s2] = yi;
+                if (t == 0) yb[s2] = yi;
             }
         }
         __syncthreads();
         for (int s2 = t; s2 < TSB; s2 += 256)
-            if (lo + s2 >= 0) y[lo + s2] = ys[s2];
-        for (int k = t; k < lo; k += 256) {
-            cpx acc = gs[k];
+            if (b0 + s2 >= bl) ys[b0 + s2 - lo] = yb[s2];
+        for (int k = lo + t; k < bl; k += 256) {
+            cpx acc = ys[k - lo];
             for (int s2 = 0; s2 < TSB; ++s2) {
-                const cpx *coli = reinterpret_cast<const cpx *>(H + 2 * hoff(lo + s2));
-                const cpx p = cmul(coli[k], ys[s2]);
-                acc = {acc.r - p.r, acc.i - p.i};
+                if (b0 + s2 < bl) continue;
+                const cpx *coli = reinterpret_cast<const cpx *>(H + 2 * hoff(b0 + s2));
+                const cpx pr = cmul(coli[k], yb[s2]);
+                acc = {acc.r - pr.r, acc.i - pr.i};
             }
-            gs[k] = acc;
+            ys[k - lo] = acc;
         }
         __syncthreads();
     }
+    for (int i = lo + t; i < hi; i += 256) y[i] = ys[i - lo];
 }
 
-// x += sum_{i<L} v_i y_i
+// Rows above panel p: y[k] -= sum_{i in [lo, hi)} R[k][i] y[i] for k < lo,
+// spread over many workgroups (the panel's R columns are read once).
+__global__ __launch_bounds__(256)
+void k_tri_update(const Job *__restrict__ jobs, SlotsDev sl, int p) {
+    __shared__ cpx ys[TPW];
+    const int q = blockIdx.y, t = threadIdx.x;
+    const Job jb = jobs[q];
+    const int hi = jb.j - p * TPW;
+    const int lo = hi > TPW ? hi - TPW : 0;
+    if (lo <= 0 || blockIdx.x * 256 >= lo) return;   // uniform per workgroup
+    const double *H = sl.H + jb.slot * sl.hstride;
+    cpx *y = reinterpret_cast<cpx *>(sl.y + (int64_t)jb.slot * sl.m * 2);
+    for (int i = lo + t; i < hi; i += 256) ys[i - lo] = y[i];
+    __syncthreads();
+    const int k = blockIdx.x * 256 + t;
+    if (k >= lo) return;
+    cpx acc = y[k];
+    for (int i = lo; i < hi; ++i) {
+        const cpx rki = reinterpret_cast<const cpx *>(H + 2 * hoff(i))[k];
+        const cpx pr = cmul(rki, ys[i - lo]);
+        acc = {acc.r - pr.r, acc.i - pr.i};
+    }
+    y[k] = acc;
+}
+
+// x += sum_{i<L} v_i y_i, the coefficients staged through LDS in chunks.
+constexpr int XCH = 1024;
 __global__ __launch_bounds__(256)
 void k_xupdate(const Job *__restrict__ jobs, SlotsDev sl, int P) {
-    extern __shared__ double ys[];
+    __shared__ cpx ys[XCH];
     const int q = blockIdx.y, t = threadIdx.x;
     const Job jb = jobs[q];
     const int L = jb.j;
-    const double *y = sl.y + (int64_t)jb.slot * sl.m * 2;
-    for (int i = t; i < 2 * L; i += 256) ys[i] = y[i];
-    __syncthreads();
+    const cpx *y = reinterpret_cast<const cpx *>(sl.y + (int64_t)jb.slot * sl.m * 2);
     const int mu = blockIdx.x * 256 + t;
-    if (mu >= P) return;
+    const bool act = mu < P;
     const int64_t vlen = (int64_t)sl.P_pad * 2;
     const double *V = sl.V + jb.slot * sl.vstride;
-    double2 *x = reinterpret_cast<double2 *>(sl.x + jb.slot * vlen) + mu;
-    double2 acc = *x;
-    for (int i = 0; i < L; ++i) {
-        const double2 v = reinterpret_cast<const double2 *>(V + (int64_t)i * vlen)[mu];
-        const double r = ys[2 * i], m = ys[2 * i + 1];
-        acc.x += v.x * r - v.y * m;
-        acc.y += v.x * m + v.y * r;
+    double2 *x = reinterpret_cast<double2 *>(sl.x + jb.slot * vlen) + (act ? mu : 0);
+    double2 acc = act ? *x : make_double2(0.0, 0.0);
+    for (int c0 = 0; c0 < L; c0 += XCH) {
+        const int n = min(XCH, L - c0);
+        __syncthreads();
+        for (int k = t; k < n; k += 256) ys[k] = y[c0 + k];
+        __syncthreads();
+        if (act)
+            for (int k = 0; k < n; ++k) {
+                const double2 v = reinterpret_cast<const double2 *>(V + (int64_t)(c0 + k) * vlen)[mu];
+                acc.x += v.x * ys[k].r - v.y * ys[k].i;
+                acc.y += v.x * ys[k].i + v.y * ys[k].r;
+            }
     }
-    *x = acc;
+    if (act) *x = acc;
 }
 
 void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
                      const SlotsDev &sl, int P, double sum_L) {
-    const size_t shm = (size_t)(jmax > 0 ? jmax : 1) * 2 * sizeof(double);
     trace_begin(t, "trisolve", s);
-    hipLaunchKernelGGL(k_trisolve, dim3(n), dim3(256), shm, s, jobs, sl);
+    hipLaunchKernelGGL(k_tri_init, dim3((jmax + 255) / 256, n), dim3(256), 0, s, jobs, sl);
+    for (int p = 0; p * TPW < jmax; ++p) {
+        hipLaunchKernelGGL(k_tri_diag, dim3(n), dim3(256), 0, s, jobs, sl, p);
+        const int above = jmax - (p + 1) * TPW;
+        if (above > 0)
+            hipLaunchKernelGGL(k_tri_update, dim3((above + 255) / 256, n), dim3(256), 0, s, jobs, sl, p);
+    }
     trace_end(t, s);
     trace_begin(t, "x_update", s);
-    hipLaunchKernelGGL(k_xupdate, dim3((P + 255) / 256, n), dim3(256), shm, s, jobs, sl, P);
+    hipLaunchKernelGGL(k_xupdate, dim3((P + 255) / 256, n), dim3(256), 0, s, jobs, sl, P);
     trace_end(t, s, 8.0 * P * sum_L, 16.0 * P * (sum_L + 2.0 * n));
 }
 
