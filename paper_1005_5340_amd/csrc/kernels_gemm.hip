@@ -663,14 +663,67 @@ void k_kmatvec_skinny(int P_pad, const double *__restrict__ K, const double *__r
         }
 }
 
+// One or two right-hand sides (nc = 2 or 4 real columns): a wavefront owns RW
+// rows and every lane reads 16-byte pairs of K columns, U pairs of chunks in
+// flight per row; the two Zin rows a lane needs (2 nc doubles, contiguous) are
+// read through the cache.  Four times the wavefronts of the LDS-staged form,
+// with no barrier in the loop.
+template <int NC, int RW>
+__global__ __launch_bounds__(256)
+void k_kmatvec_lanes(int P_pad, const double *__restrict__ K, const double *__restrict__ Zin,
+                     double *__restrict__ Zout) {
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row0 = (blockIdx.x * 4 + wv) * RW;
+    double acc[RW][NC];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[r][j] = 0.0;
+    for (int c0 = 2 * lane; c0 < P_pad; c0 += 128 * U) {
+        double2 kv[U][RW];
+        double2 zv[U][NC];   // Zin rows nu and nu + 1: 2 NC doubles
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int nu = c0 + 128 * u;
+            const bool ok = nu < P_pad;
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+                kv[u][r] = ok ? *reinterpret_cast<const double2 *>(K + (int64_t)(row0 + r) * P_pad + nu)
+                              : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int h = 0; h < NC; ++h)
+                zv[u][h] = ok ? reinterpret_cast<const double2 *>(Zin + (int64_t)nu * NC)[h]
+                              : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double *z = reinterpret_cast<const double *>(zv[u]);   // z[0..NC): row nu, z[NC..2NC): nu + 1
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int j = 0; j < NC; ++j) acc[r][j] += kv[u][r].x * z[j] + kv[u][r].y * z[NC + j];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            double v = acc[r][j];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) Zout[(int64_t)(row0 + r) * NC + j] = v;
+        }
+}
+
 void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
                            const double *Zin, double *Zout, int nc, double P) {
     dim3 grid(P_pad / 16);
     trace_begin(t, "kernel_matvec", s);
-    if (nc <= 2)
-        hipLaunchKernelGGL(k_kmatvec_skinny<2>, grid, dim3(256), 0, s, P_pad, K, Zin, Zout, nc);
-    else if (nc <= 4)
-        hipLaunchKernelGGL(k_kmatvec_skinny<4>, grid, dim3(256), 0, s, P_pad, K, Zin, Zout, nc);
+    if (nc == 2)
+        hipLaunchKernelGGL((k_kmatvec_lanes<2, 1>), dim3(P_pad / 4), dim3(256), 0, s, P_pad, K, Zin, Zout);
+    else if (nc == 4)
+        hipLaunchKernelGGL((k_kmatvec_lanes<4, 2>), dim3(P_pad / 8), dim3(256), 0, s, P_pad, K, Zin, Zout);
     else if (nc <= 8)
         hipLaunchKernelGGL(k_kmatvec_skinny<8>, grid, dim3(256), 0, s, P_pad, K, Zin, Zout, nc);
     else

@@ -355,16 +355,35 @@ void k_arnoldi_finalize(const Job *__restrict__ jobs, SlotsDev sl, int P, StepSt
 // s_i = <v_i | v~_j>, t_i = <v_i | z> for i < j; for i = j: sigma = <v~_j|v~_j>,
 // tau = <v~_j|z>.  Each wavefront takes DPW consecutive i, so v~_j and z are
 // loaded once per DPW basis vectors (DPW = 4 measured fastest: 2 re-reads more
-// of v~_j and z, 8 gives too few wavefronts).
+// of v~_j and z, 8 gives too few wavefronts).  With few jobs the rows are
+// also split into gridDim.z ranges (at least 256 rows each) so that the step
+// still fills the chip; each range writes its four sums per i to
+// part[((q R + r) ld + i) 4 + c] and k_dcgs_dots_fin adds the ranges in order.
 constexpr int DPW = 4;
+
+__device__ __forceinline__ void dcgs_store_dots(double *h, int i, int j, double a0, double a1, double a2,
+                                                double a3) {
+    if (i < j) {
+        h[2 * i] = a0; h[2 * i + 1] = a1;               // s_i
+        h[2 * (j + i)] = a2; h[2 * (j + i) + 1] = a3;   // t_i
+    } else {
+        h[4 * j] = a0; h[4 * j + 1] = 0.0;              // sigma at 2j
+        h[4 * j + 2] = a2; h[4 * j + 3] = a3;           // tau at 2j+1
+    }
+}
+
 __global__ __launch_bounds__(256)
-void k_dcgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P) {
+void k_dcgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P, int ld, double *__restrict__ part) {
     const int q = blockIdx.y, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = blockIdx.z, R = gridDim.z;
     const Job jb = jobs[q];
     const int i0 = (blockIdx.x * 4 + wv) * DPW;
     const int j = jb.j;
     if (jb.type != JOB_ARNOLDI || i0 > j) return;
     const int nv = min(DPW, j + 1 - i0);
+    // row range of this split: multiples of 64 rows, the last range takes the rest
+    const int rc = (((P + R - 1) / R) + 63) & ~63;
+    const int lo = r * rc, hi = min(P, lo + rc);
     const int64_t vlen = (int64_t)sl.P_pad * 2;
     const double *V = sl.V + jb.slot * sl.vstride;
     const double2 *vi = reinterpret_cast<const double2 *>(V + (int64_t)i0 * vlen);
@@ -379,7 +398,7 @@ void k_dcgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P) {
     int64_t off[DPW];
 #pragma unroll
     for (int k = 0; k < DPW; ++k) off[k] = (int64_t)min(k, nv - 1) * vst;
-    for (int mu = lane; mu < P; mu += 64) {
+    for (int mu = lo + lane; mu < hi; mu += 64) {
         const double2 b = vt[mu], c = z[mu];
 #pragma unroll
         for (int k = 0; k < DPW; ++k) {
@@ -396,16 +415,28 @@ void k_dcgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P) {
         const double a0 = wave_sum(sr[k]), a1 = wave_sum(si[k]), a2 = wave_sum(tr[k]), a3 = wave_sum(ti[k]);
         if (lane == 0) {
             const int i = i0 + k;
-            double *h = sl.hbuf + (int64_t)jb.slot * sl.hbstride;
-            if (i < j) {
-                h[2 * i] = a0; h[2 * i + 1] = a1;               // s_i
-                h[2 * (j + i)] = a2; h[2 * (j + i) + 1] = a3;   // t_i
+            if (R == 1) {
+                dcgs_store_dots(sl.hbuf + (int64_t)jb.slot * sl.hbstride, i, j, a0, a1, a2, a3);
             } else {
-                h[4 * j] = a0; h[4 * j + 1] = 0.0;              // sigma at 2j
-                h[4 * j + 2] = a2; h[4 * j + 3] = a3;           // tau at 2j+1
+                double *o = part + (((int64_t)q * R + r) * ld + i) * 4;
+                o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3;
             }
         }
     }
+}
+
+// Adds the R row ranges of k_dcgs_dots in order and stores the sums.
+__global__ __launch_bounds__(256)
+void k_dcgs_dots_fin(const Job *__restrict__ jobs, SlotsDev sl, int R, int ld, const double *__restrict__ part) {
+    const int q = blockIdx.y, i = blockIdx.x * 256 + threadIdx.x;
+    const Job jb = jobs[q];
+    if (jb.type != JOB_ARNOLDI || i > jb.j) return;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int r = 0; r < R; ++r) {
+        const double *o = part + (((int64_t)q * R + r) * ld + i) * 4;
+        a0 += o[0]; a1 += o[1]; a2 += o[2]; a3 += o[3];
+    }
+    dcgs_store_dots(sl.hbuf + (int64_t)jb.slot * sl.hbstride, i, jb.j, a0, a1, a2, a3);
 }
 
 // rho, correction and Givens of column j-1, coefficients c and provisional column j.
@@ -470,6 +501,9 @@ void k_dcgs_coef(const Job *__restrict__ jobs, SlotsDev sl, StepStatus *__restri
 constexpr int DCH = 512;
 
 // Sums V_[i0,i1) s and V_[i0,i1) c for row mu (all threads join the LDS staging).
+// The loads of UB basis vectors are issued together before their products, so
+// a thread keeps UB loads in flight.
+constexpr int UB = 8;
 __device__ __forceinline__ void dcgs_sums(const cpx *h, int j, const double2 *vb, int64_t vst, bool act,
                                           int i0, int i1, cpx *shs, cpx *shc, double2 &as, double2 &ac) {
     const int t = threadIdx.x;
@@ -483,8 +517,21 @@ __device__ __forceinline__ void dcgs_sums(const cpx *h, int j, const double2 *vb
         __syncthreads();
         if (act) {
             const double2 *vp = vb + (int64_t)c0 * vst;
-#pragma unroll 4
-            for (int k = 0; k < n; ++k) {
+            int k = 0;
+            for (; k + UB <= n; k += UB) {
+                double2 v[UB];
+#pragma unroll
+                for (int u = 0; u < UB; ++u) v[u] = vp[(int64_t)(k + u) * vst];
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const cpx sv = shs[k + u], cv = shc[k + u];
+                    as.x += v[u].x * sv.r - v[u].y * sv.i;
+                    as.y += v[u].x * sv.i + v[u].y * sv.r;
+                    ac.x += v[u].x * cv.r - v[u].y * cv.i;
+                    ac.y += v[u].x * cv.i + v[u].y * cv.r;
+                }
+            }
+            for (; k < n; ++k) {
                 const double2 v = vp[(int64_t)k * vst];
                 const cpx sv = shs[k], cv = shc[k];
                 as.x += v.x * sv.r - v.y * sv.i;
@@ -601,22 +648,38 @@ void k_dcgs_norm(const Job *__restrict__ jobs, SlotsDev sl, int P, StepStatus *_
 }
 
 // Basis groups of the split update: enough workgroups to fill the chip a few
-// times over, at least 256 basis vectors per group, at most 16 groups, and the
+// times over, at least 32 basis vectors per group, at most 64 groups, and the
 // partial sums within the scratch buffer.  A function of the step's shape only.
 static int update_groups(int P, int nb, int jmax, int64_t P_pad, size_t scratch_doubles) {
     const int base = ((P + 255) / 256) * nb;
     int G = 1;
-    while (G < 16 && base * G < 2048 && jmax / (2 * G) >= 256 &&
+    while (G < 64 && base * G < 1024 && jmax / (2 * G) >= 32 &&
            (size_t)(2 * G) * nb * P_pad * 4 <= scratch_doubles)
         G *= 2;
     return G;
 }
 
+// Row ranges of the projection pass: split while the step has fewer than 4096
+// wavefronts and each range keeps at least 256 rows; the partial sums must fit
+// the scratch buffer.
+static int dots_splits(int P, int nb, int jmax, size_t scratch_doubles) {
+    const int64_t waves = (int64_t)((jmax + DPW) / DPW) * nb;
+    int R = 1;
+    while (R < 16 && waves * R < 4096 && P / (2 * R) >= 256 &&
+           (size_t)(2 * R) * nb * (jmax + 1) * 4 <= scratch_doubles)
+        R *= 2;
+    return R;
+}
+
 void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, const SlotsDev &sl, int P,
                  StepStatus *status, int n_arnoldi, double sum_j1, double *scratch, size_t scratch_doubles) {
-    const dim3 gd((jmax + 1 + 4 * DPW - 1) / (4 * DPW), nb), gu((P + 255) / 256, nb);
+    const int R = scratch ? dots_splits(P, nb, jmax, scratch_doubles) : 1;
+    const dim3 gd((jmax + 1 + 4 * DPW - 1) / (4 * DPW), nb, R), gu((P + 255) / 256, nb);
     trace_begin(t, "dcgs_dots", s);
-    hipLaunchKernelGGL(k_dcgs_dots, gd, dim3(256), 0, s, jobs, sl, P);
+    hipLaunchKernelGGL(k_dcgs_dots, gd, dim3(256), 0, s, jobs, sl, P, jmax + 1, scratch);
+    if (R > 1)
+        hipLaunchKernelGGL(k_dcgs_dots_fin, dim3((jmax + 1 + 255) / 256, nb), dim3(256), 0, s, jobs, sl, R,
+                           jmax + 1, (const double *)scratch);
     trace_end(t, s, 16.0 * P * sum_j1, 16.0 * P * (sum_j1 + 2.0 * n_arnoldi));
     trace_begin(t, "dcgs_coef", s);
     hipLaunchKernelGGL(k_dcgs_coef, dim3(nb), dim3(256), 0, s, jobs, sl, status);
