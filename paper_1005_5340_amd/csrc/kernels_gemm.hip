@@ -1,13 +1,18 @@
 // Matrix-core kernels of the orbital transforms (Sec. 4.2, Table t:flops steps
 // 2-5) and the kernel matrix-vector product (Sec. 4.1), for FP64 and FP32.
 //
-// 16x16x4 MFMA on 64-lane wavefronts, lane l = 0..63:
-//   A (16 x 4):  lane l holds A[l % 16][l / 16]
+// A 16 x 16 output tile per K step of 4 on 64-lane wavefronts, lane l = 0..63:
 //   B (4 x 16):  lane l holds B[l / 16][l % 16]
-//   D (16 x 16): element r of lane l holds D[row(l, r)][l % 16] with
-//                row = 4r + l/16     for v_mfma_f64_16x16x4f64 (interleaved)
-//                row = 4(l/16) + r   for v_mfma_f32_16x16x4f32 (contiguous)
-//   (both checked on gfx950 with lane probes)
+//   D (16 x 16): element r of lane l holds D[row(l, r)][l % 16]
+// FP64 uses v_mfma_f64_4x4x4_4b_f64: four 4x4x4 products per instruction,
+// lane l = 16 h + 4 q + p holding A[q-th block][p][h], B[block q][h][p] and
+// D[block q][h][p].  Issuing one instruction per 4-row strip r of the tile,
+// with block q = the 4-column group of B, makes B and D the same lanes as a
+// 16x16x4 product:  A fragment r holds A[4r + l % 4][l / 16], and
+// row(l, r) = 4r + l/16.  On gfx950 this form runs at ~72 TFLOP/s against
+// ~50 for v_mfma_f64_16x16x4f64 (register-only throughput probes).
+// FP32 uses v_mfma_f32_16x16x4f32: A[l % 16][l / 16], row(l, r) = 4(l/16) + r.
+// (Lane layouts checked on gfx950 with one-hot lane probes.)
 #include "common.h"
 
 #include <algorithm>
@@ -18,20 +23,42 @@ namespace chi0 {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
+// NA A fragments per 16 x 16 tile and K step; a_row(l, r) is the tile row
+// that lane l supplies in fragment r.
 template <class T> struct Mma;
 template <> struct Mma<double> {
     typedef dbl4 acc;
+    static constexpr int NA = 4;
     static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
-    static __device__ __forceinline__ acc op(double a, double b, acc c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    static __device__ __forceinline__ int a_row(int lane, int r) { return 4 * r + (lane & 3); }
+    static __device__ __forceinline__ acc op(const double (&a)[NA], double b, acc c) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[r] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[r], b, c[r], 0, 0, 0);
+        return c;
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+// The gathered occupied transforms keep the single 16x16x4 FP64 product per
+// tile (A[l % 16][l / 16]): with a dozen accumulators per wave they are not
+// bound by the MFMA issue rate, and the four A fragments of the 4-block form
+// made them slower.
+struct Mma16d {
+    typedef dbl4 acc;
+    static constexpr int NA = 1;
+    static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ int a_row(int lane, int) { return lane & 15; }
+    static __device__ __forceinline__ acc op(const double (&a)[NA], double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
 };
 template <> struct Mma<float> {
     typedef flt4 acc;
+    static constexpr int NA = 1;
     static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
-    static __device__ __forceinline__ acc op(float a, float b, acc c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    static __device__ __forceinline__ int a_row(int lane, int) { return lane & 15; }
+    static __device__ __forceinline__ acc op(const float (&a)[NA], float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
@@ -148,9 +175,12 @@ void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             const int kk = ks * 4 + lane / 16;
-            T af[TM], bf[TN];
+            T af[TM][Mma<T>::NA], bf[TN];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) af[i] = As[cur][kk][wm * (BM / WM) + i * 16 + (lane & 15)];
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int r = 0; r < Mma<T>::NA; ++r)
+                    af[i][r] = As[cur][kk][wm * (BM / WM) + i * 16 + Mma<T>::a_row(lane, r)];
 #pragma unroll
             for (int j = 0; j < TN; ++j) bf[j] = Bs[cur][kk][wn * (BN / WN) + j * 16 + (lane & 15)];
 #pragma unroll
@@ -405,6 +435,9 @@ void launch_sgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int 
                     la ? *la : none, scratch, scratch_bytes, tu);
 }
 
+template <class T> struct OccMma { typedef Mma<T> type; };
+template <> struct OccMma<double> { typedef Mma16d type; };
+
 // ------------------------------------------------------- (b1) occupied transform
 // Tt[b][E*nc + j] = sum_{A in nbr(B)} sum_{a in A} Xo[a][E] dV[(k(A,B), a, b)][j]
 // One workgroup: column atom B, 64 occupied states, 16 columns.  Wave w owns
@@ -418,6 +451,7 @@ template <class T, int NBT>
 __global__ __launch_bounds__(256)
 void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
                      const double *__restrict__ dV, T *__restrict__ Tt, int nc) {
+    typedef typename OccMma<T>::type MM;
     const int B = blockIdx.x, e0 = blockIdx.y * 64, j0 = blockIdx.z * JT;
     const int g0 = bm.col_gstart[B], g1 = bm.col_gstart[B + 1];
     const int boff = bm.atom_off[B], nB = bm.atom_off[B + 1] - boff;
@@ -425,9 +459,9 @@ void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
     __shared__ T Xs[16][64 + 1];
     __shared__ T Ds[16][NBT][JT];
 
-    typename Mma<T>::acc acc[NBT];
+    typename MM::acc acc[NBT];
 #pragma unroll
-    for (int b = 0; b < NBT; ++b) acc[b] = Mma<T>::zero();
+    for (int b = 0; b < NBT; ++b) acc[b] = MM::zero();
 
     // register staging of one chunk: 4 X values and the nB dV values of (row, column)
     const int xr = t / 16, xc = (t % 16) * 4;
@@ -453,10 +487,12 @@ void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            const T a = Xs[kk][wv * 16 + (lane & 15)];
+            T a[MM::NA];
+#pragma unroll
+            for (int r = 0; r < MM::NA; ++r) a[r] = Xs[kk][wv * 16 + MM::a_row(lane, r)];
 #pragma unroll
             for (int b = 0; b < NBT; ++b)
-                if (b < nB) acc[b] = Mma<T>::op(a, Ds[kk][b][lane & 15], acc[b]);
+                if (b < nB) acc[b] = MM::op(a, Ds[kk][b][lane & 15], acc[b]);
         }
         __syncthreads();
     }
@@ -468,7 +504,7 @@ void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
             if (b < nB) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int E = e0 + wv * 16 + Mma<T>::row(lane, r);
+                    const int E = e0 + wv * 16 + MM::row(lane, r);
                     Tt[(int64_t)(boff + b) * ldT + (int64_t)E * nc + j] = acc[b][r];
                 }
             }
@@ -521,6 +557,7 @@ template <class T, int NBT>
 __global__ __launch_bounds__(256)
 void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
                 const T *__restrict__ Ut, double *__restrict__ W, int nc) {
+    typedef typename OccMma<T>::type MM;
     const int B = blockIdx.x, j0 = blockIdx.z * JT;
     const int g1 = bm.col_gstart[B + 1];
     const int g0 = bm.col_gstart[B] + blockIdx.y * 64;
@@ -531,9 +568,9 @@ void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
     __shared__ T Xs[64][16 + 1];
     __shared__ T Us[NBT][16][JT];
 
-    typename Mma<T>::acc acc[NBT];
+    typename MM::acc acc[NBT];
 #pragma unroll
-    for (int b = 0; b < NBT; ++b) acc[b] = Mma<T>::zero();
+    for (int b = 0; b < NBT; ++b) acc[b] = MM::zero();
 
     const int xr = t / 4, xc = (t % 4) * 4, xg = g0 + xr;
     const T *xsrc = (xg < g1) ? Xo + (int64_t)bm.g_xrow[xg] * no_pad + xc : nullptr;
@@ -558,10 +595,12 @@ void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            const T a = Xs[wv * 16 + (lane & 15)][kk];
+            T a[MM::NA];
+#pragma unroll
+            for (int r = 0; r < MM::NA; ++r) a[r] = Xs[wv * 16 + MM::a_row(lane, r)][kk];
 #pragma unroll
             for (int b = 0; b < NBT; ++b)
-                if (b < nB) acc[b] = Mma<T>::op(a, Us[b][kk][lane & 15], acc[b]);
+                if (b < nB) acc[b] = MM::op(a, Us[b][kk][lane & 15], acc[b]);
         }
         __syncthreads();
     }
@@ -569,7 +608,7 @@ void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
     if (j < nc) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int g = g0 + wv * 16 + Mma<T>::row(lane, r);
+            const int g = g0 + wv * 16 + MM::row(lane, r);
             if (g < g1) {
                 const int64_t base = bm.g_ent[g];
 #pragma unroll
