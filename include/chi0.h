@@ -165,8 +165,27 @@ typedef struct chi0_solve_opts {
                              slots are dealt to this many lanes, each with its own stream and
                              operator workspace, so that one lane's memory-bound Gram-Schmidt
                              passes overlap the other's matrix-core transforms */
-    int32_t reserved[2];  /* must be zero */
+    int32_t stop;         /* CHI0_STOP_*: the test that ends a point (default: residual) */
+    int32_t reserved;     /* must be zero */
 } chi0_solve_opts;
+
+/* Stopping test of a point (Sec. 4.1).
+ *   RESIDUAL  the true relative residual ||chi0 d - A x|| / ||chi0 d|| <= tol
+ *             (confirmed by an FP64 residual at the end of each cycle).
+ *   EPS_P     the paper's estimate of the relative error of the polarizability,
+ *             eps_P = ||A^-1|| |d . r| / |d . x| <= tol, where ||A^-1|| is the
+ *             Frobenius norm of the inverse triangular factor of the cycle's
+ *             Hessenberg matrix (the Krylov representation of A^-1) and r the
+ *             GMRES residual; the paper's choice for percent-level tolerances.
+ *   EPS_PX    the paper's combined test: eps_P <= tol and
+ *             eps_X = ||A^-1|| ||r|| / ||x|| <= tol.
+ * The estimates need DCGS2 steps and FP64 precision, and R^-1 of each slot's
+ * cycle: restart (restart + 1) 8 extra bytes per concurrent point.  A point
+ * whose cycle ends by the estimate counts as converged; its stats carry the
+ * estimates and the true residual of the solution returned. */
+#define CHI0_STOP_RESIDUAL    0
+#define CHI0_STOP_EPS_P       1
+#define CHI0_STOP_EPS_PX      2
 
 /* Gram-Schmidt of the Arnoldi step (eq. orthogonal-krylov-basis, done twice).
  *   CGS2   two classical passes per step: four reads of the basis.
@@ -191,6 +210,8 @@ typedef struct chi0_point_stats {
     int32_t warm_start;   /* 0 none, 1 started from the warm start, 2 warm start rejected */
     double  rel_residual; /* true ||b - A x|| / ||b|| at exit */
     double  warm_rel0;    /* ||b - A x0|| / ||b|| of the warm start (0 if none) */
+    double  eps_x;        /* CHI0_STOP_EPS_*: the last eps_X and eps_P estimates seen (else 0) */
+    double  eps_p;
 } chi0_point_stats;
 
 void chi0_solve_opts_default(chi0_solve_opts *opts);

@@ -17,13 +17,15 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["Chi0Error", "Context", "WarmStart", "lib", "LIB_PATH", "PREC_FP64", "PREC_FP32",
-           "PREC_BF16X3", "SolveStats", "NOT_CONVERGED", "debug_eigh"]
+           "PREC_BF16X3", "SolveStats", "NOT_CONVERGED", "debug_eigh", "STOP_RESIDUAL", "STOP_EPS_P",
+           "STOP_EPS_PX"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16X3 = 2
 ORTHO_AUTO, ORTHO_CGS2, ORTHO_DCGS2 = 0, 1, 2
+STOP_RESIDUAL, STOP_EPS_P, STOP_EPS_PX = 0, 1, 2
 NOT_CONVERGED = 1
 _ERRORS = {-1: "EINVAL", -2: "ENOSYS", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EASYM"}
 
@@ -36,7 +38,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("batch", C.c_int32), ("inner_tol", C.c_double),
                 ("warm", C.c_void_p), ("ortho", C.c_int32), ("lanes", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("stop", C.c_int32), ("reserved", C.c_int32)]
 
 
 class WsCfg(C.Structure):
@@ -49,7 +51,8 @@ class WsCfg(C.Structure):
 class PointStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("breakdown", C.c_int32), ("fallback", C.c_int32), ("warm_start", C.c_int32),
-                ("rel_residual", C.c_double), ("warm_rel0", C.c_double)]
+                ("rel_residual", C.c_double), ("warm_rel0", C.c_double),
+                ("eps_x", C.c_double), ("eps_p", C.c_double)]
 
 
 class TuneRecord(C.Structure):
@@ -64,7 +67,8 @@ class KernelRecord(C.Structure):
 
 SolveStats = np.dtype([("iterations", np.int32), ("restarts", np.int32), ("converged", np.int32),
                        ("breakdown", np.int32), ("fallback", np.int32), ("warm_start", np.int32),
-                       ("rel_residual", np.float64), ("warm_rel0", np.float64)])
+                       ("rel_residual", np.float64), ("warm_rel0", np.float64),
+                       ("eps_x", np.float64), ("eps_p", np.float64)])
 
 _LIB = None
 
@@ -258,7 +262,7 @@ class Context:
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
                        tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,
                        inner_tol: float = 0.0, warm: "WarmStart" = None, ortho: int = ORTHO_AUTO,
-                       return_x: bool = False, lanes: int = 0):
+                       return_x: bool = False, lanes: int = 0, stop: int = STOP_RESIDUAL):
         """GMRES polarizability over a frequency grid.
 
         Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
@@ -275,6 +279,7 @@ class Context:
         o.warm = warm._h if warm is not None else None
         o.ortho = int(ortho)
         o.lanes = int(lanes)
+        o.stop = int(stop)
         alpha = np.zeros((om.size, nd, nd, 2))
         st = (PointStats * max(1, om.size * nd))()
         if return_x:
@@ -290,7 +295,8 @@ class Context:
         flat = stats.reshape(-1)
         for i in range(om.size * nd):
             flat[i] = (st[i].iterations, st[i].restarts, st[i].converged, st[i].breakdown,
-                       st[i].fallback, st[i].warm_start, st[i].rel_residual, st[i].warm_rel0)
+                       st[i].fallback, st[i].warm_start, st[i].rel_residual, st[i].warm_rel0,
+                       st[i].eps_x, st[i].eps_p)
         a = alpha[..., 0] + 1j * alpha[..., 1]
         if return_x:
             return a, stats, rc, x[..., 0] + 1j * x[..., 1]

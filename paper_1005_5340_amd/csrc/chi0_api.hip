@@ -833,10 +833,11 @@ struct SlotState {
     double bnorm = 0.0;          // ||b|| = ||chi0 d||
     double cycle0 = 0.0;         // residual norm at the start of the current cycle
     double rel_prev = 1.0;       // true relative residual after the previous cycle
+    bool eps_met = false;        // the cycle ended by the eps_P / eps_X test
 };
 struct PointState {
     int iters = 0, restarts = 0, converged = 0, breakdown = 0, fallback = 0, warm = 0;
-    double rel = NAN, warm_rel0 = 0.0;
+    double rel = NAN, warm_rel0 = 0.0, eps_x = 0.0, eps_p = 0.0;
 };
 }  // namespace
 
@@ -925,8 +926,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     if (o.precision < CHI0_PREC_FP64 || o.precision > CHI0_PREC_BF16X3)
         return fail(c, CHI0_EINVAL, "unknown precision");
     if (!(o.inner_tol >= 0.0) || !(o.inner_tol < 1.0)) return fail(c, CHI0_EINVAL, "inner_tol must be in [0, 1)");
-    for (int i = 0; i < 2; ++i)
-        if (o.reserved[i] != 0) return fail(c, CHI0_EINVAL, "reserved option fields must be zero");
+    if (o.reserved != 0) return fail(c, CHI0_EINVAL, "reserved option fields must be zero");
+    if (o.stop < CHI0_STOP_RESIDUAL || o.stop > CHI0_STOP_EPS_PX) return fail(c, CHI0_EINVAL, "unknown stop");
     if (o.lanes < 0 || o.lanes > kLanes) return fail(c, CHI0_EINVAL, "lanes must be 0 (auto), 1 or 2");
     if (o.ortho < CHI0_ORTHO_AUTO || o.ortho > CHI0_ORTHO_DCGS2) return fail(c, CHI0_EINVAL, "unknown ortho");
     // delayed reorthogonalisation needs a few columns per cycle (one is always provisional)
@@ -934,6 +935,9 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     if (dcgs && o.restart < 3) return fail(c, CHI0_EINVAL, "DCGS2 needs restart >= 3");
     // CGS2 stages a step's coefficients in LDS (64 KB: 4095 complex)
     if (!dcgs && o.restart > 4095) return fail(c, CHI0_EINVAL, "CGS2 needs restart <= 4095");
+    const bool use_eps = o.stop != CHI0_STOP_RESIDUAL;
+    if (use_eps && (!dcgs || o.precision != CHI0_PREC_FP64))
+        return fail(c, CHI0_EINVAL, "the eps_P / eps_X stopping tests need DCGS2 steps in FP64");
     chi0_ws *ws = const_cast<chi0_ws *>(o.warm);
     if (ws && ws->ctx != c) return fail(c, CHI0_EINVAL, "warm start belongs to another context");
     const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol
@@ -980,6 +984,17 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     CHK(dalloc(c, callbuf, &alpha_dev, (int64_t)npts * n_drive * 2));
     HIPCHK(c, hipMemcpy2D(drives, (size_t)c->P_pad * 8, V_ext, (size_t)P * 8, (size_t)P * 8,
                           (size_t)n_drive, hipMemcpyHostToDevice));
+    // error estimates of the paper's stopping test: R^-1, y, d.v_i, x0^H v_i per slot
+    EpsDev epsd{};
+    if (use_eps) {
+        epsd.zstride = (int64_t)m * (m + 1);   // m(m+1)/2 complex
+        CHK(dalloc(c, callbuf, &epsd.Z, nsl * epsd.zstride));
+        CHK(dalloc(c, callbuf, &epsd.yv, (int64_t)nsl * m * 2));
+        CHK(dalloc(c, callbuf, &epsd.dl, (int64_t)nsl * (m + 1) * 2));
+        CHK(dalloc(c, callbuf, &epsd.xi, (int64_t)nsl * (m + 1) * 2));
+        CHK(dalloc(c, callbuf, &epsd.st, (int64_t)nsl * EPS_NS));
+        epsd.drives = drives;
+    }
     HIPCHK(c, hipDeviceSynchronize());
 
     std::vector<SlotState> sl(nsl);
@@ -1073,7 +1088,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
         if (n_arn > 0) {
             if (dcgs)
                 launch_dcgs(t, s, jobs_d, nb, jmax, c->slots, P, st_d, n_arn, sum_j1, ow.gemm_scratch,
-                            ow.gemm_scratch_n);
+                            ow.gemm_scratch_n, use_eps ? &epsd : nullptr);
             else
                 launch_arnoldi(t, s, jobs_d, nb, jmax, c->slots, P, st_d, n_arn, sum_j1);
         }
@@ -1106,12 +1121,19 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 // reorthogonalisation: it completes column j-1 (dimension j) and
                 // leaves column j provisional, so a cycle uses the first j columns.
                 const int Lc = dcgs ? jb.j : jb.j + 1;
-                const bool est_ok = Lc >= 1 && st.value <= stop;
+                bool crit = st.value <= stop;
+                if (use_eps) {   // Sec. 4.1: eps_P alone, or eps_P and eps_X
+                    pt.eps_x = st.eps_x;
+                    pt.eps_p = st.eps_p;
+                    crit = st.eps_p <= o.tol && (o.stop != CHI0_STOP_EPS_PX || st.eps_x <= o.tol);
+                }
+                const bool est_ok = Lc >= 1 && crit;
                 if (est_ok || brk || jb.j + 1 >= m || pt.iters >= o.max_iter || !std::isfinite(st.value)) {
                     if (Lc >= 1) ln.upd.push_back({jb.slot, 0, Lc, 0});
                     ss.state = S_RESID;
                     ss.epoch += 1;
                     ss.pend = 0;
+                    ss.eps_met = use_eps && est_ok;
                 }
                 continue;
             }
@@ -1167,8 +1189,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
             } else {
                 pt.restarts += 1;
                 pt.rel = st.value / ss.bnorm;
-                if (pt.rel <= o.tol || pt.iters >= o.max_iter || !std::isfinite(pt.rel)) {
-                    pt.converged = pt.rel <= o.tol;
+                if (pt.rel <= o.tol || ss.eps_met || pt.iters >= o.max_iter || !std::isfinite(pt.rel)) {
+                    pt.converged = pt.rel <= o.tol || ss.eps_met;
                     ln.fin.push_back({jb.slot, 0, ss.point, 0});
                     ss.state = S_FREE;
                     ++done;
@@ -1256,6 +1278,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 sl[k].pend = 0;
                 sl[k].epoch += 1;
                 sl[k].warm_check = false;
+                sl[k].eps_met = false;
                 if (ws) {
                     LaneState &ln = lanes[k % nl];
                     ln.wnew.push_back({k, 0, sl[k].point, 0});
@@ -1319,6 +1342,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 r.warm_start = ps[p].warm;
                 r.rel_residual = ps[p].rel;
                 r.warm_rel0 = ps[p].warm_rel0;
+                r.eps_x = ps[p].eps_x;
+                r.eps_p = ps[p].eps_p;
             }
         }
     c->err.clear();

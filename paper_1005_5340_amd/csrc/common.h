@@ -179,7 +179,27 @@ struct SlotsDev {
 struct StepStatus {
     double value;     // JOB_RHS: ||b||; JOB_ARNOLDI: |g_{j+1}|; JOB_RESID: ||r||
     double hnext;     // JOB_ARNOLDI: h_{j+1,j}
+    double eps_x;     // JOB_ARNOLDI with the error estimates on: eps_X and eps_P of Sec. 4.1
+    double eps_p;
 };
+
+// Error estimates of the stopping test of Sec. 4.1 (DCGS2 steps only):
+//   eps_X = ||A^-1|| ||r|| / ||X||,  eps_P = ||A^-1|| |d . r| / |P|,
+// with ||A^-1|| taken as the Frobenius norm of R^-1, R the triangular factor
+// of the cycle's Hessenberg matrix (the Krylov representation of A^-1 in the
+// least-squares sense).  Kept incrementally: column k of Z = R^-1 from the
+// column k of R, y = R^-1 g one column at a time, d.v_i and x0^H v_i per basis
+// vector, and d.r = g_k phi_k with phi_k = -s_{k-1} phi_{k-1} + c_{k-1} d.v_k.
+struct EpsDev {
+    double *Z;          // [n_slots][zstride] complex: R^-1 by columns, column k at k(k+1)/2
+    double *yv;         // [n_slots][m] complex: y = R^-1 g
+    double *dl;         // [n_slots][m+1] complex: delta_i = d . v_i
+    double *xi;         // [n_slots][m+1] complex: xi_i = x0^H v_i (x0 = the cycle's start)
+    double *st;         // [n_slots][EPS_NS]: |Z|_F^2, P (2), S = x0^H V y (2), |y|^2, phi (2), |x0|^2
+    const double *drives;   // [n_drive][P_pad] real
+    int64_t zstride;    // doubles per slot in Z
+};
+constexpr int EPS_NS = 10;
 
 void launch_gather_jobs(Tracer *t, hipStream_t s, const Job *jobs, int nb, const SlotsDev &sl,
                         double *Vb, int ncp, int P);
@@ -191,9 +211,10 @@ void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
                     const SlotsDev &sl, int P, StepStatus *status, int n_arnoldi, double sum_j1);
 // Arnoldi step with delayed reorthogonalisation (two passes over the basis).
 // scratch (may be NULL) holds the partial sums of the split update (few jobs).
+// eps (may be NULL) adds the error estimates of the stopping test to each step's status.
 void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, const SlotsDev &sl, int P,
                  StepStatus *status, int n_arnoldi, double sum_j1, double *scratch = nullptr,
-                 size_t scratch_doubles = 0);
+                 size_t scratch_doubles = 0, const EpsDev *eps = nullptr);
 void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
                      const SlotsDev &sl, int P, double sum_L);
 void launch_alpha(Tracer *t, hipStream_t s, const Job *jobs, int n, const SlotsDev &sl,

@@ -211,6 +211,11 @@ void k_cgs_update(const Job *__restrict__ jobs, SlotsDev sl, int P, int accumula
 struct cpx { double r, i; };
 __device__ __forceinline__ cpx cmul(cpx a, cpx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 __device__ __forceinline__ cpx cadd(cpx a, cpx b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cpx cdiv(cpx a, cpx b) {
+    const double d = b.r * b.r + b.i * b.i;
+    if (d == 0.0) return {0.0, 0.0};
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
 
 struct GivensShared {
     cpx A[2][256], B[2][256];
@@ -620,8 +625,11 @@ void k_dcgs_update_fin(const Job *__restrict__ jobs, SlotsDev sl, int P, int G, 
 }
 
 // beta~ = |w'|, v~_{j+1} = w' / beta~, provisional h_{j+1,j} = beta~.
+// With the error estimates on (ed.Z != NULL) also the projections of the
+// vector v_j this step finished: delta_j = d . v_j and xi_j = x0^H v_j, and at
+// j = 0 the start's d . x0 and |x0|^2.
 __global__ __launch_bounds__(256)
-void k_dcgs_norm(const Job *__restrict__ jobs, SlotsDev sl, int P, StepStatus *__restrict__ st) {
+void k_dcgs_norm(const Job *__restrict__ jobs, SlotsDev sl, int P, StepStatus *__restrict__ st, EpsDev ed) {
     __shared__ double sh[4];
     const int q = blockIdx.x, t = threadIdx.x;
     const Job jb = jobs[q];
@@ -645,6 +653,151 @@ void k_dcgs_norm(const Job *__restrict__ jobs, SlotsDev sl, int P, StepStatus *_
         colj[j + 1] = {hn, 0.0};
         st[q].hnext = hn;
     }
+    if (!ed.Z) return;
+    const double2 *v = reinterpret_cast<const double2 *>(sl.V + jb.slot * sl.vstride + (int64_t)j * vlen);
+    const double2 *x = reinterpret_cast<const double2 *>(sl.x + jb.slot * vlen);
+    const double *d = ed.drives + (int64_t)jb.drive * sl.P_pad;
+    double dr = 0.0, di = 0.0, xr = 0.0, xi = 0.0, pr = 0.0, pi = 0.0, xx = 0.0;
+    for (int mu = t; mu < P; mu += 256) {
+        const double2 a = v[mu], b = x[mu];
+        dr += d[mu] * a.x;
+        di += d[mu] * a.y;
+        xr += b.x * a.x + b.y * a.y;   // conj(x) v
+        xi += b.x * a.y - b.y * a.x;
+        if (j == 0) {
+            pr += d[mu] * b.x;
+            pi += d[mu] * b.y;
+            xx += b.x * b.x + b.y * b.y;
+        }
+    }
+    dr = block_sum(dr, sh);
+    di = block_sum(di, sh);
+    xr = block_sum(xr, sh);
+    xi = block_sum(xi, sh);
+    if (j == 0) {
+        pr = block_sum(pr, sh);
+        pi = block_sum(pi, sh);
+        xx = block_sum(xx, sh);
+    }
+    if (t == 0) {
+        const int64_t o = (int64_t)jb.slot * (sl.m + 1) * 2 + 2 * j;
+        ed.dl[o] = dr;
+        ed.dl[o + 1] = di;
+        ed.xi[o] = xr;
+        ed.xi[o + 1] = xi;
+        if (j == 0) {
+            double *S = ed.st + (int64_t)jb.slot * EPS_NS;
+            S[1] = pr;
+            S[2] = pi;
+            S[9] = xx;
+        }
+    }
+}
+
+// Column c = j - 1 of Z = R^-1 from column c of R (rotated in this step):
+//   z_i = -(sum_{i <= k < c} Z_ik R_kc) / R_cc  (i < c),   z_c = 1 / R_cc,
+// then y_i += z_i g_c and the workgroup's partial sums of |z_i|^2,
+// delta_i z_i, xi_i z_i and |y_i|^2 (rows i of this workgroup) go to
+// part[(q G + x) 8 + 0..5].  Workgroup x takes rows [256 x, 256 x + 256).
+constexpr int ECH = 1024;
+__device__ __forceinline__ int64_t zoff(int k) { return (int64_t)k * (k + 1) / 2; }
+
+__global__ __launch_bounds__(256)
+void k_eps_column(const Job *__restrict__ jobs, SlotsDev sl, EpsDev ed, int G, double *__restrict__ part) {
+    __shared__ cpx rs[ECH];
+    __shared__ double sh[4];
+    const int q = blockIdx.y, t = threadIdx.x;
+    const Job jb = jobs[q];
+    const int c = jb.j - 1;
+    const int i0 = blockIdx.x * 256;
+    if (jb.type != JOB_ARNOLDI || c < 0 || i0 > c) return;   // uniform per workgroup
+    const int i = i0 + t;
+    const bool act = i <= c;
+    const cpx *R = reinterpret_cast<const cpx *>(sl.H + jb.slot * sl.hstride + 2 * hoff(c));
+    cpx *Z = reinterpret_cast<cpx *>(ed.Z + jb.slot * ed.zstride);
+    cpx w = {0.0, 0.0};
+    for (int k0 = i0; k0 < c; k0 += ECH) {    // columns below i0 meet none of these rows
+        const int n = min(ECH, c - k0);
+        __syncthreads();
+        for (int kk = t; kk < n; kk += 256) rs[kk] = R[k0 + kk];
+        __syncthreads();
+        if (act)
+            for (int k = max(k0, i); k < k0 + n; ++k) w = cadd(w, cmul(Z[zoff(k) + i], rs[k - k0]));
+    }
+    const cpx inv = cdiv({1.0, 0.0}, R[c]);
+    cpx z = {0.0, 0.0}, y = {0.0, 0.0};
+    double a = 0.0, br = 0.0, bi = 0.0, er = 0.0, ei = 0.0, f = 0.0;
+    if (act) {
+        z = i < c ? cmul({-w.r, -w.i}, inv) : inv;
+        Z[zoff(c) + i] = z;
+        const cpx gc = reinterpret_cast<const cpx *>(sl.g + (int64_t)jb.slot * (sl.m + 1) * 2)[c];
+        cpx *yv = reinterpret_cast<cpx *>(ed.yv + (int64_t)jb.slot * sl.m * 2);
+        y = cadd(i < c ? yv[i] : cpx{0.0, 0.0}, cmul(z, gc));
+        yv[i] = y;
+        const cpx dl = reinterpret_cast<const cpx *>(ed.dl + (int64_t)jb.slot * (sl.m + 1) * 2)[i];
+        const cpx xv = reinterpret_cast<const cpx *>(ed.xi + (int64_t)jb.slot * (sl.m + 1) * 2)[i];
+        const cpx b = cmul(dl, z), e = cmul(xv, z);
+        a = z.r * z.r + z.i * z.i;
+        br = b.r; bi = b.i; er = e.r; ei = e.i;
+        f = y.r * y.r + y.i * y.i;
+    }
+    a = block_sum(a, sh);
+    br = block_sum(br, sh);
+    bi = block_sum(bi, sh);
+    er = block_sum(er, sh);
+    ei = block_sum(ei, sh);
+    f = block_sum(f, sh);
+    if (t == 0) {
+        double *o = part + ((int64_t)q * G + blockIdx.x) * 8;
+        o[0] = a; o[1] = br; o[2] = bi; o[3] = er; o[4] = ei; o[5] = f;
+    }
+}
+
+// Adds the workgroups' partial sums in order, advances the running
+// quantities and writes eps_X and eps_P of dimension j to the step's status.
+__global__ __launch_bounds__(64)
+void k_eps_finish(const Job *__restrict__ jobs, SlotsDev sl, EpsDev ed, int G, const double *__restrict__ part,
+                  StepStatus *__restrict__ st) {
+    const int q = blockIdx.x;
+    const Job jb = jobs[q];
+    if (threadIdx.x != 0 || jb.type != JOB_ARNOLDI) return;
+    const int j = jb.j;
+    double *S = ed.st + (int64_t)jb.slot * EPS_NS;
+    const cpx *dl = reinterpret_cast<const cpx *>(ed.dl + (int64_t)jb.slot * (sl.m + 1) * 2);
+    if (j == 0) {   // dimension 0: P and |x0|^2 came from the norm kernel
+        S[0] = 0.0;
+        S[3] = S[4] = 0.0;
+        S[5] = 0.0;
+        S[6] = dl[0].r;
+        S[7] = dl[0].i;
+        st[q].eps_x = st[q].eps_p = HUGE_VAL;
+        return;
+    }
+    const int c = j - 1, n = (j + 255) / 256;
+    double a = 0.0, br = 0.0, bi = 0.0, er = 0.0, ei = 0.0, f = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double *o = part + ((int64_t)q * G + k) * 8;
+        a += o[0]; br += o[1]; bi += o[2]; er += o[3]; ei += o[4]; f += o[5];
+    }
+    const cpx *g = reinterpret_cast<const cpx *>(sl.g + (int64_t)jb.slot * (sl.m + 1) * 2);
+    const cpx gc = g[c], gj = g[j];
+    S[0] += a;
+    const cpx dP = cmul(gc, {br, bi}), dS = cmul(gc, {er, ei});
+    S[1] += dP.r; S[2] += dP.i;
+    S[3] += dS.r; S[4] += dS.i;
+    S[5] = f;
+    const cpx sn = reinterpret_cast<const cpx *>(sl.sn + (int64_t)jb.slot * sl.m * 2)[c];
+    const double cs = sl.cs[(int64_t)jb.slot * sl.m + c];
+    const cpx phi = cadd(cmul({-sn.r, -sn.i}, {S[6], S[7]}), {cs * dl[j].r, cs * dl[j].i});
+    S[6] = phi.r;
+    S[7] = phi.i;
+    const double zf = sqrt(S[0]);
+    const double X2 = S[9] + 2.0 * S[3] + S[5];
+    const double rn = sqrt(gj.r * gj.r + gj.i * gj.i);
+    const cpx dr = cmul(gj, phi);
+    const double pa = sqrt(S[1] * S[1] + S[2] * S[2]);
+    st[q].eps_x = X2 > 0.0 ? zf * rn / sqrt(X2) : HUGE_VAL;
+    st[q].eps_p = pa > 0.0 ? zf * sqrt(dr.r * dr.r + dr.i * dr.i) / pa : HUGE_VAL;
 }
 
 // Basis groups of the split update: enough workgroups to fill the chip a few
@@ -672,7 +825,8 @@ static int dots_splits(int P, int nb, int jmax, size_t scratch_doubles) {
 }
 
 void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, const SlotsDev &sl, int P,
-                 StepStatus *status, int n_arnoldi, double sum_j1, double *scratch, size_t scratch_doubles) {
+                 StepStatus *status, int n_arnoldi, double sum_j1, double *scratch, size_t scratch_doubles,
+                 const EpsDev *eps) {
     const int R = scratch ? dots_splits(P, nb, jmax, scratch_doubles) : 1;
     const dim3 gd((jmax + 1 + 4 * DPW - 1) / (4 * DPW), nb, R), gu((P + 255) / 256, nb);
     trace_begin(t, "dcgs_dots", s);
@@ -694,9 +848,20 @@ void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, co
         hipLaunchKernelGGL(k_dcgs_update_fin, gu, dim3(256), 0, s, jobs, sl, P, G, scratch);
     }
     trace_end(t, s, 16.0 * P * sum_j1, 16.0 * P * (sum_j1 + 3.0 * n_arnoldi));
+    EpsDev none{};
     trace_begin(t, "dcgs_norm", s);
-    hipLaunchKernelGGL(k_dcgs_norm, dim3(nb), dim3(256), 0, s, jobs, sl, P, status);
+    hipLaunchKernelGGL(k_dcgs_norm, dim3(nb), dim3(256), 0, s, jobs, sl, P, status, eps ? *eps : none);
     trace_end(t, s, 4.0 * P * n_arnoldi, 16.0 * P * 2.0 * n_arnoldi);
+    if (eps) {
+        // partial sums in scratch: nb jobs x G workgroups x 8 (the update's
+        // partial sums are consumed by now; same stream)
+        const int G = (jmax + 255) / 256 > 0 ? (jmax + 255) / 256 : 1;
+        trace_begin(t, "eps_estimates", s);
+        hipLaunchKernelGGL(k_eps_column, dim3(G, nb), dim3(256), 0, s, jobs, sl, *eps, G, scratch);
+        hipLaunchKernelGGL(k_eps_finish, dim3(nb), dim3(64), 0, s, jobs, sl, *eps, G,
+                           (const double *)scratch, status);
+        trace_end(t, s, 0.0, 8.0 * (double)jmax * jmax * n_arnoldi);
+    }
 }
 
 void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
@@ -723,11 +888,6 @@ void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
 // lanes, the pivot broadcast by shuffles), then all threads subtract the
 // block's contribution from the rows above it.
 __device__ __forceinline__ cpx cshfl(cpx v, int src) { return {__shfl(v.r, src), __shfl(v.i, src)}; }
-__device__ __forceinline__ cpx cdiv(cpx a, cpx b) {
-    const double d = b.r * b.r + b.i * b.i;
-    if (d == 0.0) return {0.0, 0.0};
-    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
-}
 
 constexpr int TSB = 32;    // rows of a diagonal block solved by one wavefront
 constexpr int TPW = 256;   // rows of a panel (one launch pair per panel)
