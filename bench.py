@@ -99,6 +99,65 @@ def cpu_baseline(sys_, drives, n_sample, seed=0):
                       f"(grid indices {idx.tolist()}), dense chi0 + LU in FP64, {dt:.1f} s"}
 
 
+def chi0_flops(s):
+    """Table t:flops count of one chi0 z (complex z, real X and vertices)."""
+    N, No = s.n_orb, s.n_occ
+    Nv = N - No
+    S_V = int(sum(s.support(m).size for m in range(s.n_prod)))   # sum of product supports
+    return 8.0 * No * S_V + 8.0 * N * No * Nv + 6.0 * No * Nv
+
+
+def apply_only(a, s, ctx):
+    """chi0.v GFLOP/s: REPS applications of chi0(w_r) to a batch of seeded vectors."""
+    import torch
+    from paper_1005_5340_amd import chi0
+    rng = np.random.default_rng(7)
+    nb = a.batch
+    om = s.omegas[rng.choice(s.omegas.size, size=nb, replace=nb > s.omegas.size)]
+    z = torch.tensor(rng.standard_normal((nb, s.n_prod)) + 1j * rng.standard_normal((nb, s.n_prod)),
+                     dtype=torch.complex128, device="cuda")
+    F = chi0_flops(s)
+    res = {}
+    ref = None
+    for name, prec in (("fp64", chi0.PREC_FP64), ("fp32", chi0.PREC_FP32), ("bf16x3", chi0.PREC_BF16X3)):
+        if a.precision != "fp64" and name not in ("fp64", a.precision):
+            continue
+        out = ctx.apply(om, s.eps, z, precision=prec)    # first call tunes the GEMM tiles
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(a.apply_only):
+            ctx.apply(om, s.eps, z, out=out, precision=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.apply_only
+        ks = ctx.kernel_stats()
+        ctx.set_timing(False)
+        if ref is None:
+            ref = out.clone()
+        err = float((torch.linalg.vector_norm(out - ref, dim=1) / torch.linalg.vector_norm(ref, dim=1)).max())
+        kern = {k: {"ms_per_apply": v["ms"] / a.apply_only,
+                    "rate": (v["flops"] / 1e12 if bound_of(k) != "hbm" else v["bytes"] / 1e9) / (v["ms"] * 1e-3),
+                    "unit": "TFLOP/s" if bound_of(k) != "hbm" else "GB/s"} for k, v in ks.items()}
+        dom = max(ks, key=lambda k: ks[k]["ms"])
+        b = bound_of(dom)
+        peak, unit = PEAK[b]
+        work = ks[dom]["bytes"] if b == "hbm" else ks[dom]["flops"]
+        res[name] = {"gflops": F * nb / dt / 1e9, "ms_per_apply": dt * 1e3,
+                     "max_rel_diff_vs_fp64_gpu": err,
+                     "dominant": {"kernel": dom, "achieved": work / (ks[dom]["ms"] * 1e-3) / (1e9 if b == "hbm" else 1e12),
+                                  "peak": peak / (1e9 if b == "hbm" else 1e12), "unit": unit,
+                                  "frac": work / (ks[dom]["ms"] * 1e-3) / peak},
+                     "kernels": kern}
+        print(f"[bench] apply {name}: {res[name]['gflops']:.0f} GFLOP/s, {dt * 1e3:.2f} ms per batch of {nb}",
+              file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "chi0.v GFLOP/s (Table t:flops count)", "value": res["fp64"]["gflops"],
+                      "unit": "GFLOP/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+                      "config": {"workload": a.workload, "seed": a.seed, "n_orb": s.n_orb, "n_occ": s.n_occ,
+                                 "n_prod": s.n_prod, "batch": nb, "reps": a.apply_only},
+                      "flops_per_apply": F, "precisions": res}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,7 +176,18 @@ def main():
                     help="learned warm start fitted on this many seeded training frequencies (0 = off)")
     ap.add_argument("--cpu-sample", type=int, default=2, help="frequencies for the oracle baseline (0 = skip)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
-    ap.add_argument("--lanes", type=int, default=0, help="solver lanes (0 = library default)")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="solver lanes (0 = library default: 2 for 16+ concurrent points).  One lane by "
+                         "default: the timed per-launch rates are then those of each kernel alone on the "
+                         "GPU; two lanes are ~2%% faster on the 60-atom spectrum")
+    ap.add_argument("--stop", default="residual", choices=["residual", "eps_p", "eps_px"],
+                    help="stopping test: relative residual, or the paper's eps_P / eps_P+eps_X estimates")
+    ap.add_argument("--omega-sample", type=int, default=0, metavar="K",
+                    help="solve K evenly spaced frequencies of the grid (plus those of a sampled oracle "
+                         "reference) instead of the whole grid")
+    ap.add_argument("--apply-only", type=int, default=0, metavar="REPS",
+                    help="only time REPS batched chi0 applications (--batch right-hand sides each) "
+                         "and report chi0.v GFLOP/s")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 device copies of MIB MiB (reference for HBM traffic counters)")
     a = ap.parse_args()
@@ -141,19 +211,35 @@ def main():
     from paper_1005_5340_amd import chi0, synth
 
     w = synth.WORKLOADS[a.workload]
+    t0 = time.perf_counter()
     s = synth.make_system(a.workload, a.seed)
+    print(f"[bench] {a.workload} generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     drives = s.drives()
     tol = a.tol or w.tol
     restart = a.restart or s.n_prod
     ctx = chi0.Context(0)
+    t0 = time.perf_counter()
     ctx.set_system_from(s)
+    print(f"[bench] set_system {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    if a.apply_only:
+        return apply_only(a, s, ctx)
 
-    ref = None
+    # the oracle's stored polarizability: the whole grid, or a sample of grid points
+    ref, ref_idx = None, None
     refpath = os.path.join(ROOT, "tests", "golden", f"reference_{a.workload}_s{a.seed}.json")
     if os.path.exists(refpath):
         r = json.load(open(refpath))
-        if synth.same_inputs(s, r["fingerprint"]) and r["omega_index"] == list(range(s.omegas.size)):
+        if synth.same_inputs(s, r["fingerprint"]):
             ref = np.array(r["alpha_re"]) + 1j * np.array(r["alpha_im"])
+            ref_idx = np.asarray(r["omega_index"], dtype=int)
+
+    # the frequencies solved: the whole grid, or an evenly spaced sample of it
+    grid = np.arange(s.omegas.size)
+    if a.omega_sample:
+        extra = ref_idx if ref_idx is not None else np.zeros(0, int)
+        k = max(1, a.omega_sample - extra.size)
+        grid = np.unique(np.concatenate([np.round(np.linspace(0, s.omegas.size - 1, k)).astype(int), extra]))
+    omegas = s.omegas[grid]
 
     prec = {"fp64": chi0.PREC_FP64, "fp32": chi0.PREC_FP32, "bf16x3": chi0.PREC_BF16X3}[a.precision]
     ws, warm_info = None, None
@@ -170,12 +256,14 @@ def main():
               file=sys.stderr, flush=True)
 
     def run(lanes=None):
-        return ctx.solve_response(s.omegas, s.eps, drives, restart=restart, max_iter=a.max_iter,
+        return ctx.solve_response(omegas, s.eps, drives, restart=restart, max_iter=a.max_iter,
                                   tol=tol, batch=a.batch, precision=prec, inner_tol=a.inner_tol,
-                                  warm=ws, lanes=a.lanes if lanes is None else lanes)
+                                  warm=ws, lanes=a.lanes if lanes is None else lanes,
+                                  stop={"residual": chi0.STOP_RESIDUAL, "eps_p": chi0.STOP_EPS_P,
+                                        "eps_px": chi0.STOP_EPS_PX}[a.stop])
 
     print(f"[bench] {a.workload}: N={s.n_orb} N_occ={s.n_occ} n_prod={s.n_prod} points="
-          f"{s.omegas.size * drives.shape[0]} batch={a.batch} GMRES({restart}) tol={tol:g}",
+          f"{omegas.size * drives.shape[0]} batch={a.batch} GMRES({restart}) tol={tol:g}",
           file=sys.stderr, flush=True)
     # One untimed solve on a single lane times every kernel (the per-kernel
     # breakdown, each kernel alone on the GPU); the warmup and timed steps use
@@ -215,15 +303,28 @@ def main():
             for f in ("launches", "ms", "flops", "bytes"):
                 v[f] = v[f] / a.steps
 
-    npts = s.omegas.size * drives.shape[0]
+    npts = omegas.size * drives.shape[0]
     diag = np.stack([alpha[:, i, i] for i in range(drives.shape[0])], 1)
+    if ref is not None and not np.all(np.isin(ref_idx, grid)):
+        ref = None      # a reference for frequencies this run did not solve
     if ref is not None:
+        full = ref_idx.size == grid.size and np.array_equal(ref_idx, grid)
+        diag = diag[np.searchsorted(grid, ref_idx)]
         rdiag = np.stack([ref[:, i, i] for i in range(drives.shape[0])], 1)
         err = np.stack([im_errors(diag[:, i], rdiag[:, i]) for i in range(drives.shape[0])], 1)
-        passing = int((err <= 1e-6).sum())
-        acc = {"checked": True, "max_im_rel_err": float(err.max()),
+        if full:
+            passing = int((err <= 1e-6).sum())
+        else:   # a sample of the grid: the converged points, scaled by the sample's pass rate
+            passing = int(stats["converged"].sum()) * float((err <= 1e-6).mean())
+        acc = {"checked": True, "sampled": None if full else
+               f"{ref_idx.size} of {grid.size} frequencies solved (grid indices {ref_idx.tolist()}), "
+               "value scaled by their pass rate",
+               "max_im_rel_err": float(err.max()),
+               "median_im_rel_err": float(np.median(err)),
+               "max_abs_rel_err": float(np.max(np.abs(diag - rdiag) / np.abs(rdiag))),
+               "points_passing_1e-2": int((err <= 1e-2).sum()),
                "max_re_rel_err": float(np.max(np.abs(diag.real - rdiag.real) / np.abs(rdiag.real))),
-               "points_passing_1e-6": passing, "points_passing_1e-10": int((err <= 1e-10).sum())}
+               "points_passing_1e-6": int((err <= 1e-6).sum()), "points_passing_1e-10": int((err <= 1e-10).sum())}
     else:
         passing = npts
         acc = {"checked": False}
@@ -250,15 +351,12 @@ def main():
                 "launches": rec["launches"] // a.steps, "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
                 "share_of_gpu_time": (ks_all[dom]["ms"] / tot_all) if dom in ks_all else None,
                 "lanes": a.lanes or ("auto: 2" if a.batch >= 16 else "auto: 1"),
-                "note": "per-launch rate of the timed steps; with 2 lanes a launch shares the GPU "
-                        "with the other lane's kernels (single-lane rates: stderr breakdown, chi0_gflops)"}
+                "note": "per-launch rate over the timed steps (HIP events on the lane's stream); with "
+                        "more than one lane a launch shares the GPU with the other lanes' kernels"}
         # chi0 rate and the per-kernel breakdown: every kernel timed (the
         # single-lane breakdown run, or the timed steps when there is no warmup)
         chi0_ms = sum(ks_all[k]["ms"] for k in CHI0_KERNELS if k in ks_all)
-        N, No = s.n_orb, s.n_occ
-        Nv = N - No
-        S_V = int(sum(s.support(m).size for m in range(s.n_prod)))
-        F = 8.0 * No * S_V + 8.0 * N * No * Nv + 6.0 * No * Nv      # Table t:flops count per chi0 z
+        F = chi0_flops(s)
         if chi0_ms > 0:
             chi0_gflops = F * applications / (chi0_ms * 1e-3) / 1e9
         print("[bench] per-step breakdown (one lane, all kernels timed)", file=sys.stderr)
@@ -290,10 +388,11 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16x3": "f64+bf16x3"}[a.precision],
         "data": "synthetic",
         "config": {"workload": a.workload, "seed": a.seed, "n_orb": s.n_orb, "n_occ": s.n_occ,
-                   "n_prod": s.n_prod, "n_omega": int(s.omegas.size), "drives": w.drives,
+                   "n_prod": s.n_prod, "n_omega": int(omegas.size), "drives": w.drives,
+                   "omega_grid": int(s.omegas.size), "omega_sample": a.omega_sample or None,
                    "eps": s.eps, "tol": tol, "restart": restart, "batch": a.batch,
                    "points": npts, "precision": a.precision, "warm_start_train": a.warm,
-                   "lanes": a.lanes},
+                   "lanes": a.lanes, "stop": a.stop},
         "chi0_gflops": chi0_gflops,
         "autotune": {k: v["tile"] for k, v in sorted(tuned.items())},
         "chi0_applications_per_step": applications,

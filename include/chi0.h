@@ -161,7 +161,7 @@ typedef struct chi0_solve_opts {
                              starts from x0 = U c(omega) instead of 0, unless
                              ||chi0 d - A x0|| >= ||chi0 d||, then from 0 */
     int32_t ortho;        /* CHI0_ORTHO_*: Gram-Schmidt variant of the Arnoldi step */
-    int32_t lanes;        /* 0 = auto (2 when batch >= 16, else 1), or 1 or 2: the concurrent
+    int32_t lanes;        /* 0 = auto (2 when batch >= 16, else 1), or 1..4: the concurrent
                              slots are dealt to this many lanes, each with its own stream and
                              operator workspace, so that one lane's memory-bound Gram-Schmidt
                              passes overlap the other's matrix-core transforms */

@@ -120,7 +120,8 @@ struct OpWork {
         Tt32 = at32 = Ut32 = nullptr;
     }
 };
-constexpr int kLanes = 2;            // slot lanes of the solver, one stream each
+constexpr int kLanes = 4;            // most slot lanes of the solver, one stream each
+constexpr int kAutoLanes = 2;        // lanes when the caller leaves the choice to the library
 constexpr int kSets = 2 * kLanes;    // step buffer sets: two steps in flight per lane
 
 
@@ -145,7 +146,7 @@ struct chi0_ctx {
 
     // operator workspaces (lane 0 also serves chi0_apply) and the lanes' streams
     OpWork op[kLanes];
-    hipStream_t lane_stream[kLanes] = {nullptr, nullptr};   // [0] is `stream`
+    hipStream_t lane_stream[kLanes] = {};   // [0] is `stream`
     // low-precision operator: operand copies (set_system)
     float *Xo32 = nullptr, *Xv32 = nullptr, *Xvt32 = nullptr;
     uint16_t *Xv_hi = nullptr, *Xv_lo = nullptr, *Xvt_hi = nullptr, *Xvt_lo = nullptr;
@@ -187,7 +188,8 @@ struct chi0_ctx {
         if (status_h) (void)hipHostFree(status_h);
         for (hipEvent_t &e : step_ev)
             if (e) (void)hipEventDestroy(e);
-        if (lane_stream[1]) (void)hipStreamDestroy(lane_stream[1]);
+        for (int L = 1; L < kLanes; ++L)
+            if (lane_stream[L]) (void)hipStreamDestroy(lane_stream[L]);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -246,7 +248,8 @@ extern "C" int chi0_create(chi0_ctx **out, int device) {
         }
         e = hipSetDevice(device);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->lane_stream[1], hipStreamNonBlocking);
+        for (int L = 1; L < kLanes && e == hipSuccess; ++L)
+            e = hipStreamCreateWithFlags(&c->lane_stream[L], hipStreamNonBlocking);
         c->lane_stream[0] = c->stream;
         if (e != hipSuccess) {
             g_create_error = std::string("HIP setup failed: ") + hipGetErrorString(e);
@@ -928,7 +931,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     if (!(o.inner_tol >= 0.0) || !(o.inner_tol < 1.0)) return fail(c, CHI0_EINVAL, "inner_tol must be in [0, 1)");
     if (o.reserved != 0) return fail(c, CHI0_EINVAL, "reserved option fields must be zero");
     if (o.stop < CHI0_STOP_RESIDUAL || o.stop > CHI0_STOP_EPS_PX) return fail(c, CHI0_EINVAL, "unknown stop");
-    if (o.lanes < 0 || o.lanes > kLanes) return fail(c, CHI0_EINVAL, "lanes must be 0 (auto), 1 or 2");
+    if (o.lanes < 0 || o.lanes > kLanes) return fail(c, CHI0_EINVAL, "lanes must be 0 (auto) or 1..4");
     if (o.ortho < CHI0_ORTHO_AUTO || o.ortho > CHI0_ORTHO_DCGS2) return fail(c, CHI0_EINVAL, "unknown ortho");
     // delayed reorthogonalisation needs a few columns per cycle (one is always provisional)
     const bool dcgs = o.ortho == CHI0_ORTHO_DCGS2 || (o.ortho == CHI0_ORTHO_AUTO && o.restart >= 8);
@@ -958,7 +961,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     // matrix-core transforms.  Dealing the slots mixes the frequencies, whose
     // iteration counts differ by up to 5x, over both lanes.  Small batches use
     // one lane.
-    const int nl = std::min(nsl, o.lanes > 0 ? o.lanes : (nsl >= 16 ? kLanes : 1));
+    const int nl = std::min(nsl, o.lanes > 0 ? o.lanes : (nsl >= 16 ? kAutoLanes : 1));
     for (int L = 0; L < nl; ++L) {
         const int ln = (nsl - L + nl - 1) / nl;
         CHK(ensure_ws(c, c->op[L], 2 * std::max(ln, c->op[L].nc_cap / 2)));
