@@ -55,11 +55,14 @@ void k_bgemm3(int M, int N, int K, const uint16_t *__restrict__ Ahi, const uint1
     const int wm = wv % 2, wn = wv / 2;
 
     const int a_row = t / 4, a_k = (t % 4) * 8;          // 64 rows x 32 k, 8 per thread
-    const int b_k = t / 8, b_n = (t % 8) * 8;            // 32 k x 64 n, 8 per thread
+    // B: thread t takes column n0 + (t % 64) and the 8 k of group t / 64, so each
+    // wavefront's loads are 64 consecutive columns of one row (coalesced) and the
+    // split values go to the transposed LDS tile as two 16-byte stores.
+    const int b_n = t & 63, b_k = (t >> 6) * 8;
     const uint16_t *ah = Ahi + (int64_t)(m0 + a_row) * lda + a_k;
     const uint16_t *al = Alo + (int64_t)(m0 + a_row) * lda + a_k;
     const float *bp0 = B + (int64_t)b_k * ldb + n0 + b_n;
-    const bool b_full = (n0 + b_n + 7) < N;
+    const bool b_ok = n0 + b_n < N;
 
     uint4 rah, ral;
     float rb[8];
@@ -67,25 +70,22 @@ void k_bgemm3(int M, int N, int K, const uint16_t *__restrict__ Ahi, const uint1
         rah = *reinterpret_cast<const uint4 *>(ah + kt * BK);
         ral = *reinterpret_cast<const uint4 *>(al + kt * BK);
         const float *bp = bp0 + (int64_t)kt * BK * ldb;
-        if (b_full) {
-            const float4 x0 = reinterpret_cast<const float4 *>(bp)[0];
-            const float4 x1 = reinterpret_cast<const float4 *>(bp)[1];
-            rb[0] = x0.x; rb[1] = x0.y; rb[2] = x0.z; rb[3] = x0.w;
-            rb[4] = x1.x; rb[5] = x1.y; rb[6] = x1.z; rb[7] = x1.w;
-        } else {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) rb[c] = (n0 + b_n + c < N) ? bp[c] : 0.f;
-        }
+        for (int c = 0; c < 8; ++c) rb[c] = b_ok ? bp[(int64_t)c * ldb] : 0.f;
     };
     auto store = [&](int buf) {
         *reinterpret_cast<uint4 *>(&Ash[buf][a_row][a_k]) = rah;
         *reinterpret_cast<uint4 *>(&Asl[buf][a_row][a_k]) = ral;
+        uint32_t hw[4], lw[4];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const uint16_t h = f2bf(rb[c]);
-            Bsh[buf][b_n + c][b_k] = h;
-            Bsl[buf][b_n + c][b_k] = f2bf(rb[c] - bf2f(h));
+        for (int c = 0; c < 8; c += 2) {
+            const uint16_t h0 = f2bf(rb[c]), h1 = f2bf(rb[c + 1]);
+            const uint16_t l0 = f2bf(rb[c] - bf2f(h0)), l1 = f2bf(rb[c + 1] - bf2f(h1));
+            hw[c / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+            lw[c / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
         }
+        *reinterpret_cast<uint4 *>(&Bsh[buf][b_n][b_k]) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        *reinterpret_cast<uint4 *>(&Bsl[buf][b_n][b_k]) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
     };
 
     flt4 acc[2][2];
