@@ -113,11 +113,13 @@ struct OpWork {
     double *gemm_scratch = nullptr;
     size_t gemm_scratch_n = 0;
     float *Tt32 = nullptr, *at32 = nullptr, *Ut32 = nullptr;
+    uint16_t *Bhi = nullptr, *Blo = nullptr;   // split-BF16 planes of the dense GEMMs' B operand
     void release() {
         lpbuf.release();
         buf.release();
         nc_cap = lp_cap = 0;
         Tt32 = at32 = Ut32 = nullptr;
+        Bhi = Blo = nullptr;
     }
 };
 constexpr int kLanes = 4;            // most slot lanes of the solver, one stream each
@@ -687,6 +689,12 @@ static int ensure_lp(chi0_ctx *c, OpWork &o) {
     CHK(dalloc(c, o.lpbuf, &o.Tt32, (int64_t)c->N_pad * mcol));
     CHK(dalloc(c, o.lpbuf, &o.Ut32, (int64_t)c->N_pad * mcol));
     CHK(dalloc(c, o.lpbuf, &o.at32, (int64_t)c->Nv_pad * mcol));
+    // two uint16 planes of max(N_pad, Nv_pad) x mcol: as many bytes as one FP32 copy
+    const int64_t kmax = std::max(c->N_pad, c->Nv_pad);
+    double *planes = nullptr;
+    CHK(dalloc(c, o.lpbuf, &planes, (kmax * mcol + 3) / 4 * 2));
+    o.Bhi = reinterpret_cast<uint16_t *>(planes);
+    o.Blo = o.Bhi + (kmax * mcol + 3) / 4 * 4;
     HIPCHK(c, hipDeviceSynchronize());
     o.lp_cap = o.nc_cap;
     return CHI0_OK;
@@ -728,10 +736,10 @@ static void run_chi0(chi0_ctx *c, OpWork &o, hipStream_t s, int nb, double eps, 
                          o.gemm_scratch, sb, &c->tuner);
         } else {   // split BF16 x 3: three BF16 products per multiply-add
             launch_bgemm3(t, s, "virt_transform_lorentz_bf16x3", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt_hi,
-                          c->Xvt_lo, c->N_pad, o.Tt32, (int)mcol, o.at32, (int)mcol, 3.0 * fl,
+                          c->Xvt_lo, c->N_pad, o.Tt32, (int)mcol, o.Bhi, o.Blo, o.at32, (int)mcol, 3.0 * fl,
                           by + 4.0 * w.N * w.Nv, &la, o.gemm_scratch, sb);
             launch_bgemm3(t, s, "virt_back_bf16x3", c->N_pad, (int)mcol, c->Nv_pad, c->Xv_hi, c->Xv_lo,
-                          c->Nv_pad, o.at32, (int)mcol, o.Ut32, (int)mcol, 3.0 * fl,
+                          c->Nv_pad, o.at32, (int)mcol, o.Bhi, o.Blo, o.Ut32, (int)mcol, 3.0 * fl,
                           by + 4.0 * w.N * w.Nv, nullptr, o.gemm_scratch, sb);
         }
         launch_occ_back_f32(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo32, c->No_pad, o.Ut32, o.W, nc, w);

@@ -138,10 +138,11 @@ void launch_sgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int 
                   const float *A, int lda, const float *B, int ldb, float *C, int ldc,
                   double flops, double bytes, const LorentzArgs *la, void *scratch,
                   size_t scratch_bytes, GemmTuner *tu = nullptr);
+// Bhi/Blo: workspace of K * N uint16 each, filled with B's split (k-blocks of 8).
 void launch_bgemm3(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                    const uint16_t *Ahi, const uint16_t *Alo, int lda, const float *B, int ldb,
-                   float *C, int ldc, double flops, double bytes, const LorentzArgs *la,
-                   void *scratch, size_t scratch_bytes);
+                   uint16_t *Bhi, uint16_t *Blo, float *C, int ldc, double flops, double bytes,
+                   const LorentzArgs *la, void *scratch, size_t scratch_bytes);
 void launch_to_f32(hipStream_t s, const double *x, float *y, int64_t n);
 void launch_split_bf16(hipStream_t s, const double *x, uint16_t *hi, uint16_t *lo, int64_t n);
 

@@ -31,19 +31,22 @@ __device__ __forceinline__ int xcd_remap_b(int wid, int n) {
 }
 
 // C[M x N] (FP32) = A B with A given as BF16 hi/lo planes [M][lda] and B as
-// FP32 [K][ldb] split on the fly.  M % 64 == 0, K % 32 == 0 (per split), N
-// masked.  blockIdx.y selects a K split as in the FP64 GEMM.
+// BF16 hi/lo planes in k-blocks of 8: element (k, n) at ((k / 8) N + n) 8 + k % 8
+// (k_split_kblk), so the 8 k of one column that an MFMA lane needs are one
+// 16-byte load.  M % 64 == 0, K % 32 == 0 (per split), N masked.  blockIdx.y
+// selects a K split as in the FP64 GEMM.
 template <bool LORENTZ>
 __global__ __launch_bounds__(256)
 void k_bgemm3(int M, int N, int K, const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
-              int lda, const float *__restrict__ B, int ldb, float *__restrict__ C, int ldc,
-              int m_fastest, LorentzArgs la) {
+              int lda, const uint16_t *__restrict__ Bhi, const uint16_t *__restrict__ Blo,
+              float *__restrict__ C, int ldc, int m_fastest, LorentzArgs la) {
     constexpr int BM = 64, BN = 64, BK = 32, PADK = BK + 8;
     __shared__ uint16_t Ash[2][BM][PADK], Asl[2][BM][PADK];
     __shared__ uint16_t Bsh[2][BN][PADK], Bsl[2][BN][PADK];   // transposed: [n][k]
     Ahi += (int64_t)blockIdx.y * K;
     Alo += (int64_t)blockIdx.y * K;
-    B += (int64_t)blockIdx.y * K * ldb;
+    Bhi += (int64_t)blockIdx.y * K * N;
+    Blo += (int64_t)blockIdx.y * K * N;
     C += (int64_t)blockIdx.y * M * ldc;
 
     const int ntm = M / BM, ntn = (N + BN - 1) / BN;
@@ -55,37 +58,27 @@ void k_bgemm3(int M, int N, int K, const uint16_t *__restrict__ Ahi, const uint1
     const int wm = wv % 2, wn = wv / 2;
 
     const int a_row = t / 4, a_k = (t % 4) * 8;          // 64 rows x 32 k, 8 per thread
-    // B: thread t takes column n0 + (t % 64) and the 8 k of group t / 64, so each
-    // wavefront's loads are 64 consecutive columns of one row (coalesced) and the
-    // split values go to the transposed LDS tile as two 16-byte stores.
-    const int b_n = t & 63, b_k = (t >> 6) * 8;
+    // B: thread t takes column n0 + (t % 64) and the k-block t / 64 (8 k): one
+    // 16-byte load per plane, stored as one 16-byte row piece of the [n][k] tile.
+    const int b_n = t & 63, b_kb = t >> 6;
     const uint16_t *ah = Ahi + (int64_t)(m0 + a_row) * lda + a_k;
     const uint16_t *al = Alo + (int64_t)(m0 + a_row) * lda + a_k;
-    const float *bp0 = B + (int64_t)b_k * ldb + n0 + b_n;
     const bool b_ok = n0 + b_n < N;
+    const int64_t boff = ((int64_t)b_kb * N + n0 + (b_ok ? b_n : 0)) * 8;
 
-    uint4 rah, ral;
-    float rb[8];
+    uint4 rah, ral, rbh, rbl;
     auto load = [&](int kt) {
         rah = *reinterpret_cast<const uint4 *>(ah + kt * BK);
         ral = *reinterpret_cast<const uint4 *>(al + kt * BK);
-        const float *bp = bp0 + (int64_t)kt * BK * ldb;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) rb[c] = b_ok ? bp[(int64_t)c * ldb] : 0.f;
+        const int64_t o = boff + (int64_t)kt * (BK / 8) * N * 8;
+        rbh = b_ok ? *reinterpret_cast<const uint4 *>(Bhi + o) : make_uint4(0, 0, 0, 0);
+        rbl = b_ok ? *reinterpret_cast<const uint4 *>(Blo + o) : make_uint4(0, 0, 0, 0);
     };
     auto store = [&](int buf) {
         *reinterpret_cast<uint4 *>(&Ash[buf][a_row][a_k]) = rah;
         *reinterpret_cast<uint4 *>(&Asl[buf][a_row][a_k]) = ral;
-        uint32_t hw[4], lw[4];
-#pragma unroll
-        for (int c = 0; c < 8; c += 2) {
-            const uint16_t h0 = f2bf(rb[c]), h1 = f2bf(rb[c + 1]);
-            const uint16_t l0 = f2bf(rb[c] - bf2f(h0)), l1 = f2bf(rb[c + 1] - bf2f(h1));
-            hw[c / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-            lw[c / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
-        }
-        *reinterpret_cast<uint4 *>(&Bsh[buf][b_n][b_k]) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-        *reinterpret_cast<uint4 *>(&Bsl[buf][b_n][b_k]) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        *reinterpret_cast<uint4 *>(&Bsh[buf][b_n][b_kb * 8]) = rbh;
+        *reinterpret_cast<uint4 *>(&Bsl[buf][b_n][b_kb * 8]) = rbl;
     };
 
     flt4 acc[2][2];
@@ -166,10 +159,41 @@ void k_bgemm3(int M, int N, int K, const uint16_t *__restrict__ Ahi, const uint1
 void launch_splitk_reduce_f32(Tracer *t, hipStream_t s, int M, int N, int S, const float *part,
                               float *C, int ldc, const LorentzArgs *la);
 
+// B (FP32 [K][ldb], K % 8 == 0) -> hi/lo BF16 planes in k-blocks of 8 for
+// k_bgemm3: thread (kb, n) reads the 8 rows of its block in column n
+// (coalesced over n) and writes 16 bytes per plane.
+__global__ __launch_bounds__(256)
+void k_split_kblk(const float *__restrict__ B, int K, int N, int ldb, uint16_t *__restrict__ hi,
+                  uint16_t *__restrict__ lo) {
+    const int64_t total = (int64_t)(K / 8) * N;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+        const int kb = (int)(idx / N), n = (int)(idx % N);
+        const float *src = B + (int64_t)kb * 8 * ldb + n;
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int c = 0; c < 8; c += 2) {
+            const float x0 = src[(int64_t)c * ldb], x1 = src[(int64_t)(c + 1) * ldb];
+            const uint16_t h0 = f2bf(x0), h1 = f2bf(x1);
+            const uint16_t l0 = f2bf(x0 - bf2f(h0)), l1 = f2bf(x1 - bf2f(h1));
+            hw[c / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+            lw[c / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+        }
+        reinterpret_cast<uint4 *>(hi)[idx] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        reinterpret_cast<uint4 *>(lo)[idx] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
+}
+
 void launch_bgemm3(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                    const uint16_t *Ahi, const uint16_t *Alo, int lda, const float *B, int ldb,
-                   float *C, int ldc, double flops, double bytes, const LorentzArgs *la,
-                   void *scratch, size_t scratch_bytes) {
+                   uint16_t *Bhi, uint16_t *Blo, float *C, int ldc, double flops, double bytes,
+                   const LorentzArgs *la, void *scratch, size_t scratch_bytes) {
+    {   // B split once into the k-blocked hi/lo planes
+        int64_t blocks = ((int64_t)(K / 8) * N + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        trace_begin(t, "bf16_split", s);
+        hipLaunchKernelGGL(k_split_kblk, dim3((unsigned)blocks), dim3(256), 0, s, B, K, N, ldb, Bhi, Blo);
+        trace_end(t, s, 0.0, 8.0 * (double)K * N);
+    }
     const int tiles = (M / 64) * ((N + 63) / 64);
     const int KT = K / 32;
     int S = 1;
@@ -182,16 +206,16 @@ void launch_bgemm3(Tracer *t, hipStream_t s, const char *name, int M, int N, int
     if (S == 1) {
         if (la)
             hipLaunchKernelGGL(k_bgemm3<true>, dim3(tiles, 1), dim3(256), 0, s, M, N, K, Ahi, Alo, lda,
-                               B, ldb, C, ldc, m_fastest, *la);
+                               (const uint16_t *)Bhi, (const uint16_t *)Blo, C, ldc, m_fastest, *la);
         else
             hipLaunchKernelGGL(k_bgemm3<false>, dim3(tiles, 1), dim3(256), 0, s, M, N, K, Ahi, Alo, lda,
-                               B, ldb, C, ldc, m_fastest, none);
+                               (const uint16_t *)Bhi, (const uint16_t *)Blo, C, ldc, m_fastest, none);
         trace_end(t, s, flops, bytes);
         return;
     }
     float *part = static_cast<float *>(scratch);
     hipLaunchKernelGGL(k_bgemm3<false>, dim3(tiles, S), dim3(256), 0, s, M, N, K / S, Ahi, Alo, lda,
-                       B, ldb, part, N, m_fastest, none);
+                       (const uint16_t *)Bhi, (const uint16_t *)Blo, part, N, m_fastest, none);
     trace_end(t, s, flops, bytes);
     launch_splitk_reduce_f32(t, s, M, N, S, part, C, ldc, la);
 }
