@@ -174,7 +174,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=0.0)
     ap.add_argument("--warm", type=int, default=0,
                     help="learned warm start fitted on this many seeded training frequencies (0 = off)")
-    ap.add_argument("--cpu-sample", type=int, default=2, help="frequencies for the oracle baseline (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=5,
+                    help="frequencies for the oracle baseline (0 = skip; ~3.5 s each at 60 atoms)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
     ap.add_argument("--lanes", type=int, default=1,
                     help="solver lanes (0 = library default: 2 for 16+ concurrent points).  One lane by "
