@@ -32,6 +32,14 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 
 __device__ __forceinline__ int64_t hoff(int j) { return (int64_t)j * (j + 3) / 2; }
 
+// Streaming load of a basis element: the basis is read once per pass and is
+// far larger than the caches, so the load is marked non-temporal.
+typedef double nt_dbl2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ldnt(const double2 *p) {
+    const nt_dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_dbl2 *>(p));
+    return make_double2(v.x, v.y);
+}
+
 // ------------------------------------------------------------- gather inputs
 // Operator input column pair (2q, 2q+1) <- the job's vector (zeros for b jobs).
 __global__ __launch_bounds__(256)
@@ -156,7 +164,7 @@ void k_cgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P) {
     const double2 *w = reinterpret_cast<const double2 *>(V + (int64_t)(jb.j + 1) * vlen);
     double re = 0.0, im = 0.0;
     for (int mu = lane; mu < P; mu += 64) {
-        const double2 a = vi[mu], c = w[mu];
+        const double2 a = ldnt(&vi[mu]), c = w[mu];
         re += a.x * c.x + a.y * c.y;
         im += a.x * c.y - a.y * c.x;
     }
@@ -191,7 +199,7 @@ void k_cgs_update(const Job *__restrict__ jobs, SlotsDev sl, int P, int accumula
     double2 *w = reinterpret_cast<double2 *>(const_cast<double *>(V) + (int64_t)n * vlen) + mu;
     double2 acc = *w;
     for (int i = 0; i < n; ++i) {
-        const double2 v = reinterpret_cast<const double2 *>(V + (int64_t)i * vlen)[mu];
+        const double2 v = ldnt(reinterpret_cast<const double2 *>(V + (int64_t)i * vlen) + mu);
         const double hr = hs[2 * i], hi = hs[2 * i + 1];
         acc.x -= v.x * hr - v.y * hi;
         acc.y -= v.x * hi + v.y * hr;
@@ -407,7 +415,7 @@ void k_dcgs_dots(const Job *__restrict__ jobs, SlotsDev sl, int P, int ld, doubl
         const double2 b = vt[mu], c = z[mu];
 #pragma unroll
         for (int k = 0; k < DPW; ++k) {
-            const double2 a = vi[off[k] + mu];
+            const double2 a = ldnt(&vi[off[k] + mu]);
             sr[k] += a.x * b.x + a.y * b.y;
             si[k] += a.x * b.y - a.y * b.x;
             tr[k] += a.x * c.x + a.y * c.y;
@@ -526,7 +534,7 @@ __device__ __forceinline__ void dcgs_sums(const cpx *h, int j, const double2 *vb
             for (; k + UB <= n; k += UB) {
                 double2 v[UB];
 #pragma unroll
-                for (int u = 0; u < UB; ++u) v[u] = vp[(int64_t)(k + u) * vst];
+                for (int u = 0; u < UB; ++u) v[u] = ldnt(&vp[(int64_t)(k + u) * vst]);
 #pragma unroll
                 for (int u = 0; u < UB; ++u) {
                     const cpx sv = shs[k + u], cv = shc[k + u];
@@ -537,7 +545,7 @@ __device__ __forceinline__ void dcgs_sums(const cpx *h, int j, const double2 *vb
                 }
             }
             for (; k < n; ++k) {
-                const double2 v = vp[(int64_t)k * vst];
+                const double2 v = ldnt(&vp[(int64_t)k * vst]);
                 const cpx sv = shs[k], cv = shc[k];
                 as.x += v.x * sv.r - v.y * sv.i;
                 as.y += v.x * sv.i + v.y * sv.r;
@@ -1012,7 +1020,7 @@ void k_xupdate(const Job *__restrict__ jobs, SlotsDev sl, int P) {
         __syncthreads();
         if (act)
             for (int k = 0; k < n; ++k) {
-                const double2 v = reinterpret_cast<const double2 *>(V + (int64_t)(c0 + k) * vlen)[mu];
+                const double2 v = ldnt(reinterpret_cast<const double2 *>(V + (int64_t)(c0 + k) * vlen) + mu);
                 acc.x += v.x * ys[k].r - v.y * ys[k].i;
                 acc.y += v.x * ys[k].i + v.y * ys[k].r;
             }
