@@ -192,3 +192,21 @@ def test_split_update_on_long_bases():
         print(f"[split]   Im alpha error vs oracle {e.max():.2e}", flush=True)
         assert e.max() < 1e-6
     assert np.max(np.abs(a1 - a2)) < 1e-8 * np.max(np.abs(a2))
+
+
+@pytest.mark.parametrize("lanes", [2, 3, 4])
+def test_lanes_agree_with_one_lane_and_oracle(lanes):
+    """Slots dealt to 2-4 lanes (own streams and workspaces): the same points as
+    one lane, to the conditioning of the solves, and the oracle's alpha."""
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("z")
+    om = np.linspace(0.0, 1.4, 21)
+    ctx = _ctx(sys)
+    a1, s1, r1 = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-13, batch=om.size, lanes=1)
+    aL, sL, rL = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=1e-13, batch=om.size, lanes=lanes)
+    ctx.close()
+    ref = orc.polarizability(sys, om, d)
+    print(f"[lanes] {lanes}: iterations {sL['iterations'].ravel().tolist()}", flush=True)
+    assert r1 == 0 and rL == 0 and sL["converged"].all()
+    assert np.max(np.abs(aL - a1)) < 1e-10 * np.max(np.abs(ref))
+    assert im_err(aL[:, 0, 0], ref[:, 0, 0]).max() < 1e-10
