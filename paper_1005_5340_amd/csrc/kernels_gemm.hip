@@ -227,7 +227,8 @@ void k_dgemm(int M, int N, int K, const T *__restrict__ A, int lda,
                     const double re = par ? (double)other : (double)v, im = par ? (double)v : (double)other;
                     v = (T)(par ? (re * Li + im * Lr) : (re * Lr - im * Li));
                 }
-                if (ok) C[(int64_t)row * ldc + col] = v;
+                // the output is read by the next kernel only: a streaming store
+                if (ok) __builtin_nontemporal_store(v, &C[(int64_t)row * ldc + col]);
             }
         }
     }
