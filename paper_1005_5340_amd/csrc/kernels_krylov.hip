@@ -943,27 +943,39 @@ void k_tri_diag(const Job *__restrict__ jobs, SlotsDev sl, int p) {
                 const cpx *coli = reinterpret_cast<const cpx *>(H + 2 * hoff(i < bl ? bl : i));
                 R[s2] = (rv && i >= bl && r <= i) ? coli[r] : cpx{0.0, 0.0};
             }
+            // each lane inverts its own diagonal entry, so the sequential
+            // sweep below multiplies instead of dividing
+            cpx dinv = {0.0, 0.0};
+#pragma unroll
+            for (int s2 = 0; s2 < TSB; ++s2)
+                if (t == s2) dinv = cdiv({1.0, 0.0}, R[s2]);
 #pragma unroll
             for (int s2 = TSB - 1; s2 >= 0; --s2) {
                 if (b0 + s2 < bl) continue;                // uniform
-                const cpx vi = cshfl(v, s2), di = cshfl(R[s2], s2);
-                const cpx yi = cdiv(vi, di);
+                const cpx yi = cmul(cshfl(v, s2), cshfl(dinv, s2));
                 if (t < s2) {
                     const cpx pr = cmul(R[s2], yi);
                     v = {v.r - pr.r, v.i - pr.i};
                 }
                 if (t == 0) yb[s2] = yi;
             }
+            // rows of the block's top part outside the panel contribute nothing
+            if (t < TSB && b0 + t < bl) yb[t] = {0.0, 0.0};
         }
         __syncthreads();
         for (int s2 = t; s2 < TSB; s2 += 256)
             if (b0 + s2 >= bl) ys[b0 + s2 - lo] = yb[s2];
         for (int k = lo + t; k < bl; k += 256) {
             cpx acc = ys[k - lo];
+            cpx rk[TSB];
+#pragma unroll
+            for (int s2 = 0; s2 < TSB; ++s2) {   // loads first (columns below bl have yb = 0)
+                const int i = b0 + s2 < bl ? bl : b0 + s2;
+                rk[s2] = reinterpret_cast<const cpx *>(H + 2 * hoff(i))[k];
+            }
+#pragma unroll
             for (int s2 = 0; s2 < TSB; ++s2) {
-                if (b0 + s2 < bl) continue;
-                const cpx *coli = reinterpret_cast<const cpx *>(H + 2 * hoff(b0 + s2));
-                const cpx pr = cmul(coli[k], yb[s2]);
+                const cpx pr = cmul(rk[s2], yb[s2]);
                 acc = {acc.r - pr.r, acc.i - pr.i};
             }
             ys[k - lo] = acc;
@@ -974,28 +986,45 @@ void k_tri_diag(const Job *__restrict__ jobs, SlotsDev sl, int p) {
 }
 
 // Rows above panel p: y[k] -= sum_{i in [lo, hi)} R[k][i] y[i] for k < lo,
-// spread over many workgroups (the panel's R columns are read once).
+// spread over many workgroups (the panel's R columns are read once).  A
+// workgroup takes 64 rows; its wavefront w sums the panel's columns
+// [lo + 64 w, lo + 64 w + 64), eight loads in flight per lane, and wavefront 0
+// adds the four partial sums in order.
 __global__ __launch_bounds__(256)
 void k_tri_update(const Job *__restrict__ jobs, SlotsDev sl, int p) {
     __shared__ cpx ys[TPW];
-    const int q = blockIdx.y, t = threadIdx.x;
+    __shared__ cpx part[4][64];
+    const int q = blockIdx.y, t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const Job jb = jobs[q];
     const int hi = jb.j - p * TPW;
     const int lo = hi > TPW ? hi - TPW : 0;
-    if (lo <= 0 || blockIdx.x * 256 >= lo) return;   // uniform per workgroup
+    if (lo <= 0 || blockIdx.x * 64 >= lo) return;   // uniform per workgroup
     const double *H = sl.H + jb.slot * sl.hstride;
     cpx *y = reinterpret_cast<cpx *>(sl.y + (int64_t)jb.slot * sl.m * 2);
     for (int i = lo + t; i < hi; i += 256) ys[i - lo] = y[i];
     __syncthreads();
-    const int k = blockIdx.x * 256 + t;
-    if (k >= lo) return;
-    cpx acc = y[k];
-    for (int i = lo; i < hi; ++i) {
-        const cpx rki = reinterpret_cast<const cpx *>(H + 2 * hoff(i))[k];
-        const cpx pr = cmul(rki, ys[i - lo]);
-        acc = {acc.r - pr.r, acc.i - pr.i};
+    const int k = blockIdx.x * 64 + lane;
+    const int kk = k < lo ? k : lo - 1;             // rows past lo read a valid row, unused
+    cpx acc = {0.0, 0.0};
+    const int c0 = wv * (TPW / 4);                  // hi - lo == TPW here (lo > 0)
+    for (int c = c0; c < c0 + TPW / 4; c += 8) {
+        cpx rk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rk[u] = reinterpret_cast<const cpx *>(H + 2 * hoff(lo + c + u))[kk];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const cpx pr = cmul(rk[u], ys[c + u]);
+            acc = {acc.r + pr.r, acc.i + pr.i};
+        }
     }
-    y[k] = acc;
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && k < lo) {
+        cpx sum = y[k];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) sum = {sum.r - part[w][lane].r, sum.i - part[w][lane].i};
+        y[k] = sum;
+    }
 }
 
 // x += sum_{i<L} v_i y_i, the coefficients staged through LDS in chunks.
@@ -1036,7 +1065,7 @@ void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
         hipLaunchKernelGGL(k_tri_diag, dim3(n), dim3(256), 0, s, jobs, sl, p);
         const int above = jmax - (p + 1) * TPW;
         if (above > 0)
-            hipLaunchKernelGGL(k_tri_update, dim3((above + 255) / 256, n), dim3(256), 0, s, jobs, sl, p);
+            hipLaunchKernelGGL(k_tri_update, dim3((above + 63) / 64, n), dim3(256), 0, s, jobs, sl, p);
     }
     trace_end(t, s);
     trace_begin(t, "x_update", s);
