@@ -154,7 +154,10 @@ typedef struct chi0_solve_opts {
     double  tol;          /* stop when ||chi0 d - A x||_2 <= tol ||chi0 d||_2 (default 1e-10) */
     int32_t precision;    /* CHI0_PREC_* of the Arnoldi steps (default FP64); b = chi0 d and
                              every true residual are FP64 (iterative refinement) */
-    int32_t batch;        /* (omega, drive) points solved concurrently, 1..256; 1 = one at a time */
+    int32_t batch;        /* (omega, drive) points solved concurrently, 1..256; 1 = one at a time.
+                             Capped at what fits in free device memory: each point holds
+                             (restart+2) n_prod 16 + restart^2 8 bytes of Krylov basis and
+                             Hessenberg matrix (twice the latter with the eps stopping tests) */
     double  inner_tol;    /* low precision only: a cycle ends when the Arnoldi residual
                              estimate falls by this factor (0 = 1e-6 for FP32, 1e-4 for BF16X3) */
     const chi0_ws *warm;  /* NULL, or a warm start fitted on this context and system: every point

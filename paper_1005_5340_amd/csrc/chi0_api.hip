@@ -958,11 +958,26 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     HIPCHK(c, hipSetDevice(c->device));
 
     const int npts = n_omega * n_drive;
-    const int nsl = std::min(std::min(o.batch, npts), kMaxBatch);
     // storage for m columns per cycle; the delayed scheme keeps one extra
     // provisional column, so it gets one more basis vector
     const int m = o.restart + (dcgs ? 1 : 0);
     const int P = c->P;
+    // Concurrent slots: the batch, capped so that the slots' Krylov bases and
+    // Hessenberg matrices (and R^-1 of the error estimates) fit in the device
+    // memory that is free, less a reserve for the operator workspaces.
+    int nsl = std::min(std::min(o.batch, npts), kMaxBatch);
+    if (!(c->slot_n >= nsl && c->slot_m == m)) {
+        const double per_slot = 8.0 * (2.0 * (m + 1) * c->P_pad + (double)m * (m + 3) + 4.0 * c->P_pad +
+                                       16.0 * m + 16.0) +
+                                (o.stop != CHI0_STOP_RESIDUAL ? 8.0 * ((double)m * (m + 1) + 8.0 * m + 16.0) : 0.0);
+        size_t free_b = 0, total_b = 0;
+        HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+        const double held = (double)c->slot_n * (c->slot_m > 0 ? 8.0 * (2.0 * (c->slot_m + 1) * c->P_pad +
+                                                                        (double)c->slot_m * (c->slot_m + 3)) : 0.0);
+        const double avail = (double)free_b + held - 0.05 * (double)total_b - 4e9;
+        const int fit = avail > per_slot ? (int)std::min(avail / per_slot, 1e6) : 1;
+        nsl = std::max(1, std::min(nsl, fit));
+    }
     // Slots are dealt to lanes (slot k to lane k mod nl), each lane with its own
     // stream, operator workspace and step buffers, so that one lane's
     // memory-bound Gram-Schmidt passes can run beside the other lane's
