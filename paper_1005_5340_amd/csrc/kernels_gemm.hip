@@ -529,6 +529,8 @@ static void occ_transform_any(Tracer *t, hipStream_t s, const char *name, const 
         occ_transform_nbt<T, 4>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
     else if (bm.nb_max <= 8)
         occ_transform_nbt<T, 8>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
+    else if (bm.nb_max <= 9)
+        occ_transform_nbt<T, 9>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
     else if (bm.nb_max <= 12)
         occ_transform_nbt<T, 12>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
     else
@@ -636,6 +638,8 @@ static void occ_back_any(Tracer *t, hipStream_t s, const char *name, const Block
         occ_back_nbt<T, 4>(s, grid, bm, Xo, no_pad, Ut, W, nc);
     else if (bm.nb_max <= 8)
         occ_back_nbt<T, 8>(s, grid, bm, Xo, no_pad, Ut, W, nc);
+    else if (bm.nb_max <= 9)
+        occ_back_nbt<T, 9>(s, grid, bm, Xo, no_pad, Ut, W, nc);
     else if (bm.nb_max <= 12)
         occ_back_nbt<T, 12>(s, grid, bm, Xo, no_pad, Ut, W, nc);
     else
