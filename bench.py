@@ -183,6 +183,7 @@ def main():
                          "GPU; two lanes are ~2%% faster on the 60-atom spectrum")
     ap.add_argument("--stop", default="residual", choices=["residual", "eps_p", "eps_px"],
                     help="stopping test: relative residual, or the paper's eps_P / eps_P+eps_X estimates")
+    ap.add_argument("--drives", default="", help="dipole drives to solve, e.g. z (default: the workload's)")
     ap.add_argument("--omega-sample", type=int, default=0, metavar="K",
                     help="solve K evenly spaced frequencies of the grid (plus those of a sampled oracle "
                          "reference) instead of the whole grid")
@@ -215,7 +216,8 @@ def main():
     t0 = time.perf_counter()
     s = synth.make_system(a.workload, a.seed)
     print(f"[bench] {a.workload} generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    drives = s.drives()
+    drive_letters = a.drives or w.drives
+    drives = s.drives(drive_letters)
     tol = a.tol or w.tol
     restart = a.restart or s.n_prod
     ctx = chi0.Context(0)
@@ -230,9 +232,10 @@ def main():
     refpath = os.path.join(ROOT, "tests", "golden", f"reference_{a.workload}_s{a.seed}.json")
     if os.path.exists(refpath):
         r = json.load(open(refpath))
-        if synth.same_inputs(s, r["fingerprint"]):
+        if synth.same_inputs(s, r["fingerprint"]) and all(c in r["drives"] for c in drive_letters):
             ref = np.array(r["alpha_re"]) + 1j * np.array(r["alpha_im"])
             ref_idx = np.asarray(r["omega_index"], dtype=int)
+            ref_drive = [r["drives"].index(c) for c in drive_letters]   # solved drive -> reference index
 
     # the frequencies solved: the whole grid, or an evenly spaced sample of it
     grid = np.arange(s.omegas.size)
@@ -311,7 +314,7 @@ def main():
     if ref is not None:
         full = ref_idx.size == grid.size and np.array_equal(ref_idx, grid)
         diag = diag[np.searchsorted(grid, ref_idx)]
-        rdiag = np.stack([ref[:, i, i] for i in range(drives.shape[0])], 1)
+        rdiag = np.stack([ref[:, ref_drive[i], ref_drive[i]] for i in range(drives.shape[0])], 1)
         err = np.stack([im_errors(diag[:, i], rdiag[:, i]) for i in range(drives.shape[0])], 1)
         if full:
             passing = int((err <= 1e-6).sum())
@@ -389,7 +392,7 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16x3": "f64+bf16x3"}[a.precision],
         "data": "synthetic",
         "config": {"workload": a.workload, "seed": a.seed, "n_orb": s.n_orb, "n_occ": s.n_occ,
-                   "n_prod": s.n_prod, "n_omega": int(omegas.size), "drives": w.drives,
+                   "n_prod": s.n_prod, "n_omega": int(omegas.size), "drives": drive_letters,
                    "omega_grid": int(s.omegas.size), "omega_sample": a.omega_sample or None,
                    "eps": s.eps, "tol": tol, "restart": restart, "batch": a.batch,
                    "points": npts, "precision": a.precision, "warm_start_train": a.warm,

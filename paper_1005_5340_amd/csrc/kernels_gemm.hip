@@ -443,7 +443,7 @@ template <> struct OccMma<double> { typedef Mma16d type; };
 // Tt[b][E*nc + j] = sum_{A in nbr(B)} sum_{a in A} Xo[a][E] dV[(k(A,B), a, b)][j]
 // One workgroup: column atom B, 64 occupied states, 16 columns.  Wave w owns
 // states 16w..16w+15 and every orbital b of B (one accumulator per b; NBT is
-// the system's largest atom rounded up to a multiple of 4).  The gathered rows
+// the system's largest atom: 4, 8, 9, 12, 13 or 16).  The gathered rows
 // come in chunks of 16; the next chunk's global loads are issued before the
 // current chunk's MFMAs so their latency overlaps the arithmetic.
 // T is the arithmetic type (FP64, or FP32 for the low-precision operator);
@@ -533,6 +533,8 @@ static void occ_transform_any(Tracer *t, hipStream_t s, const char *name, const 
         occ_transform_nbt<T, 9>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
     else if (bm.nb_max <= 12)
         occ_transform_nbt<T, 12>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
+    else if (bm.nb_max <= 13)
+        occ_transform_nbt<T, 13>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
     else
         occ_transform_nbt<T, 16>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
     trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
@@ -642,6 +644,8 @@ static void occ_back_any(Tracer *t, hipStream_t s, const char *name, const Block
         occ_back_nbt<T, 9>(s, grid, bm, Xo, no_pad, Ut, W, nc);
     else if (bm.nb_max <= 12)
         occ_back_nbt<T, 12>(s, grid, bm, Xo, no_pad, Ut, W, nc);
+    else if (bm.nb_max <= 13)
+        occ_back_nbt<T, 13>(s, grid, bm, Xo, no_pad, Ut, W, nc);
     else
         occ_back_nbt<T, 16>(s, grid, bm, Xo, no_pad, Ut, W, nc);
     trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
