@@ -143,6 +143,20 @@ int chi0_get_sizes(const chi0_ctx *ctx, int32_t *n_orb, int32_t *n_occ,
 int chi0_apply(chi0_ctx *ctx, int32_t n_rhs, const double *omega, double eps,
                const double *z, double *out, int32_t precision, void *stream);
 
+/*
+ * Replay chi0_apply from a HIP graph (enable != 0; default off).  A call with
+ * n_rhs <= 256 is captured the second time its (n_rhs, precision, z, out,
+ * eps) repeat (the first such call runs eagerly and tunes the GEMM tiles) and
+ * replayed while they keep repeating: the frequencies are copied to the
+ * device before each replay, the vectors z are read at replay time.  For
+ * callers that apply chi0 many times to the same buffers, e.g. their own
+ * Krylov loop on a small system, where launching the ~10 kernels of a pass
+ * costs as much as running them.  The graph is dropped when the system or the
+ * workspaces change, while kernel timing (chi0_set_timing) is on no graph is
+ * used.  Synchronises the device.
+ */
+int chi0_set_graphs(chi0_ctx *ctx, int32_t enable);
+
 /* Options of chi0_solve_response.  Zero-initialise, then set what you need;
  * chi0_solve_opts_default() fills the defaults. */
 typedef struct chi0_ws chi0_ws;        /* learned warm start (see chi0_ws_fit) */

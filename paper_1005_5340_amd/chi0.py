@@ -113,6 +113,8 @@ def lib():
     L.chi0_set_timing.restype = C.c_int
     L.chi0_set_autotune.argtypes = [C.c_void_p, C.c_int32]
     L.chi0_set_autotune.restype = C.c_int
+    L.chi0_set_graphs.argtypes = [C.c_void_p, C.c_int32]
+    L.chi0_set_graphs.restype = C.c_int
     L.chi0_autotune_table.argtypes = [C.c_void_p, C.POINTER(TuneRecord), C.c_int32]
     L.chi0_autotune_table.restype = C.c_int
     L.chi0_set_timing_filter.argtypes = [C.c_void_p, C.c_char_p]
@@ -301,6 +303,10 @@ class Context:
         if return_x:
             return a, stats, rc, x[..., 0] + 1j * x[..., 1]
         return a, stats, rc
+
+    def set_graphs(self, enable: bool):
+        """Replay repeated chi0_apply calls from a HIP graph (chi0_set_graphs)."""
+        self._check(self._L.chi0_set_graphs(self._h, int(bool(enable))))
 
     # --------------------------------------------------------------- tracing
     def set_timing(self, enable: bool, only=None):
