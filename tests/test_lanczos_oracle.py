@@ -1,0 +1,226 @@
+"""Pins of the Lanczos (Krylov) route to the spectrum and its poles.
+
+The oracle (oracle/lanczos_oracle.py) runs the symmetric Lanczos recursion on
+the transition-space matrix Om2 = D^2 + S V_t^T f V_t S from c = S V_t^T d and
+reads alpha(w), the poles and their residues off the tridiagonal T_k.  These
+tests tie it to facts that do not come from its own code:
+
+* the hand-derived two-level closed form alpha = -1/((w + i eps)^2 - 1.25)
+  (one transition: a single pole 1.25 with residue 1);
+* at full dimension (k = T) the recursion is exact, so alpha_k equals the
+  dense LU solve of eq. sle (chi0_oracle) and the Casida eigen-route of the
+  pins at every frequency, and the poles are the eigenvalues of Om2 that
+  carry weight;
+* Gauss quadrature: the k-point rule (theta_j, residue_j) integrates the
+  moments c^T Om2^p c exactly for p = 0 .. 2k-1 (computed here by repeated
+  products with the dense Om2), with or without reorthogonalisation while
+  the basis stays orthogonal;
+* Ritz values lie inside [lambda_min, lambda_max] of Om2 and interlace
+  between k and k + 1; residues are positive and sum to |c|^2;
+* |c|^2 is the large-w coefficient sum 2 n D (d.v)^2 of the pins, and
+  alpha_k(-w) = conj alpha_k(w), Im alpha_k(w) >= 0 for w > 0;
+* on a 12-atom system the error against the LU solve falls as k grows.
+
+Planted mistakes (S without its factor 2, no S on the start vector, a
+dropped three-term coefficient, (w + i eps) not squared, residues from the
+last eigenvector component) each fail one of the pins.
+"""
+import json
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import gpu_systems
+import pins
+from oracle import chi0_oracle as orc
+from oracle import lanczos_oracle as lo
+from paper_1005_5340_amd import synth
+
+GOLD = Path(__file__).parent / "golden"
+
+
+def _a4():
+    return synth.make_system("atoms4_orb4", seed=0)
+
+
+def _run(sys, drive, k, reorth=True):
+    Om2 = lo.casida_matrix(sys)
+    c = lo.start_vector(sys, drive)
+    return Om2, c, lo.lanczos(Om2, c, k, reorth=reorth)
+
+
+def test_two_level_closed_form():
+    two = pins.two_level_system()
+    with open(GOLD / "two_level.json") as f:
+        g = json.load(f)
+    d = two.drives("z")[0]
+    Om2, c, (a, b, cn2) = _run(two, d, 4)
+    assert a.size == 1
+    np.testing.assert_allclose(a, [1.25], rtol=1e-14)
+    np.testing.assert_allclose(cn2, 1.0, rtol=1e-14)
+    vals = np.asarray(g["values"], float)            # columns: omega, Re alpha, Im alpha (12 digits)
+    got = lo.spectrum(a, b, cn2, vals[:, 0], two.eps)
+    np.testing.assert_allclose(got.real, vals[:, 1], rtol=0, atol=2e-12 * np.abs(vals[:, 1:]).max())
+    np.testing.assert_allclose(got.imag, vals[:, 2], rtol=0, atol=2e-12 * np.abs(vals[:, 1:]).max())
+    th, r = lo.poles(a, b, cn2)
+    np.testing.assert_allclose(th, [1.25], rtol=1e-14)
+    np.testing.assert_allclose(r, [1.0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("axis", ["x", "z"])
+def test_full_dimension_equals_lu_and_casida(axis):
+    sys = _a4()
+    d = sys.drives(axis)[0]
+    T = sys.n_occ * (sys.n_orb - sys.n_occ)
+    Om2, c, (a, b, cn2) = _run(sys, d, T)
+    om = np.linspace(0.0, 1.5, 13)
+    got = lo.spectrum(a, b, cn2, om, sys.eps)
+    lu = orc.polarizability(sys, om, d[None, :])[:, 0, 0]
+    assert pins.rel(got, lu) < 1e-10
+    assert pins.rel(got, pins.casida_alpha(sys, om, d)) < 1e-10
+    # poles: every Ritz value is an eigenvalue of Om2
+    th, r = lo.poles(a, b, cn2)
+    lam = np.linalg.eigvalsh(Om2)
+    assert np.all(np.min(np.abs(th[:, None] - lam[None, :]), axis=1) <= 1e-10 * np.abs(lam).max())
+
+
+@pytest.mark.parametrize("reorth", [True, False])
+def test_gauss_quadrature_moments(reorth):
+    sys = _a4()
+    d = sys.drives("y")[0]
+    k = 5
+    Om2, c, (a, b, cn2) = _run(sys, d, k, reorth=reorth)
+    th, r = lo.poles(a, b, cn2)
+    scale = np.abs(np.linalg.eigvalsh(Om2)).max()
+    v = c.copy()
+    for p in range(2 * k):
+        exact = c @ v
+        quad = float((r * th ** p).sum())
+        assert abs(quad - exact) <= 1e-11 * (cn2 * scale ** p), (p, quad, exact)
+        v = Om2 @ v
+
+
+def test_ritz_bounds_interlacing_and_weights():
+    sys = _a4()
+    d = sys.drives("z")[0]
+    Om2, c, (a, b, cn2) = _run(sys, d, 12)
+    lam = np.linalg.eigvalsh(Om2)
+    prev = None
+    for k in range(1, a.size + 1):
+        th, r = lo.poles(a[:k], b[:k], cn2)
+        tol = 1e-12 * np.abs(lam).max()
+        assert th.min() >= lam.min() - tol and th.max() <= lam.max() + tol
+        assert np.all(r > 0)
+        np.testing.assert_allclose(r.sum(), cn2, rtol=1e-12)
+        if prev is not None:   # theta^(k)_i <= theta^(k-1)_i <= theta^(k)_{i+1}
+            assert np.all(th[:-1] <= prev + tol) and np.all(prev <= th[1:] + tol)
+        prev = th
+
+
+def test_strength_symmetry_and_sign():
+    sys = _a4()
+    d = sys.drives("z")[0]
+    Om2, c, (a, b, cn2) = _run(sys, d, 10)
+    np.testing.assert_allclose(cn2, pins.sum_rule_strength(sys, d), rtol=1e-12)
+    om = np.linspace(0.05, 1.5, 11)
+    s = lo.spectrum(a, b, cn2, om, sys.eps)
+    np.testing.assert_allclose(lo.spectrum(a, b, cn2, -om, sys.eps), np.conj(s), rtol=1e-12)
+    assert np.all(s.imag >= 0)
+    big = 1e4
+    z = (big + 1j * sys.eps) ** 2
+    np.testing.assert_allclose((lo.spectrum(a, b, cn2, [big], sys.eps)[0] * z).real, -cn2, rtol=1e-5)
+
+
+def test_error_falls_with_dimension():
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("z")[0]
+    om = np.linspace(0.0, 1.5, 9)
+    lu = orc.polarizability(sys, om, d[None, :])[:, 0, 0]
+    Om2, c, (a, b, cn2) = _run(sys, d, 160)
+    errs = [pins.rel(lo.spectrum(a[:k], b[:k], cn2, om, sys.eps), lu) for k in (20, 80, 160)]
+    assert errs[0] > errs[1] > errs[2]
+
+
+# --------------------------------------------------------- planted mistakes
+def _pins_pass():
+    try:
+        test_two_level_closed_form()
+        for ax in ("x", "z"):
+            test_full_dimension_equals_lu_and_casida(ax)
+        for ro in (True, False):
+            test_gauss_quadrature_moments(ro)
+        test_strength_symmetry_and_sign()
+    except AssertionError:
+        return False
+    return True
+
+
+def test_pins_pass_unmutated():
+    assert _pins_pass()
+
+
+def test_mutation_s_without_factor_two(monkeypatch):
+    real = lo.casida_parts
+
+    def wrong(sys):
+        S, D2, B = real(sys)
+        return S / np.sqrt(2.0), D2, B / np.sqrt(2.0)
+
+    monkeypatch.setattr(lo, "casida_parts", wrong)
+    assert not _pins_pass()
+
+
+def test_mutation_start_without_s(monkeypatch):
+    def wrong(sys, drive):
+        return orc.transition_vertices(sys).reshape(sys.n_prod, -1).T @ np.asarray(drive, float)
+
+    monkeypatch.setattr(lo, "start_vector", wrong)
+    assert not _pins_pass()
+
+
+def test_mutation_dropped_three_term_coefficient(monkeypatch):
+    def wrong(Om2, c, k, reorth=True, breakdown=1e-12):
+        c = np.asarray(c, float)
+        cn2 = float(c @ c)
+        k = min(k, c.size)
+        Q = [c / np.sqrt(cn2)]
+        a, b = [], []
+        for j in range(k):
+            w = Om2 @ Q[j]
+            aj = Q[j] @ w
+            w = w - aj * Q[j]                       # b_{j-1} q_{j-1} never subtracted
+            if reorth:
+                B = np.array(Q)
+                w = w - B.T @ (B @ w)               # one pass only
+            bj = float(np.linalg.norm(w))
+            a.append(float(aj))
+            b.append(bj)
+            if bj <= breakdown * abs(aj):
+                break
+            Q.append(w / bj)
+        return np.array(a), np.array(b), cn2
+
+    monkeypatch.setattr(lo, "lanczos", wrong)
+    assert not _pins_pass()
+
+
+def test_mutation_unsquared_frequency(monkeypatch):
+    def wrong(a, b, cn2, omegas, eps):
+        T = lo.tridiagonal(a, b)
+        k = T.shape[0]
+        e1 = np.eye(k)[0]
+        return np.array([cn2 * np.linalg.solve(T - (w + 1j * eps) * np.eye(k), e1)[0]
+                         for w in np.asarray(omegas, float)])
+
+    monkeypatch.setattr(lo, "spectrum", wrong)
+    assert not _pins_pass()
+
+
+def test_mutation_residue_from_last_component(monkeypatch):
+    def wrong(a, b, cn2):
+        theta, U = np.linalg.eigh(lo.tridiagonal(a, b))
+        return theta, cn2 * U[-1] ** 2
+
+    monkeypatch.setattr(lo, "poles", wrong)
+    assert not _pins_pass()
