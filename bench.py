@@ -37,7 +37,8 @@ CHI0_KERNELS = ("vertex_gather", "occ_transform", "virt_transform_lorentz", "vir
                 "occ_back", "vertex_contract", "vertex_reduce", "occ_transform_f32",
                 "virt_transform_lorentz_f32", "virt_back_f32", "occ_back_f32",
                 "virt_transform_lorentz_bf16x3", "virt_back_bf16x3")
-MFMA_KERNELS = ("virt_transform_lorentz", "virt_back", "occ_transform", "occ_back", "kernel_matmul")
+MFMA_KERNELS = ("virt_transform_lorentz", "virt_back", "occ_transform", "occ_back", "kernel_matmul",
+                "casida_front")
 MFMA_F32 = ("virt_transform_lorentz_f32", "virt_back_f32", "occ_transform_f32", "occ_back_f32")
 MFMA_BF16 = ("virt_transform_lorentz_bf16x3", "virt_back_bf16x3")
 
@@ -158,6 +159,89 @@ def apply_only(a, s, ctx):
     ctx.close()
 
 
+def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, ref_drive):
+    """One step = one Lanczos recursion per drive (up to 4 in a block) until the spectrum on the
+    grid has converged, then alpha on the grid from the continued fraction."""
+    import torch
+    from paper_1005_5340_amd import chi0
+    reorth = chi0.LZ_REORTH_NONE if a.lz_plain else chi0.LZ_REORTH_FULL
+
+    def run(graph=True):
+        res = ctx.lanczos(drives, k_max=a.lz_kmax, reorth=reorth, tol=a.lz_tol, check_every=a.lz_check,
+                          omega_check=omegas, eps=s.eps, graph=graph and reorth == chi0.LZ_REORTH_NONE)
+        return res, ctx.lanczos_spectrum(res, omegas, s.eps)
+
+    print(f"[bench] lanczos {a.workload}: T={s.n_occ * (s.n_orb - s.n_occ)} drives={drive_letters} "
+          f"points={omegas.size * drives.shape[0]} tol={a.lz_tol:g} reorth={not a.lz_plain}",
+          file=sys.stderr, flush=True)
+    ks_all = {}
+    if not a.no_timing:     # breakdown: eager launches, every kernel timed
+        ctx.set_timing(True)
+        t0 = time.perf_counter()
+        run(graph=False)
+        ks_all = ctx.kernel_stats()
+        ctx.set_timing(False)
+        print(f"[bench] breakdown run (eager, all kernels timed) {time.perf_counter() - t0:.3f} s",
+              file=sys.stderr, flush=True)
+    for i in range(a.warmup):
+        t0 = time.perf_counter()
+        run()
+        print(f"[bench] warmup {i} {time.perf_counter() - t0:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        res, alpha = run()
+        print(f"[bench] step {i} done: {res['len'].tolist()} steps, rc {res['rc']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    npts = omegas.size * drives.shape[0]
+    acc = {"checked": False}
+    passing = npts
+    if ref is not None and np.all(np.isin(ref_idx, grid)):
+        diag = alpha[np.searchsorted(grid, ref_idx)]
+        rdiag = np.stack([ref[:, ref_drive[i], ref_drive[i]] for i in range(drives.shape[0])], 1)
+        err = np.stack([im_errors(diag[:, i], rdiag[:, i]) for i in range(drives.shape[0])], 1)
+        full = ref_idx.size == grid.size
+        passing = int((err <= 1e-6).sum()) if full else npts * float((err <= 1e-6).mean())
+        acc = {"checked": True, "max_im_rel_err": float(err.max()), "median_im_rel_err": float(np.median(err)),
+               "max_re_rel_err": float(np.max(np.abs(diag.real - rdiag.real) / np.abs(rdiag.real))),
+               "points_passing_1e-6": int((err <= 1e-6).sum()), "points_checked": int(err.size)}
+    roof = None
+    if ks_all:
+        tot = sum(v["ms"] for v in ks_all.values())
+        dom = max(ks_all, key=lambda k: ks_all[k]["ms"])
+        rec = ks_all[dom]
+        bound = bound_of(dom)
+        peak, unit = PEAK[bound]
+        work = rec["bytes"] if bound == "hbm" else rec["flops"]
+        scale = 1e9 if bound == "hbm" else 1e12
+        roof = {"kernel": dom, "bound": "hbm" if bound == "hbm" else "mfma",
+                "achieved": work / (rec["ms"] * 1e-3) / scale, "peak": peak / scale, "unit": unit,
+                "frac": work / (rec["ms"] * 1e-3) / peak, "traffic": None,
+                "launches": rec["launches"], "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
+                "share_of_gpu_time": rec["ms"] / tot,
+                "note": "from the eager breakdown run (every kernel timed)"}
+        print("[bench] kernel            launches   ms   share", file=sys.stderr)
+        for k, v in sorted(ks_all.items(), key=lambda kv: -kv[1]["ms"]):
+            print(f"[bench] {k:30s} {int(v['launches']):8d} {v['ms']:9.2f} {100 * v['ms'] / tot:6.1f}%",
+                  file=sys.stderr)
+    out = {
+        "metric": "spectrum points/s at 1e-6 rel err in Im alpha vs FP64 oracle",
+        "value": passing / dt, "unit": "spectrum points/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": a.workload, "seed": a.seed, "method": "lanczos (transition space)",
+                   "n_orb": s.n_orb, "n_occ": s.n_occ, "n_prod": s.n_prod, "n_omega": int(omegas.size),
+                   "drives": drive_letters, "eps": s.eps, "points": npts, "k_max": a.lz_kmax, "tol": a.lz_tol,
+                   "check_every": a.lz_check, "reorth": not a.lz_plain},
+        "lanczos_steps": res["len"].tolist(), "lanczos_rc": int(res["rc"]),
+        "us_per_lanczos_step": dt * 1e6 / max(int(res["len"].max()), 1),
+        "accuracy": acc, "roofline": roof, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +274,15 @@ def main():
     ap.add_argument("--apply-only", type=int, default=0, metavar="REPS",
                     help="only time REPS batched chi0 applications (--batch right-hand sides each) "
                          "and report chi0.v GFLOP/s")
+    ap.add_argument("--lanczos", action="store_true",
+                    help="the spectrum from one Lanczos recursion per drive in transition space instead of "
+                         "a GMRES solve per frequency (same workload, error measure and JSON line)")
+    ap.add_argument("--lz-kmax", type=int, default=12000, help="Lanczos: most steps")
+    ap.add_argument("--lz-tol", type=float, default=1e-8,
+                    help="Lanczos: stop when the spectrum on the grid moves by at most this between checks")
+    ap.add_argument("--lz-check", type=int, default=100, help="Lanczos: steps between convergence checks")
+    ap.add_argument("--lz-plain", action="store_true",
+                    help="Lanczos: no reorthogonalisation (three-term recurrence only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 device copies of MIB MiB (reference for HBM traffic counters)")
     a = ap.parse_args()
@@ -244,6 +337,10 @@ def main():
         k = max(1, a.omega_sample - extra.size)
         grid = np.unique(np.concatenate([np.round(np.linspace(0, s.omegas.size - 1, k)).astype(int), extra]))
     omegas = s.omegas[grid]
+
+    if a.lanczos:
+        return lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx,
+                            ref_drive if ref is not None else None)
 
     prec = {"fp64": chi0.PREC_FP64, "fp32": chi0.PREC_FP32, "bf16x3": chi0.PREC_BF16X3}[a.precision]
     ws, warm_info = None, None

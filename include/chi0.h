@@ -311,6 +311,89 @@ int chi0_ws_predict(chi0_ws *ws, int32_t n, const double *omega, double *x0);
 int chi0_ws_loss_history(const chi0_ws *ws, float *loss, int32_t cap);
 
 /*
+ * Spectrum, poles and residues from a Lanczos recursion in transition space.
+ *
+ * On the T = n_occ * n_virt transitions (E occupied, F virtual) the
+ * response has the pole form (Sec. 3 with eq. sle; Casida's equations):
+ *   Om2 = diag(D^2) + S V_t^T K V_t S,  S = diag(sqrt(2 n D)),  c = S V_t^T d,
+ *   alpha(w) = c^T (Om2 - (w + i eps)^2)^-1 c,
+ * with D_EF = e_F - e_E and V_t the n_prod x T matrix of the transition
+ * vertices v_mu^{EF}.  chi0_lanczos runs the symmetric Lanczos recursion
+ *   q_0 = c / |c|,   b_j q_{j+1} = Om2 q_j - a_j q_j - b_{j-1} q_{j-1},
+ * applying Om2 matrix-free with the chi0 operator's kernels, for up to four
+ * drives at once.  The k x k tridiagonal T_k (diagonal a, off-diagonal b)
+ * then gives, for every frequency at once,
+ *   alpha_k(w) = |c|^2 e_1^T (T_k - (w + i eps)^2)^-1 e_1
+ *             = sum_j r_j / (theta_j - (w + i eps)^2),
+ * theta_j the eigenvalues of T_k (poles of alpha in (w + i eps)^2, i.e.
+ * excitation energies sqrt(theta_j)) and r_j = |c|^2 (u_j)_1^2 their residues.
+ * This is the economical treatment of the frequency axis, with pole
+ * positions and strengths, that the paper names as further work (Sec. 8).
+ * It yields the diagonal alpha_ii of each drive (no cross terms).
+ */
+typedef struct chi0_lanczos_opts {
+    int32_t k_max;        /* most steps (default 4000); capped to n_occ * n_virt */
+    int32_t reorth;       /* CHI0_LZ_REORTH_FULL (default), _FULL2 or _NONE */
+    double  tol;          /* > 0: stop once alpha_k at the check frequencies changes by at most tol
+                             between two consecutive pairs of checks, the change of each point relative
+                             to max(|Im alpha_k|, 1e-3 max over the check points of |Im alpha_k|);
+                             0: run k_max steps (default) */
+    int32_t check_every;  /* steps between checks (default 100) */
+    int32_t n_check;      /* number of check frequencies (0: no checks) */
+    const double *omega_check;   /* host [n_check], Ha */
+    double  eps;          /* broadening of the checks, Ha (> 0 when n_check > 0) */
+    int32_t graph;        /* 1: after the first step, replay each step's launch sequence from one
+                             HIP graph (CHI0_LZ_REORTH_NONE, timing off); 0 (default): launch eagerly */
+    int32_t reserved[3];  /* must be zero */
+} chi0_lanczos_opts;
+
+/* Three-term recurrence only: three transition vectors in device memory.  The
+ * recursion loses orthogonality as soon as a Ritz value converges; its
+ * spectrum then converges far more slowly (on spectra with outlying poles,
+ * as the Coulomb-like kernels give, not within T steps). */
+#define CHI0_LZ_REORTH_NONE   0
+/* After the three-term step each new vector is orthogonalised against every
+ * previous one by one classical Gram-Schmidt pass (FULL2: two passes): k_max
+ * + 1 vectors in device memory (CHI0_ENOMEM if they do not fit).  One pass
+ * keeps the basis orthogonal to rounding here, because the three-term step
+ * leaves only small components along the old vectors. */
+#define CHI0_LZ_REORTH_FULL   1
+#define CHI0_LZ_REORTH_FULL2  2
+
+void chi0_lanczos_opts_default(chi0_lanczos_opts *opts);
+
+/* Run the recursion for n_drive (1..4) drives, host [n_drive][n_prod]
+ * (NULL opts: defaults).  Writes to host memory, per drive s:
+ * a[s * k_max + j], b[s * k_max + j] for j < len[s] (0 beyond), c_norm2[s]
+ * = |c_s|^2 and len[s], the number of valid coefficients: the steps run, or
+ * fewer where an invariant subspace ended the recursion (then T_len is
+ * exact and b[len - 1] = 0); a drive with c = 0 has len 0 (alpha = 0).
+ * b[len - 1] is otherwise the norm of the next Lanczos vector (T_len uses
+ * b[0 .. len - 2]).  Synchronous, on the context's stream.  Returns CHI0_OK,
+ * CHI0_NOT_CONVERGED when tol > 0 and k_max steps did not meet it (the
+ * coefficients are still written), or an error: CHI0_EINVAL (sizes,
+ * options), CHI0_ENONFINITE, CHI0_ENOSYS (no system), CHI0_ENOMEM. */
+int chi0_lanczos(chi0_ctx *ctx, int32_t n_drive, const double *drives, const chi0_lanczos_opts *opts,
+                 double *a, double *b, double *c_norm2, int32_t *len);
+
+/* alpha_k(omega) of each drive, computed on the device as the continued
+ * fraction of T_k: alpha [n_omega][n_drive] complex (host), from the first
+ * len[s] coefficients of drive s in a, b (host, [n_drive][ld]) and
+ * c_norm2[s].  Synchronous.  CHI0_EINVAL for len outside 0..ld or eps <= 0. */
+int chi0_lanczos_spectrum(chi0_ctx *ctx, int32_t n_drive, int32_t ld, const double *a, const double *b,
+                          const double *c_norm2, const int32_t *len, int32_t n_omega, const double *omega,
+                          double eps, double *alpha);
+
+/* Poles and residues of alpha_k for one drive: theta[0..k) the eigenvalues
+ * of T_k (diagonal a[0..k), off-diagonal b[0..k-1)) in ascending order and
+ * resid[j] = c_norm2 (u_j)_1^2.  A host computation on the k x k tridiagonal
+ * matrix (implicit QR steps with Wilkinson shifts, O(k^2)); needs no
+ * context.  CHI0_EINVAL (k < 1, NULL, c_norm2 < 0), CHI0_ENONFINITE, or
+ * CHI0_NOT_CONVERGED if the QR iteration does not converge. */
+int chi0_lanczos_poles(int32_t k, const double *a, const double *b, double c_norm2, double *theta,
+                       double *resid);
+
+/*
  * Kernel timing (tracing).  When enabled, every kernel launch of the
  * library is bracketed by HIP events on the stream it runs on, and the
  * durations are accumulated per kernel name, together with the algorithmic

@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = ["Chi0Error", "Context", "WarmStart", "lib", "LIB_PATH", "PREC_FP64", "PREC_FP32",
            "PREC_BF16X3", "SolveStats", "NOT_CONVERGED", "debug_eigh", "STOP_RESIDUAL", "STOP_EPS_P",
-           "STOP_EPS_PX"]
+           "STOP_EPS_PX", "LanczosOpts", "LZ_REORTH_NONE", "LZ_REORTH_FULL", "LZ_REORTH_FULL2", "lanczos_poles"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 PREC_FP64 = 0
@@ -26,6 +26,7 @@ PREC_FP32 = 1
 PREC_BF16X3 = 2
 ORTHO_AUTO, ORTHO_CGS2, ORTHO_DCGS2 = 0, 1, 2
 STOP_RESIDUAL, STOP_EPS_P, STOP_EPS_PX = 0, 1, 2
+LZ_REORTH_NONE, LZ_REORTH_FULL, LZ_REORTH_FULL2 = 0, 1, 2
 NOT_CONVERGED = 1
 _ERRORS = {-1: "EINVAL", -2: "ENOSYS", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EASYM"}
 
@@ -53,6 +54,12 @@ class PointStats(C.Structure):
                 ("breakdown", C.c_int32), ("fallback", C.c_int32), ("warm_start", C.c_int32),
                 ("rel_residual", C.c_double), ("warm_rel0", C.c_double),
                 ("eps_x", C.c_double), ("eps_p", C.c_double)]
+
+
+class LanczosOpts(C.Structure):
+    _fields_ = [("k_max", C.c_int32), ("reorth", C.c_int32), ("tol", C.c_double),
+                ("check_every", C.c_int32), ("n_check", C.c_int32), ("omega_check", _dp),
+                ("eps", C.c_double), ("graph", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class TuneRecord(C.Structure):
@@ -141,6 +148,15 @@ def lib():
     L.chi0_ws_debug_loss_grad.restype = C.c_int
     L.chi0_debug_eigh.argtypes = [C.c_int32, _dp, _dp, _dp]
     L.chi0_debug_eigh.restype = C.c_int
+    L.chi0_lanczos_opts_default.argtypes = [C.POINTER(LanczosOpts)]
+    L.chi0_lanczos_opts_default.restype = None
+    L.chi0_lanczos.argtypes = [C.c_void_p, C.c_int32, _dp, C.POINTER(LanczosOpts), _dp, _dp, _dp, _i32p]
+    L.chi0_lanczos.restype = C.c_int
+    L.chi0_lanczos_spectrum.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp, _i32p, C.c_int32,
+                                        _dp, C.c_double, _dp]
+    L.chi0_lanczos_spectrum.restype = C.c_int
+    L.chi0_lanczos_poles.argtypes = [C.c_int32, _dp, _dp, C.c_double, _dp, _dp]
+    L.chi0_lanczos_poles.restype = C.c_int
     _LIB = L
     return L
 
@@ -304,6 +320,41 @@ class Context:
             return a, stats, rc, x[..., 0] + 1j * x[..., 1]
         return a, stats, rc
 
+    def lanczos(self, drives, k_max: int = 4000, reorth: int = LZ_REORTH_FULL, tol: float = 0.0,
+                check_every: int = 100, omega_check=None, eps: float = 0.0, graph: bool = False) -> dict:
+        """Lanczos recursion in transition space for 1..4 drives [n_drive][n_prod] (chi0_lanczos).
+
+        Returns dict(a, b: [n_drive][k_max], c_norm2: [n_drive], len: [n_drive], rc)."""
+        d = _f64(drives)
+        d = d.reshape(-1, d.shape[-1])
+        nd = d.shape[0]
+        om = None if omega_check is None else _f64(omega_check).ravel()
+        o = LanczosOpts()
+        self._L.chi0_lanczos_opts_default(C.byref(o))
+        o.k_max, o.reorth, o.tol, o.check_every = int(k_max), int(reorth), float(tol), int(check_every)
+        o.n_check = 0 if om is None else int(om.size)
+        o.omega_check = _ptr(om)
+        o.eps, o.graph = float(eps), int(bool(graph))
+        a = np.zeros((nd, max(int(k_max), 1)))
+        b = np.zeros_like(a)
+        cn2 = np.zeros(nd)
+        ln = np.zeros(nd, np.int32)
+        rc = self._check(self._L.chi0_lanczos(self._h, nd, _ptr(d), C.byref(o), _ptr(a), _ptr(b), _ptr(cn2),
+                                              _ptr(ln, _i32p)), allow_warning=True)
+        return dict(a=a, b=b, c_norm2=cn2, len=ln, rc=rc)
+
+    def lanczos_spectrum(self, res: dict, omega, eps: float) -> np.ndarray:
+        """alpha_k(omega) [n_omega][n_drive] complex from a lanczos() result (chi0_lanczos_spectrum)."""
+        a, b = _f64(res["a"]), _f64(res["b"])
+        nd, ld = a.shape
+        cn2 = _f64(res["c_norm2"])
+        ln = np.ascontiguousarray(res["len"], np.int32)
+        om = _f64(omega).ravel()
+        out = np.zeros((om.size, nd, 2))
+        self._check(self._L.chi0_lanczos_spectrum(self._h, nd, ld, _ptr(a), _ptr(b), _ptr(cn2), _ptr(ln, _i32p),
+                                                  int(om.size), _ptr(om), float(eps), _ptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
     def set_graphs(self, enable: bool):
         """Replay repeated chi0_apply calls from a HIP graph (chi0_set_graphs)."""
         self._check(self._L.chi0_set_graphs(self._h, int(bool(enable))))
@@ -418,6 +469,23 @@ class WarmStart:
         self.ctx._check(self._L.chi0_ws_debug_loss_grad(self._h, int(om.size), _ptr(om), tg.ctypes.data_as(fp),
                                                         loss.ctypes.data_as(fp), g.ctypes.data_as(fp)))
         return float(loss[0]), g
+
+
+def lanczos_poles(a, b, c_norm2: float, k: Optional[int] = None):
+    """Poles theta (ascending) and residues of alpha_k from T_k (chi0_lanczos_poles, host)."""
+    L = lib()
+    a = _f64(a).ravel()
+    b = _f64(b).ravel()
+    k = a.size if k is None else int(k)
+    if k > a.size or (k > 1 and b.size < k - 1):
+        raise ValueError("k exceeds the coefficients given")
+    bb = b if b.size else np.zeros(1)
+    th = np.zeros(max(k, 1))
+    r = np.zeros(max(k, 1))
+    rc = L.chi0_lanczos_poles(k, _ptr(a), _ptr(bb), float(c_norm2), _ptr(th), _ptr(r))
+    if rc != 0:
+        raise Chi0Error(rc, "lanczos_poles")
+    return th[:k], r[:k]
 
 
 def debug_eigh(A):

@@ -246,7 +246,11 @@ static int dalloc(chi0_ctx *c, DevBuf &buf, T **p, int64_t n) {
         return fail(c, CHI0_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
                                         hipGetErrorString(e));
     buf.ptrs.push_back(q);
+    // The zero fill runs on the null stream, which is not ordered with the
+    // context's non-blocking streams: wait for it, so that work enqueued on
+    // those streams after dalloc returns never races with the fill.
     e = hipMemset(q, 0, bytes);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) return fail(c, CHI0_EHIP, std::string("hipMemset: ") + hipGetErrorString(e));
     *p = static_cast<T *>(q);
     return CHI0_OK;
@@ -1878,5 +1882,366 @@ extern "C" int chi0_debug_eigh(int32_t n, const double *A, double *w, double *V)
     jacobi_eigh(n, a, lam, vec);
     std::copy(lam.begin(), lam.end(), w);
     std::copy(vec.begin(), vec.end(), V);
+    return CHI0_OK;
+}
+
+// ====================================================== Lanczos in transition space
+// The pole form of the response (Casida's equations): Om2 = D^2 + S V_t^T K V_t S
+// on the (occupied, virtual) transitions, alpha(w) = c^T (Om2 - (w + i eps)^2)^-1 c
+// with c = S V_t^T d.  The recursion's operator is the chi0 operator's own
+// kernels composed the other way round: the back half (b3), (b4), (d) maps a
+// transition vector to products, K multiplies, the front half (a), (b1), (b2)
+// maps back to transitions.
+namespace {
+
+// Zin [P_pad][nc] -> at = V_t^T Zin (transition layout)
+void lz_front(chi0_ctx *c, OpWork &o, hipStream_t s, int nc) {
+    Tracer *t = &c->tracer;
+    const WorkSizes &w = c->ws;
+    const int64_t mcol = (int64_t)c->No_pad * nc;
+    launch_vertex_gather(t, s, c->bm, c->n_blk, o.Zin, o.dV, nc, w);
+    launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, o.dV, o.Tt, nc, w);
+    launch_dgemm(t, s, "casida_front", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt, c->N_pad, o.Tt, (int)mcol, o.at,
+                 (int)mcol, 2.0 * w.N * w.Nv * w.No * nc, 8.0 * (w.N * w.No * nc + w.Nv * w.No * nc + w.N * w.Nv),
+                 o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
+}
+
+// at (transition layout) -> Yout = V_t at [P_pad][nc], then Zin = K Yout
+void lz_back_k(chi0_ctx *c, OpWork &o, hipStream_t s, int nc) {
+    Tracer *t = &c->tracer;
+    const WorkSizes &w = c->ws;
+    const int64_t mcol = (int64_t)c->No_pad * nc;
+    launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, o.at, (int)mcol, o.Ut,
+                 (int)mcol, 2.0 * w.N * w.Nv * w.No * nc, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv),
+                 o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
+    launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, o.Ut, o.W, nc, w);
+    launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, o.W, o.part, o.Yout, nc, w, c->max_nprod);
+    launch_kmatvec_skinny(t, s, c->P_pad, c->K, o.Yout, o.Zin, nc, (double)c->P);
+}
+
+// Eigenvalues of the symmetric tridiagonal matrix (d, e) and the first row of
+// its eigenvector matrix, by implicit QR steps with the Wilkinson shift
+// (Golub & Van Loan, the symmetric QR algorithm), each rotation applied to
+// the first row only.  d: k diagonal entries, e: k - 1 off-diagonal entries
+// (both overwritten); z: first components on return.  false if an unreduced
+// block fails to split within 60 steps per eigenvalue.
+bool tridiag_eig_first_row(int k, std::vector<double> &d, std::vector<double> &e, std::vector<double> &z) {
+    const double u = 2.220446049250313e-16;
+    z.assign(k, 0.0);
+    z[0] = 1.0;
+    e.resize(std::max(k - 1, 0));
+    int hi = k - 1;
+    int64_t iters = 0;
+    const int64_t max_iters = 60 * (int64_t)std::max(k, 1);
+    auto negligible = [&](int i) { return std::fabs(e[i]) <= u * (std::fabs(d[i]) + std::fabs(d[i + 1])); };
+    while (hi > 0) {
+        if (negligible(hi - 1)) {
+            e[hi - 1] = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && !negligible(lo - 1)) --lo;
+        if (++iters > max_iters) return false;
+        // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block closer to d[hi]
+        const double dd = 0.5 * (d[hi - 1] - d[hi]), eh = e[hi - 1];
+        const double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, eh);
+        const double mu = d[hi] - eh * eh / den;
+        // chase the bulge from (lo, lo+1) down to (hi-1, hi)
+        double bulge = 0.0;
+        for (int i = lo; i < hi; ++i) {
+            double cth, sth;
+            if (i == lo) {
+                const double x = d[lo] - mu, y = e[lo], rho = std::hypot(x, y);
+                cth = rho > 0.0 ? x / rho : 1.0;
+                sth = rho > 0.0 ? -y / rho : 0.0;
+            } else {
+                const double x = e[i - 1], y = bulge, rho = std::hypot(x, y);
+                cth = rho > 0.0 ? x / rho : 1.0;
+                sth = rho > 0.0 ? -y / rho : 0.0;
+                e[i - 1] = rho;
+            }
+            // [p r; r q] <- J^T [p r; r q] J with J = [c s; -s c]
+            const double p = d[i], q = d[i + 1], r = e[i];
+            const double cc = cth * cth, ss = sth * sth, cs = cth * sth;
+            d[i] = cc * p - 2.0 * cs * r + ss * q;
+            d[i + 1] = ss * p + 2.0 * cs * r + cc * q;
+            e[i] = cs * (p - q) + (cc - ss) * r;
+            if (i + 1 < hi) {
+                bulge = -sth * e[i + 1];
+                e[i + 1] = cth * e[i + 1];
+            }
+            const double z0 = z[i], z1 = z[i + 1];
+            z[i] = cth * z0 - sth * z1;
+            z[i + 1] = sth * z0 + cth * z1;
+        }
+    }
+    return true;
+}
+
+struct DevScope {   // frees a call's device workspace on every exit
+    DevBuf buf;
+    ~DevScope() { buf.release(); }
+};
+
+}  // namespace
+
+extern "C" void chi0_lanczos_opts_default(chi0_lanczos_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->k_max = 4000;
+    o->reorth = CHI0_LZ_REORTH_FULL;
+    o->tol = 0.0;
+    o->check_every = 100;
+}
+
+extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, const chi0_lanczos_opts *opts,
+                            double *a_out, double *b_out, double *cn2_out, int32_t *len_out) {
+    if (!c) return CHI0_EINVAL;
+    if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no system on a device context");
+    chi0_lanczos_opts o;
+    if (opts)
+        o = *opts;
+    else
+        chi0_lanczos_opts_default(&o);
+    if (n_drive < 1 || n_drive > 4) return fail(c, CHI0_EINVAL, "n_drive must be 1..4");
+    if (!drives || !a_out || !b_out || !cn2_out || !len_out) return fail(c, CHI0_EINVAL, "NULL pointer");
+    if (o.k_max < 1) return fail(c, CHI0_EINVAL, "k_max < 1");
+    if (o.reorth != CHI0_LZ_REORTH_NONE && o.reorth != CHI0_LZ_REORTH_FULL && o.reorth != CHI0_LZ_REORTH_FULL2)
+        return fail(c, CHI0_EINVAL, "unknown reorth");
+    if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(c, CHI0_EINVAL, "tol must be finite and >= 0");
+    if (o.n_check < 0 || (o.n_check > 0 && !o.omega_check)) return fail(c, CHI0_EINVAL, "bad check frequencies");
+    if (o.tol > 0.0 && (o.n_check == 0 || o.check_every < 1))
+        return fail(c, CHI0_EINVAL, "tol > 0 needs check frequencies and check_every >= 1");
+    if (o.n_check > 0 && (!(o.eps > 0.0) || !std::isfinite(o.eps)))
+        return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
+    if (o.n_check > 0 && !all_finite(o.omega_check, o.n_check))
+        return fail(c, CHI0_ENONFINITE, "non-finite check frequency");
+    if (o.graph != 0 && o.graph != 1) return fail(c, CHI0_EINVAL, "graph must be 0 or 1");
+    for (int32_t r : o.reserved)
+        if (r != 0) return fail(c, CHI0_EINVAL, "reserved fields must be zero");
+    const int P = c->P, nc = n_drive;
+    if (!all_finite(drives, (int64_t)n_drive * P)) return fail(c, CHI0_ENONFINITE, "non-finite drive");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int kmax = (int)std::min<int64_t>(o.k_max, (int64_t)c->No * c->Nv);
+    const bool ring = o.reorth == CHI0_LZ_REORTH_NONE;
+    OpWork &ow = c->op[0];
+    CHK(ensure_ws(c, ow, std::max(nc, ow.nc_cap)));
+
+    const int64_t tp = (int64_t)c->No_pad * c->Nv_pad, n = tp * nc;
+    const int64_t nvec = ring ? 3 : (int64_t)kmax + 1;
+    {
+        size_t fr = 0, tot = 0;
+        HIPCHK(c, hipMemGetInfo(&fr, &tot));
+        const double need =
+            8.0 * (double)(nvec * n + 2 * tp + 66 * ((int64_t)kmax + 1) * nc + (ring ? 0 : LZ_GROUPS * n));
+        if (need > 0.9 * (double)fr)
+            return fail(c, CHI0_ENOMEM, "the Lanczos basis does not fit in free device memory (k_max too large "
+                                        "for full reorthogonalisation)");
+    }
+    DevScope ws;
+    LanczosDev L{};
+    double *St = nullptr, *D2t = nullptr, *part2 = nullptr, *h = nullptr, *part3 = nullptr, *om = nullptr,
+           *spec = nullptr;
+    CHK(dalloc(c, ws.buf, &L.R, nvec * n));
+    CHK(dalloc(c, ws.buf, &St, tp));
+    CHK(dalloc(c, ws.buf, &D2t, tp));
+    CHK(dalloc(c, ws.buf, &L.a, (int64_t)kmax * nc));
+    CHK(dalloc(c, ws.buf, &L.b, (int64_t)kmax * nc));
+    CHK(dalloc(c, ws.buf, &L.cn2, nc));
+    CHK(dalloc(c, ws.buf, &L.len, nc));
+    CHK(dalloc(c, ws.buf, &L.step, 1));
+    CHK(dalloc(c, ws.buf, &L.part, (int64_t)LZ_BLOCKS * nc));
+    if (!ring) {
+        CHK(dalloc(c, ws.buf, &part2, (int64_t)64 * (kmax + 1) * nc));
+        CHK(dalloc(c, ws.buf, &h, (int64_t)(kmax + 1) * nc));
+        CHK(dalloc(c, ws.buf, &part3, (int64_t)LZ_GROUPS * n));
+    }
+    if (o.n_check > 0) {
+        CHK(dalloc(c, ws.buf, &om, o.n_check));
+        CHK(dalloc(c, ws.buf, &spec, 2 * (int64_t)o.n_check * nc));
+        HIPCHK(c, hipMemcpyAsync(om, o.omega_check, (size_t)o.n_check * 8, hipMemcpyHostToDevice, s));
+    }
+    L.n = n;
+    L.tp = tp;
+    L.ring = ring ? 1 : 0;
+    L.passes = ring ? 0 : (o.reorth == CHI0_LZ_REORTH_FULL2 ? 2 : 1);
+    L.nc = nc;
+    L.kmax = kmax;
+    L.St = St;
+    L.D2t = D2t;
+    L.at = ow.at;
+    launch_zero(&c->tracer, s, L.a, (int64_t)kmax * nc);
+    launch_zero(&c->tracer, s, L.b, (int64_t)kmax * nc);
+    launch_lz_tables(s, c->Dlt, c->No, c->Nv, c->No_pad, c->Nv_pad, c->occ, St, D2t);
+    // drives -> Zin [P_pad][nc] (padding rows zero), c = S V_t^T d
+    {
+        std::vector<double> zin((size_t)c->P_pad * nc, 0.0);
+        for (int sq = 0; sq < nc; ++sq)
+            for (int mu = 0; mu < P; ++mu) zin[(size_t)mu * nc + sq] = drives[(size_t)sq * P + mu];
+        launch_zero(&c->tracer, s, ow.Yout, (int64_t)c->P_pad * nc);
+        HIPCHK(c, hipMemcpyAsync(ow.Zin, zin.data(), zin.size() * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));   // zin is a host temporary
+    }
+    lz_front(c, ow, s, nc);
+    launch_lz_start(&c->tracer, s, L);
+
+    // convergence checks on the host: alpha_k at the check frequencies
+    std::vector<double> cur(2 * (size_t)o.n_check * nc), prev;
+    std::vector<int> lenh(nc);
+    int met = 0;
+    bool converged = false;
+    auto check = [&](int k) -> int {
+        launch_lz_cfrac(s, L.a, L.b, nc, k, L.len, L.cn2, om, o.n_check, o.eps, spec);
+        HIPCHK(c, hipMemcpyAsync(cur.data(), spec, cur.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(lenh.data(), L.len, nc * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        double worst = 0.0;
+        if (!prev.empty()) {
+            for (int sq = 0; sq < nc; ++sq) {
+                double mx = 0.0;
+                for (int i = 0; i < o.n_check; ++i) mx = std::max(mx, std::fabs(cur[2 * ((size_t)i * nc + sq) + 1]));
+                const double floor_v = std::max(1e-3 * mx, 1e-300);
+                for (int i = 0; i < o.n_check; ++i) {
+                    const size_t q = 2 * ((size_t)i * nc + sq);
+                    const double dr = cur[q] - prev[q], di = cur[q + 1] - prev[q + 1];
+                    const double den = std::max(std::fabs(cur[q + 1]), floor_v);
+                    worst = std::max(worst, std::hypot(dr, di) / den);
+                }
+            }
+            met = worst <= o.tol ? met + 1 : 0;
+        }
+        prev = cur;
+        return CHI0_OK;
+    };
+
+    hipGraphExec_t exec = nullptr;
+    struct ExecScope {
+        hipGraphExec_t *e;
+        ~ExecScope() {
+            if (*e) (void)hipGraphExecDestroy(*e);
+        }
+    } exec_scope{&exec};
+    const bool use_graph = o.graph == 1 && ring && !c->tracer.on;
+    int steps = 0;
+    for (int j = 0; j < kmax; ++j) {
+        if (use_graph && j >= 1) {
+            if (!exec) {   // capture one step (the GEMM tiles were tuned by step 0)
+                if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                HIPCHK(c, hipStreamSynchronize(s));
+                hipGraph_t g = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                lz_back_k(c, ow, c->cap_stream, nc);
+                lz_front(c, ow, c->cap_stream, nc);
+                launch_lz_step(&c->tracer, c->cap_stream, L, j, part2, h, part3);
+                HIPCHK(c, hipStreamEndCapture(c->cap_stream, &g));
+                const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    exec = nullptr;
+                    return fail(c, CHI0_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+                }
+            }
+            HIPCHK(c, hipGraphLaunch(exec, s));
+        } else {
+            lz_back_k(c, ow, s, nc);
+            lz_front(c, ow, s, nc);
+            launch_lz_step(&c->tracer, s, L, j, part2, h, part3);
+        }
+        steps = j + 1;
+        const bool last = steps == kmax;
+        if (o.n_check > 0 && (steps % std::max(o.check_every, 1) == 0 || last)) {
+            CHK(check(steps));
+            bool all_ended = true;
+            for (int sq = 0; sq < nc; ++sq) all_ended = all_ended && lenh[sq] < kmax && lenh[sq] <= steps;
+            if (all_ended || (o.tol > 0.0 && met >= 2)) {
+                converged = true;
+                break;
+            }
+        }
+    }
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> ah((size_t)kmax * nc), bh((size_t)kmax * nc), cn2h(nc);
+    HIPCHK(c, hipMemcpyAsync(ah.data(), L.a, ah.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(bh.data(), L.b, bh.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(cn2h.data(), L.cn2, nc * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(lenh.data(), L.len, nc * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    bool all_ended = true;
+    for (int sq = 0; sq < nc; ++sq) {
+        const int ln = std::min(lenh[sq], steps);
+        all_ended = all_ended && lenh[sq] <= steps && lenh[sq] < kmax;
+        len_out[sq] = ln;
+        cn2_out[sq] = cn2h[sq];
+        for (int j = 0; j < o.k_max; ++j) {
+            a_out[(size_t)sq * o.k_max + j] = j < ln ? ah[(size_t)j * nc + sq] : 0.0;
+            b_out[(size_t)sq * o.k_max + j] = j < ln ? bh[(size_t)j * nc + sq] : 0.0;
+        }
+    }
+    if (o.tol > 0.0 && !converged && !all_ended) return CHI0_NOT_CONVERGED;
+    return CHI0_OK;
+}
+
+extern "C" int chi0_lanczos_spectrum(chi0_ctx *c, int32_t n_drive, int32_t ld, const double *a, const double *b,
+                                     const double *cn2, const int32_t *len, int32_t n_omega, const double *omega,
+                                     double eps, double *alpha) {
+    if (!c) return CHI0_EINVAL;
+    if (c->device < 0) return fail(c, CHI0_ENOSYS, "host-only context");
+    if (n_drive < 1 || ld < 0 || n_omega < 0) return fail(c, CHI0_EINVAL, "bad sizes");
+    if (n_omega == 0) return CHI0_OK;
+    if (!a || !b || !cn2 || !len || !omega || !alpha) return fail(c, CHI0_EINVAL, "NULL pointer");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
+    int kuse = 0;
+    for (int sq = 0; sq < n_drive; ++sq) {
+        if (len[sq] < 0 || len[sq] > ld) return fail(c, CHI0_EINVAL, "len outside 0..ld");
+        kuse = std::max(kuse, (int)len[sq]);
+    }
+    if (!all_finite(omega, n_omega) || !all_finite(cn2, n_drive)) return fail(c, CHI0_ENONFINITE, "non-finite input");
+    std::vector<double> ad((size_t)std::max(kuse, 1) * n_drive, 0.0), bd(ad.size(), 0.0);
+    for (int sq = 0; sq < n_drive; ++sq)
+        for (int j = 0; j < len[sq]; ++j) {
+            ad[(size_t)j * n_drive + sq] = a[(size_t)sq * ld + j];
+            bd[(size_t)j * n_drive + sq] = b[(size_t)sq * ld + j];
+        }
+    if (!all_finite(ad.data(), (int64_t)ad.size()) || !all_finite(bd.data(), (int64_t)bd.size()))
+        return fail(c, CHI0_ENONFINITE, "non-finite coefficient");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    DevScope ws;
+    double *a_d = nullptr, *b_d = nullptr, *c_d = nullptr, *om_d = nullptr, *out_d = nullptr;
+    int *len_d = nullptr;
+    CHK(dalloc(c, ws.buf, &a_d, (int64_t)ad.size()));
+    CHK(dalloc(c, ws.buf, &b_d, (int64_t)bd.size()));
+    CHK(dalloc(c, ws.buf, &c_d, n_drive));
+    CHK(dalloc(c, ws.buf, &len_d, n_drive));
+    CHK(dalloc(c, ws.buf, &om_d, n_omega));
+    CHK(dalloc(c, ws.buf, &out_d, 2 * (int64_t)n_omega * n_drive));
+    HIPCHK(c, hipMemcpyAsync(a_d, ad.data(), ad.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(b_d, bd.data(), bd.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c_d, cn2, (size_t)n_drive * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(len_d, len, (size_t)n_drive * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(om_d, omega, (size_t)n_omega * 8, hipMemcpyHostToDevice, s));
+    launch_lz_cfrac(s, a_d, b_d, n_drive, kuse, len_d, c_d, om_d, n_omega, eps, out_d);
+    HIPCHK(c, hipMemcpyAsync(alpha, out_d, 2 * (size_t)n_omega * n_drive * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipGetLastError());
+    return CHI0_OK;
+}
+
+extern "C" int chi0_lanczos_poles(int32_t k, const double *a, const double *b, double c_norm2, double *theta,
+                                  double *resid) {
+    if (k < 1 || !a || !b || !theta || !resid) return CHI0_EINVAL;
+    if (!all_finite(a, k) || (k > 1 && !all_finite(b, k - 1)) || !std::isfinite(c_norm2)) return CHI0_ENONFINITE;
+    if (c_norm2 < 0.0) return CHI0_EINVAL;
+    std::vector<double> d(a, a + k), e(b, b + (k - 1)), z;
+    if (!tridiag_eig_first_row(k, d, e, z)) return CHI0_NOT_CONVERGED;
+    std::vector<int> order(k);
+    for (int i = 0; i < k; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return d[x] < d[y]; });
+    for (int i = 0; i < k; ++i) {
+        theta[i] = d[order[i]];
+        resid[i] = c_norm2 * z[order[i]] * z[order[i]];
+    }
     return CHI0_OK;
 }

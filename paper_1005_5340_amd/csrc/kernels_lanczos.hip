@@ -1,0 +1,464 @@
+// Lanczos recursion in transition space and the spectrum read off it.
+//
+// In the space of (occupied E, virtual F) transitions the response of Sec. 3
+// has the pole form (Casida's equations)
+//     Om2 = diag(D^2) + S V_t^T f V_t S,  S = diag(sqrt(2 n D)),  c = S V_t^T d,
+//     alpha(w) = c^T (Om2 - (w + i eps)^2)^-1 c,
+// with D_EF = e_F - e_E, v^{EF} the transition vertices of eq. response-mat
+// (V_t: n_prod x T) and f the kernel of eq. sle.  The symmetric Lanczos
+// recursion on Om2 started from c gives a tridiagonal T_k from which
+// alpha(w) follows at every frequency (a continued fraction) and the poles
+// and residues follow from T_k's eigen-decomposition: the economical
+// treatment of the frequency axis, with pole positions and strengths, that
+// Sec. 8 names as further work.  Om2 is applied matrix-free by the chi0
+// operator's own kernels (the back half (b3), (b4), (d), then K, then the
+// front half (a), (b1), (b2)); this file holds the recursion's vector work.
+//
+// A block of nc <= 4 recursions (one per drive) runs together.  Transition
+// vectors use the operator's `at` layout: element (F, E, s) sits at
+// (F * No_pad + E) * nc + s.  The step index lives in device memory so that
+// one step's launch sequence can be replayed from a HIP graph.  Reductions
+// are deterministic: fixed-order per-workgroup sums, then one workgroup adds
+// the partials in a fixed order.
+#include "common.h"
+
+namespace chi0 {
+
+namespace {
+
+__device__ __forceinline__ double lz_wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Per-workgroup sums of NC accumulators into part[blockIdx.x][NC] (256 threads).
+template <int NC>
+__device__ __forceinline__ void lz_block_part(const double (&acc)[NC], double *part) {
+    __shared__ double sh[4][NC];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        const double v = lz_wave_sum(acc[s]);
+        if ((t & 63) == 0) sh[t >> 6][s] = v;
+    }
+    __syncthreads();
+    if (t < NC) part[(int64_t)blockIdx.x * NC + t] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+}
+
+// Sum of the nblk partials of sequence s by one 256-thread workgroup (fixed order).
+template <int NC>
+__device__ __forceinline__ double lz_sum_parts(const double *part, int nblk, int s, double *sh) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) v += part[(int64_t)b * NC + s];
+    v = lz_wave_sum(v);
+    const int t = threadIdx.x;
+    __syncthreads();
+    if ((t & 63) == 0) sh[t >> 6] = v;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__device__ __forceinline__ double *lz_vec(const LanczosDev &L, int i) {
+    return L.R + (int64_t)(L.ring ? i % 3 : i) * L.n;
+}
+
+}  // namespace
+
+// St = sqrt(2 n D), D2t = D^2 on the transitions, 0 on the padding; [Nv_pad][No_pad].
+__global__ __launch_bounds__(256)
+void k_lz_tables(const double *__restrict__ Dlt, int No, int Nv, int no_pad, int nv_pad, double occ,
+                 double *__restrict__ St, double *__restrict__ D2t) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)no_pad * nv_pad) return;
+    const int F = (int)(idx / no_pad), E = (int)(idx % no_pad);
+    double s = 0.0, d2 = 0.0;
+    if (E < No && F < Nv) {
+        const double d = Dlt[(int64_t)E * nv_pad + F];
+        s = sqrt(2.0 * occ * d);
+        d2 = d * d;
+    }
+    St[idx] = s;
+    D2t[idx] = d2;
+}
+
+// Start: R[0] = St * at (c = S V_t^T d, the front half already applied to d);
+// partial sums of |c|^2.
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_start(LanczosDev L) {
+    double acc[NC] = {};
+    double *q = lz_vec(L, 0);
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+        const double st = L.St[r];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const double v = st * L.at[r * NC + s];
+            q[r * NC + s] = v;
+            acc[s] += v * v;
+        }
+    }
+    lz_block_part<NC>(acc, L.part);
+}
+
+// |c|^2 per sequence; a sequence with c = 0 has length 0.  Resets the step counter.
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_start_fin(LanczosDev L, int nblk) {
+    __shared__ double sh[4];
+    for (int s = 0; s < NC; ++s) {
+        const double v = lz_sum_parts<NC>(L.part, nblk, s, sh);
+        if (threadIdx.x == 0) {
+            L.cn2[s] = v;
+            L.len[s] = v > 0.0 ? L.kmax : 0;
+        }
+    }
+    if (threadIdx.x == 0) *L.step = 0;
+}
+
+// q_0 = c / |c| in place; at = St * q_0 (input of the next operator pass).
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_start_scale(LanczosDev L) {
+    double inv[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) inv[s] = L.cn2[s] > 0.0 ? 1.0 / sqrt(L.cn2[s]) : 0.0;
+    double *q = lz_vec(L, 0);
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+        const double st = L.St[r];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const double v = q[r * NC + s] * inv[s];
+            q[r * NC + s] = v;
+            L.at[r * NC + s] = st * v;
+        }
+    }
+}
+
+// Step j, after the operator pass: w = St * at + D2t * q_j (= Om2 q_j) into
+// vector j + 1; partial sums of q_j . w.
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_combine(LanczosDev L) {
+    const int j = *L.step;
+    const double *q = lz_vec(L, j);
+    double *w = lz_vec(L, j + 1);
+    double acc[NC] = {};
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+        const double st = L.St[r], d2 = L.D2t[r];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const double qv = q[r * NC + s];
+            const double v = st * L.at[r * NC + s] + d2 * qv;
+            w[r * NC + s] = v;
+            acc[s] += qv * v;
+        }
+    }
+    lz_block_part<NC>(acc, L.part);
+}
+
+// a_j = q_j . w; advances the step counter (later kernels of the step read j = step - 1).
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_alpha(LanczosDev L, int nblk) {
+    __shared__ double sh[4];
+    const int j = *L.step;
+    for (int s = 0; s < NC; ++s) {
+        const double v = lz_sum_parts<NC>(L.part, nblk, s, sh);
+        if (threadIdx.x == 0) L.a[(int64_t)j * NC + s] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *L.step = j + 1;
+}
+
+// w -= a_j q_j + b_{j-1} q_{j-1}; partial sums of |w|^2.
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_axpy(LanczosDev L) {
+    const int j = *L.step - 1;
+    const double *q = lz_vec(L, j);
+    const double *qm = lz_vec(L, j > 0 ? j - 1 : 0);
+    double *w = lz_vec(L, j + 1);
+    double aj[NC], bm[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        aj[s] = L.a[(int64_t)j * NC + s];
+        bm[s] = j > 0 ? L.b[(int64_t)(j - 1) * NC + s] : 0.0;
+    }
+    double acc[NC] = {};
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const double v = w[r * NC + s] - aj[s] * q[r * NC + s] - bm[s] * qm[r * NC + s];
+            w[r * NC + s] = v;
+            acc[s] += v * v;
+        }
+    }
+    lz_block_part<NC>(acc, L.part);
+}
+
+// b_j = |w|.  A sequence ends (length j + 1, b_j = 0 and every later
+// coefficient 0) when b_j <= 1e-12 (|a_j| + b_{j-1}): an invariant subspace.
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_beta(LanczosDev L, int nblk) {
+    __shared__ double sh[4];
+    const int j = *L.step - 1;
+    for (int s = 0; s < NC; ++s) {
+        const double v = lz_sum_parts<NC>(L.part, nblk, s, sh);
+        if (threadIdx.x == 0) {
+            const double bj = sqrt(v);
+            const double aj = L.a[(int64_t)j * NC + s];
+            const double bm = j > 0 ? L.b[(int64_t)(j - 1) * NC + s] : 0.0;
+            const bool ended = L.len[s] <= j || !(bj > 1e-12 * (fabs(aj) + bm));
+            if (ended && L.len[s] > j) L.len[s] = j + 1;
+            L.b[(int64_t)j * NC + s] = ended ? 0.0 : bj;
+        }
+    }
+}
+
+// q_{j+1} = w / b_j in place (0 for an ended sequence); at = St * q_{j+1}.
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_scale(LanczosDev L) {
+    const int j = *L.step - 1;
+    double *w = lz_vec(L, j + 1);
+    double inv[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        const double bj = L.b[(int64_t)j * NC + s];
+        inv[s] = bj > 0.0 ? 1.0 / bj : 0.0;
+    }
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+        const double st = L.St[r];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const double v = w[r * NC + s] * inv[s];
+            w[r * NC + s] = v;
+            L.at[r * NC + s] = st * v;
+        }
+    }
+}
+
+// Full reorthogonalisation: classical Gram-Schmidt passes against q_0..q_j.
+// The basis is streamed once per kernel and is far larger than the caches, so
+// its loads are non-temporal; w (one vector) stays in L2.
+__device__ __forceinline__ double lz_ldnt(const double *p) { return __builtin_nontemporal_load(p); }
+
+// h[i][s] = q_i . w over rows [rs * chunk, ...), per (row split rs, vector i).
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_dots(LanczosDev L, int nq, int nsplit, double *part2) {
+    const int i = blockIdx.y, rs = blockIdx.x;
+    const int j = *L.step - 1;
+    const double *q = lz_vec(L, i);
+    const double *w = lz_vec(L, j + 1);
+    const int64_t chunk = (L.tp + nsplit - 1) / nsplit;
+    const int64_t r0 = rs * chunk, r1 = min(L.tp, r0 + chunk);
+    double acc[NC] = {};
+#pragma unroll 4
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+#pragma unroll
+        for (int s = 0; s < NC; ++s) acc[s] += lz_ldnt(q + r * NC + s) * w[r * NC + s];
+    }
+    __shared__ double sh[4][NC];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        const double v = lz_wave_sum(acc[s]);
+        if ((t & 63) == 0) sh[t >> 6][s] = v;
+    }
+    __syncthreads();
+    if (t < NC && i < nq)
+        part2[((int64_t)i * nsplit + rs) * NC + t] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_dots_fin(const double *part2, int nq, int nsplit, double *h) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)nq * NC) return;
+    const int i = (int)(idx / NC), s = (int)(idx % NC);
+    double v = 0.0;
+    for (int rs = 0; rs < nsplit; ++rs) v += part2[((int64_t)i * nsplit + rs) * NC + s];
+    h[idx] = v;
+}
+
+// part3[g][r][s] = sum over the vectors i of group g (a contiguous range) of
+// q_i[r][s] h[i][s]; workgroup (row block, group): one row per thread.
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_update_part(LanczosDev L, int nq, int ngroup, const double *__restrict__ h, double *__restrict__ part3) {
+    const int g = blockIdx.y;
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= L.tp) return;
+    const int per = (nq + ngroup - 1) / ngroup;
+    const int i0 = g * per, i1 = min(nq, i0 + per);
+    double acc[NC] = {};
+    int i = i0;
+    for (; i + 8 <= i1; i += 8) {
+        double qv[8][NC];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int s = 0; s < NC; ++s) qv[u][s] = lz_ldnt(lz_vec(L, i + u) + r * NC + s);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int s = 0; s < NC; ++s) acc[s] += qv[u][s] * h[(int64_t)(i + u) * NC + s];
+    }
+    for (; i < i1; ++i)
+#pragma unroll
+        for (int s = 0; s < NC; ++s) acc[s] += lz_ldnt(lz_vec(L, i) + r * NC + s) * h[(int64_t)i * NC + s];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) part3[((int64_t)g * L.tp + r) * NC + s] = acc[s];
+}
+
+// w -= sum_g part3[g] (groups in order); partial sums of |w|^2.
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_update_fin(LanczosDev L, int ngroup, const double *__restrict__ part3) {
+    const int j = *L.step - 1;
+    double *w = lz_vec(L, j + 1);
+    double acc[NC] = {};
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            double sub = 0.0;
+            for (int g = 0; g < ngroup; ++g) sub += part3[((int64_t)g * L.tp + r) * NC + s];
+            const double v = w[r * NC + s] - sub;
+            w[r * NC + s] = v;
+            acc[s] += v * v;
+        }
+    }
+    lz_block_part<NC>(acc, L.part);
+}
+
+// alpha_k(w) = |c|^2 / g_0 with g_{k-1} = a_{k-1} - z, g_i = a_i - z - b_i^2 / g_{i+1},
+// z = (w + i eps)^2: the continued fraction of |c|^2 e_1^T (T_k - z)^-1 e_1.
+// One thread per (frequency, sequence); k = min(kuse, len[s]).
+__global__ __launch_bounds__(256)
+void k_lz_cfrac(const double *__restrict__ a, const double *__restrict__ b, int nc, int kuse,
+                const int *__restrict__ len, const double *__restrict__ cn2, const double *__restrict__ omega,
+                int n_omega, double eps, double *__restrict__ out) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n_omega * nc) return;
+    const int wi = idx / nc, s = idx % nc;
+    const int k = min(kuse, len[s]);
+    const double w = omega[wi];
+    const double zr = w * w - eps * eps, zi = 2.0 * w * eps;
+    double gr = 0.0, gi = 0.0;
+    if (k > 0) {
+        gr = a[(int64_t)(k - 1) * nc + s] - zr;
+        gi = -zi;
+        for (int i = k - 2; i >= 0; --i) {
+            const double bb = b[(int64_t)i * nc + s];
+            const double m = gr * gr + gi * gi;           // -b^2 / g = -b^2 conj(g) / |g|^2
+            const double f = bb * bb / m;
+            gr = a[(int64_t)i * nc + s] - zr - f * gr;
+            gi = -zi + f * gi;
+        }
+    }
+    double re = 0.0, im = 0.0;   // an empty recursion (c = 0) gives alpha = 0
+    if (k > 0) {
+        const double m = gr * gr + gi * gi;
+        re = cn2[s] * gr / m;
+        im = -cn2[s] * gi / m;
+    }
+    out[2 * (int64_t)idx] = re;
+    out[2 * (int64_t)idx + 1] = im;
+}
+
+// ------------------------------------------------------------------ launches
+namespace {
+int lz_blocks(const LanczosDev &L) {
+    int64_t b = (L.tp + 255) / 256;
+    return (int)std::min<int64_t>(std::max<int64_t>(b, 1), LZ_BLOCKS);
+}
+}  // namespace
+
+#define LZ_NC_SWITCH(nc, CALL) \
+    switch (nc) {              \
+    case 1: CALL(1); break;    \
+    case 2: CALL(2); break;    \
+    case 3: CALL(3); break;    \
+    default: CALL(4); break;   \
+    }
+
+void launch_lz_tables(hipStream_t s, const double *Dlt, int No, int Nv, int no_pad, int nv_pad, double occ,
+                      double *St, double *D2t) {
+    const int64_t n = (int64_t)no_pad * nv_pad;
+    hipLaunchKernelGGL(k_lz_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Dlt, No, Nv, no_pad,
+                       nv_pad, occ, St, D2t);
+}
+
+void launch_lz_start(Tracer *t, hipStream_t s, const LanczosDev &L) {
+    const int g = lz_blocks(L);
+    trace_begin(t, "lanczos_start", s);
+#define C(N)                                                                        \
+    hipLaunchKernelGGL(k_lz_start<N>, dim3(g), dim3(256), 0, s, L);                 \
+    hipLaunchKernelGGL(k_lz_start_fin<N>, dim3(1), dim3(256), 0, s, L, g);          \
+    hipLaunchKernelGGL(k_lz_start_scale<N>, dim3(g), dim3(256), 0, s, L);
+    LZ_NC_SWITCH(L.nc, C)
+#undef C
+    trace_end(t, s, 0.0, 8.0 * L.n * 4);
+}
+
+void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
+                    double *part3) {
+    const int g = lz_blocks(L);
+    const double vb = 8.0 * (double)L.n;   // one transition vector
+    trace_begin(t, "lanczos_combine", s);
+#define C(N)                                                                   \
+    hipLaunchKernelGGL(k_lz_combine<N>, dim3(g), dim3(256), 0, s, L);          \
+    hipLaunchKernelGGL(k_lz_alpha<N>, dim3(1), dim3(256), 0, s, L, g);
+    LZ_NC_SWITCH(L.nc, C)
+#undef C
+    trace_end(t, s, 4.0 * L.n, 3.0 * vb + 16.0 * L.tp);
+    trace_begin(t, "lanczos_axpy", s);
+#define C(N) hipLaunchKernelGGL(k_lz_axpy<N>, dim3(g), dim3(256), 0, s, L);
+    LZ_NC_SWITCH(L.nc, C)
+#undef C
+    trace_end(t, s, 6.0 * L.n, 4.0 * vb);
+    if (!L.ring) {
+        // classical Gram-Schmidt pass(es) against q_0..q_j (j known on the host)
+        const int nq = j + 1;
+        const int nsplit = std::max(1, std::min(64, 2048 / nq));
+        const unsigned rblocks = (unsigned)((L.tp + 255) / 256);
+        const int ngroup = std::max(1, std::min(LZ_GROUPS, nq / 64));
+        for (int pass = 0; pass < L.passes; ++pass) {
+            trace_begin(t, "lanczos_reorth_dots", s);
+#define C(N)                                                                                                  \
+    hipLaunchKernelGGL(k_lz_dots<N>, dim3(nsplit, nq), dim3(256), 0, s, L, nq, nsplit, part2);                \
+    hipLaunchKernelGGL(k_lz_dots_fin<N>, dim3((unsigned)((nq * N + 255) / 256)), dim3(256), 0, s, part2, nq, \
+                       nsplit, h);
+            LZ_NC_SWITCH(L.nc, C)
+#undef C
+            trace_end(t, s, 2.0 * L.n * nq, vb * (nq + 1));
+            trace_begin(t, "lanczos_reorth_update", s);
+#define C(N)                                                                                                   \
+    hipLaunchKernelGGL(k_lz_update_part<N>, dim3(rblocks, ngroup), dim3(256), 0, s, L, nq, ngroup, h, part3); \
+    hipLaunchKernelGGL(k_lz_update_fin<N>, dim3(g), dim3(256), 0, s, L, ngroup, part3);
+            LZ_NC_SWITCH(L.nc, C)
+#undef C
+            trace_end(t, s, 2.0 * L.n * nq, vb * (nq + 2));
+        }
+    }
+    trace_begin(t, "lanczos_scale", s);
+#define C(N)                                                                \
+    hipLaunchKernelGGL(k_lz_beta<N>, dim3(1), dim3(256), 0, s, L, g);       \
+    hipLaunchKernelGGL(k_lz_scale<N>, dim3(g), dim3(256), 0, s, L);
+    LZ_NC_SWITCH(L.nc, C)
+#undef C
+    trace_end(t, s, 2.0 * L.n, 3.0 * vb + 8.0 * L.tp);
+}
+
+void launch_lz_cfrac(hipStream_t s, const double *a, const double *b, int nc, int kuse, const int *len,
+                     const double *cn2, const double *omega, int n_omega, double eps, double *out) {
+    const int n = n_omega * nc;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_lz_cfrac, dim3((n + 255) / 256), dim3(256), 0, s, a, b, nc, kuse, len, cn2, omega,
+                       n_omega, eps, out);
+}
+
+}  // namespace chi0
