@@ -711,7 +711,7 @@ void k_kmatvec_skinny(int P_pad, const double *__restrict__ K, const double *__r
         }
 }
 
-// One or two right-hand sides (nc = 2 or 4 real columns): a wavefront owns RW
+// Up to two right-hand sides (nc = 1..4 real columns): a wavefront owns RW
 // rows and every lane reads 16-byte pairs of K columns, U pairs of chunks in
 // flight per row; the two Zin rows a lane needs (2 nc doubles, contiguous) are
 // read through the cache.  Four times the wavefronts of the LDS-staged form,
@@ -768,8 +768,12 @@ void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
                            const double *Zin, double *Zout, int nc, double P) {
     dim3 grid(P_pad / 16);
     trace_begin(t, "kernel_matvec", s);
-    if (nc == 2)
+    if (nc == 1)
+        hipLaunchKernelGGL((k_kmatvec_lanes<1, 1>), dim3(P_pad / 4), dim3(256), 0, s, P_pad, K, Zin, Zout);
+    else if (nc == 2)
         hipLaunchKernelGGL((k_kmatvec_lanes<2, 1>), dim3(P_pad / 4), dim3(256), 0, s, P_pad, K, Zin, Zout);
+    else if (nc == 3)
+        hipLaunchKernelGGL((k_kmatvec_lanes<3, 1>), dim3(P_pad / 4), dim3(256), 0, s, P_pad, K, Zin, Zout);
     else if (nc == 4)
         hipLaunchKernelGGL((k_kmatvec_lanes<4, 2>), dim3(P_pad / 8), dim3(256), 0, s, P_pad, K, Zin, Zout);
     else if (nc <= 8)

@@ -242,10 +242,18 @@ void k_lz_scale(LanczosDev L) {
 
 // Full reorthogonalisation: classical Gram-Schmidt passes against q_0..q_j.
 // The basis is streamed once per kernel and is far larger than the caches, so
-// its loads are non-temporal; w (one vector) stays in L2.
+// its loads are non-temporal 16-byte loads; w (one vector) stays in L2.  A
+// vector of n = tp * NC doubles is read as n / 2 pairs (tp is even); pair p
+// holds the elements of sequences (2p) % NC and (2p + 1) % NC.  For NC = 1, 2
+// and 4 a thread's pairs all hold the same two sequences (its pairs are 256
+// apart, and 512 elements is a multiple of NC); NC = 3 reads single elements.
+typedef double lz_dbl2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ lz_dbl2 lz_ld2nt(const double *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const lz_dbl2 *>(p));
+}
 __device__ __forceinline__ double lz_ldnt(const double *p) { return __builtin_nontemporal_load(p); }
 
-// h[i][s] = q_i . w over rows [rs * chunk, ...), per (row split rs, vector i).
+// h[i][s] = q_i . w over pairs [rs * chunk, ...), per (split rs, vector i).
 template <int NC>
 __global__ __launch_bounds__(256)
 void k_lz_dots(LanczosDev L, int nq, int nsplit, double *part2) {
@@ -253,13 +261,29 @@ void k_lz_dots(LanczosDev L, int nq, int nsplit, double *part2) {
     const int j = *L.step - 1;
     const double *q = lz_vec(L, i);
     const double *w = lz_vec(L, j + 1);
-    const int64_t chunk = (L.tp + nsplit - 1) / nsplit;
-    const int64_t r0 = rs * chunk, r1 = min(L.tp, r0 + chunk);
     double acc[NC] = {};
+    if (NC != 3) {
+        const int64_t np = L.n / 2, chunk = ((np + nsplit - 1) / nsplit + 255) / 256 * 256;
+        const int64_t p0 = rs * chunk, p1 = min(np, p0 + chunk);
+        const int sa = (int)((2 * (p0 + threadIdx.x)) % NC), sb = (sa + 1) % NC;
+        double x = 0.0, y = 0.0;
 #pragma unroll 4
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+            const lz_dbl2 qv = lz_ld2nt(q + 2 * p);
+            const double2 wv = *reinterpret_cast<const double2 *>(w + 2 * p);
+            x += qv.x * wv.x;
+            y += qv.y * wv.y;
+        }
 #pragma unroll
-        for (int s = 0; s < NC; ++s) acc[s] += lz_ldnt(q + r * NC + s) * w[r * NC + s];
+        for (int s = 0; s < NC; ++s) acc[s] = (s == sa ? x : 0.0) + (s == sb ? y : 0.0);
+    } else {
+        const int64_t chunk = (L.tp + nsplit - 1) / nsplit;
+        const int64_t r0 = rs * chunk, r1 = min(L.tp, r0 + chunk);
+#pragma unroll 4
+        for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+#pragma unroll
+            for (int s = 0; s < NC; ++s) acc[s] += lz_ldnt(q + r * NC + s) * w[r * NC + s];
+        }
     }
     __shared__ double sh[4][NC];
     const int t = threadIdx.x;
@@ -284,34 +308,47 @@ void k_lz_dots_fin(const double *part2, int nq, int nsplit, double *h) {
     h[idx] = v;
 }
 
-// part3[g][r][s] = sum over the vectors i of group g (a contiguous range) of
-// q_i[r][s] h[i][s]; workgroup (row block, group): one row per thread.
+// part3[g][e] = sum over the vectors i of group g (a contiguous range) of
+// q_i[e] h[i][seq(e)]; workgroup (block of pairs, group): one pair per thread
+// (NC = 3: one row of three per thread).
 template <int NC>
 __global__ __launch_bounds__(256)
 void k_lz_update_part(LanczosDev L, int nq, int ngroup, const double *__restrict__ h, double *__restrict__ part3) {
     const int g = blockIdx.y;
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= L.tp) return;
     const int per = (nq + ngroup - 1) / ngroup;
     const int i0 = g * per, i1 = min(nq, i0 + per);
-    double acc[NC] = {};
-    int i = i0;
-    for (; i + 8 <= i1; i += 8) {
-        double qv[8][NC];
+    const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (NC != 3) {
+        if (u >= L.n / 2) return;
+        const int sa = (int)((2 * u) % NC), sb = (sa + 1) % NC;
+        double x = 0.0, y = 0.0;
+        int i = i0;
+        for (; i + 8 <= i1; i += 8) {
+            lz_dbl2 qv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+            for (int k = 0; k < 8; ++k) qv[k] = lz_ld2nt(lz_vec(L, i + k) + 2 * u);
 #pragma unroll
-            for (int s = 0; s < NC; ++s) qv[u][s] = lz_ldnt(lz_vec(L, i + u) + r * NC + s);
+            for (int k = 0; k < 8; ++k) {
+                x += qv[k].x * h[(int64_t)(i + k) * NC + sa];
+                y += qv[k].y * h[(int64_t)(i + k) * NC + sb];
+            }
+        }
+        for (; i < i1; ++i) {
+            const lz_dbl2 qv = lz_ld2nt(lz_vec(L, i) + 2 * u);
+            x += qv.x * h[(int64_t)i * NC + sa];
+            y += qv.y * h[(int64_t)i * NC + sb];
+        }
+        *reinterpret_cast<double2 *>(part3 + (int64_t)g * L.n + 2 * u) = make_double2(x, y);
+    } else {
+        const int64_t r = u;
+        if (r >= L.tp) return;
+        double acc[NC] = {};
+        for (int i = i0; i < i1; ++i)
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+            for (int s = 0; s < NC; ++s) acc[s] += lz_ldnt(lz_vec(L, i) + r * NC + s) * h[(int64_t)i * NC + s];
 #pragma unroll
-            for (int s = 0; s < NC; ++s) acc[s] += qv[u][s] * h[(int64_t)(i + u) * NC + s];
+        for (int s = 0; s < NC; ++s) part3[(int64_t)g * L.n + r * NC + s] = acc[s];
     }
-    for (; i < i1; ++i)
-#pragma unroll
-        for (int s = 0; s < NC; ++s) acc[s] += lz_ldnt(lz_vec(L, i) + r * NC + s) * h[(int64_t)i * NC + s];
-#pragma unroll
-    for (int s = 0; s < NC; ++s) part3[((int64_t)g * L.tp + r) * NC + s] = acc[s];
 }
 
 // w -= sum_g part3[g] (groups in order); partial sums of |w|^2.
@@ -325,7 +362,7 @@ void k_lz_update_fin(LanczosDev L, int ngroup, const double *__restrict__ part3)
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             double sub = 0.0;
-            for (int g = 0; g < ngroup; ++g) sub += part3[((int64_t)g * L.tp + r) * NC + s];
+            for (int g = 0; g < ngroup; ++g) sub += part3[(int64_t)g * L.n + r * NC + s];
             const double v = w[r * NC + s] - sub;
             w[r * NC + s] = v;
             acc[s] += v * v;
@@ -424,7 +461,7 @@ void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double
         // classical Gram-Schmidt pass(es) against q_0..q_j (j known on the host)
         const int nq = j + 1;
         const int nsplit = std::max(1, std::min(64, 2048 / nq));
-        const unsigned rblocks = (unsigned)((L.tp + 255) / 256);
+        const unsigned rblocks = (unsigned)(((L.nc == 3 ? L.tp : L.n / 2) + 255) / 256);
         const int ngroup = std::max(1, std::min(LZ_GROUPS, nq / 64));
         for (int pass = 0; pass < L.passes; ++pass) {
             trace_begin(t, "lanczos_reorth_dots", s);
