@@ -225,6 +225,17 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
         for k, v in sorted(ks_all.items(), key=lambda kv: -kv[1]["ms"]):
             print(f"[bench] {k:30s} {int(v['launches']):8d} {v['ms']:9.2f} {100 * v['ms'] / tot:6.1f}%",
                   file=sys.stderr)
+    # poles and residues of the first drive's recursion (host, after the timed region)
+    k0 = int(res["len"][0])
+    t0 = time.perf_counter()
+    th, rr = chi0.lanczos_poles(res["a"][0, :k0], res["b"][0, :k0], res["c_norm2"][0])
+    t_poles = time.perf_counter() - t0
+    top = np.argsort(rr)[::-1][:5]
+    poles = {"k": k0, "seconds": t_poles, "c_norm2": float(res["c_norm2"][0]),
+             "with_residue_above_1e-6_of_c_norm2": int((rr > 1e-6 * res["c_norm2"][0]).sum()),
+             "negative": int((th < 0).sum()),
+             "strongest": [{"theta": float(th[i]), "excitation_energy": float(np.sqrt(th[i])) if th[i] > 0 else None,
+                            "residue": float(rr[i])} for i in top]}
     out = {
         "metric": "spectrum points/s at 1e-6 rel err in Im alpha vs FP64 oracle",
         "value": passing / dt, "unit": "spectrum points/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -236,7 +247,7 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
                    "check_every": a.lz_check, "reorth": not a.lz_plain},
         "lanczos_steps": res["len"].tolist(), "lanczos_rc": int(res["rc"]),
         "us_per_lanczos_step": dt * 1e6 / max(int(res["len"].max()), 1),
-        "accuracy": acc, "roofline": roof, "cpu_baseline": None,
+        "accuracy": acc, "roofline": roof, "cpu_baseline": None, "poles": poles,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

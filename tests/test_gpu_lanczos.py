@@ -11,7 +11,9 @@ solve of eq. sle (chi0_oracle):
 * the first coefficients, element by element, on a 12-atom system (ragged
   tiles), with and without reorthogonalisation;
 * the converged spectrum against the LU solve to the 1e-6 floored relative
-  error of Im alpha, the error measure of the spectrum benchmark;
+  error of Im alpha, the error measure of the spectrum benchmark, and its ten
+  strongest poles against the eigenvalues of the oracle's Om2 and their
+  weights (c . u)^2;
 * graph replay of the (plain) steps is bit-identical to eager launches;
 * the two-level worked example ends after one step (invariant subspace),
   a zero drive gives length 0 and alpha = 0, and bad arguments are errors.
@@ -107,6 +109,17 @@ def test_converged_spectrum_meets_benchmark_error(reorth):
           f"floored Im err {err:.2e}, Re err {pins.rel(alpha.real, ref.real):.2e}", flush=True)
     assert err <= 1e-6
     assert alpha[0].imag == 0.0          # w = 0: z real, the continued fraction is real
+    # poles: the strongest ones are converged eigenvalues of Om2, with the
+    # weight (c . u)^2 of the oracle's eigenvector
+    from paper_1005_5340_amd import chi0
+    k = int(res["len"][0])
+    th, r = chi0.lanczos_poles(res["a"][0, :k], res["b"][0, :k], res["c_norm2"][0])
+    lam, U = np.linalg.eigh(lo.casida_matrix(sys))
+    wt = (U.T @ lo.start_vector(sys, d[0])) ** 2
+    for idx in np.argsort(r)[::-1][:10]:
+        m = np.argmin(np.abs(lam - th[idx]))
+        assert abs(lam[m] - th[idx]) <= 1e-9 * np.abs(lam).max(), (th[idx], lam[m])
+        assert abs(wt[m] - r[idx]) <= 1e-6 * res["c_norm2"][0], (r[idx], wt[m])
 
 
 def test_repeated_calls_identical():
