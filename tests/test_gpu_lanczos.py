@@ -198,4 +198,26 @@ def test_errors():
     res = ctx.lanczos(d, k_max=5)
     with pytest.raises(chi0.Chi0Error):
         ctx.lanczos_spectrum(res, [0.5], 0.0)
+    # a tolerance that k_max steps cannot meet: a warning, coefficients still written
+    res = ctx.lanczos(d, k_max=5, tol=1e-300, check_every=1, omega_check=[0.5], eps=sys.eps)
+    assert res["rc"] == chi0.NOT_CONVERGED and int(res["len"][0]) == 5
+    # k_max above the number of transitions is capped to it
+    T = sys.n_occ * (sys.n_orb - sys.n_occ)
+    res = ctx.lanczos(d, k_max=T + 50)
+    assert 1 <= int(res["len"][0]) <= T
+    ctx.close()
+
+
+def test_four_drives_match_single_recursions():
+    """A block of four recursions (nc = 4) equals four single ones, coefficient by coefficient."""
+    sys = gpu_systems.get("atoms12_orb9")
+    d = np.concatenate([sys.drives("xyz"), sys.drives("z") + 0.5 * sys.drives("x")])
+    print("[lanczos] four drives in one block", flush=True)
+    ctx = _ctx(sys)
+    blk = ctx.lanczos(d, k_max=40)
+    for s in range(4):
+        one = ctx.lanczos(d[s:s + 1], k_max=40)
+        assert np.abs(blk["a"][s] - one["a"][0]).max() <= 1e-10 * np.abs(one["a"][0]).max()
+        assert np.abs(blk["b"][s] - one["b"][0]).max() <= 1e-10 * np.abs(one["a"][0]).max()
+        np.testing.assert_allclose(blk["c_norm2"][s], one["c_norm2"][0], rtol=1e-12)
     ctx.close()
