@@ -59,6 +59,8 @@ KERNEL_SOURCES = {  # kernel -> source file that defines it (for the counter-sta
     "occ_transform": "kernels_gemm.hip", "occ_back": "kernels_gemm.hip",
     "vertex_gather": "kernels_vertex.hip", "vertex_contract": "kernels_vertex.hip",
     "vertex_reduce": "kernels_vertex.hip",
+    "lanczos_reorth_dots": "kernels_lanczos.hip", "lanczos_reorth_update": "kernels_lanczos.hip",
+    "casida_front": "kernels_gemm.hip",
 }
 
 
@@ -215,9 +217,12 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
         peak, unit = PEAK[bound]
         work = rec["bytes"] if bound == "hbm" else rec["flops"]
         scale = 1e9 if bound == "hbm" else 1e12
+        traffic = load_traffic(dom, a.workload) if not a.lz_plain else None
         roof = {"kernel": dom, "bound": "hbm" if bound == "hbm" else "mfma",
                 "achieved": work / (rec["ms"] * 1e-3) / scale, "peak": peak / scale, "unit": unit,
-                "frac": work / (rec["ms"] * 1e-3) / peak, "traffic": None,
+                "frac": work / (rec["ms"] * 1e-3) / peak, "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+                "traffic_over_algorithmic": (traffic / (work / rec["launches"])) if traffic else None,
                 "launches": rec["launches"], "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
                 "share_of_gpu_time": rec["ms"] / tot,
                 "note": "from the eager breakdown run (every kernel timed)"}

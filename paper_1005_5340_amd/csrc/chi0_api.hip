@@ -2029,13 +2029,13 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
     OpWork &ow = c->op[0];
     CHK(ensure_ws(c, ow, std::max(nc, ow.nc_cap)));
 
-    const int64_t tp = (int64_t)c->No_pad * c->Nv_pad, n = tp * nc;
+    const int64_t tp = (int64_t)c->No_pad * c->Nv_pad, tc = round_up((int64_t)c->No * c->Nv, 64), n = tc * nc;
     const int64_t nvec = ring ? 3 : (int64_t)kmax + 1;
     {
         size_t fr = 0, tot = 0;
         HIPCHK(c, hipMemGetInfo(&fr, &tot));
         const double need =
-            8.0 * (double)(nvec * n + 2 * tp + 66 * ((int64_t)kmax + 1) * nc + (ring ? 0 : LZ_GROUPS * n));
+            8.0 * (double)(nvec * n + 2 * tc + 66 * ((int64_t)kmax + 1) * nc + (ring ? 0 : LZ_GROUPS * n));
         if (need > 0.9 * (double)fr)
             return fail(c, CHI0_ENOMEM, "the Lanczos basis does not fit in free device memory (k_max too large "
                                         "for full reorthogonalisation)");
@@ -2045,8 +2045,8 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
     double *St = nullptr, *D2t = nullptr, *part2 = nullptr, *h = nullptr, *part3 = nullptr, *om = nullptr,
            *spec = nullptr;
     CHK(dalloc(c, ws.buf, &L.R, nvec * n));
-    CHK(dalloc(c, ws.buf, &St, tp));
-    CHK(dalloc(c, ws.buf, &D2t, tp));
+    CHK(dalloc(c, ws.buf, &St, tc));
+    CHK(dalloc(c, ws.buf, &D2t, tc));
     CHK(dalloc(c, ws.buf, &L.a, (int64_t)kmax * nc));
     CHK(dalloc(c, ws.buf, &L.b, (int64_t)kmax * nc));
     CHK(dalloc(c, ws.buf, &L.cn2, nc));
@@ -2064,7 +2064,12 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
         HIPCHK(c, hipMemcpyAsync(om, o.omega_check, (size_t)o.n_check * 8, hipMemcpyHostToDevice, s));
     }
     L.n = n;
+    L.tc = tc;
     L.tp = tp;
+    L.t_alg = (int64_t)c->No * c->Nv;
+    L.no = c->No;
+    L.nv = c->Nv;
+    L.no_pad = c->No_pad;
     L.ring = ring ? 1 : 0;
     L.passes = ring ? 0 : (o.reorth == CHI0_LZ_REORTH_FULL2 ? 2 : 1);
     L.nc = nc;
@@ -2074,7 +2079,7 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
     L.at = ow.at;
     launch_zero(&c->tracer, s, L.a, (int64_t)kmax * nc);
     launch_zero(&c->tracer, s, L.b, (int64_t)kmax * nc);
-    launch_lz_tables(s, c->Dlt, c->No, c->Nv, c->No_pad, c->Nv_pad, c->occ, St, D2t);
+    launch_lz_tables(s, c->Dlt, c->No, c->Nv, c->Nv_pad, tc, c->occ, St, D2t);
     // drives -> Zin [P_pad][nc] (padding rows zero), c = S V_t^T d
     {
         std::vector<double> zin((size_t)c->P_pad * nc, 0.0);

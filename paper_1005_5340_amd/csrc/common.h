@@ -246,15 +246,20 @@ void launch_store_x(hipStream_t s, const Job *jobs, int n, const SlotsDev &sl, i
 constexpr int LZ_BLOCKS = 1024;   // most workgroups of the recursion's vector kernels
 constexpr int LZ_GROUPS = 16;     // most vector groups of the reorthogonalisation update
 // One block of nc <= 4 Lanczos recursions on Om2 = D^2 + S V_t^T f V_t S.
-// Vectors are Tp x nc in the operator's `at` layout (Tp = Nv_pad * No_pad).
+// The recursion's vectors are compact, tc x nc: transition (F, E) in row
+// F * No + E (tc = No * Nv rounded up to 64, tail rows zero); the operator's
+// buffer `at` keeps its layout, tp = Nv_pad * No_pad rows, row F * No_pad + E.
 struct LanczosDev {
     double *R;             // basis: a ring of 3 vectors (ring = 1) or kmax + 1 vectors
-    int64_t n;             // doubles per vector, tp * nc
-    int64_t tp;            // transitions including padding
+    int64_t n;             // doubles per vector, tc * nc
+    int64_t tc;            // compact rows
+    int64_t tp;            // rows of `at`
+    int64_t t_alg;         // transitions, No * Nv (also the tracer's work counts)
+    int no, nv, no_pad;
     int ring, nc, kmax;
     int passes;            // Gram-Schmidt passes against the whole basis (0 with the ring)
-    const double *St;      // [tp] sqrt(2 n D), 0 on padding
-    const double *D2t;     // [tp] D^2, 0 on padding
+    const double *St;      // [tc] sqrt(2 n D), 0 on the tail
+    const double *D2t;     // [tc] D^2, 0 on the tail
     double *at;            // operator buffer: St q before the back half, V_t^T f V_t S q after the front half
     double *a, *b;         // [kmax][nc] recursion coefficients
     double *cn2;           // [nc] |c|^2
@@ -262,13 +267,13 @@ struct LanczosDev {
     int *step;             // current step (device counter)
     double *part;          // [LZ_BLOCKS][nc] partial sums
 };
-void launch_lz_tables(hipStream_t s, const double *Dlt, int No, int Nv, int no_pad, int nv_pad, double occ,
+void launch_lz_tables(hipStream_t s, const double *Dlt, int No, int Nv, int nv_pad, int64_t tc, double occ,
                       double *St, double *D2t);
 // after the front half of the operator applied to the drives: q_0 = c / |c|, at = St q_0
 void launch_lz_start(Tracer *t, hipStream_t s, const LanczosDev &L);
 // after an operator pass on at = St q_j: a_j, b_j, q_{j+1} and at = St q_{j+1};
 // without the ring, w is reorthogonalised against q_0..q_j (L.passes passes; j from the
-// host, part2 [64 * (kmax + 1) * nc], h [(kmax + 1) * nc], part3 [LZ_GROUPS * tp * nc]).
+// host, part2 [64 * (kmax + 1) * nc], h [(kmax + 1) * nc], part3 [LZ_GROUPS * tc * nc]).
 void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
                     double *part3);
 // alpha(omega) [n_omega][nc] complex from the first min(kuse, len[s]) coefficients

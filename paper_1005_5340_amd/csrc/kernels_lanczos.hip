@@ -14,9 +14,12 @@
 // operator's own kernels (the back half (b3), (b4), (d), then K, then the
 // front half (a), (b1), (b2)); this file holds the recursion's vector work.
 //
-// A block of nc <= 4 recursions (one per drive) runs together.  Transition
-// vectors use the operator's `at` layout: element (F, E, s) sits at
-// (F * No_pad + E) * nc + s.  The step index lives in device memory so that
+// A block of nc <= 4 recursions (one per drive) runs together.  The
+// recursion's vectors are compact: transition (F, E) is row F * No + E of
+// tc rows (No * Nv rounded up to 64, the tail kept at zero), sequence s in
+// column s, so the basis passes stream no padding.  The operator's buffer
+// `at` keeps its GEMM layout, row F * No_pad + E; the kernels that meet both
+// map one row index to the other.  The step index lives in device memory so that
 // one step's launch sequence can be replayed from a HIP graph.  Reductions
 // are deterministic: fixed-order per-workgroup sums, then one workgroup adds
 // the partials in a fixed order.
@@ -65,21 +68,26 @@ __device__ __forceinline__ double *lz_vec(const LanczosDev &L, int i) {
 
 }  // namespace
 
-// St = sqrt(2 n D), D2t = D^2 on the transitions, 0 on the padding; [Nv_pad][No_pad].
+// St = sqrt(2 n D), D2t = D^2 on the compact rows (0 on the tail).
 __global__ __launch_bounds__(256)
-void k_lz_tables(const double *__restrict__ Dlt, int No, int Nv, int no_pad, int nv_pad, double occ,
+void k_lz_tables(const double *__restrict__ Dlt, int No, int Nv, int nv_pad, int64_t tc, double occ,
                  double *__restrict__ St, double *__restrict__ D2t) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int64_t)no_pad * nv_pad) return;
-    const int F = (int)(idx / no_pad), E = (int)(idx % no_pad);
+    if (idx >= tc) return;
     double s = 0.0, d2 = 0.0;
-    if (E < No && F < Nv) {
+    if (idx < (int64_t)No * Nv) {
+        const int F = (int)(idx / No), E = (int)(idx % No);
         const double d = Dlt[(int64_t)E * nv_pad + F];
         s = sqrt(2.0 * occ * d);
         d2 = d * d;
     }
     St[idx] = s;
     D2t[idx] = d2;
+}
+
+// Row of `at` (GEMM layout) of compact row r < No * Nv.
+__device__ __forceinline__ int64_t lz_prow(const LanczosDev &L, int64_t r) {
+    return (r / L.no) * L.no_pad + r % L.no;
 }
 
 // Start: R[0] = St * at (c = S V_t^T d, the front half already applied to d);
@@ -89,11 +97,12 @@ __global__ __launch_bounds__(256)
 void k_lz_start(LanczosDev L) {
     double acc[NC] = {};
     double *q = lz_vec(L, 0);
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.t_alg; r += (int64_t)gridDim.x * 256) {
         const double st = L.St[r];
+        const int64_t rp = lz_prow(L, r);
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
-            const double v = st * L.at[r * NC + s];
+            const double v = st * L.at[rp * NC + s];
             q[r * NC + s] = v;
             acc[s] += v * v;
         }
@@ -116,6 +125,28 @@ void k_lz_start_fin(LanczosDev L, int nblk) {
     if (threadIdx.x == 0) *L.step = 0;
 }
 
+// q *= inv (per sequence) in place on the compact rows, and at = St * q on
+// every row of `at` (0 on its padding), one thread per row of `at`.
+template <int NC>
+__device__ __forceinline__ void lz_normalise_to_at(const LanczosDev &L, double *q, const double (&inv)[NC]) {
+    for (int64_t rp = (int64_t)blockIdx.x * 256 + threadIdx.x; rp < L.tp; rp += (int64_t)gridDim.x * 256) {
+        const int F = (int)(rp / L.no_pad), E = (int)(rp % L.no_pad);
+        if (E < L.no && F < L.nv) {
+            const int64_t r = (int64_t)F * L.no + E;
+            const double st = L.St[r];
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                const double v = q[r * NC + s] * inv[s];
+                q[r * NC + s] = v;
+                L.at[rp * NC + s] = st * v;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NC; ++s) L.at[rp * NC + s] = 0.0;
+        }
+    }
+}
+
 // q_0 = c / |c| in place; at = St * q_0 (input of the next operator pass).
 template <int NC>
 __global__ __launch_bounds__(256)
@@ -124,15 +155,7 @@ void k_lz_start_scale(LanczosDev L) {
 #pragma unroll
     for (int s = 0; s < NC; ++s) inv[s] = L.cn2[s] > 0.0 ? 1.0 / sqrt(L.cn2[s]) : 0.0;
     double *q = lz_vec(L, 0);
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
-        const double st = L.St[r];
-#pragma unroll
-        for (int s = 0; s < NC; ++s) {
-            const double v = q[r * NC + s] * inv[s];
-            q[r * NC + s] = v;
-            L.at[r * NC + s] = st * v;
-        }
-    }
+    lz_normalise_to_at<NC>(L, q, inv);
 }
 
 // Step j, after the operator pass: w = St * at + D2t * q_j (= Om2 q_j) into
@@ -144,12 +167,13 @@ void k_lz_combine(LanczosDev L) {
     const double *q = lz_vec(L, j);
     double *w = lz_vec(L, j + 1);
     double acc[NC] = {};
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.t_alg; r += (int64_t)gridDim.x * 256) {
         const double st = L.St[r], d2 = L.D2t[r];
+        const int64_t rp = lz_prow(L, r);
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             const double qv = q[r * NC + s];
-            const double v = st * L.at[r * NC + s] + d2 * qv;
+            const double v = st * L.at[rp * NC + s] + d2 * qv;
             w[r * NC + s] = v;
             acc[s] += qv * v;
         }
@@ -186,7 +210,7 @@ void k_lz_axpy(LanczosDev L) {
         bm[s] = j > 0 ? L.b[(int64_t)(j - 1) * NC + s] : 0.0;
     }
     double acc[NC] = {};
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tc; r += (int64_t)gridDim.x * 256) {
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             const double v = w[r * NC + s] - aj[s] * q[r * NC + s] - bm[s] * qm[r * NC + s];
@@ -229,15 +253,7 @@ void k_lz_scale(LanczosDev L) {
         const double bj = L.b[(int64_t)j * NC + s];
         inv[s] = bj > 0.0 ? 1.0 / bj : 0.0;
     }
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
-        const double st = L.St[r];
-#pragma unroll
-        for (int s = 0; s < NC; ++s) {
-            const double v = w[r * NC + s] * inv[s];
-            w[r * NC + s] = v;
-            L.at[r * NC + s] = st * v;
-        }
-    }
+    lz_normalise_to_at<NC>(L, w, inv);
 }
 
 // Full reorthogonalisation: classical Gram-Schmidt passes against q_0..q_j.
@@ -277,8 +293,8 @@ void k_lz_dots(LanczosDev L, int nq, int nsplit, double *part2) {
 #pragma unroll
         for (int s = 0; s < NC; ++s) acc[s] = (s == sa ? x : 0.0) + (s == sb ? y : 0.0);
     } else {
-        const int64_t chunk = (L.tp + nsplit - 1) / nsplit;
-        const int64_t r0 = rs * chunk, r1 = min(L.tp, r0 + chunk);
+        const int64_t chunk = (L.tc + nsplit - 1) / nsplit;
+        const int64_t r0 = rs * chunk, r1 = min(L.tc, r0 + chunk);
 #pragma unroll 4
         for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
 #pragma unroll
@@ -341,7 +357,7 @@ void k_lz_update_part(LanczosDev L, int nq, int ngroup, const double *__restrict
         *reinterpret_cast<double2 *>(part3 + (int64_t)g * L.n + 2 * u) = make_double2(x, y);
     } else {
         const int64_t r = u;
-        if (r >= L.tp) return;
+        if (r >= L.tc) return;
         double acc[NC] = {};
         for (int i = i0; i < i1; ++i)
 #pragma unroll
@@ -358,7 +374,7 @@ void k_lz_update_fin(LanczosDev L, int ngroup, const double *__restrict__ part3)
     const int j = *L.step - 1;
     double *w = lz_vec(L, j + 1);
     double acc[NC] = {};
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tp; r += (int64_t)gridDim.x * 256) {
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < L.tc; r += (int64_t)gridDim.x * 256) {
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             double sub = 0.0;
@@ -409,7 +425,7 @@ void k_lz_cfrac(const double *__restrict__ a, const double *__restrict__ b, int 
 // ------------------------------------------------------------------ launches
 namespace {
 int lz_blocks(const LanczosDev &L) {
-    int64_t b = (L.tp + 255) / 256;
+    int64_t b = (std::max(L.tp, L.tc) + 255) / 256;
     return (int)std::min<int64_t>(std::max<int64_t>(b, 1), LZ_BLOCKS);
 }
 }  // namespace
@@ -422,11 +438,10 @@ int lz_blocks(const LanczosDev &L) {
     default: CALL(4); break;   \
     }
 
-void launch_lz_tables(hipStream_t s, const double *Dlt, int No, int Nv, int no_pad, int nv_pad, double occ,
+void launch_lz_tables(hipStream_t s, const double *Dlt, int No, int Nv, int nv_pad, int64_t tc, double occ,
                       double *St, double *D2t) {
-    const int64_t n = (int64_t)no_pad * nv_pad;
-    hipLaunchKernelGGL(k_lz_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Dlt, No, Nv, no_pad,
-                       nv_pad, occ, St, D2t);
+    hipLaunchKernelGGL(k_lz_tables, dim3((unsigned)((tc + 255) / 256)), dim3(256), 0, s, Dlt, No, Nv, nv_pad, tc,
+                       occ, St, D2t);
 }
 
 void launch_lz_start(Tracer *t, hipStream_t s, const LanczosDev &L) {
@@ -438,30 +453,31 @@ void launch_lz_start(Tracer *t, hipStream_t s, const LanczosDev &L) {
     hipLaunchKernelGGL(k_lz_start_scale<N>, dim3(g), dim3(256), 0, s, L);
     LZ_NC_SWITCH(L.nc, C)
 #undef C
-    trace_end(t, s, 0.0, 8.0 * L.n * 4);
+    trace_end(t, s, 0.0, 8.0 * (double)L.t_alg * L.nc * 4);
 }
 
 void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
                     double *part3) {
     const int g = lz_blocks(L);
-    const double vb = 8.0 * (double)L.n;   // one transition vector
+    // algorithmic work on unpadded transitions: one vector of the block is 8 T nc bytes
+    const double ta = (double)L.t_alg * L.nc, vb = 8.0 * ta;
     trace_begin(t, "lanczos_combine", s);
 #define C(N)                                                                   \
     hipLaunchKernelGGL(k_lz_combine<N>, dim3(g), dim3(256), 0, s, L);          \
     hipLaunchKernelGGL(k_lz_alpha<N>, dim3(1), dim3(256), 0, s, L, g);
     LZ_NC_SWITCH(L.nc, C)
 #undef C
-    trace_end(t, s, 4.0 * L.n, 3.0 * vb + 16.0 * L.tp);
+    trace_end(t, s, 4.0 * ta, 3.0 * vb + 16.0 * L.t_alg);
     trace_begin(t, "lanczos_axpy", s);
 #define C(N) hipLaunchKernelGGL(k_lz_axpy<N>, dim3(g), dim3(256), 0, s, L);
     LZ_NC_SWITCH(L.nc, C)
 #undef C
-    trace_end(t, s, 6.0 * L.n, 4.0 * vb);
+    trace_end(t, s, 6.0 * ta, 4.0 * vb);
     if (!L.ring) {
         // classical Gram-Schmidt pass(es) against q_0..q_j (j known on the host)
         const int nq = j + 1;
         const int nsplit = std::max(1, std::min(64, 2048 / nq));
-        const unsigned rblocks = (unsigned)(((L.nc == 3 ? L.tp : L.n / 2) + 255) / 256);
+        const unsigned rblocks = (unsigned)(((L.nc == 3 ? L.tc : L.n / 2) + 255) / 256);
         const int ngroup = std::max(1, std::min(LZ_GROUPS, nq / 64));
         for (int pass = 0; pass < L.passes; ++pass) {
             trace_begin(t, "lanczos_reorth_dots", s);
@@ -471,14 +487,14 @@ void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double
                        nsplit, h);
             LZ_NC_SWITCH(L.nc, C)
 #undef C
-            trace_end(t, s, 2.0 * L.n * nq, vb * (nq + 1));
+            trace_end(t, s, 2.0 * ta * nq, vb * (nq + 1));
             trace_begin(t, "lanczos_reorth_update", s);
 #define C(N)                                                                                                   \
     hipLaunchKernelGGL(k_lz_update_part<N>, dim3(rblocks, ngroup), dim3(256), 0, s, L, nq, ngroup, h, part3); \
     hipLaunchKernelGGL(k_lz_update_fin<N>, dim3(g), dim3(256), 0, s, L, ngroup, part3);
             LZ_NC_SWITCH(L.nc, C)
 #undef C
-            trace_end(t, s, 2.0 * L.n * nq, vb * (nq + 2));
+            trace_end(t, s, 2.0 * ta * nq, vb * (nq + 2));
         }
     }
     trace_begin(t, "lanczos_scale", s);
@@ -487,7 +503,7 @@ void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double
     hipLaunchKernelGGL(k_lz_scale<N>, dim3(g), dim3(256), 0, s, L);
     LZ_NC_SWITCH(L.nc, C)
 #undef C
-    trace_end(t, s, 2.0 * L.n, 3.0 * vb + 8.0 * L.tp);
+    trace_end(t, s, 2.0 * ta, 3.0 * vb + 8.0 * L.t_alg);
 }
 
 void launch_lz_cfrac(hipStream_t s, const double *a, const double *b, int nc, int kuse, const int *len,
