@@ -197,6 +197,8 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / a.steps
     npts = omegas.size * drives.shape[0]
+    if a.dump_alpha:
+        np.save(a.dump_alpha, alpha)
     acc = {"checked": False}
     passing = npts
     if ref is not None and np.all(np.isin(ref_idx, grid)):
@@ -293,6 +295,10 @@ def main():
     ap.add_argument("--lanczos", action="store_true",
                     help="the spectrum from one Lanczos recursion per drive in transition space instead of "
                          "a GMRES solve per frequency (same workload, error measure and JSON line)")
+    ap.add_argument("--n-omega", type=int, default=0,
+                    help="solve this many frequencies, evenly spaced on the workload's interval, instead of its "
+                         "grid (accuracy then unchecked)")
+    ap.add_argument("--dump-alpha", default="", help="save the computed alpha (diagonal, [n_omega][drive]) as .npy")
     ap.add_argument("--lz-kmax", type=int, default=12000, help="Lanczos: most steps")
     ap.add_argument("--lz-tol", type=float, default=1e-8,
                     help="Lanczos: stop when the spectrum on the grid moves by at most this between checks")
@@ -353,6 +359,10 @@ def main():
         k = max(1, a.omega_sample - extra.size)
         grid = np.unique(np.concatenate([np.round(np.linspace(0, s.omegas.size - 1, k)).astype(int), extra]))
     omegas = s.omegas[grid]
+    if a.n_omega:   # a denser inclusive grid on the same interval (no stored reference for it)
+        omegas = np.linspace(0.0, w.omega_max, a.n_omega)
+        grid = np.arange(a.n_omega)
+        ref = None
 
     if a.lanczos:
         return lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx,
@@ -422,6 +432,8 @@ def main():
 
     npts = omegas.size * drives.shape[0]
     diag = np.stack([alpha[:, i, i] for i in range(drives.shape[0])], 1)
+    if a.dump_alpha:
+        np.save(a.dump_alpha, diag)
     if ref is not None and not np.all(np.isin(ref_idx, grid)):
         ref = None      # a reference for frequencies this run did not solve
     if ref is not None:
