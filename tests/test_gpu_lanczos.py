@@ -14,6 +14,8 @@ solve of eq. sle (chi0_oracle):
   error of Im alpha, the error measure of the spectrum benchmark, and its ten
   strongest poles against the eigenvalues of the oracle's Om2 and their
   weights (c . u)^2;
+* the device continued fraction against the oracle's dense solve with T_k;
+* the 60-atom benchmark workload against the stored oracle spectrum;
 * graph replay of the (plain) steps is bit-identical to eager launches;
 * the two-level worked example ends after one step (invariant subspace),
   a zero drive gives length 0 and alpha = 0, and bad arguments are errors.
@@ -120,6 +122,44 @@ def test_converged_spectrum_meets_benchmark_error(reorth):
         m = np.argmin(np.abs(lam - th[idx]))
         assert abs(lam[m] - th[idx]) <= 1e-9 * np.abs(lam).max(), (th[idx], lam[m])
         assert abs(wt[m] - r[idx]) <= 1e-6 * res["c_norm2"][0], (r[idx], wt[m])
+
+
+def test_continued_fraction_matches_dense_solve():
+    """chi0_lanczos_spectrum (the device continued fraction) against the oracle's dense
+    solve with T_k for the same coefficients, three drives, frequencies of both signs."""
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("xyz")
+    print("[lanczos] continued fraction vs dense solve", flush=True)
+    ctx = _ctx(sys)
+    res = ctx.lanczos(d, k_max=200)
+    om = np.concatenate([np.linspace(0.0, 2.0, 41), [-0.7, 5.0]])
+    got = ctx.lanczos_spectrum(res, om, sys.eps)
+    ctx.close()
+    for s in range(3):
+        k = int(res["len"][s])
+        ref = lo.spectrum(res["a"][s, :k], res["b"][s, :k], res["c_norm2"][s], om, sys.eps)
+        assert np.abs(got[:, s] - ref).max() <= 1e-11 * np.abs(ref).max(), s
+
+
+def test_full_size_spectrum_against_stored_reference():
+    """The 60-atom workload (T = 72 000) as the benchmark runs it: every point of the
+    stored oracle spectrum within 1e-6 (floored Im alpha), and alpha(0) real."""
+    import json
+    from pathlib import Path
+    sys = synth.make_system("atoms60_orb9", seed=0)
+    g = json.load(open(Path(__file__).parent / "golden" / "reference_atoms60_orb9_s0.json"))
+    assert synth.same_inputs(sys, g["fingerprint"])
+    ref = (np.array(g["alpha_re"]) + 1j * np.array(g["alpha_im"]))[:, 0, 0]
+    om = sys.omegas[np.asarray(g["omega_index"], int)]
+    print("[lanczos] atoms60_orb9 full spectrum", flush=True)
+    ctx = _ctx(sys)
+    res = ctx.lanczos(sys.drives("z"), k_max=12000, tol=1e-7, check_every=100, omega_check=om, eps=sys.eps)
+    alpha = ctx.lanczos_spectrum(res, om, sys.eps)[:, 0]
+    ctx.close()
+    err = _floored_err(alpha, ref)
+    print(f"[lanczos] steps {int(res['len'][0])}, floored Im err {err:.2e}", flush=True)
+    assert res["rc"] == 0 and err <= 1e-6
+    assert alpha[om == 0.0].imag.tolist() == [0.0] * int((om == 0.0).sum())
 
 
 def test_repeated_calls_identical():
