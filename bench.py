@@ -232,6 +232,23 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
         for k, v in sorted(ks_all.items(), key=lambda kv: -kv[1]["ms"]):
             print(f"[bench] {k:30s} {int(v['launches']):8d} {v['ms']:9.2f} {100 * v['ms'] / tot:6.1f}%",
                   file=sys.stderr)
+    sol = None
+    if a.lz_solutions and not a.lz_plain:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = ctx.lanczos(drives, k_max=a.lz_kmax, reorth=reorth, tol=a.lz_tol, check_every=a.lz_check,
+                         omega_check=omegas, eps=s.eps, omega_x=omegas)
+        t_all = time.perf_counter() - t0
+        diag_x = np.stack([rs["alpha_x"][:, i, i] for i in range(drives.shape[0])], 1)
+        sol = {"seconds_with_recursion": t_all, "seconds_solutions": t_all - dt, "n_x": int(omegas.size),
+               "max_rel_diff_alpha_x_vs_continued_fraction": float(np.max(np.abs(diag_x - alpha)) /
+                                                                    np.max(np.abs(alpha)))}
+        if acc.get("checked"):
+            dx = diag_x[np.searchsorted(grid, ref_idx)]
+            ex = np.stack([im_errors(dx[:, i], rdiag[:, i]) for i in range(drives.shape[0])], 1)
+            sol["max_im_rel_err_alpha_x"] = float(ex.max())
+        print(f"[bench] solutions at {omegas.size} frequencies: {t_all:.3f} s with the recursion",
+              file=sys.stderr, flush=True)
     # poles and residues of the first drive's recursion (host, after the timed region)
     k0 = int(res["len"][0])
     t0 = time.perf_counter()
@@ -254,7 +271,7 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
                    "check_every": a.lz_check, "reorth": not a.lz_plain},
         "lanczos_steps": res["len"].tolist(), "lanczos_rc": int(res["rc"]),
         "us_per_lanczos_step": dt * 1e6 / max(int(res["len"].max()), 1),
-        "accuracy": acc, "roofline": roof, "cpu_baseline": None, "poles": poles,
+        "accuracy": acc, "roofline": roof, "cpu_baseline": None, "poles": poles, "solutions": sol,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
@@ -303,6 +320,9 @@ def main():
     ap.add_argument("--lz-tol", type=float, default=1e-8,
                     help="Lanczos: stop when the spectrum on the grid moves by at most this between checks")
     ap.add_argument("--lz-check", type=int, default=100, help="Lanczos: steps between convergence checks")
+    ap.add_argument("--lz-solutions", action="store_true",
+                    help="Lanczos: also the solutions x(w) and the alpha tensor at every grid frequency "
+                         "(after the timed steps, timed on their own)")
     ap.add_argument("--lz-plain", action="store_true",
                     help="Lanczos: no reorthogonalisation (three-term recurrence only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

@@ -344,7 +344,14 @@ typedef struct chi0_lanczos_opts {
     double  eps;          /* broadening of the checks, Ha (> 0 when n_check > 0) */
     int32_t graph;        /* 1: after the first step, replay each step's launch sequence from one
                              HIP graph (CHI0_LZ_REORTH_NONE, timing off); 0 (default): launch eagerly */
-    int32_t reserved[3];  /* must be zero */
+    int32_t n_x;          /* > 0: also the solutions of eq. sle at n_x frequencies (needs a stored
+                             basis, i.e. CHI0_LZ_REORTH_FULL or _FULL2, and eps > 0) */
+    const double *omega_x;   /* host [n_x], Ha */
+    double *x;            /* host [n_x][n_drive][n_prod] complex, or NULL: x_i(w) = -B Q_k y(w),
+                             B = V_t S, y = |c_i| (T_k - (w + i eps)^2)^-1 e_1, k = len[i] */
+    double *alpha_x;      /* host [n_x][n_drive][n_drive] complex, or NULL: the full tensor
+                             alpha_ki(w) = -d_k . x_i(w) (eq. eqpolarizability, alpha = -P) */
+    int32_t reserved[2];  /* must be zero */
 } chi0_lanczos_opts;
 
 /* Three-term recurrence only: three transition vectors in device memory.  The

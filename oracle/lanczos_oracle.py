@@ -25,7 +25,10 @@ diagonal b) with
 
 for every w at once; the eigenvalues theta_j of T_k approximate the poles of
 alpha in (w + i eps)^2 and |c|^2 (u_j)_1^2 their residues.  At k = T (or at an
-invariant subspace) the recursion is exact.
+invariant subspace) the recursion is exact.  The solution of eq. sle itself is
+X(w) = -B (Om2 - (w + i eps)^2)^-1 c with B = V_t S (the push-through identity
+applied to chi0 = -B diag(D^2 - z)^-1 B^T), which the Krylov basis Q_k
+approximates as -|c| B Q_k (T_k - z)^-1 e_1.
 
 Everything here is written out from those definitions: the dense Om2, the
 start vector, Lanczos with classical Gram-Schmidt against the whole basis
@@ -38,7 +41,7 @@ import numpy as np
 
 from . import chi0_oracle as co
 
-__all__ = ["casida_parts", "casida_matrix", "start_vector", "lanczos", "spectrum", "poles"]
+__all__ = ["casida_parts", "casida_matrix", "start_vector", "lanczos", "spectrum", "poles", "pole_form_solution"]
 
 
 def casida_parts(sys):
@@ -122,3 +125,13 @@ def poles(a, b, cn2: float):
     """Eigenvalues theta of T_k (ascending) and residues |c|^2 (u_j)_1^2."""
     theta, U = np.linalg.eigh(tridiagonal(a, b))
     return theta, cn2 * U[0] ** 2
+
+
+def pole_form_solution(sys, omega: float, drive, eps: float | None = None) -> np.ndarray:
+    """X(w) = -B (Om2 - (w + i eps)^2)^-1 c by a dense solve in transition space."""
+    eps = sys.eps if eps is None else eps
+    S, D2, B = casida_parts(sys)
+    Om2 = np.diag(D2) + B.T @ sys.K @ B
+    c = B.T @ np.asarray(drive, float)
+    z = (omega + 1j * eps) ** 2
+    return -B @ np.linalg.solve(Om2 - z * np.eye(Om2.shape[0]), c)

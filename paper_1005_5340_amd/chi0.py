@@ -59,7 +59,8 @@ class PointStats(C.Structure):
 class LanczosOpts(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("reorth", C.c_int32), ("tol", C.c_double),
                 ("check_every", C.c_int32), ("n_check", C.c_int32), ("omega_check", _dp),
-                ("eps", C.c_double), ("graph", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("eps", C.c_double), ("graph", C.c_int32), ("n_x", C.c_int32), ("omega_x", _dp),
+                ("x", _dp), ("alpha_x", _dp), ("reserved", C.c_int32 * 2)]
 
 
 class TuneRecord(C.Structure):
@@ -321,27 +322,39 @@ class Context:
         return a, stats, rc
 
     def lanczos(self, drives, k_max: int = 4000, reorth: int = LZ_REORTH_FULL, tol: float = 0.0,
-                check_every: int = 100, omega_check=None, eps: float = 0.0, graph: bool = False) -> dict:
+                check_every: int = 100, omega_check=None, eps: float = 0.0, graph: bool = False,
+                omega_x=None) -> dict:
         """Lanczos recursion in transition space for 1..4 drives [n_drive][n_prod] (chi0_lanczos).
 
-        Returns dict(a, b: [n_drive][k_max], c_norm2: [n_drive], len: [n_drive], rc)."""
+        Returns dict(a, b: [n_drive][k_max], c_norm2: [n_drive], len: [n_drive], rc); with
+        omega_x also x [n_x][n_drive][n_prod] and alpha_x [n_x][n_drive][n_drive] complex."""
         d = _f64(drives)
         d = d.reshape(-1, d.shape[-1])
         nd = d.shape[0]
         om = None if omega_check is None else _f64(omega_check).ravel()
+        omx = None if omega_x is None else _f64(omega_x).ravel()
         o = LanczosOpts()
         self._L.chi0_lanczos_opts_default(C.byref(o))
         o.k_max, o.reorth, o.tol, o.check_every = int(k_max), int(reorth), float(tol), int(check_every)
         o.n_check = 0 if om is None else int(om.size)
         o.omega_check = _ptr(om)
         o.eps, o.graph = float(eps), int(bool(graph))
+        x = ax = None
+        if omx is not None:
+            x = np.zeros((omx.size, nd, d.shape[-1], 2))
+            ax = np.zeros((omx.size, nd, nd, 2))
+            o.n_x, o.omega_x, o.x, o.alpha_x = int(omx.size), _ptr(omx), _ptr(x), _ptr(ax)
         a = np.zeros((nd, max(int(k_max), 1)))
         b = np.zeros_like(a)
         cn2 = np.zeros(nd)
         ln = np.zeros(nd, np.int32)
         rc = self._check(self._L.chi0_lanczos(self._h, nd, _ptr(d), C.byref(o), _ptr(a), _ptr(b), _ptr(cn2),
                                               _ptr(ln, _i32p)), allow_warning=True)
-        return dict(a=a, b=b, c_norm2=cn2, len=ln, rc=rc)
+        out = dict(a=a, b=b, c_norm2=cn2, len=ln, rc=rc)
+        if omx is not None:
+            out["x"] = x[..., 0] + 1j * x[..., 1]
+            out["alpha_x"] = ax[..., 0] + 1j * ax[..., 1]
+        return out
 
     def lanczos_spectrum(self, res: dict, omega, eps: float) -> np.ndarray:
         """alpha_k(omega) [n_omega][n_drive] complex from a lanczos() result (chi0_lanczos_spectrum)."""

@@ -1906,8 +1906,8 @@ void lz_front(chi0_ctx *c, OpWork &o, hipStream_t s, int nc) {
                  o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
 }
 
-// at (transition layout) -> Yout = V_t at [P_pad][nc], then Zin = K Yout
-void lz_back_k(chi0_ctx *c, OpWork &o, hipStream_t s, int nc) {
+// at (transition layout) -> Yout = V_t at [P_pad][nc]
+void lz_back(chi0_ctx *c, OpWork &o, hipStream_t s, int nc) {
     Tracer *t = &c->tracer;
     const WorkSizes &w = c->ws;
     const int64_t mcol = (int64_t)c->No_pad * nc;
@@ -1916,7 +1916,12 @@ void lz_back_k(chi0_ctx *c, OpWork &o, hipStream_t s, int nc) {
                  o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
     launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, o.Ut, o.W, nc, w);
     launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, o.W, o.part, o.Yout, nc, w, c->max_nprod);
-    launch_kmatvec_skinny(t, s, c->P_pad, c->K, o.Yout, o.Zin, nc, (double)c->P);
+}
+
+// the back half, then Zin = K Yout
+void lz_back_k(chi0_ctx *c, OpWork &o, hipStream_t s, int nc) {
+    lz_back(c, o, s, nc);
+    launch_kmatvec_skinny(&c->tracer, s, c->P_pad, c->K, o.Yout, o.Zin, nc, (double)c->P);
 }
 
 // Eigenvalues of the symmetric tridiagonal matrix (d, e) and the first row of
@@ -2018,6 +2023,13 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
     if (o.n_check > 0 && !all_finite(o.omega_check, o.n_check))
         return fail(c, CHI0_ENONFINITE, "non-finite check frequency");
     if (o.graph != 0 && o.graph != 1) return fail(c, CHI0_EINVAL, "graph must be 0 or 1");
+    if (o.n_x < 0 || (o.n_x > 0 && (!o.omega_x || (!o.x && !o.alpha_x))))
+        return fail(c, CHI0_EINVAL, "bad solution frequencies or outputs");
+    if (o.n_x > 0 && o.reorth == CHI0_LZ_REORTH_NONE)
+        return fail(c, CHI0_EINVAL, "solutions need the stored basis of a reorthogonalised recursion");
+    if (o.n_x > 0 && (!(o.eps > 0.0) || !std::isfinite(o.eps)))
+        return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
+    if (o.n_x > 0 && !all_finite(o.omega_x, o.n_x)) return fail(c, CHI0_ENONFINITE, "non-finite solution frequency");
     for (int32_t r : o.reserved)
         if (r != 0) return fail(c, CHI0_EINVAL, "reserved fields must be zero");
     const int P = c->P, nc = n_drive;
@@ -2027,7 +2039,8 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
     const int kmax = (int)std::min<int64_t>(o.k_max, (int64_t)c->No * c->Nv);
     const bool ring = o.reorth == CHI0_LZ_REORTH_NONE;
     OpWork &ow = c->op[0];
-    CHK(ensure_ws(c, ow, std::max(nc, ow.nc_cap)));
+    // the operator passes of the solutions carry 2 LZ_XCOL real columns
+    CHK(ensure_ws(c, ow, std::max({nc, ow.nc_cap, o.n_x > 0 ? 2 * LZ_XCOL : 0})));
 
     const int64_t tp = (int64_t)c->No_pad * c->Nv_pad, tc = round_up((int64_t)c->No * c->Nv, 64), n = tc * nc;
     const int64_t nvec = ring ? 3 : (int64_t)kmax + 1;
@@ -2035,7 +2048,8 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
         size_t fr = 0, tot = 0;
         HIPCHK(c, hipMemGetInfo(&fr, &tot));
         const double need =
-            8.0 * (double)(nvec * n + 2 * tc + 66 * ((int64_t)kmax + 1) * nc + (ring ? 0 : LZ_GROUPS * n));
+            8.0 * (double)(nvec * n + 2 * tc + 66 * ((int64_t)kmax + 1) * nc + (ring ? 0 : LZ_GROUPS * n) +
+                           (o.n_x > 0 ? (int64_t)kmax * LZ_XCOL * 6 + (int64_t)P * (nc + 2 * LZ_XCOL) : 0));
         if (need > 0.9 * (double)fr)
             return fail(c, CHI0_ENOMEM, "the Lanczos basis does not fit in free device memory (k_max too large "
                                         "for full reorthogonalisation)");
@@ -2057,6 +2071,16 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
         CHK(dalloc(c, ws.buf, &part2, (int64_t)64 * (kmax + 1) * nc));
         CHK(dalloc(c, ws.buf, &h, (int64_t)(kmax + 1) * nc));
         CHK(dalloc(c, ws.buf, &part3, (int64_t)LZ_GROUPS * n));
+    }
+    double *xdw = nullptr, *xY = nullptr, *xom = nullptr, *xdrv = nullptr, *xrows = nullptr, *xalpha = nullptr;
+    if (o.n_x > 0) {
+        CHK(dalloc(c, ws.buf, &xdw, (int64_t)kmax * LZ_XCOL * 4));
+        CHK(dalloc(c, ws.buf, &xY, (int64_t)kmax * LZ_XCOL * 2));
+        CHK(dalloc(c, ws.buf, &xom, LZ_XCOL));
+        CHK(dalloc(c, ws.buf, &xdrv, (int64_t)nc * P));
+        CHK(dalloc(c, ws.buf, &xrows, (int64_t)LZ_XCOL * P * 2));
+        CHK(dalloc(c, ws.buf, &xalpha, (int64_t)LZ_XCOL * nc * 2));
+        HIPCHK(c, hipMemcpy(xdrv, drives, (size_t)nc * P * 8, hipMemcpyHostToDevice));
     }
     if (o.n_check > 0) {
         CHK(dalloc(c, ws.buf, &om, o.n_check));
@@ -2183,6 +2207,33 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
             a_out[(size_t)sq * o.k_max + j] = j < ln ? ah[(size_t)j * nc + sq] : 0.0;
             b_out[(size_t)sq * o.k_max + j] = j < ln ? bh[(size_t)j * nc + sq] : 0.0;
         }
+    }
+    if (o.n_x > 0) {
+        // solutions of eq. sle from the stored basis, W frequencies per operator pass
+        int kuse = 0;
+        for (int sq = 0; sq < nc; ++sq) kuse = std::max(kuse, std::min(lenh[sq], steps));
+        const int W = LZ_XCOL / nc, M = W * nc;
+        std::vector<double> omb(W);
+        for (int p0 = 0; p0 < o.n_x; p0 += W) {
+            const int nw = std::min(W, o.n_x - p0);
+            for (int w = 0; w < W; ++w) omb[w] = o.omega_x[p0 + std::min(w, nw - 1)];
+            HIPCHK(c, hipMemcpyAsync(xom, omb.data(), W * 8, hipMemcpyHostToDevice, s));
+            if (kuse > 0) {
+                launch_lz_solution_cols(&c->tracer, s, L, kuse, L.len, xom, nw, o.eps, xdw, xY, ow.at);
+                lz_back(c, ow, s, 2 * M);
+            } else {
+                launch_zero(&c->tracer, s, ow.Yout, (int64_t)c->P_pad * 2 * M);
+            }
+            launch_lz_solution_out(s, ow.Yout, nc, nw, P, xdrv, o.x ? xrows : nullptr, o.alpha_x ? xalpha : nullptr);
+            if (o.x)
+                HIPCHK(c, hipMemcpyAsync(o.x + (size_t)p0 * nc * P * 2, xrows, (size_t)nw * nc * P * 16,
+                                         hipMemcpyDeviceToHost, s));
+            if (o.alpha_x)
+                HIPCHK(c, hipMemcpyAsync(o.alpha_x + (size_t)p0 * nc * nc * 2, xalpha, (size_t)nw * nc * nc * 16,
+                                         hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+        }
+        HIPCHK(c, hipGetLastError());
     }
     if (o.tol > 0.0 && !converged && !all_ended) return CHI0_NOT_CONVERGED;
     return CHI0_OK;

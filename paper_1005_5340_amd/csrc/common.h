@@ -276,6 +276,17 @@ void launch_lz_start(Tracer *t, hipStream_t s, const LanczosDev &L);
 // host, part2 [64 * (kmax + 1) * nc], h [(kmax + 1) * nc], part3 [LZ_GROUPS * tc * nc]).
 void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
                     double *part3);
+// Solutions of eq. sle from the stored basis, LZ_XCOL / nc frequencies per pass
+// (omega [LZ_XCOL / nc], nw of them valid): y = |c| (T_k - z)^-1 e_1 (dw
+// [kuse][LZ_XCOL][4], Y [kuse][LZ_XCOL] complex), then at = St Q_k y in the
+// operator's layout with 2 (LZ_XCOL / nc) nc real columns, for the back half.
+constexpr int LZ_XCOL = 16;
+void launch_lz_solution_cols(Tracer *t, hipStream_t s, const LanczosDev &L, int kuse, const int *len,
+                             const double *omega, int nw, double eps, double *dw, double *Y, double *at);
+// From Yb = B Q_k y [P_pad][2M]: x rows [nw][nc][P] complex (= -Yb) and alpha [nw][nc][nc]
+// complex (alpha_ki = -d_k . x_i; drives [nc][P]); either output may be NULL.
+void launch_lz_solution_out(hipStream_t s, const double *Yb, int nc, int nw, int P, const double *drives,
+                            double *x_rows, double *alpha);
 // alpha(omega) [n_omega][nc] complex from the first min(kuse, len[s]) coefficients
 void launch_lz_cfrac(hipStream_t s, const double *a, const double *b, int nc, int kuse, const int *len,
                      const double *cn2, const double *omega, int n_omega, double eps, double *out);

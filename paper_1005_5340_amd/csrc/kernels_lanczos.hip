@@ -422,6 +422,148 @@ void k_lz_cfrac(const double *__restrict__ a, const double *__restrict__ b, int 
     out[2 * (int64_t)idx + 1] = im;
 }
 
+// ------------------------------------------------------- solutions of eq. sle
+// x_i(w) = -B (Om2 - z)^-1 c_i with B = V_t S, approximated in the Krylov basis
+// as -B Q_k y, y = |c_i| (T_k - z)^-1 e_1, z = (w + i eps)^2.  LZ_XW frequencies
+// per pass, LZ_XW / NC... columns: column m = w * NC + s of sequence s.
+
+// y for every (frequency w, sequence s) of a pass: T_k - z is complex symmetric
+// tridiagonal with Im z > 0 for w > 0, so elimination without pivoting keeps
+// every pivot's imaginary part <= -Im z (never zero).  Forward pivots and
+// right-hand side in dw, then back substitution into Y[i][m] (complex), zero for
+// i >= len[s] up to kuse.
+__global__ __launch_bounds__(64)
+void k_lz_tsolve(const double *__restrict__ a, const double *__restrict__ b, int nc, int kuse,
+                 const int *__restrict__ len, const double *__restrict__ cn2, const double *__restrict__ omega,
+                 int nw, double eps, double *__restrict__ dw, double *__restrict__ Y) {
+    const int m = blockIdx.x * 64 + threadIdx.x, ncol = nw * nc;
+    if (m >= ncol) return;
+    const int w = m / nc, s = m % nc;
+    const int k = min(kuse, len[s]);
+    const double om = omega[w];
+    const double zr = om * om - eps * eps, zi = 2.0 * om * eps;
+    // dw[i] = (d_r, d_i, g_r, g_i) of row i
+    double dr = 0.0, di = 0.0, gr = 0.0, gi = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double ai = a[(int64_t)i * nc + s];
+        if (i == 0) {
+            dr = ai - zr;
+            di = -zi;
+            gr = sqrt(cn2[s]);
+            gi = 0.0;
+        } else {
+            const double bb = b[(int64_t)(i - 1) * nc + s];
+            // l = bb / d_{i-1};  d_i = a_i - z - l bb;  g_i = -l g_{i-1}
+            const double m2 = dr * dr + di * di;
+            const double lr = bb * dr / m2, li = -bb * di / m2;
+            const double ngr = -(lr * gr - li * gi), ngi = -(lr * gi + li * gr);
+            dr = ai - zr - lr * bb;
+            di = -zi - li * bb;
+            gr = ngr;
+            gi = ngi;
+        }
+        double *p = dw + ((int64_t)i * ncol + m) * 4;
+        p[0] = dr;
+        p[1] = di;
+        p[2] = gr;
+        p[3] = gi;
+    }
+    double yr = 0.0, yi = 0.0;   // y_{i+1}
+    for (int i = kuse - 1; i >= 0; --i) {
+        double vr = 0.0, vi = 0.0;
+        if (i < k) {
+            const double *p = dw + ((int64_t)i * ncol + m) * 4;
+            const double bb = i + 1 < k ? b[(int64_t)i * nc + s] : 0.0;
+            const double tr = p[2] - bb * yr, ti = p[3] - bb * yi;   // (g_i - b_i y_{i+1}) / d_i
+            const double m2 = p[0] * p[0] + p[1] * p[1];
+            vr = (tr * p[0] + ti * p[1]) / m2;
+            vi = (ti * p[0] - tr * p[1]) / m2;
+        }
+        Y[((int64_t)i * ncol + m) * 2] = vr;
+        Y[((int64_t)i * ncol + m) * 2 + 1] = vi;
+        yr = vr;
+        yi = vi;
+    }
+}
+
+// at[rp][2m + re/im] = St[r] * sum_{i < kuse} q_i[r][s] Y[i][m] for the W * NC columns
+// of a pass (0 on the padding of `at`): the back half then gives B Q_k y.
+template <int NC>
+__global__ __launch_bounds__(256)
+void k_lz_expand(LanczosDev L, int kuse, const double *__restrict__ Y, double *__restrict__ at) {
+    constexpr int W = LZ_XCOL / NC, M = W * NC;
+    const int64_t rp = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (rp >= L.tp) return;
+    const int F = (int)(rp / L.no_pad), E = (int)(rp % L.no_pad);
+    double acc[M][2];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m][0] = acc[m][1] = 0.0;
+    if (E < L.no && F < L.nv) {
+        const int64_t r = (int64_t)F * L.no + E;
+        for (int i = 0; i < kuse; ++i) {
+            double qv[NC];
+#pragma unroll
+            for (int s = 0; s < NC; ++s) qv[s] = lz_ldnt(lz_vec(L, i) + r * NC + s);
+            const double *y = Y + (int64_t)i * M * 2;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                acc[m][0] += qv[m % NC] * y[2 * m];
+                acc[m][1] += qv[m % NC] * y[2 * m + 1];
+            }
+        }
+        const double st = L.St[r];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            acc[m][0] *= st;
+            acc[m][1] *= st;
+        }
+    }
+    double *o = at + rp * (2 * M);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        o[2 * m] = acc[m][0];
+        o[2 * m + 1] = acc[m][1];
+    }
+}
+
+// From Yb = B Q_k y [P_pad][2M] (column 2m + re/im): x rows out[w][s][mu] = -Yb[mu][m]
+// (complex) for the nw valid frequencies, and alpha[w][k][i] = -d_k . x_i = d_k . Yb[:, m(w, i)].
+__global__ __launch_bounds__(256)
+void k_lz_x_rows(const double *__restrict__ Yb, int M, int nc, int nw, int P, double *__restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)nw * nc * P) return;
+    const int m = (int)(idx / P), mu = (int)(idx % P);
+    out[2 * idx] = -Yb[(int64_t)mu * 2 * M + 2 * m];
+    out[2 * idx + 1] = -Yb[(int64_t)mu * 2 * M + 2 * m + 1];
+}
+
+__global__ __launch_bounds__(256)
+void k_lz_alpha_x(const double *__restrict__ Yb, int M, int nc, int P, const double *__restrict__ drives,
+                  double *__restrict__ alpha) {
+    // workgroup (w, k, i): drives [nc][P] host order
+    const int w = blockIdx.x, k = blockIdx.y, i = blockIdx.z;
+    const int m = w * nc + i;
+    double sr = 0.0, si = 0.0;
+    for (int mu = threadIdx.x; mu < P; mu += 256) {
+        const double dk = drives[(int64_t)k * P + mu];
+        sr += dk * Yb[(int64_t)mu * 2 * M + 2 * m];
+        si += dk * Yb[(int64_t)mu * 2 * M + 2 * m + 1];
+    }
+    __shared__ double sh[2][4];
+    sr = lz_wave_sum(sr);
+    si = lz_wave_sum(si);
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = sr;
+        sh[1][threadIdx.x >> 6] = si;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t o = (((int64_t)w * nc + k) * nc + i) * 2;
+        alpha[o] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+        alpha[o + 1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    }
+}
+
 // ------------------------------------------------------------------ launches
 namespace {
 int lz_blocks(const LanczosDev &L) {
@@ -504,6 +646,31 @@ void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double
     LZ_NC_SWITCH(L.nc, C)
 #undef C
     trace_end(t, s, 2.0 * ta, 3.0 * vb + 8.0 * L.t_alg);
+}
+
+void launch_lz_solution_cols(Tracer *t, hipStream_t s, const LanczosDev &L, int kuse, const int *len,
+                             const double *omega, int nw, double eps, double *dw, double *Y, double *at) {
+    const int W = LZ_XCOL / L.nc, M = W * L.nc;
+    trace_begin(t, "lanczos_solution", s);
+    hipLaunchKernelGGL(k_lz_tsolve, dim3((M + 63) / 64), dim3(64), 0, s, L.a, L.b, L.nc, kuse, len, L.cn2, omega,
+                       W, eps, dw, Y);
+    const unsigned g = (unsigned)((L.tp + 255) / 256);
+#define C(N) hipLaunchKernelGGL(k_lz_expand<N>, dim3(g), dim3(256), 0, s, L, kuse, Y, at);
+    LZ_NC_SWITCH(L.nc, C)
+#undef C
+    trace_end(t, s, 4.0 * (double)L.t_alg * M * kuse, 8.0 * (double)L.t_alg * L.nc * kuse);
+    (void)nw;
+}
+
+void launch_lz_solution_out(hipStream_t s, const double *Yb, int nc, int nw, int P, const double *drives,
+                            double *x_rows, double *alpha) {
+    const int M = (LZ_XCOL / nc) * nc;
+    const int64_t n = (int64_t)nw * nc * P;
+    if (x_rows && n > 0)
+        hipLaunchKernelGGL(k_lz_x_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Yb, M, nc, nw, P,
+                           x_rows);
+    if (alpha && nw > 0)
+        hipLaunchKernelGGL(k_lz_alpha_x, dim3(nw, nc, nc), dim3(256), 0, s, Yb, M, nc, P, drives, alpha);
 }
 
 void launch_lz_cfrac(hipStream_t s, const double *a, const double *b, int nc, int kuse, const int *len,

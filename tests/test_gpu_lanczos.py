@@ -16,6 +16,9 @@ solve of eq. sle (chi0_oracle):
   weights (c . u)^2;
 * the device continued fraction against the oracle's dense solve with T_k;
 * the 60-atom benchmark workload against the stored oracle spectrum;
+* the solutions x(w) of eq. sle from the stored basis and the full tensor
+  alpha_ki against the LU solve (exact at full dimension, 2e-5 when stopped
+  on the spectrum);
 * graph replay of the (plain) steps is bit-identical to eager launches;
 * the two-level worked example ends after one step (invariant subspace),
   a zero drive gives length 0 and alpha = 0, and bad arguments are errors.
@@ -162,6 +165,49 @@ def test_full_size_spectrum_against_stored_reference():
     assert alpha[om == 0.0].imag.tolist() == [0.0] * int((om == 0.0).sum())
 
 
+def test_solutions_full_dimension():
+    """x(w) = -B Q_k y(w) at k = T equals the LU solve of eq. sle, and the full tensor
+    alpha_ki = -d_k . x_i equals the oracle's, for three drives in one block."""
+    sys = synth.make_system("atoms4_orb4", seed=0)
+    T = sys.n_occ * (sys.n_orb - sys.n_occ)
+    d = sys.drives("xyz")
+    omx = np.array([0.0, 0.3, 0.77, 1.5, -0.4, 0.91])
+    print("[lanczos] atoms4_orb4 solutions at full dimension", flush=True)
+    ctx = _ctx(sys)
+    res = ctx.lanczos(d, k_max=T, eps=sys.eps, omega_x=omx)
+    ctx.close()
+    for w, om in enumerate(omx):
+        ref = orc.solve_response(sys, om, d)
+        for i in range(3):
+            assert np.linalg.norm(res["x"][w, i] - ref[i]) <= 1e-9 * np.linalg.norm(ref[i]), (om, i)
+    tens = orc.polarizability(sys, omx, d)
+    assert np.abs(res["alpha_x"] - tens).max() <= 1e-9 * np.abs(tens).max()
+
+
+def test_solutions_converged():
+    """On the 12-atom system, stopped on the spectrum: solutions within 2e-5 of the LU
+    solve (they converge more slowly than the quadratic form alpha) and the tensor
+    within 1e-5 of the oracle's."""
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("xz")
+    om = np.linspace(0.0, 1.5, 64)
+    omx = np.array([0.0, 0.2, 0.6, 1.3])
+    print("[lanczos] atoms12_orb9 solutions", flush=True)
+    ctx = _ctx(sys)
+    res = ctx.lanczos(d, k_max=4000, tol=1e-9, check_every=50, omega_check=om, eps=sys.eps, omega_x=omx)
+    ctx.close()
+    assert res["rc"] == 0
+    worst = 0.0
+    for w, o in enumerate(omx):
+        ref = orc.solve_response(sys, o, d)
+        for i in range(2):
+            worst = max(worst, np.linalg.norm(res["x"][w, i] - ref[i]) / np.linalg.norm(ref[i]))
+    tens = orc.polarizability(sys, omx, d)
+    terr = np.abs(res["alpha_x"] - tens).max() / np.abs(tens).max()
+    print(f"[lanczos] solutions: max rel err {worst:.2e}, tensor err {terr:.2e}", flush=True)
+    assert worst <= 2e-5 and terr <= 1e-5
+
+
 def test_repeated_calls_identical():
     """Two calls on one context, each allocating a 3.9 GB basis (whose zero fill
     must be complete before the recursion writes to it), give the same recursion."""
@@ -241,6 +287,10 @@ def test_errors():
     # a tolerance that k_max steps cannot meet: a warning, coefficients still written
     res = ctx.lanczos(d, k_max=5, tol=1e-300, check_every=1, omega_check=[0.5], eps=sys.eps)
     assert res["rc"] == chi0.NOT_CONVERGED and int(res["len"][0]) == 5
+    # solutions need the stored basis
+    with pytest.raises(chi0.Chi0Error) as e:
+        ctx.lanczos(d, k_max=5, reorth=0, eps=sys.eps, omega_x=[0.5])
+    assert e.value.code == -1
     # k_max above the number of transitions is capped to it
     T = sys.n_occ * (sys.n_orb - sys.n_occ)
     res = ctx.lanczos(d, k_max=T + 50)

@@ -19,7 +19,8 @@ tests tie it to facts that do not come from its own code:
   between k and k + 1; residues are positive and sum to |c|^2;
 * |c|^2 is the large-w coefficient sum 2 n D (d.v)^2 of the pins, and
   alpha_k(-w) = conj alpha_k(w), Im alpha_k(w) >= 0 for w > 0;
-* on a 12-atom system the error against the LU solve falls as k grows.
+* on a 12-atom system the error against the LU solve falls as k grows;
+* the solution X = -B (Om2 - z)^-1 c of the pole form equals the LU solve of eq. sle.
 
 Planted mistakes (S without its factor 2, no S on the start vector, a
 dropped three-term coefficient, (w + i eps) not squared, residues from the
@@ -130,6 +131,18 @@ def test_strength_symmetry_and_sign():
     big = 1e4
     z = (big + 1j * sys.eps) ** 2
     np.testing.assert_allclose((lo.spectrum(a, b, cn2, [big], sys.eps)[0] * z).real, -cn2, rtol=1e-5)
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.35, 1.1])
+def test_pole_form_solution_equals_lu_solution(omega):
+    """X = -B (Om2 - z)^-1 c equals the LU solve of eq. sle for every drive (the
+    identity behind the library's solutions from the Lanczos basis)."""
+    sys = _a4()
+    for ax in "xyz":
+        d = sys.drives(ax)[0]
+        got = lo.pole_form_solution(sys, omega, d)
+        ref = orc.solve_response(sys, omega, d[None, :])[0]
+        assert pins.rel(got, ref) < 1e-11, ax
 
 
 def test_error_falls_with_dimension():
