@@ -166,7 +166,8 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
     grid has converged, then alpha on the grid from the continued fraction."""
     import torch
     from paper_1005_5340_amd import chi0
-    reorth = chi0.LZ_REORTH_NONE if a.lz_plain else chi0.LZ_REORTH_FULL
+    reorth = (chi0.LZ_REORTH_NONE if a.lz_plain else
+              chi0.LZ_REORTH_FULL if a.lz_full else chi0.LZ_REORTH_PARTIAL)
 
     def run(graph=True):
         res = ctx.lanczos(drives, k_max=a.lz_kmax, reorth=reorth, tol=a.lz_tol, check_every=a.lz_check,
@@ -174,7 +175,7 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
         return res, ctx.lanczos_spectrum(res, omegas, s.eps)
 
     print(f"[bench] lanczos {a.workload}: T={s.n_occ * (s.n_orb - s.n_occ)} drives={drive_letters} "
-          f"points={omegas.size * drives.shape[0]} tol={a.lz_tol:g} reorth={not a.lz_plain}",
+          f"points={omegas.size * drives.shape[0]} tol={a.lz_tol:g} reorth={reorth}",
           file=sys.stderr, flush=True)
     ks_all = {}
     if not a.no_timing:     # breakdown: eager launches, every kernel timed
@@ -219,7 +220,7 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
         peak, unit = PEAK[bound]
         work = rec["bytes"] if bound == "hbm" else rec["flops"]
         scale = 1e9 if bound == "hbm" else 1e12
-        traffic = load_traffic(dom, a.workload) if not a.lz_plain else None
+        traffic = load_traffic(dom, a.workload) if reorth != chi0.LZ_REORTH_NONE else None
         roof = {"kernel": dom, "bound": "hbm" if bound == "hbm" else "mfma",
                 "achieved": work / (rec["ms"] * 1e-3) / scale, "peak": peak / scale, "unit": unit,
                 "frac": work / (rec["ms"] * 1e-3) / peak, "traffic": traffic,
@@ -268,7 +269,8 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
         "config": {"workload": a.workload, "seed": a.seed, "method": "lanczos (transition space)",
                    "n_orb": s.n_orb, "n_occ": s.n_occ, "n_prod": s.n_prod, "n_omega": int(omegas.size),
                    "drives": drive_letters, "eps": s.eps, "points": npts, "k_max": a.lz_kmax, "tol": a.lz_tol,
-                   "check_every": a.lz_check, "reorth": not a.lz_plain},
+                   "check_every": a.lz_check,
+                   "reorth": "none" if a.lz_plain else "full" if a.lz_full else "partial"},
         "lanczos_steps": res["len"].tolist(), "lanczos_rc": int(res["rc"]),
         "us_per_lanczos_step": dt * 1e6 / max(int(res["len"].max()), 1),
         "accuracy": acc, "roofline": roof, "cpu_baseline": None, "poles": poles, "solutions": sol,
@@ -325,6 +327,9 @@ def main():
                          "(after the timed steps, timed on their own)")
     ap.add_argument("--lz-plain", action="store_true",
                     help="Lanczos: no reorthogonalisation (three-term recurrence only)")
+    ap.add_argument("--lz-full", action="store_true",
+                    help="Lanczos: reorthogonalise every step (default: partial reorthogonalisation, "
+                         "Simon's estimates decided on the host)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 device copies of MIB MiB (reference for HBM traffic counters)")
     a = ap.parse_args()

@@ -333,7 +333,7 @@ int chi0_ws_loss_history(const chi0_ws *ws, float *loss, int32_t cap);
  */
 typedef struct chi0_lanczos_opts {
     int32_t k_max;        /* most steps (default 4000); capped to n_occ * n_virt */
-    int32_t reorth;       /* CHI0_LZ_REORTH_FULL (default), _FULL2 or _NONE */
+    int32_t reorth;       /* CHI0_LZ_REORTH_PARTIAL (default), _FULL, _FULL2 or _NONE */
     double  tol;          /* > 0: stop once alpha_k at the check frequencies changes by at most tol
                              between two consecutive pairs of checks, the change of each point relative
                              to max(|Im alpha_k|, 1e-3 max over the check points of |Im alpha_k|);
@@ -348,7 +348,9 @@ typedef struct chi0_lanczos_opts {
                              basis, i.e. CHI0_LZ_REORTH_FULL or _FULL2, and eps > 0) */
     const double *omega_x;   /* host [n_x], Ha */
     double *x;            /* host [n_x][n_drive][n_prod] complex, or NULL: x_i(w) = -B Q_k y(w),
-                             B = V_t S, y = |c_i| (T_k - (w + i eps)^2)^-1 e_1, k = len[i] */
+                             B = V_t S, y = |c_i| (T_k - (w + i eps)^2)^-1 e_1, k = len[i]; with
+                             CHI0_LZ_REORTH_PARTIAL the basis, and so x, is orthogonal only to about
+                             sqrt(machine epsilon) (1e-8 relative); _FULL keeps it to rounding */
     double *alpha_x;      /* host [n_x][n_drive][n_drive] complex, or NULL: the full tensor
                              alpha_ki(w) = -d_k . x_i(w) (eq. eqpolarizability, alpha = -P) */
     int32_t reserved[2];  /* must be zero */
@@ -366,6 +368,11 @@ typedef struct chi0_lanczos_opts {
  * leaves only small components along the old vectors. */
 #define CHI0_LZ_REORTH_FULL   1
 #define CHI0_LZ_REORTH_FULL2  2
+/* Partial reorthogonalisation (Simon's omega recurrence, evaluated on the host
+ * from a_j and b_j): a step runs the pass only when the estimated loss of
+ * orthogonality of the new vector exceeds sqrt(machine epsilon), and then the
+ * next step too; a host synchronisation per step.  Same memory as FULL. */
+#define CHI0_LZ_REORTH_PARTIAL 3
 
 void chi0_lanczos_opts_default(chi0_lanczos_opts *opts);
 

@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = ["Chi0Error", "Context", "WarmStart", "lib", "LIB_PATH", "PREC_FP64", "PREC_FP32",
            "PREC_BF16X3", "SolveStats", "NOT_CONVERGED", "debug_eigh", "STOP_RESIDUAL", "STOP_EPS_P",
-           "STOP_EPS_PX", "LanczosOpts", "LZ_REORTH_NONE", "LZ_REORTH_FULL", "LZ_REORTH_FULL2", "lanczos_poles"]
+           "STOP_EPS_PX", "LanczosOpts", "LZ_REORTH_NONE", "LZ_REORTH_FULL", "LZ_REORTH_FULL2", "LZ_REORTH_PARTIAL", "lanczos_poles"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 PREC_FP64 = 0
@@ -26,7 +26,7 @@ PREC_FP32 = 1
 PREC_BF16X3 = 2
 ORTHO_AUTO, ORTHO_CGS2, ORTHO_DCGS2 = 0, 1, 2
 STOP_RESIDUAL, STOP_EPS_P, STOP_EPS_PX = 0, 1, 2
-LZ_REORTH_NONE, LZ_REORTH_FULL, LZ_REORTH_FULL2 = 0, 1, 2
+LZ_REORTH_NONE, LZ_REORTH_FULL, LZ_REORTH_FULL2, LZ_REORTH_PARTIAL = 0, 1, 2, 3
 NOT_CONVERGED = 1
 _ERRORS = {-1: "EINVAL", -2: "ENOSYS", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EASYM"}
 
@@ -321,7 +321,7 @@ class Context:
             return a, stats, rc, x[..., 0] + 1j * x[..., 1]
         return a, stats, rc
 
-    def lanczos(self, drives, k_max: int = 4000, reorth: int = LZ_REORTH_FULL, tol: float = 0.0,
+    def lanczos(self, drives, k_max: int = 4000, reorth: int = LZ_REORTH_PARTIAL, tol: float = 0.0,
                 check_every: int = 100, omega_check=None, eps: float = 0.0, graph: bool = False,
                 omega_x=None) -> dict:
         """Lanczos recursion in transition space for 1..4 drives [n_drive][n_prod] (chi0_lanczos).

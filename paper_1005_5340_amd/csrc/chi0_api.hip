@@ -1995,7 +1995,7 @@ extern "C" void chi0_lanczos_opts_default(chi0_lanczos_opts *o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
     o->k_max = 4000;
-    o->reorth = CHI0_LZ_REORTH_FULL;
+    o->reorth = CHI0_LZ_REORTH_PARTIAL;
     o->tol = 0.0;
     o->check_every = 100;
 }
@@ -2012,7 +2012,7 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
     if (n_drive < 1 || n_drive > 4) return fail(c, CHI0_EINVAL, "n_drive must be 1..4");
     if (!drives || !a_out || !b_out || !cn2_out || !len_out) return fail(c, CHI0_EINVAL, "NULL pointer");
     if (o.k_max < 1) return fail(c, CHI0_EINVAL, "k_max < 1");
-    if (o.reorth != CHI0_LZ_REORTH_NONE && o.reorth != CHI0_LZ_REORTH_FULL && o.reorth != CHI0_LZ_REORTH_FULL2)
+    if (o.reorth < CHI0_LZ_REORTH_NONE || o.reorth > CHI0_LZ_REORTH_PARTIAL)
         return fail(c, CHI0_EINVAL, "unknown reorth");
     if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(c, CHI0_EINVAL, "tol must be finite and >= 0");
     if (o.n_check < 0 || (o.n_check > 0 && !o.omega_check)) return fail(c, CHI0_EINVAL, "bad check frequencies");
@@ -2095,7 +2095,7 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
     L.nv = c->Nv;
     L.no_pad = c->No_pad;
     L.ring = ring ? 1 : 0;
-    L.passes = ring ? 0 : (o.reorth == CHI0_LZ_REORTH_FULL2 ? 2 : 1);
+    L.passes = ring ? 0 : (o.reorth == CHI0_LZ_REORTH_FULL2 ? 2 : 1);   // PARTIAL: 1 where it reorthogonalises
     L.nc = nc;
     L.kmax = kmax;
     L.St = St;
@@ -2153,9 +2153,74 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
         }
     } exec_scope{&exec};
     const bool use_graph = o.graph == 1 && ring && !c->tracer.on;
-    int steps = 0;
+    // partial reorthogonalisation: Simon's estimates om[s][i] ~ q_j . q_i of the
+    // newest vector j (om_prev: of vector j - 1), advanced with a_j and b_j
+    const bool partial = o.reorth == CHI0_LZ_REORTH_PARTIAL;
+    const double ueps = 2.220446049250313e-16, thresh = std::sqrt(ueps);
+    std::vector<std::vector<double>> om_cur, om_prev, om_new;
+    std::vector<double> ah_p, bh_p, anorm(nc, 0.0);
+    double *pin = nullptr;
+    struct PinScope {
+        double **p;
+        ~PinScope() {
+            if (*p) (void)hipHostFree(*p);
+        }
+    } pin_scope{&pin};
+    bool force = false;
+    if (partial) {
+        HIPCHK(c, hipHostMalloc((void **)&pin, 3 * nc * sizeof(double), 0));
+        om_cur.assign(nc, std::vector<double>(kmax + 2, 0.0));
+        om_prev = om_cur;
+        om_new = om_cur;
+        for (int sq = 0; sq < nc; ++sq) om_cur[sq][0] = 1.0;
+        ah_p.assign((size_t)kmax * nc, 0.0);
+        bh_p.assign((size_t)kmax * nc, 0.0);
+    }
+    int steps = 0, reorth_steps = 0;
     for (int j = 0; j < kmax; ++j) {
-        if (use_graph && j >= 1) {
+        if (partial) {
+            lz_back_k(c, ow, s, nc);
+            lz_front(c, ow, s, nc);
+            launch_lz_step_head(&c->tracer, s, L);
+            HIPCHK(c, hipMemcpyAsync(pin, L.a + (size_t)j * nc, nc * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(pin + nc, L.b + (size_t)j * nc, nc * 8, hipMemcpyDeviceToHost, s));
+            if (j > 0)
+                HIPCHK(c, hipMemcpyAsync(pin + 2 * nc, L.b + (size_t)(j - 1) * nc, nc * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            bool need = force;
+            for (int sq = 0; sq < nc; ++sq) {
+                double *ap = &ah_p[0], *bp = &bh_p[0];
+                ap[(size_t)j * nc + sq] = pin[sq];
+                if (j > 0) bp[(size_t)(j - 1) * nc + sq] = pin[2 * nc + sq];   // final b_{j-1}
+                const double aj = pin[sq], bj = pin[nc + sq];
+                if (!(bj > 0.0)) continue;   // ended sequence
+                const double bm = j > 0 ? bp[(size_t)(j - 1) * nc + sq] : 0.0;
+                anorm[sq] = std::max(anorm[sq], std::fabs(aj) + bj + bm);
+                std::vector<double> &wc = om_cur[sq], &wp = om_prev[sq], &wn = om_new[sq];
+                double mx = 0.0;
+                for (int i = 0; i < j; ++i) {
+                    const double bi = bp[(size_t)i * nc + sq];
+                    const double bim = i > 0 ? bp[(size_t)(i - 1) * nc + sq] : 0.0;
+                    double tv = bi * wc[i + 1] + (ap[(size_t)i * nc + sq] - aj) * wc[i] - bm * wp[i];
+                    if (i > 0) tv += bim * wc[i - 1];
+                    const double v = (tv + (tv >= 0.0 ? 1.0 : -1.0) * 2.0 * ueps * anorm[sq]) / bj;
+                    wn[i] = v;
+                    mx = std::max(mx, std::fabs(v));
+                }
+                wn[j] = ueps * anorm[sq] / bj;
+                wn[j + 1] = 1.0;
+                if (mx > thresh) need = true;
+            }
+            launch_lz_step_tail(&c->tracer, s, L, j, need ? 1 : 0, part2, h, part3);
+            if (need) {
+                ++reorth_steps;
+                for (int sq = 0; sq < nc; ++sq)
+                    for (int i = 0; i <= j; ++i) om_new[sq][i] = ueps;
+                force = !force;
+            }
+            std::swap(om_prev, om_cur);
+            std::swap(om_cur, om_new);
+        } else if (use_graph && j >= 1) {
             if (!exec) {   // capture one step (the GEMM tiles were tuned by step 0)
                 if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
                 HIPCHK(c, hipStreamSynchronize(s));

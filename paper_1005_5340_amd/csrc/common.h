@@ -276,6 +276,12 @@ void launch_lz_start(Tracer *t, hipStream_t s, const LanczosDev &L);
 // host, part2 [64 * (kmax + 1) * nc], h [(kmax + 1) * nc], part3 [LZ_GROUPS * tc * nc]).
 void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
                     double *part3);
+// The same step in two halves, for partial reorthogonalisation decided on the host: the
+// head ends with a_j and the norm b_j of the three-term residual; the tail runs npass
+// passes against q_0..q_j (then b_j again) and the normalisation.
+void launch_lz_step_head(Tracer *t, hipStream_t s, const LanczosDev &L);
+void launch_lz_step_tail(Tracer *t, hipStream_t s, const LanczosDev &L, int j, int npass, double *part2, double *h,
+                         double *part3);
 // Solutions of eq. sle from the stored basis, LZ_XCOL / nc frequencies per pass
 // (omega [LZ_XCOL / nc], nw of them valid): y = |c| (T_k - z)^-1 e_1 (dw
 // [kuse][LZ_XCOL][4], Y [kuse][LZ_XCOL] complex), then at = St Q_k y in the

@@ -598,11 +598,9 @@ void launch_lz_start(Tracer *t, hipStream_t s, const LanczosDev &L) {
     trace_end(t, s, 0.0, 8.0 * (double)L.t_alg * L.nc * 4);
 }
 
-void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
-                    double *part3) {
-    const int g = lz_blocks(L);
-    // algorithmic work on unpadded transitions: one vector of the block is 8 T nc bytes
-    const double ta = (double)L.t_alg * L.nc, vb = 8.0 * ta;
+namespace {
+// combine (w = Om2 q_j), a_j, the three-term update
+void lz_head(Tracer *t, hipStream_t s, const LanczosDev &L, int g, double ta, double vb) {
     trace_begin(t, "lanczos_combine", s);
 #define C(N)                                                                   \
     hipLaunchKernelGGL(k_lz_combine<N>, dim3(g), dim3(256), 0, s, L);          \
@@ -615,37 +613,78 @@ void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double
     LZ_NC_SWITCH(L.nc, C)
 #undef C
     trace_end(t, s, 6.0 * ta, 4.0 * vb);
-    if (!L.ring) {
-        // classical Gram-Schmidt pass(es) against q_0..q_j (j known on the host)
-        const int nq = j + 1;
-        const int nsplit = std::max(1, std::min(64, 2048 / nq));
-        const unsigned rblocks = (unsigned)(((L.nc == 3 ? L.tc : L.n / 2) + 255) / 256);
-        const int ngroup = std::max(1, std::min(LZ_GROUPS, nq / 64));
-        for (int pass = 0; pass < L.passes; ++pass) {
-            trace_begin(t, "lanczos_reorth_dots", s);
+}
+
+// npass classical Gram-Schmidt passes of w against q_0..q_j (j known on the host)
+void lz_passes(Tracer *t, hipStream_t s, const LanczosDev &L, int j, int npass, int g, double ta, double vb,
+               double *part2, double *h, double *part3) {
+    const int nq = j + 1;
+    const int nsplit = std::max(1, std::min(64, 2048 / nq));
+    const unsigned rblocks = (unsigned)(((L.nc == 3 ? L.tc : L.n / 2) + 255) / 256);
+    const int ngroup = std::max(1, std::min(LZ_GROUPS, nq / 64));
+    for (int pass = 0; pass < npass; ++pass) {
+        trace_begin(t, "lanczos_reorth_dots", s);
 #define C(N)                                                                                                  \
     hipLaunchKernelGGL(k_lz_dots<N>, dim3(nsplit, nq), dim3(256), 0, s, L, nq, nsplit, part2);                \
     hipLaunchKernelGGL(k_lz_dots_fin<N>, dim3((unsigned)((nq * N + 255) / 256)), dim3(256), 0, s, part2, nq, \
                        nsplit, h);
-            LZ_NC_SWITCH(L.nc, C)
+        LZ_NC_SWITCH(L.nc, C)
 #undef C
-            trace_end(t, s, 2.0 * ta * nq, vb * (nq + 1));
-            trace_begin(t, "lanczos_reorth_update", s);
+        trace_end(t, s, 2.0 * ta * nq, vb * (nq + 1));
+        trace_begin(t, "lanczos_reorth_update", s);
 #define C(N)                                                                                                   \
     hipLaunchKernelGGL(k_lz_update_part<N>, dim3(rblocks, ngroup), dim3(256), 0, s, L, nq, ngroup, h, part3); \
     hipLaunchKernelGGL(k_lz_update_fin<N>, dim3(g), dim3(256), 0, s, L, ngroup, part3);
-            LZ_NC_SWITCH(L.nc, C)
+        LZ_NC_SWITCH(L.nc, C)
 #undef C
-            trace_end(t, s, 2.0 * ta * nq, vb * (nq + 2));
-        }
+        trace_end(t, s, 2.0 * ta * nq, vb * (nq + 2));
     }
+}
+
+void lz_beta(Tracer *t, hipStream_t s, const LanczosDev &L, int g) {
+    trace_begin(t, "lanczos_beta", s);
+#define C(N) hipLaunchKernelGGL(k_lz_beta<N>, dim3(1), dim3(256), 0, s, L, g);
+    LZ_NC_SWITCH(L.nc, C)
+#undef C
+    trace_end(t, s);
+}
+
+void lz_scale(Tracer *t, hipStream_t s, const LanczosDev &L, int g, double ta, double vb) {
     trace_begin(t, "lanczos_scale", s);
-#define C(N)                                                                \
-    hipLaunchKernelGGL(k_lz_beta<N>, dim3(1), dim3(256), 0, s, L, g);       \
-    hipLaunchKernelGGL(k_lz_scale<N>, dim3(g), dim3(256), 0, s, L);
+#define C(N) hipLaunchKernelGGL(k_lz_scale<N>, dim3(g), dim3(256), 0, s, L);
     LZ_NC_SWITCH(L.nc, C)
 #undef C
     trace_end(t, s, 2.0 * ta, 3.0 * vb + 8.0 * L.t_alg);
+}
+}  // namespace
+
+void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
+                    double *part3) {
+    const int g = lz_blocks(L);
+    // algorithmic work on unpadded transitions: one vector of the block is 8 T nc bytes
+    const double ta = (double)L.t_alg * L.nc, vb = 8.0 * ta;
+    lz_head(t, s, L, g, ta, vb);
+    if (!L.ring) lz_passes(t, s, L, j, L.passes, g, ta, vb, part2, h, part3);
+    lz_beta(t, s, L, g);
+    lz_scale(t, s, L, g, ta, vb);
+}
+
+void launch_lz_step_head(Tracer *t, hipStream_t s, const LanczosDev &L) {
+    const int g = lz_blocks(L);
+    const double ta = (double)L.t_alg * L.nc, vb = 8.0 * ta;
+    lz_head(t, s, L, g, ta, vb);
+    lz_beta(t, s, L, g);
+}
+
+void launch_lz_step_tail(Tracer *t, hipStream_t s, const LanczosDev &L, int j, int npass, double *part2, double *h,
+                         double *part3) {
+    const int g = lz_blocks(L);
+    const double ta = (double)L.t_alg * L.nc, vb = 8.0 * ta;
+    if (npass > 0) {
+        lz_passes(t, s, L, j, npass, g, ta, vb, part2, h, part3);
+        lz_beta(t, s, L, g);
+    }
+    lz_scale(t, s, L, g, ta, vb);
 }
 
 void launch_lz_solution_cols(Tracer *t, hipStream_t s, const LanczosDev &L, int kuse, const int *len,
