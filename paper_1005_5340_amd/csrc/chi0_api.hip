@@ -2176,7 +2176,7 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
         ah_p.assign((size_t)kmax * nc, 0.0);
         bh_p.assign((size_t)kmax * nc, 0.0);
     }
-    int steps = 0, reorth_steps = 0;
+    int steps = 0;
     for (int j = 0; j < kmax; ++j) {
         if (partial) {
             lz_back_k(c, ow, s, nc);
@@ -2213,7 +2213,6 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
             }
             launch_lz_step_tail(&c->tracer, s, L, j, need ? 1 : 0, part2, h, part3);
             if (need) {
-                ++reorth_steps;
                 for (int sq = 0; sq < nc; ++sq)
                     for (int i = 0; i <= j; ++i) om_new[sq][i] = ueps;
                 force = !force;
