@@ -329,7 +329,9 @@ int chi0_ws_loss_history(const chi0_ws *ws, float *loss, int32_t cap);
  * excitation energies sqrt(theta_j)) and r_j = |c|^2 (u_j)_1^2 their residues.
  * This is the economical treatment of the frequency axis, with pole
  * positions and strengths, that the paper names as further work (Sec. 8).
- * It yields the diagonal alpha_ii of each drive (no cross terms).
+ * The continued fraction yields the diagonal alpha_ii of each drive; with a
+ * stored basis (any reorthogonalised recursion) the solutions of eq. sle and
+ * the full tensor alpha_ki follow at requested frequencies (n_x below).
  */
 typedef struct chi0_lanczos_opts {
     int32_t k_max;        /* most steps (default 4000); capped to n_occ * n_virt */
@@ -345,7 +347,7 @@ typedef struct chi0_lanczos_opts {
     int32_t graph;        /* 1: after the first step, replay each step's launch sequence from one
                              HIP graph (CHI0_LZ_REORTH_NONE, timing off); 0 (default): launch eagerly */
     int32_t n_x;          /* > 0: also the solutions of eq. sle at n_x frequencies (needs a stored
-                             basis, i.e. CHI0_LZ_REORTH_FULL or _FULL2, and eps > 0) */
+                             basis: any mode but CHI0_LZ_REORTH_NONE; and eps > 0) */
     const double *omega_x;   /* host [n_x], Ha */
     double *x;            /* host [n_x][n_drive][n_prod] complex, or NULL: x_i(w) = -B Q_k y(w),
                              B = V_t S, y = |c_i| (T_k - (w + i eps)^2)^-1 e_1, k = len[i]; with
