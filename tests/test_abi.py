@@ -122,3 +122,22 @@ def test_autotune_switch_on_host_context(L):
         assert ctx.autotune_table() == {}
         ctx.set_autotune(True)
     assert L.chi0_set_autotune(None, 1) == -1
+
+
+def test_lanczos_defaults_and_host_context(L):
+    o = chi0.LanczosOpts()
+    L.chi0_lanczos_opts_default(C.byref(o))
+    assert (o.k_max, o.reorth, o.tol, o.check_every, o.n_check, o.graph, o.n_x) == \
+        (4000, chi0.LZ_REORTH_PARTIAL, 0.0, 100, 0, 0, 0)
+    assert list(o.reserved) == [0, 0]
+    s = synth.make_system("atoms4_orb4", seed=0)
+    with chi0.Context(-1) as ctx:
+        ctx.set_system_from(s)
+        with pytest.raises(chi0.Chi0Error) as e:      # host-only: no device to run on
+            ctx.lanczos(s.drives("z"), k_max=5)
+        assert e.value.code == -2
+        res = dict(a=np.ones((1, 2)), b=np.ones((1, 2)), c_norm2=np.ones(1), len=np.array([2], np.int32))
+        with pytest.raises(chi0.Chi0Error) as e:
+            ctx.lanczos_spectrum(res, [0.5], 0.01)
+        assert e.value.code == -2
+    assert L.chi0_lanczos(None, 1, None, None, None, None, None, None) == -1
