@@ -314,6 +314,9 @@ def main():
     ap.add_argument("--lanczos", action="store_true",
                     help="the spectrum from one Lanczos recursion per drive in transition space instead of "
                          "a GMRES solve per frequency (same workload, error measure and JSON line)")
+    ap.add_argument("--warm-prev", action="store_true",
+                    help="after the timed steps, solve the odd grid points again starting from the "
+                         "solution at the next lower grid point (x0) and report the iterations saved")
     ap.add_argument("--n-omega", type=int, default=0,
                     help="solve this many frequencies, evenly spaced on the workload's interval, instead of its "
                          "grid (accuracy then unchecked)")
@@ -522,6 +525,36 @@ def main():
                   f"{100 * v['ms'] / tot_all:6.1f}%  {ach:9.2f} {'GB/s' if b == 'hbm' else 'TFLOP/s'}",
                   file=sys.stderr)
 
+    warm_prev = None
+    if a.warm_prev:
+        ctx.set_timing(False)
+        ev, od = np.arange(0, omegas.size, 2), np.arange(1, omegas.size, 2)
+        _, _, _, xe = ctx.solve_response(omegas[ev], s.eps, drives, restart=restart, max_iter=a.max_iter, tol=tol,
+                                         batch=a.batch, lanes=a.lanes, return_x=True)
+        x0 = torch.from_numpy(np.ascontiguousarray(xe[: od.size])).to("cuda")   # grid point 2m for 2m + 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st_cold, _ = ctx.solve_response(omegas[od], s.eps, drives, restart=restart, max_iter=a.max_iter,
+                                           tol=tol, batch=a.batch, lanes=a.lanes)
+        t_cold = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        a_w, st_w, _ = ctx.solve_response(omegas[od], s.eps, drives, restart=restart, max_iter=a.max_iter,
+                                          tol=tol, batch=a.batch, lanes=a.lanes, x0=x0)
+        t_w = time.perf_counter() - t0
+        warm_prev = {"points": int(od.size * drives.shape[0]), "seconds_cold": t_cold, "seconds_x0": t_w,
+                     "iterations_cold": int(st_cold["iterations"].sum()),
+                     "iterations_x0": int(st_w["iterations"].sum()),
+                     "max_iterations_cold": int(st_cold["iterations"].max()),
+                     "max_iterations_x0": int(st_w["iterations"].max()),
+                     "median_rel_residual_of_x0": float(np.median(st_w["warm_rel0"])),
+                     "rejected": int((st_w["warm_start"] == 2).sum())}
+        if ref is not None and np.all(np.isin(ref_idx, grid)):
+            sel = np.searchsorted(ref_idx, grid[od])
+            rw = np.stack([ref[sel, ref_drive[i], ref_drive[i]] for i in range(drives.shape[0])], 1)
+            ew = np.stack([im_errors(a_w[:, i, i], rw[:, i]) for i in range(drives.shape[0])], 1)
+            warm_prev["max_im_rel_err"] = float(ew.max())
+        print(f"[bench] previous-frequency start: {warm_prev}", file=sys.stderr, flush=True)
+
     tuned = ctx.autotune_table()
     for k, v in sorted(tuned.items()):
         us = ", ".join(f"{x:.0f}" if x > 0 else "-" for x in v["us"][:6])
@@ -560,6 +593,7 @@ def main():
         "accuracy": acc,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "warm_previous_frequency": warm_prev,
     }
     print(json.dumps(out), flush=True)
     if ws is not None:

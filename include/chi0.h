@@ -184,6 +184,10 @@ typedef struct chi0_solve_opts {
                              passes overlap the other's matrix-core transforms */
     int32_t stop;         /* CHI0_STOP_*: the test that ends a point (default: residual) */
     int32_t reserved;     /* must be zero */
+    const double *x0;     /* NULL, or DEVICE memory [n_omega][n_drive][n_prod] complex: point
+                             (omega_i, drive k) starts from x0[i][k] instead of 0 (for example the
+                             solution at a neighbouring frequency), unless
+                             ||chi0 d - A x0|| >= ||chi0 d||, then from 0; not with `warm` */
 } chi0_solve_opts;
 
 /* Stopping test of a point (Sec. 4.1).

@@ -39,7 +39,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("batch", C.c_int32), ("inner_tol", C.c_double),
                 ("warm", C.c_void_p), ("ortho", C.c_int32), ("lanes", C.c_int32),
-                ("stop", C.c_int32), ("reserved", C.c_int32)]
+                ("stop", C.c_int32), ("reserved", C.c_int32), ("x0", C.c_void_p)]
 
 
 class WsCfg(C.Structure):
@@ -281,12 +281,13 @@ class Context:
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
                        tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,
                        inner_tol: float = 0.0, warm: "WarmStart" = None, ortho: int = ORTHO_AUTO,
-                       return_x: bool = False, lanes: int = 0, stop: int = STOP_RESIDUAL):
+                       return_x: bool = False, lanes: int = 0, stop: int = STOP_RESIDUAL, x0=None):
         """GMRES polarizability over a frequency grid.
 
         Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
         where rc is 0 or NOT_CONVERGED; with return_x also the solutions
-        x [n_omega, n_drive, n_prod] complex (chi0_solve_response_x).
+        x [n_omega, n_drive, n_prod] complex (chi0_solve_response_x).  x0: optional start
+        vectors, a contiguous complex128 device tensor [n_omega, n_drive, n_prod].
         """
         om = _f64(np.atleast_1d(omega))
         D = _f64(np.atleast_2d(V_ext))
@@ -299,6 +300,13 @@ class Context:
         o.ortho = int(ortho)
         o.lanes = int(lanes)
         o.stop = int(stop)
+        if x0 is not None:
+            import torch
+            n_prod = self.sizes()["n_prod"]
+            if (not isinstance(x0, torch.Tensor) or x0.device.type != "cuda" or x0.dtype != torch.complex128
+                    or not x0.is_contiguous() or tuple(x0.shape) != (om.size, nd, n_prod)):
+                raise ValueError("x0 must be a contiguous complex128 cuda tensor [n_omega, n_drive, n_prod]")
+            o.x0 = x0.data_ptr()
         alpha = np.zeros((om.size, nd, nd, 2))
         st = (PointStats * max(1, om.size * nd))()
         if return_x:

@@ -1027,6 +1027,9 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
         return fail(c, CHI0_EINVAL, "the eps_P / eps_X stopping tests need DCGS2 steps in FP64");
     chi0_ws *ws = const_cast<chi0_ws *>(o.warm);
     if (ws && ws->ctx != c) return fail(c, CHI0_EINVAL, "warm start belongs to another context");
+    const double *x0 = o.x0;
+    if (ws && x0) return fail(c, CHI0_EINVAL, "a learned warm start and x0 are exclusive");
+    const bool warm_any = ws || x0;
     const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol
                              : (o.precision == CHI0_PREC_FP32 ? 1e-6 : 1e-4);
     if (!all_finite(omega, n_omega)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
@@ -1117,7 +1120,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     } fl[kSets];
     struct LaneState {
         int q_launch = 0, n_inflight = 0, q_oldest = 0, last_q = 0;
-        std::vector<Job> fin, upd, rst, wnew;
+        std::vector<Job> fin, upd, rst, wnew, xnew;
         std::vector<double> wom;
     } lanes[kLanes];
     for (int L = 0; L < nl; ++L) lanes[L].q_launch = lanes[L].q_oldest = lanes[L].last_q = 2 * L;
@@ -1153,7 +1156,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                     sum_j1 += jb.j + 1;
                 } else {
                     jb.type = ss.state == S_RHS ? JOB_RHS : JOB_RESID;
-                    jb.j = jb.type == JOB_RHS ? (ws ? 1 : 0) : 0;
+                    jb.j = jb.type == JOB_RHS ? (warm_any ? 1 : 0) : 0;
                     ss.busy = true;
                 }
                 jobs_h[nb] = jb;
@@ -1249,11 +1252,11 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 if (!(st.value > 0.0) || !std::isfinite(st.value)) {
                     pt.rel = st.value == 0.0 ? 0.0 : NAN;
                     pt.converged = st.value == 0.0;
-                    if (ws) ln.rst.push_back({jb.slot, 0, 0, 0});   // x = 0 is the answer
+                    if (warm_any) ln.rst.push_back({jb.slot, 0, 0, 0});   // x = 0 is the answer
                     ln.fin.push_back({jb.slot, 0, ss.point, 0});
                     ss.state = S_FREE;
                     ++done;
-                } else if (ws) {
+                } else if (warm_any) {
                     ss.state = S_RESID;       // r0 = b - A x0 decides on the warm start
                     ss.warm_check = true;
                 } else {
@@ -1352,6 +1355,11 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
             launch_update_x(t, s, upd_d, (int)ln.upd.size(), jm, c->slots, P, sumL);
             ln.upd.clear();
         }
+        // points new in this lane's slots with a given start vector get it now
+        for (const Job &jn : ln.xnew)
+            HIPCHK(c, hipMemcpyAsync(c->slots.x + (int64_t)jn.slot * c->P_pad * 2, x0 + (int64_t)jn.j * P * 2,
+                                     (size_t)P * 16, hipMemcpyDeviceToDevice, s));
+        ln.xnew.clear();
         // warm-started points new in this lane's slots get x0 = U c(omega) now
         if (!ln.wnew.empty()) {
             // the network's buffers are shared by the lanes: this stream finishes
@@ -1385,6 +1393,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                     LaneState &ln = lanes[k % nl];
                     ln.wnew.push_back({k, 0, sl[k].point, 0});
                     ln.wom.push_back(omega[sl[k].point / n_drive]);
+                } else if (x0) {
+                    lanes[k % nl].xnew.push_back({k, 0, sl[k].point, 0});
                 }
             }
     };
