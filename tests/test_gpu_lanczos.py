@@ -190,6 +190,35 @@ def test_solutions_full_dimension():
     ctx.close()
 
 
+def test_solutions_edge_cases():
+    """Solutions in several passes with four drives (4 frequencies per pass, the last pass
+    ragged), the two-level system (one step), and a zero drive (length 0: x = 0)."""
+    from paper_1005_5340_amd import chi0
+    sys = synth.make_system("atoms4_orb4", seed=0)
+    T = sys.n_occ * (sys.n_orb - sys.n_occ)
+    d = np.concatenate([sys.drives("xyz"), np.zeros((1, sys.n_prod))])
+    omx = np.array([0.1, 0.45, 0.8, 1.1, 1.3, 1.45])
+    print("[lanczos] solution passes with four drives", flush=True)
+    ctx = _ctx(sys)
+    res = ctx.lanczos(d, k_max=T, reorth=chi0.LZ_REORTH_FULL, eps=sys.eps, omega_x=omx)
+    ctx.close()
+    assert int(res["len"][3]) == 0
+    assert np.all(res["x"][:, 3] == 0) and np.all(res["alpha_x"][:, :, 3] == 0)
+    for w, om in enumerate(omx):
+        ref = orc.solve_response(sys, om, d[:3])
+        for i in range(3):
+            assert np.linalg.norm(res["x"][w, i] - ref[i]) <= 1e-9 * np.linalg.norm(ref[i]), (om, i)
+    tens = orc.polarizability(sys, omx, d[:3])
+    assert np.abs(res["alpha_x"][:, :3, :3] - tens).max() <= 1e-9 * np.abs(tens).max()
+    two = pins.two_level_system()
+    ctx = _ctx(two)
+    om2 = np.linspace(-2, 2, 9)
+    r2 = ctx.lanczos(two.drives("z"), k_max=4, eps=two.eps, omega_x=om2)
+    ctx.close()
+    assert int(r2["len"][0]) == 1
+    assert pins.rel(r2["alpha_x"][:, 0, 0], pins.two_level_alpha(om2)) < 1e-13
+
+
 def test_solutions_converged():
     """On the 12-atom system, stopped on the spectrum: solutions within 2e-5 of the LU
     solve (they converge more slowly than the quadratic form alpha) and the tensor
