@@ -374,10 +374,11 @@ typedef struct chi0_lanczos_opts {
  * leaves only small components along the old vectors. */
 #define CHI0_LZ_REORTH_FULL   1
 #define CHI0_LZ_REORTH_FULL2  2
-/* Partial reorthogonalisation (Simon's omega recurrence, evaluated on the host
+/* Partial reorthogonalisation (Simon's omega recurrence, advanced on the device
  * from a_j and b_j): a step runs the pass only when the estimated loss of
  * orthogonality of the new vector exceeds sqrt(machine epsilon), and then the
- * next step too; a host synchronisation per step.  Same memory as FULL. */
+ * next step too; the decision is a device flag, so the host is not waited on
+ * between convergence checks.  Same memory as FULL. */
 #define CHI0_LZ_REORTH_PARTIAL 3
 
 void chi0_lanczos_opts_default(chi0_lanczos_opts *opts);

@@ -2163,72 +2163,39 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
         }
     } exec_scope{&exec};
     const bool use_graph = o.graph == 1 && ring && !c->tracer.on;
-    // partial reorthogonalisation: Simon's estimates om[s][i] ~ q_j . q_i of the
-    // newest vector j (om_prev: of vector j - 1), advanced with a_j and b_j
+    // partial reorthogonalisation: the estimates and the decision live on the device
     const bool partial = o.reorth == CHI0_LZ_REORTH_PARTIAL;
-    const double ueps = 2.220446049250313e-16, thresh = std::sqrt(ueps);
-    std::vector<std::vector<double>> om_cur, om_prev, om_new;
-    std::vector<double> ah_p, bh_p, anorm(nc, 0.0);
-    double *pin = nullptr;
+    int *flag_h = nullptr;
     struct PinScope {
-        double **p;
+        int **p;
         ~PinScope() {
             if (*p) (void)hipHostFree(*p);
         }
-    } pin_scope{&pin};
-    bool force = false;
+    } pin_scope{&flag_h};
     if (partial) {
-        HIPCHK(c, hipHostMalloc((void **)&pin, 3 * nc * sizeof(double), 0));
-        om_cur.assign(nc, std::vector<double>(kmax + 2, 0.0));
-        om_prev = om_cur;
-        om_new = om_cur;
-        for (int sq = 0; sq < nc; ++sq) om_cur[sq][0] = 1.0;
-        ah_p.assign((size_t)kmax * nc, 0.0);
-        bh_p.assign((size_t)kmax * nc, 0.0);
+        CHK(dalloc(c, ws.buf, &L.omega, 3 * (int64_t)nc * (kmax + 2)));
+        CHK(dalloc(c, ws.buf, &L.anorm, nc));
+        CHK(dalloc(c, ws.buf, &L.flag, 2));
+        const double one = 1.0;
+        for (int sq = 0; sq < nc; ++sq)   // row 0: q_0 . q_0 = 1
+            HIPCHK(c, hipMemcpy(L.omega + (int64_t)sq * (kmax + 2), &one, 8, hipMemcpyHostToDevice));
+        if (c->tracer.on) HIPCHK(c, hipHostMalloc((void **)&flag_h, sizeof(int), 0));
     }
     int steps = 0;
     for (int j = 0; j < kmax; ++j) {
         if (partial) {
             lz_back_k(c, ow, s, nc);
             lz_front(c, ow, s, nc);
-            launch_lz_step_head(&c->tracer, s, L);
-            HIPCHK(c, hipMemcpyAsync(pin, L.a + (size_t)j * nc, nc * 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipMemcpyAsync(pin + nc, L.b + (size_t)j * nc, nc * 8, hipMemcpyDeviceToHost, s));
-            if (j > 0)
-                HIPCHK(c, hipMemcpyAsync(pin + 2 * nc, L.b + (size_t)(j - 1) * nc, nc * 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipStreamSynchronize(s));
-            bool need = force;
-            for (int sq = 0; sq < nc; ++sq) {
-                double *ap = &ah_p[0], *bp = &bh_p[0];
-                ap[(size_t)j * nc + sq] = pin[sq];
-                if (j > 0) bp[(size_t)(j - 1) * nc + sq] = pin[2 * nc + sq];   // final b_{j-1}
-                const double aj = pin[sq], bj = pin[nc + sq];
-                if (!(bj > 0.0)) continue;   // ended sequence
-                const double bm = j > 0 ? bp[(size_t)(j - 1) * nc + sq] : 0.0;
-                anorm[sq] = std::max(anorm[sq], std::fabs(aj) + bj + bm);
-                std::vector<double> &wc = om_cur[sq], &wp = om_prev[sq], &wn = om_new[sq];
-                double mx = 0.0;
-                for (int i = 0; i < j; ++i) {
-                    const double bi = bp[(size_t)i * nc + sq];
-                    const double bim = i > 0 ? bp[(size_t)(i - 1) * nc + sq] : 0.0;
-                    double tv = bi * wc[i + 1] + (ap[(size_t)i * nc + sq] - aj) * wc[i] - bm * wp[i];
-                    if (i > 0) tv += bim * wc[i - 1];
-                    const double v = (tv + (tv >= 0.0 ? 1.0 : -1.0) * 2.0 * ueps * anorm[sq]) / bj;
-                    wn[i] = v;
-                    mx = std::max(mx, std::fabs(v));
-                }
-                wn[j] = ueps * anorm[sq] / bj;
-                wn[j + 1] = 1.0;
-                if (mx > thresh) need = true;
+            if (c->tracer.on) {
+                // per-kernel timing: read the decision, so that the pass is launched
+                // (and counted) only where it runs; same arithmetic as the gated launch
+                launch_lz_step_head(&c->tracer, s, L, j);
+                HIPCHK(c, hipMemcpyAsync(flag_h, L.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(c, hipStreamSynchronize(s));
+                launch_lz_step_tail(&c->tracer, s, L, j, *flag_h ? 1 : 0, part2, h, part3);
+            } else {
+                launch_lz_step_partial(&c->tracer, s, L, j, part2, h, part3);
             }
-            launch_lz_step_tail(&c->tracer, s, L, j, need ? 1 : 0, part2, h, part3);
-            if (need) {
-                for (int sq = 0; sq < nc; ++sq)
-                    for (int i = 0; i <= j; ++i) om_new[sq][i] = ueps;
-                force = !force;
-            }
-            std::swap(om_prev, om_cur);
-            std::swap(om_cur, om_new);
         } else if (use_graph && j >= 1) {
             if (!exec) {   // capture one step (the GEMM tiles were tuned by step 0)
                 if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));

@@ -266,6 +266,12 @@ struct LanczosDev {
     int *len;              // [nc] recursion length (kmax until an invariant subspace ends it)
     int *step;             // current step (device counter)
     double *part;          // [LZ_BLOCKS][nc] partial sums
+    // partial reorthogonalisation (null otherwise): Simon's estimates of q_j . q_i in a
+    // ring of three rows [3][nc][kmax + 2], the running |T| estimate [nc], and the step's
+    // decision: flag[0] = run the pass, flag[1] = the next step must run it too
+    double *omega;
+    double *anorm;
+    int *flag;
 };
 void launch_lz_tables(hipStream_t s, const double *Dlt, int No, int Nv, int nv_pad, int64_t tc, double occ,
                       double *St, double *D2t);
@@ -276,10 +282,15 @@ void launch_lz_start(Tracer *t, hipStream_t s, const LanczosDev &L);
 // host, part2 [64 * (kmax + 1) * nc], h [(kmax + 1) * nc], part3 [LZ_GROUPS * tc * nc]).
 void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
                     double *part3);
-// The same step in two halves, for partial reorthogonalisation decided on the host: the
-// head ends with a_j and the norm b_j of the three-term residual; the tail runs npass
-// passes against q_0..q_j (then b_j again) and the normalisation.
-void launch_lz_step_head(Tracer *t, hipStream_t s, const LanczosDev &L);
+// Partial reorthogonalisation (L.omega, L.anorm, L.flag set): the head of step j
+// ends with a_j, the norm b_j of the three-term residual and the device-side
+// decision on the pass (L.flag[0]).  The whole step launches the gated pass and
+// the second b_j every step (they return at once where the flag is clear); no
+// host synchronisation.  The tail runs npass passes against q_0..q_j (then b_j
+// again) and the normalisation, for a caller that has read the flag.
+void launch_lz_step_head(Tracer *t, hipStream_t s, const LanczosDev &L, int j);
+void launch_lz_step_partial(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
+                            double *part3);
 void launch_lz_step_tail(Tracer *t, hipStream_t s, const LanczosDev &L, int j, int npass, double *part2, double *h,
                          double *part3);
 // Solutions of eq. sle from the stored basis, LZ_XCOL / nc frequencies per pass

@@ -225,7 +225,8 @@ void k_lz_axpy(LanczosDev L) {
 // coefficient 0) when b_j <= 1e-12 (|a_j| + b_{j-1}): an invariant subspace.
 template <int NC>
 __global__ __launch_bounds__(256)
-void k_lz_beta(LanczosDev L, int nblk) {
+void k_lz_beta(LanczosDev L, int nblk, int gated) {
+    if (gated && L.flag && !L.flag[0]) return;   // no pass: b_j of the head stands
     __shared__ double sh[4];
     const int j = *L.step - 1;
     for (int s = 0; s < NC; ++s) {
@@ -273,6 +274,7 @@ __device__ __forceinline__ double lz_ldnt(const double *p) { return __builtin_no
 template <int NC>
 __global__ __launch_bounds__(256)
 void k_lz_dots(LanczosDev L, int nq, int nsplit, double *part2) {
+    if (L.flag && !L.flag[0]) return;   // partial reorthogonalisation: no pass this step
     const int i = blockIdx.y, rs = blockIdx.x;
     const int j = *L.step - 1;
     const double *q = lz_vec(L, i);
@@ -315,7 +317,8 @@ void k_lz_dots(LanczosDev L, int nq, int nsplit, double *part2) {
 
 template <int NC>
 __global__ __launch_bounds__(256)
-void k_lz_dots_fin(const double *part2, int nq, int nsplit, double *h) {
+void k_lz_dots_fin(const double *part2, int nq, int nsplit, double *h, const int *flag) {
+    if (flag && !flag[0]) return;
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= (int64_t)nq * NC) return;
     const int i = (int)(idx / NC), s = (int)(idx % NC);
@@ -330,6 +333,7 @@ void k_lz_dots_fin(const double *part2, int nq, int nsplit, double *h) {
 template <int NC>
 __global__ __launch_bounds__(256)
 void k_lz_update_part(LanczosDev L, int nq, int ngroup, const double *__restrict__ h, double *__restrict__ part3) {
+    if (L.flag && !L.flag[0]) return;
     const int g = blockIdx.y;
     const int per = (nq + ngroup - 1) / ngroup;
     const int i0 = g * per, i1 = min(nq, i0 + per);
@@ -371,6 +375,7 @@ void k_lz_update_part(LanczosDev L, int nq, int ngroup, const double *__restrict
 template <int NC>
 __global__ __launch_bounds__(256)
 void k_lz_update_fin(LanczosDev L, int ngroup, const double *__restrict__ part3) {
+    if (L.flag && !L.flag[0]) return;
     const int j = *L.step - 1;
     double *w = lz_vec(L, j + 1);
     double acc[NC] = {};
@@ -420,6 +425,67 @@ void k_lz_cfrac(const double *__restrict__ a, const double *__restrict__ b, int 
     }
     out[2 * (int64_t)idx] = re;
     out[2 * (int64_t)idx + 1] = im;
+}
+
+// Partial reorthogonalisation (Simon's omega recurrence), one workgroup: from a_j,
+// the head's b_j and the earlier coefficients, the estimates of q_{j+1} . q_i for
+// i < j; the pass runs when one exceeds sqrt(eps) (or the previous step ran it on
+// its own estimate: the next vector is reorthogonalised too), and the estimates of
+// a reorthogonalised vector restart at eps.  Same arithmetic as the recurrence
+// written out sequentially; the maximum does not depend on the order.
+constexpr int LZ_OMEGA_THREADS = 1024;
+__global__ __launch_bounds__(LZ_OMEGA_THREADS)
+void k_lz_omega(LanczosDev L, int j) {
+    const int nc = L.nc, t = threadIdx.x;
+    const int64_t rl = (int64_t)L.kmax + 2;
+    const double ueps = 2.220446049250313e-16, thresh = 1.4901161193847656e-08;   // sqrt(eps)
+    double *const Wr = L.omega;
+    __shared__ double sh[LZ_OMEGA_THREADS / 64];
+    __shared__ int need_s;
+    if (t == 0) need_s = L.flag[1];
+    __syncthreads();
+    for (int s = 0; s < nc; ++s) {
+        const double *wc = Wr + ((int64_t)(j % 3) * nc + s) * rl;         // row j
+        const double *wp = Wr + ((int64_t)((j + 2) % 3) * nc + s) * rl;   // row j - 1
+        double *wn = Wr + ((int64_t)((j + 1) % 3) * nc + s) * rl;         // row j + 1
+        const double aj = L.a[(int64_t)j * nc + s], bj = L.b[(int64_t)j * nc + s];
+        const double bm = j > 0 ? L.b[(int64_t)(j - 1) * nc + s] : 0.0;
+        if (!(bj > 0.0)) continue;   // ended sequence (uniform across the workgroup)
+        const double an = fmax(L.anorm[s], fabs(aj) + bj + bm);
+        double mx = 0.0;
+        for (int i = t; i < j; i += LZ_OMEGA_THREADS) {
+            const double bi = L.b[(int64_t)i * nc + s];
+            double tv = bi * wc[i + 1] + (L.a[(int64_t)i * nc + s] - aj) * wc[i] - bm * wp[i];
+            if (i > 0) tv += L.b[(int64_t)(i - 1) * nc + s] * wc[i - 1];
+            const double v = (tv + (tv >= 0.0 ? 1.0 : -1.0) * 2.0 * ueps * an) / bj;
+            wn[i] = v;
+            mx = fmax(mx, fabs(v));
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+        __syncthreads();
+        if ((t & 63) == 0) sh[t >> 6] = mx;
+        __syncthreads();
+        if (t == 0) {
+            double m = 0.0;
+            for (int w = 0; w < LZ_OMEGA_THREADS / 64; ++w) m = fmax(m, sh[w]);
+            if (m > thresh) need_s = 1;
+            wn[j] = ueps * an / bj;
+            wn[j + 1] = 1.0;
+            L.anorm[s] = an;
+        }
+        __syncthreads();
+    }
+    const int need = need_s;
+    if (need)   // the new vector is reorthogonalised: its estimates restart at eps
+        for (int s = 0; s < nc; ++s) {
+            double *wn = Wr + ((int64_t)((j + 1) % 3) * nc + s) * rl;
+            for (int i = t; i <= j; i += LZ_OMEGA_THREADS) wn[i] = ueps;
+        }
+    if (t == 0) {
+        L.flag[0] = need;
+        L.flag[1] = need ? !L.flag[1] : 0;
+    }
 }
 
 // ------------------------------------------------------- solutions of eq. sle
@@ -627,7 +693,7 @@ void lz_passes(Tracer *t, hipStream_t s, const LanczosDev &L, int j, int npass, 
 #define C(N)                                                                                                  \
     hipLaunchKernelGGL(k_lz_dots<N>, dim3(nsplit, nq), dim3(256), 0, s, L, nq, nsplit, part2);                \
     hipLaunchKernelGGL(k_lz_dots_fin<N>, dim3((unsigned)((nq * N + 255) / 256)), dim3(256), 0, s, part2, nq, \
-                       nsplit, h);
+                       nsplit, h, L.flag);
         LZ_NC_SWITCH(L.nc, C)
 #undef C
         trace_end(t, s, 2.0 * ta * nq, vb * (nq + 1));
@@ -641,9 +707,9 @@ void lz_passes(Tracer *t, hipStream_t s, const LanczosDev &L, int j, int npass, 
     }
 }
 
-void lz_beta(Tracer *t, hipStream_t s, const LanczosDev &L, int g) {
+void lz_beta(Tracer *t, hipStream_t s, const LanczosDev &L, int g, int gated = 0) {
     trace_begin(t, "lanczos_beta", s);
-#define C(N) hipLaunchKernelGGL(k_lz_beta<N>, dim3(1), dim3(256), 0, s, L, g);
+#define C(N) hipLaunchKernelGGL(k_lz_beta<N>, dim3(1), dim3(256), 0, s, L, g, gated);
     LZ_NC_SWITCH(L.nc, C)
 #undef C
     trace_end(t, s);
@@ -669,11 +735,29 @@ void launch_lz_step(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double
     lz_scale(t, s, L, g, ta, vb);
 }
 
-void launch_lz_step_head(Tracer *t, hipStream_t s, const LanczosDev &L) {
+// head of a step with partial reorthogonalisation: the three-term update, b_j and
+// the device-side decision (flag[0]) on the pass
+void launch_lz_step_head(Tracer *t, hipStream_t s, const LanczosDev &L, int j) {
     const int g = lz_blocks(L);
     const double ta = (double)L.t_alg * L.nc, vb = 8.0 * ta;
     lz_head(t, s, L, g, ta, vb);
     lz_beta(t, s, L, g);
+    trace_begin(t, "lanczos_omega", s);
+    hipLaunchKernelGGL(k_lz_omega, dim3(1), dim3(LZ_OMEGA_THREADS), 0, s, L, j);
+    trace_end(t, s);
+}
+
+// a whole step with partial reorthogonalisation, no host decision: the pass
+// kernels and the second b_j are launched every step and return at once when
+// the flag is clear
+void launch_lz_step_partial(Tracer *t, hipStream_t s, const LanczosDev &L, int j, double *part2, double *h,
+                            double *part3) {
+    const int g = lz_blocks(L);
+    const double ta = (double)L.t_alg * L.nc, vb = 8.0 * ta;
+    launch_lz_step_head(t, s, L, j);
+    lz_passes(t, s, L, j, 1, g, ta, vb, part2, h, part3);
+    lz_beta(t, s, L, g, 1);
+    lz_scale(t, s, L, g, ta, vb);
 }
 
 void launch_lz_step_tail(Tracer *t, hipStream_t s, const LanczosDev &L, int j, int npass, double *part2, double *h,

@@ -346,3 +346,31 @@ def test_four_drives_match_single_recursions():
         assert np.abs(blk["b"][s] - one["b"][0]).max() <= 1e-10 * np.abs(one["a"][0]).max()
         np.testing.assert_allclose(blk["c_norm2"][s], one["c_norm2"][0], rtol=1e-12)
     ctx.close()
+
+
+def test_partial_timed_matches_gated():
+    """Partial reorthogonalisation decides on the device: the untimed step launches
+    the pass every step behind the device flag, the timed step reads the flag and
+    launches it only where it runs.  Both give the same recursion bit for bit; the
+    timed run counts the executed passes, which is fewer than the steps."""
+    from paper_1005_5340_amd import chi0
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("xz")
+    print("[lanczos] partial: timed vs gated launches", flush=True)
+    ctx = _ctx(sys)
+    kw = dict(k_max=600, reorth=chi0.LZ_REORTH_PARTIAL, tol=1e300, check_every=100, omega_check=[0.5],
+              eps=sys.eps)
+    gated = ctx.lanczos(d, **kw)
+    ctx.set_timing(True)
+    timed = ctx.lanczos(d, **kw)
+    stats = ctx.kernel_stats()
+    ctx.set_timing(False)
+    ctx.close()
+    assert np.array_equal(gated["a"], timed["a"]) and np.array_equal(gated["b"], timed["b"])
+    assert np.array_equal(gated["len"], timed["len"])
+    steps = int(timed["len"].max())
+    npass = stats["lanczos_reorth_dots"]["launches"]
+    assert stats["lanczos_omega"]["launches"] == steps
+    assert 0 < npass < steps, (npass, steps)
+    assert stats["lanczos_reorth_update"]["launches"] == npass
+    print(f"[lanczos] {steps} steps, {npass} reorthogonalisation passes", flush=True)
