@@ -2058,7 +2058,7 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
         size_t fr = 0, tot = 0;
         HIPCHK(c, hipMemGetInfo(&fr, &tot));
         const double need =
-            8.0 * (double)(nvec * n + 2 * tc + 66 * ((int64_t)kmax + 1) * nc + (ring ? 0 : LZ_GROUPS * n) +
+            8.0 * (double)(nvec * n + 2 * tc + 69 * ((int64_t)kmax + 2) * nc + (ring ? 0 : LZ_GROUPS * n) +
                            (o.n_x > 0 ? (int64_t)kmax * LZ_XCOL * 6 + (int64_t)P * (nc + 2 * LZ_XCOL) : 0));
         if (need > 0.9 * (double)fr)
             return fail(c, CHI0_ENOMEM, "the Lanczos basis does not fit in free device memory (k_max too large "
