@@ -79,17 +79,19 @@ def test_full_dimension_three_drives():
 # converge), so the plain recursion is compared over its first 8 steps.  Partial
 # reorthogonalisation keeps the basis orthogonal only to about sqrt(eps), so its
 # coefficients follow the fully reorthogonalised ones to 1e-7.
-@pytest.mark.parametrize("reorth,k,tol", [(1, 60, 1e-9), (2, 60, 1e-9), (3, 60, 1e-7), (0, 8, 1e-9)])
-def test_coefficients_match_oracle(reorth, k, tol):
-    from paper_1005_5340_amd import chi0
+# A block of three drives and single drives (the operator at three and at one
+# column) are both compared.
+@pytest.mark.parametrize("reorth,k,tol,drives", [(1, 60, 1e-9, "xyz"), (2, 60, 1e-9, "xyz"), (3, 60, 1e-7, "xyz"),
+                                                 (0, 8, 1e-9, "xyz"), (1, 60, 1e-9, "y"), (0, 8, 1e-9, "z")])
+def test_coefficients_match_oracle(reorth, k, tol, drives):
     sys = gpu_systems.get("atoms12_orb9")
-    d = sys.drives("xyz")
-    print(f"[lanczos] atoms12_orb9 coefficients reorth={reorth} k={k}", flush=True)
+    d = sys.drives(drives)
+    print(f"[lanczos] atoms12_orb9 coefficients reorth={reorth} k={k} drives={drives}", flush=True)
     ctx = _ctx(sys)
     res = ctx.lanczos(d, k_max=k, reorth=reorth)
     ctx.close()
     Om2 = lo.casida_matrix(sys)
-    for s in range(3):
+    for s in range(len(drives)):
         c = lo.start_vector(sys, d[s])
         a, b, cn2 = lo.lanczos(Om2, c, k, reorth=bool(reorth))   # the oracle: two passes
         assert int(res["len"][s]) == k
