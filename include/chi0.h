@@ -183,12 +183,32 @@ typedef struct chi0_solve_opts {
                              operator workspace, so that one lane's memory-bound Gram-Schmidt
                              passes overlap the other's matrix-core transforms */
     int32_t stop;         /* CHI0_STOP_*: the test that ends a point (default: residual) */
-    int32_t reserved;     /* must be zero */
+    int32_t alpha_form;   /* CHI0_ALPHA_*: how alpha is formed from the final iterate
+                             (default CHI0_ALPHA_CORRECTED) */
     const double *x0;     /* NULL, or DEVICE memory [n_omega][n_drive][n_prod] complex: point
                              (omega_i, drive k) starts from x0[i][k] instead of 0 (for example the
                              solution at a neighbouring frequency), unless
                              ||chi0 d - A x0|| >= ||chi0 d||, then from 0; not with `warm` */
+    int32_t mixed;        /* precision != FP64 only: CHI0_MIXED_REFINE (default) or _RELAXED */
+    double  relax;        /* CHI0_MIXED_RELAXED: switch to `precision` once the residual estimate is
+                             at most relax tol ||chi0 d|| / u, u the low-precision operator's
+                             relative error (3e-7 FP32, 6e-6 BF16X3); 0 = 1 */
 } chi0_solve_opts;
+
+/* How a low-precision operator enters the solve (precision != FP64).  Both end
+ * every cycle with an FP64 true residual, so the stopping test is unchanged.
+ *   REFINE   iterative refinement: each cycle runs all its Arnoldi steps in
+ *            low precision and ends when its residual estimate has fallen by
+ *            inner_tol (or met tol); the FP64 residual then starts the next.
+ *   RELAXED  one Krylov space as in FP64, whose operator precision is relaxed
+ *            as the residual falls (inexact Krylov: a step may apply an
+ *            operator with relative error up to ~tol ||b|| / ||r_k||): FP64
+ *            steps until the estimate reaches relax tol ||b|| / u, then
+ *            low-precision steps; the cycle ends on the estimate at tol.
+ * In both, a low-precision cycle whose true residual did not halve hands the
+ * point to FP64 steps (stats.fallback). */
+#define CHI0_MIXED_REFINE     0
+#define CHI0_MIXED_RELAXED    1
 
 /* Stopping test of a point (Sec. 4.1).
  *   RESIDUAL  the true relative residual ||chi0 d - A x|| / ||chi0 d|| <= tol
@@ -207,6 +227,22 @@ typedef struct chi0_solve_opts {
 #define CHI0_STOP_RESIDUAL    0
 #define CHI0_STOP_EPS_P       1
 #define CHI0_STOP_EPS_PX      2
+
+/* Polarizability from the final iterate x_i of drive i and its FP64 true
+ * residual r_i = chi0 d_i - A x_i (Sec. 4.1 gives the error of P = d . x as
+ * d . A^-1 r).
+ *   CORRECTED  alpha_ki = -(d_k . x_i + (d_k + K x_k) . r_i): d_k + K x_k is
+ *              A^-T d_k at the exact x_k (chi0 and K are complex symmetric, so
+ *              A^T = 1 - K chi0), so the residual term is taken to first order
+ *              and the error of alpha is second order in the residuals, where
+ *              -d_k . x_i alone is first order.  K x_k and r_i come from the
+ *              last true-residual computation of each point at no extra
+ *              operator cost.  With more than one drive the call keeps r and
+ *              d + K x of every point on the device for the cross terms:
+ *              n_omega n_drive n_prod 32 extra bytes for the call.
+ *   PLAIN      alpha_ki = -d_k . x_i (eq. eqpolarizability as written). */
+#define CHI0_ALPHA_CORRECTED  0
+#define CHI0_ALPHA_PLAIN      1
 
 /* Gram-Schmidt of the Arnoldi step (eq. orthogonal-krylov-basis, done twice).
  *   CGS2   two classical passes per step: four reads of the basis.
@@ -240,7 +276,8 @@ void chi0_solve_opts_default(chi0_solve_opts *opts);
 /*
  * Polarizability tensor over a frequency grid (Sec. 4.1 and Algorithm a:main):
  * for each omega[w] and each drive i, GMRES solves (1 - chi0 K) x = chi0 d_i
- * from x = 0, then alpha[w][k][i] = -d_k . x for every drive k.
+ * from x = 0, then alpha[w][k][i] = -d_k . x for every drive k, with the
+ * residual term of CHI0_ALPHA_CORRECTED unless opts->alpha_form says PLAIN.
  *
  *  omega    host [n_omega] (Ha).
  *  eps      broadening (Ha), > 0.

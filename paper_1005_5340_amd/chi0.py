@@ -18,7 +18,7 @@ import numpy as np
 
 __all__ = ["Chi0Error", "Context", "WarmStart", "lib", "LIB_PATH", "PREC_FP64", "PREC_FP32",
            "PREC_BF16X3", "SolveStats", "NOT_CONVERGED", "debug_eigh", "STOP_RESIDUAL", "STOP_EPS_P",
-           "STOP_EPS_PX", "LanczosOpts", "LZ_REORTH_NONE", "LZ_REORTH_FULL", "LZ_REORTH_FULL2", "LZ_REORTH_PARTIAL", "lanczos_poles"]
+           "STOP_EPS_PX", "ALPHA_CORRECTED", "ALPHA_PLAIN", "MIXED_REFINE", "MIXED_RELAXED", "LanczosOpts", "LZ_REORTH_NONE", "LZ_REORTH_FULL", "LZ_REORTH_FULL2", "LZ_REORTH_PARTIAL", "lanczos_poles"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchi0.so")
 PREC_FP64 = 0
@@ -26,6 +26,8 @@ PREC_FP32 = 1
 PREC_BF16X3 = 2
 ORTHO_AUTO, ORTHO_CGS2, ORTHO_DCGS2 = 0, 1, 2
 STOP_RESIDUAL, STOP_EPS_P, STOP_EPS_PX = 0, 1, 2
+ALPHA_CORRECTED, ALPHA_PLAIN = 0, 1
+MIXED_REFINE, MIXED_RELAXED = 0, 1
 LZ_REORTH_NONE, LZ_REORTH_FULL, LZ_REORTH_FULL2, LZ_REORTH_PARTIAL = 0, 1, 2, 3
 NOT_CONVERGED = 1
 _ERRORS = {-1: "EINVAL", -2: "ENOSYS", -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE", -6: "EASYM"}
@@ -39,7 +41,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("precision", C.c_int32), ("batch", C.c_int32), ("inner_tol", C.c_double),
                 ("warm", C.c_void_p), ("ortho", C.c_int32), ("lanes", C.c_int32),
-                ("stop", C.c_int32), ("reserved", C.c_int32), ("x0", C.c_void_p)]
+                ("stop", C.c_int32), ("alpha_form", C.c_int32), ("x0", C.c_void_p),
+                ("mixed", C.c_int32), ("relax", C.c_double)]
 
 
 class WsCfg(C.Structure):
@@ -281,7 +284,8 @@ class Context:
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
                        tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,
                        inner_tol: float = 0.0, warm: "WarmStart" = None, ortho: int = ORTHO_AUTO,
-                       return_x: bool = False, lanes: int = 0, stop: int = STOP_RESIDUAL, x0=None):
+                       return_x: bool = False, lanes: int = 0, stop: int = STOP_RESIDUAL, x0=None,
+                       alpha_form: int = ALPHA_CORRECTED, mixed: int = MIXED_REFINE, relax: float = 0.0):
         """GMRES polarizability over a frequency grid.
 
         Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
@@ -300,6 +304,8 @@ class Context:
         o.ortho = int(ortho)
         o.lanes = int(lanes)
         o.stop = int(stop)
+        o.alpha_form = int(alpha_form)
+        o.mixed, o.relax = int(mixed), float(relax)
         if x0 is not None:
             import torch
             n_prod = self.sizes()["n_prod"]

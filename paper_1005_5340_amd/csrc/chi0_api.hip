@@ -735,10 +735,10 @@ static int ensure_lp(chi0_ctx *c, OpWork &o) {
 
 // Y = chi0(omega) Zin for nb column pairs already in Zin; omega: device [nb].
 // prec selects the arithmetic of the orbital transforms (ensure_lp first).
+// t, tu: the tracer and GEMM tuner to use (the context's; NULL for none).
 static void run_chi0(chi0_ctx *c, OpWork &o, hipStream_t s, int nb, double eps, int prec,
-                     const double *omega) {
+                     const double *omega, Tracer *t, GemmTuner *tu) {
     const int nc = 2 * nb;
-    Tracer *t = &c->tracer;
     const WorkSizes &w = c->ws;
     const int64_t mcol = (int64_t)c->No_pad * nc;
     // algorithmic work of the two dense transforms (unpadded sizes)
@@ -750,10 +750,10 @@ static void run_chi0(chi0_ctx *c, OpWork &o, hipStream_t s, int nb, double eps, 
                              o.at, (int)mcol, c->Dlt, c->Nv_pad, omega, eps, c->occ, nc,
                              fl + 6.0 * w.No * w.Nv * nb,
                              8.0 * (w.N * w.No * nc + w.Nv * w.No * nc + w.N * w.Nv + w.No * w.Nv),
-                             o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
+                             o.gemm_scratch, o.gemm_scratch_n, tu);
         launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, o.at, (int)mcol,
                      o.Ut, (int)mcol, fl, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv),
-                     o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
+                     o.gemm_scratch, o.gemm_scratch_n, tu);
         launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, o.Ut, o.W, nc, w);
     } else {
         launch_occ_transform_f32(t, s, c->bm, c->n_atoms, c->Xo32, c->No_pad, o.dV, o.Tt32, nc, w);
@@ -763,10 +763,10 @@ static void run_chi0(chi0_ctx *c, OpWork &o, hipStream_t s, int nb, double eps, 
         if (prec == CHI0_PREC_FP32) {
             launch_sgemm(t, s, "virt_transform_lorentz_f32", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt32,
                          c->N_pad, o.Tt32, (int)mcol, o.at32, (int)mcol, fl + 6.0 * w.No * w.Nv * nb,
-                         by + 4.0 * w.N * w.Nv, &la, o.gemm_scratch, sb, &c->tuner);
+                         by + 4.0 * w.N * w.Nv, &la, o.gemm_scratch, sb, tu);
             launch_sgemm(t, s, "virt_back_f32", c->N_pad, (int)mcol, c->Nv_pad, c->Xv32, c->Nv_pad,
                          o.at32, (int)mcol, o.Ut32, (int)mcol, fl, by + 4.0 * w.N * w.Nv, nullptr,
-                         o.gemm_scratch, sb, &c->tuner);
+                         o.gemm_scratch, sb, tu);
         } else {   // split BF16 x 3: three BF16 products per multiply-add
             launch_bgemm3(t, s, "virt_transform_lorentz_bf16x3", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt_hi,
                           c->Xvt_lo, c->N_pad, o.Tt32, (int)mcol, o.Bhi, o.Blo, o.at32, (int)mcol, 3.0 * fl,
@@ -781,6 +781,9 @@ static void run_chi0(chi0_ctx *c, OpWork &o, hipStream_t s, int nb, double eps, 
 }
 
 static const int kMaxBatch = 256;   // complex columns per operator pass
+// normwise relative error of one low-precision chi0 application (measured on
+// the test systems: ~3e-7 with FP32 transforms, ~5-7e-6 with split BF16 x 3)
+static const double kOpErrFP32 = 3e-7, kOpErrBF16X3 = 6e-6;
 
 extern "C" int chi0_apply(chi0_ctx *c, int32_t n_rhs, const double *omega, double eps,
                           const double *z, double *out, int32_t precision, void *stream) {
@@ -815,7 +818,7 @@ extern "C" int chi0_apply(chi0_ctx *c, int32_t n_rhs, const double *omega, doubl
             hipGraph_t g = nullptr;
             HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
             launch_rows_to_cols(&c->tracer, c->cap_stream, z, n_rhs, c->P, ow.Zin, nc);
-            run_chi0(c, ow, c->cap_stream, n_rhs, eps, precision, ow.omega_dev);
+            run_chi0(c, ow, c->cap_stream, n_rhs, eps, precision, ow.omega_dev, &c->tracer, &c->tuner);
             launch_cols_to_rows(&c->tracer, c->cap_stream, ow.Yout, n_rhs, c->P, nc, out);
             HIPCHK(c, hipStreamEndCapture(c->cap_stream, &g));
             const hipError_t e = hipGraphInstantiate(&c->apply_exec, g, nullptr, nullptr, 0);
@@ -837,7 +840,7 @@ extern "C" int chi0_apply(chi0_ctx *c, int32_t n_rhs, const double *omega, doubl
         const int nb = std::min(cap, n_rhs - r0), nc = 2 * nb;
         HIPCHK(c, hipMemcpyAsync(ow.omega_dev, omega + r0, (size_t)nb * 8, hipMemcpyHostToDevice, s));
         launch_rows_to_cols(&c->tracer, s, z + (int64_t)r0 * c->P * 2, nb, c->P, ow.Zin, nc);
-        run_chi0(c, ow, s, nb, eps, precision, ow.omega_dev);
+        run_chi0(c, ow, s, nb, eps, precision, ow.omega_dev, &c->tracer, &c->tuner);
         launch_cols_to_rows(&c->tracer, s, ow.Yout, nb, c->P, nc, out + (int64_t)r0 * c->P * 2);
     }
     HIPCHK(c, hipGetLastError());
@@ -876,6 +879,7 @@ static int ensure_slots(chi0_ctx *c, int n, int m) {
     CHK(dalloc(c, b, &sl.b, (int64_t)n * c->P_pad * 2));
     CHK(dalloc(c, b, &sl.hbuf, (int64_t)n * sl.hbstride));
     CHK(dalloc(c, b, &sl.y, (int64_t)n * m * 2));
+    CHK(dalloc(c, b, &sl.w, (int64_t)n * c->P_pad * 2));
     const int64_t ab = (int64_t)n * (sizeof(Job) + sizeof(double));
     double *arena = nullptr;
     CHK(dalloc(c, b, &arena, kSets * ab / 8));
@@ -1013,7 +1017,10 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     if (o.precision < CHI0_PREC_FP64 || o.precision > CHI0_PREC_BF16X3)
         return fail(c, CHI0_EINVAL, "unknown precision");
     if (!(o.inner_tol >= 0.0) || !(o.inner_tol < 1.0)) return fail(c, CHI0_EINVAL, "inner_tol must be in [0, 1)");
-    if (o.reserved != 0) return fail(c, CHI0_EINVAL, "reserved option fields must be zero");
+    if (o.mixed != CHI0_MIXED_REFINE && o.mixed != CHI0_MIXED_RELAXED) return fail(c, CHI0_EINVAL, "unknown mixed");
+    if (!(o.relax >= 0.0) || !std::isfinite(o.relax)) return fail(c, CHI0_EINVAL, "relax must be finite and >= 0");
+    if (o.alpha_form != CHI0_ALPHA_CORRECTED && o.alpha_form != CHI0_ALPHA_PLAIN)
+        return fail(c, CHI0_EINVAL, "unknown alpha_form");
     if (o.stop < CHI0_STOP_RESIDUAL || o.stop > CHI0_STOP_EPS_PX) return fail(c, CHI0_EINVAL, "unknown stop");
     if (o.lanes < 0 || o.lanes > kLanes) return fail(c, CHI0_EINVAL, "lanes must be 0 (auto) or 1..4");
     if (o.ortho < CHI0_ORTHO_AUTO || o.ortho > CHI0_ORTHO_DCGS2) return fail(c, CHI0_EINVAL, "unknown ortho");
@@ -1032,6 +1039,12 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     const bool warm_any = ws || x0;
     const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol
                              : (o.precision == CHI0_PREC_FP32 ? 1e-6 : 1e-4);
+    // relaxed low precision: a point's Arnoldi steps leave FP64 once the
+    // residual estimate is at most relax_at ||b|| (the operator error allowed
+    // by tol ||b|| / ||r|| has then grown to the low-precision operator's own)
+    const bool relaxed = o.precision != CHI0_PREC_FP64 && o.mixed == CHI0_MIXED_RELAXED;
+    const double relax_at = (o.relax > 0.0 ? o.relax : 1.0) * o.tol /
+                            (o.precision == CHI0_PREC_FP32 ? kOpErrFP32 : kOpErrBF16X3);
     if (!all_finite(omega, n_omega)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
     if (!all_finite(V_ext, (int64_t)n_drive * c->P)) return fail(c, CHI0_ENONFINITE, "non-finite V_ext");
     HIPCHK(c, hipSetDevice(c->device));
@@ -1041,12 +1054,31 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     // provisional column, so it gets one more basis vector
     const int m = o.restart + (dcgs ? 1 : 0);
     const int P = c->P;
+    // per-call device buffers: drives, alpha, and the residuals r and adjoint
+    // vectors d + K x of every point for the cross-drive residual terms
+    DevBuf callbuf;
+    // on every exit (also an error with steps in flight) drain the lanes first
+    struct Guard {
+        DevBuf *b;
+        chi0_ctx *c;
+        ~Guard() {
+            for (hipStream_t ls : c->lane_stream)
+                if (ls) (void)hipStreamSynchronize(ls);
+            b->release();
+        }
+    } guard{&callbuf, c};
+    const bool correct = o.alpha_form == CHI0_ALPHA_CORRECTED;
+    double *Rst = nullptr, *Wst = nullptr;
+    if (correct && n_drive > 1) {
+        CHK(dalloc(c, callbuf, &Rst, (int64_t)npts * P * 2));
+        CHK(dalloc(c, callbuf, &Wst, (int64_t)npts * P * 2));
+    }
     // Concurrent slots: the batch, capped so that the slots' Krylov bases and
     // Hessenberg matrices (and R^-1 of the error estimates) fit in the device
     // memory that is free, less a reserve for the operator workspaces.
     int nsl = std::min(std::min(o.batch, npts), kMaxBatch);
     if (!(c->slot_n >= nsl && c->slot_m == m)) {
-        const double per_slot = 8.0 * (2.0 * (m + 1) * c->P_pad + (double)m * (m + 3) + 4.0 * c->P_pad +
+        const double per_slot = 8.0 * (2.0 * (m + 1) * c->P_pad + (double)m * (m + 3) + 6.0 * c->P_pad +
                                        16.0 * m + 16.0) +
                                 (o.stop != CHI0_STOP_RESIDUAL ? 8.0 * ((double)m * (m + 1) + 8.0 * m + 16.0) : 0.0);
         size_t free_b = 0, total_b = 0;
@@ -1072,18 +1104,6 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     CHK(ensure_slots(c, nsl, m));
     Tracer *t = &c->tracer;
 
-    // per-call device buffers: drives and alpha
-    DevBuf callbuf;
-    // on every exit (also an error with steps in flight) drain the lanes first
-    struct Guard {
-        DevBuf *b;
-        chi0_ctx *c;
-        ~Guard() {
-            for (hipStream_t ls : c->lane_stream)
-                if (ls) (void)hipStreamSynchronize(ls);
-            b->release();
-        }
-    } guard{&callbuf, c};
     double *drives = nullptr, *alpha_dev = nullptr;
     CHK(dalloc(c, callbuf, &drives, (int64_t)n_drive * c->P_pad));
     CHK(dalloc(c, callbuf, &alpha_dev, (int64_t)npts * n_drive * 2));
@@ -1185,8 +1205,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                              nc, 2.0 * P * (double)P * nc, 8.0 * ((double)P * P + 2.0 * P * nc),
                              ow.gemm_scratch, ow.gemm_scratch_n, &c->tuner);
             launch_put_drive(t, s, jg, gn, drives, c->P_pad, ow.Zin, nc, P);
-            run_chi0(c, ow, s, gn, eps, prec, om_d + g0);
-            launch_post_jobs(t, s, jg, gn, c->slots, ow.Yout, nc, P, st_d + g0);
+            run_chi0(c, ow, s, gn, eps, prec, om_d + g0, t, &c->tuner);
+            launch_post_jobs(t, s, jg, gn, c->slots, ow.Yout, ow.Zin, drives, nc, P, st_d + g0);
         };
         if (nb64 > 0) run_group(0, nb64, CHI0_PREC_FP64);
         if (nb > nb64) run_group(nb64, nb - nb64, o.precision);
@@ -1201,6 +1221,11 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
         HIPCHK(c, hipMemcpyAsync(c->status_h + q * nsl, st_d, sizeof(StepStatus) * nb, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipEventRecord(c->step_ev[q], s));
         return CHI0_OK;
+    };
+
+    // relaxed low precision: the arithmetic a cycle starts in, from its residual norm
+    auto start_prec = [&](double rnorm, double bnorm) {
+        return rnorm <= relax_at * bnorm ? o.precision : (int32_t)CHI0_PREC_FP64;
     };
 
     // Advance the slot state machines of lane L with the status of its step in set q.
@@ -1219,7 +1244,12 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 ss.pend -= 1;
                 pt.iters += 1;
                 double stop = o.tol * ss.bnorm;
-                if (ss.prec != CHI0_PREC_FP64) stop = std::max(stop, inner_tol * ss.cycle0);
+                if (relaxed) {
+                    if (ss.prec == CHI0_PREC_FP64 && !pt.fallback && st.value <= relax_at * ss.bnorm)
+                        ss.prec = o.precision;   // for the steps launched from now on
+                } else if (ss.prec != CHI0_PREC_FP64) {
+                    stop = std::max(stop, inner_tol * ss.cycle0);
+                }
                 const bool brk = st.hnext == 0.0;
                 if (brk) pt.breakdown = 1;
                 // CGS2: the step completes column j (dimension j+1).  Delayed
@@ -1248,7 +1278,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 ss.bnorm = st.value;
                 ss.cycle0 = st.value;
                 ss.rel_prev = 1.0;
-                ss.prec = o.precision;
+                ss.prec = relaxed ? start_prec(ss.cycle0, ss.bnorm) : o.precision;
                 if (!(st.value > 0.0) || !std::isfinite(st.value)) {
                     pt.rel = st.value == 0.0 ? 0.0 : NAN;
                     pt.converged = st.value == 0.0;
@@ -1287,6 +1317,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                     pt.warm = 1;
                     ss.cycle0 = st.value;
                     ss.rel_prev = rel0;
+                    if (relaxed) ss.prec = start_prec(ss.cycle0, ss.bnorm);
                     ss.state = S_ARNOLDI;
                     ss.j = 0;
                     ss.pend = 0;
@@ -1305,6 +1336,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                     if (ss.prec != CHI0_PREC_FP64 && pt.rel > 0.5 * ss.rel_prev) {
                         ss.prec = CHI0_PREC_FP64;
                         pt.fallback = 1;
+                    } else if (relaxed && !pt.fallback) {   // by the residual the new cycle starts from
+                        ss.prec = start_prec(st.value, ss.bnorm);
                     }
                     ss.rel_prev = pt.rel;
                     ss.cycle0 = st.value;
@@ -1337,8 +1370,8 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
         if (!ln.fin.empty()) {
             std::copy(ln.fin.begin(), ln.fin.end(), fin_h);
             HIPCHK(c, hipMemcpyAsync(fin_d, fin_h, sizeof(Job) * ln.fin.size(), hipMemcpyHostToDevice, s));
-            launch_alpha(t, s, fin_d, (int)ln.fin.size(), c->slots, drives, n_drive, c->P_pad, P, nullptr,
-                         alpha_dev);
+            launch_alpha(t, s, fin_d, (int)ln.fin.size(), c->slots, drives, n_drive, c->P_pad, P, correct,
+                         Rst, Wst, alpha_dev);
             if (x_out) launch_store_x(s, fin_d, (int)ln.fin.size(), c->slots, P, x_out);
             ln.fin.clear();
         }
@@ -1431,6 +1464,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     for (int L = 0; L < nl; ++L) CHK(issue_pending(L, lanes[L].last_q));   // alpha of the last points
     for (int L = 0; L < nl; ++L) HIPCHK(c, hipStreamSynchronize(c->lane_stream[L]));
     hipStream_t s = c->stream;
+    if (Rst) launch_alpha_cross(t, s, n_omega, n_drive, P, Rst, Wst, alpha_dev);
     std::vector<double> ah((size_t)npts * n_drive * 2);
     HIPCHK(c, hipMemcpyAsync(ah.data(), alpha_dev, ah.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));

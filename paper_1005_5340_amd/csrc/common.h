@@ -170,6 +170,7 @@ struct SlotsDev {
     double *b;        // [n_slots][P_pad] complex
     double *hbuf;     // [n_slots][hbstride] scratch for Gram-Schmidt coefficients (>= 3m+4 complex)
     double *y;        // [n_slots][m] complex least-squares solution
+    double *w;        // [n_slots][P_pad] complex: d + K x of the last true residual (d after b)
     int64_t vstride;  // doubles between slots in V  = (m+1)*P_pad*2
     int64_t hstride;  // doubles between slots in H
     int64_t hbstride; // doubles between slots in hbuf
@@ -206,8 +207,10 @@ void launch_gather_jobs(Tracer *t, hipStream_t s, const Job *jobs, int nb, const
                         double *Vb, int ncp, int P);
 void launch_put_drive(Tracer *t, hipStream_t s, const Job *jobs, int nb, const double *drives,
                       int P_pad, double *Zin, int ncp, int P);
+// Y = chi0 Zin; Zin = K x (residual jobs) or d (b jobs); drives [n_drive][P_pad].
 void launch_post_jobs(Tracer *t, hipStream_t s, const Job *jobs, int nb, const SlotsDev &sl,
-                      const double *Y, int ncp, int P, StepStatus *status);
+                      const double *Y, const double *Zin, const double *drives, int ncp, int P,
+                      StepStatus *status);
 void launch_arnoldi(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax,
                     const SlotsDev &sl, int P, StepStatus *status, int n_arnoldi, double sum_j1);
 // Arnoldi step with delayed reorthogonalisation (two passes over the basis).
@@ -218,9 +221,16 @@ void launch_dcgs(Tracer *t, hipStream_t s, const Job *jobs, int nb, int jmax, co
                  size_t scratch_doubles = 0, const EpsDev *eps = nullptr);
 void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
                      const SlotsDev &sl, int P, double sum_L);
+// alpha[p][k] = -d_k . x of each finished point p (jobs[q].j); with `correct`
+// the first-order term -(d_i + K x) . r of the point's own drive i is added
+// to alpha[p][i] (r = the last true residual).  Rst, Wst (NULL, or
+// [npts][P] complex) receive r and d_i + K x for the cross-drive terms.
 void launch_alpha(Tracer *t, hipStream_t s, const Job *jobs, int n, const SlotsDev &sl,
-                  const double *drives, int n_drive, int P_pad, int P, const int32_t *out_index,
-                  double *alpha_out);
+                  const double *drives, int n_drive, int P_pad, int P, bool correct,
+                  double *Rst, double *Wst, double *alpha_out);
+// alpha[(w, i)][k] -= Wst[(w, k)] . Rst[(w, i)] for k != i (every frequency w).
+void launch_alpha_cross(Tracer *t, hipStream_t s, int n_omega, int n_drive, int P, const double *Rst,
+                        const double *Wst, double *alpha_out);
 // learned warm start (kernels_mlp.hip)
 void launch_mlp_gemm(hipStream_t s, int M, int N, int K, const float *A, int sam, int sak,
                      const float *B, int sbk, int sbn, float *C, int ldc);

@@ -93,8 +93,12 @@ void launch_put_drive(Tracer *t, hipStream_t s, const Job *jobs, int nb, const d
 // ----------------------------------------------------------------- post step
 // RHS:     b = Y, x = 0 (kept if warm), r = b.   ARNOLDI: w = v_j - Y -> V[j+1].
 // RESID:   r = b - (x - Y).                RHS/RESID: V[0] = r/||r||, g0 = ||r||.
+// RHS/RESID also keep wa = d + K x (Zin = K x for a residual job; d alone
+// after b): the solution of the transposed system A^T wa = d for the exact x,
+// which the polarizability's first-order residual term uses.
 __global__ __launch_bounds__(256)
-void k_post_jobs(const Job *__restrict__ jobs, SlotsDev sl, const double *__restrict__ Y, int nc,
+void k_post_jobs(const Job *__restrict__ jobs, SlotsDev sl, const double *__restrict__ Y,
+                 const double *__restrict__ Zin, const double *__restrict__ drives, int nc,
                  int P, StepStatus *__restrict__ st) {
     __shared__ double sh[4];
     const int q = blockIdx.x, t = threadIdx.x;
@@ -112,6 +116,8 @@ void k_post_jobs(const Job *__restrict__ jobs, SlotsDev sl, const double *__rest
     }
     double2 *x = reinterpret_cast<double2 *>(sl.x + jb.slot * vlen);
     double2 *b = reinterpret_cast<double2 *>(sl.b + jb.slot * vlen);
+    double2 *wa = reinterpret_cast<double2 *>(sl.w + jb.slot * vlen);
+    const double *d = drives + (int64_t)jb.drive * sl.P_pad;
     double2 *v0 = reinterpret_cast<double2 *>(V);
     double ss = 0.0;
     for (int mu = t; mu < P; mu += 256) {
@@ -121,10 +127,12 @@ void k_post_jobs(const Job *__restrict__ jobs, SlotsDev sl, const double *__rest
             b[mu] = make_double2(yr, yi);
             if (jb.j == 0) x[mu] = make_double2(0.0, 0.0);   // else a warm start is in x
             rr = yr; ri = yi;
+            wa[mu] = make_double2(d[mu], 0.0);
         } else {
             const double2 bb = b[mu], xx = x[mu];
             rr = bb.x - (xx.x - yr);
             ri = bb.y - (xx.y - yi);
+            wa[mu] = make_double2(d[mu] + Zin[(int64_t)mu * nc + 2 * q], Zin[(int64_t)mu * nc + 2 * q + 1]);
         }
         v0[mu] = make_double2(rr, ri);
         ss += rr * rr + ri * ri;
@@ -144,9 +152,10 @@ void k_post_jobs(const Job *__restrict__ jobs, SlotsDev sl, const double *__rest
 }
 
 void launch_post_jobs(Tracer *t, hipStream_t s, const Job *jobs, int nb, const SlotsDev &sl,
-                      const double *Y, int nc, int P, StepStatus *status) {
+                      const double *Y, const double *Zin, const double *drives, int nc, int P,
+                      StepStatus *status) {
     trace_begin(t, "post_jobs", s);
-    hipLaunchKernelGGL(k_post_jobs, dim3(nb), dim3(256), 0, s, jobs, sl, Y, nc, P, status);
+    hipLaunchKernelGGL(k_post_jobs, dim3(nb), dim3(256), 0, s, jobs, sl, Y, Zin, drives, nc, P, status);
     trace_end(t, s);
 }
 
@@ -1075,13 +1084,24 @@ void launch_update_x(Tracer *t, hipStream_t s, const Job *jobs, int n, int jmax,
 
 // ------------------------------------------------------------ polarizability
 // alpha[point][k] = -d_k . x  (bilinear, eq. eqpolarizability with alpha = -P);
-// jobs[q].j holds the point index.
+// jobs[q].j holds the point index, whose drive is i = point % n_drive.
+//
+// Residual term (Sec. 4.1 writes the error of P as d . A^-1 r): A^-T d_k is
+// d_k + K x_k exactly at the solution x_k of drive k, because chi0 and K are
+// complex symmetric (A^T = 1 - K chi0 and (1 - K chi0)(d + K x) = d when
+// (1 - chi0 K) x = chi0 d).  So P_ki = d_k . x_i + (d_k + K x_k) . r_i holds
+// up to (K (x_k* - x_k)) . r_i, second order in the residuals.  With
+// `correct` the diagonal term (k = i, both factors from this slot: r =
+// g_0 V_0 and wa = d_i + K x_i of its last FP64 true residual) is added here;
+// Rst / Wst keep r and wa of the point for the cross terms (k != i).
 __global__ __launch_bounds__(256)
 void k_alpha(const Job *__restrict__ jobs, SlotsDev sl, const double *__restrict__ drives,
-             int n_drive, int P_pad, int P, double *__restrict__ out) {
+             int n_drive, int P_pad, int P, int correct, double *__restrict__ Rst,
+             double *__restrict__ Wst, double *__restrict__ out) {
     __shared__ double sh[4];
     const int q = blockIdx.x, t = threadIdx.x;
     const Job jb = jobs[q];
+    const int64_t p = jb.j;
     const double2 *x = reinterpret_cast<const double2 *>(sl.x + (int64_t)jb.slot * P_pad * 2);
     for (int k = 0; k < n_drive; ++k) {
         const double *d = drives + (int64_t)k * P_pad;
@@ -1094,18 +1114,73 @@ void k_alpha(const Job *__restrict__ jobs, SlotsDev sl, const double *__restrict
         re = block_sum(re, sh);
         im = block_sum(im, sh);
         if (t == 0) {
-            out[((int64_t)jb.j * n_drive + k) * 2] = -re;
-            out[((int64_t)jb.j * n_drive + k) * 2 + 1] = -im;
+            out[(p * n_drive + k) * 2] = -re;
+            out[(p * n_drive + k) * 2 + 1] = -im;
         }
+    }
+    if (!correct) return;
+    const double2 *v0 = reinterpret_cast<const double2 *>(sl.V + jb.slot * sl.vstride);
+    const double2 *wa = reinterpret_cast<const double2 *>(sl.w + (int64_t)jb.slot * P_pad * 2);
+    const double g0 = sl.g[(int64_t)jb.slot * (sl.m + 1) * 2];   // ||r||; v0 = r / ||r||
+    double re = 0.0, im = 0.0;
+    for (int mu = t; mu < P; mu += 256) {
+        const double2 v = v0[mu], w = wa[mu];
+        const double2 r = make_double2(g0 * v.x, g0 * v.y);
+        re += w.x * r.x - w.y * r.y;
+        im += w.x * r.y + w.y * r.x;
+        if (Rst) {
+            reinterpret_cast<double2 *>(Rst)[p * P + mu] = r;
+            reinterpret_cast<double2 *>(Wst)[p * P + mu] = w;
+        }
+    }
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    if (t == 0) {
+        const int64_t i = p % n_drive;
+        out[(p * n_drive + i) * 2] -= re;
+        out[(p * n_drive + i) * 2 + 1] -= im;
     }
 }
 
 void launch_alpha(Tracer *t, hipStream_t s, const Job *jobs, int n, const SlotsDev &sl,
-                  const double *drives, int n_drive, int P_pad, int P, const int32_t *out_index,
-                  double *alpha_out) {
-    (void)out_index;
+                  const double *drives, int n_drive, int P_pad, int P, bool correct,
+                  double *Rst, double *Wst, double *alpha_out) {
     trace_begin(t, "alpha", s);
-    hipLaunchKernelGGL(k_alpha, dim3(n), dim3(256), 0, s, jobs, sl, drives, n_drive, P_pad, P, alpha_out);
+    hipLaunchKernelGGL(k_alpha, dim3(n), dim3(256), 0, s, jobs, sl, drives, n_drive, P_pad, P, correct ? 1 : 0,
+                       Rst, Wst, alpha_out);
+    trace_end(t, s);
+}
+
+// Cross-drive residual terms: one workgroup per (frequency w, drive k, drive i != k).
+__global__ __launch_bounds__(256)
+void k_alpha_cross(int n_drive, int P, const double *__restrict__ Rst, const double *__restrict__ Wst,
+                   double *__restrict__ out) {
+    __shared__ double sh[4];
+    const int w = blockIdx.x, k = blockIdx.y, i = blockIdx.z, t = threadIdx.x;
+    if (k == i) return;
+    const int64_t pi = (int64_t)w * n_drive + i, pk = (int64_t)w * n_drive + k;
+    const double2 *r = reinterpret_cast<const double2 *>(Rst) + pi * P;
+    const double2 *wa = reinterpret_cast<const double2 *>(Wst) + pk * P;
+    double re = 0.0, im = 0.0;
+    for (int mu = t; mu < P; mu += 256) {
+        const double2 a = wa[mu], b = r[mu];
+        re += a.x * b.x - a.y * b.y;
+        im += a.x * b.y + a.y * b.x;
+    }
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    if (t == 0) {
+        out[(pi * n_drive + k) * 2] -= re;
+        out[(pi * n_drive + k) * 2 + 1] -= im;
+    }
+}
+
+void launch_alpha_cross(Tracer *t, hipStream_t s, int n_omega, int n_drive, int P, const double *Rst,
+                        const double *Wst, double *alpha_out) {
+    if (n_drive < 2 || n_omega < 1) return;
+    trace_begin(t, "alpha_cross", s);
+    hipLaunchKernelGGL(k_alpha_cross, dim3(n_omega, n_drive, n_drive), dim3(256), 0, s, n_drive, P, Rst, Wst,
+                       alpha_out);
     trace_end(t, s);
 }
 

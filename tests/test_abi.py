@@ -106,6 +106,7 @@ def test_default_options(L):
     o = chi0.SolveOpts()
     L.chi0_solve_opts_default(C.byref(o))
     assert (o.restart, o.max_iter, o.tol, o.precision, o.batch) == (30, 10000, 1e-10, 0, 1)
+    assert o.alpha_form == chi0.ALPHA_CORRECTED
 
 
 def test_timing_filter_on_host_context(L):

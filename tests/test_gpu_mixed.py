@@ -13,8 +13,13 @@ from oracle import chi0_oracle as orc
 
 pytestmark = pytest.mark.gpu
 
-# normwise relative error bounds of one chi0 application
-BOUND = {1: 2e-5, 2: 2e-3}
+# normwise relative error bounds of one chi0 application (derived and checked
+# against an emulation of the arithmetic in test_mixed_bounds.py: a split
+# BF16 product that lost a cross term would be ~60x above its bound), and
+# floors that show the reduced arithmetic really ran (FP32 ~3e-7, BF16 x 3
+# ~5e-6 observed; an FP64 transform would be ~1e-15)
+BOUND = {1: 3e-6, 2: 3e-5}
+FLOOR = {1: 1e-9, 2: 1e-7}
 
 
 def _ctx(sys):
@@ -38,7 +43,7 @@ def test_low_precision_operator(prec, name, n_rhs):
                 for k, w in enumerate(om))
     print(f"[mixed] {name} prec={prec} worst operator rel err {worst:.2e}", flush=True)
     assert worst < BOUND[prec]
-    assert worst > 1e-13    # really ran in reduced precision
+    assert worst > FLOOR[prec]    # really ran in reduced precision
     ctx.close()
 
 

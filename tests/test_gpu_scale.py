@@ -4,11 +4,12 @@
 * the operator chi0(w) z is compared with stored oracle values on sampled
   entries (tests/golden/make_sampled_apply.py, matrix-free oracle) for seeded
   random vectors and the three dipole drives, and
-* batched x/y/z solves are checked by properties that hold at any size: the
-  residual of eq. sle recomputed outside the solver (chi0 through chi0_apply,
-  whose values the first test ties to the oracle, and K x in torch FP64), the
-  polarizability identity alpha_ki = -d_k . x_i, the symmetry alpha_ki = alpha_ik
-  and Im alpha_ii >= 0 for w > 0.
+* batched x/y/z solves are checked against the oracle's dense solve at the
+  frequencies stored in tests/golden/reference_atoms200_orb9_s0.json, and by
+  properties that hold at any size: the residual of eq. sle recomputed
+  outside the solver (chi0 through chi0_apply, whose values the first test
+  ties to the oracle, and K x in torch FP64), alpha from x and that residual,
+  the symmetry alpha_ki = alpha_ik and Im alpha_ii >= 0 for w > 0.
 """
 import json
 import os
@@ -58,8 +59,19 @@ def test_apply_sampled_entries_match_oracle(big):
 
 
 def test_batched_xyz_solve_at_full_size(big):
+    """Unrestarted x/y/z solves at the frequencies of the stored oracle
+    reference (tests/golden/reference_atoms200_orb9_s0.json, dense chi0 + LU)
+    at the workload's tolerance 1e-10: every diagonal element within 1e-10 of
+    the oracle in floored Im alpha, the whole tensor within 1e-10 of its
+    largest element; and properties that hold at any size: the residual of
+    eq. sle recomputed outside the solver, alpha from x and that residual
+    (the Sec. 4.1 residual term), alpha_ki = alpha_ik and Im alpha_ii >= 0."""
     torch, s, ctx, rec = big
-    om = np.asarray(rec["omega"])
+    gold = json.load(open(os.path.join(os.path.dirname(GOLD), "reference_atoms200_orb9_s0.json")))
+    assert synth.same_inputs(s, gold["fingerprint"]) and gold["drives"] == "xyz"
+    ref = np.array(gold["alpha_re"]) + 1j * np.array(gold["alpha_im"])
+    om = s.omegas[np.asarray(gold["omega_index"])]
+    assert np.allclose(om, gold["omega"], rtol=0, atol=1e-15)
     D = s.drives("xyz")
     tol = 1e-10
     # unrestarted GMRES, as the benchmark runs it: bases of up to 12k vectors
@@ -68,11 +80,17 @@ def test_batched_xyz_solve_at_full_size(big):
     print(f"[scale] iterations {st['iterations'].ravel().tolist()} rel {st['rel_residual'].ravel()}", flush=True)
     assert rc == 0 and st["converged"].all()
     assert (st["rel_residual"] <= tol).all()
-    # alpha_ki = -d_k . x_i, bilinear
-    al = -np.einsum("kp,wip->wki", D, x)
-    assert np.max(np.abs(al - a)) <= 1e-12 * np.max(np.abs(a))
+    for i in range(3):
+        e = im_err(a[:, i, i], ref[:, i, i])
+        print(f"[scale] drive {'xyz'[i]}: floored Im alpha error vs oracle {e.tolist()}", flush=True)
+        assert e.max() <= 1e-10
+    tr = np.einsum("wii->w", a)
+    etr = im_err(tr, np.einsum("wii->w", ref))
+    print(f"[scale] Tr alpha: floored Im error {etr.tolist()}", flush=True)
+    assert etr.max() <= 1e-10
+    assert np.max(np.abs(a - ref)) <= 1e-10 * np.max(np.abs(ref))
     # symmetric tensor, absorption
-    assert np.max(np.abs(a - np.swapaxes(a, 1, 2))) <= 1e-8 * np.max(np.abs(a))
+    assert np.max(np.abs(a - np.swapaxes(a, 1, 2))) <= 1e-10 * np.max(np.abs(a))
     assert (np.einsum("wii->wi", a).imag >= 0).all()
     # residual of eq. sle outside the solver: b = chi0 d, A x = x - chi0 (K x)
     K = torch.from_numpy(s.K).cuda()
@@ -85,5 +103,14 @@ def test_batched_xyz_solve_at_full_size(big):
         rel = (torch.linalg.norm(r, dim=1) / torch.linalg.norm(b, dim=1)).cpu().numpy()
         print(f"[scale] omega={w}: recomputed residual {rel}", flush=True)
         assert (rel <= 2 * tol).all()
+        # alpha_ki = -(d_k . x_i + (d_k + K x_k) . r_i), bilinear
+        Xh, KXh, Rh = X.cpu().numpy(), KX.cpu().numpy(), r.cpu().numpy()
+        al = -(D @ Xh.T + (D + KXh) @ Rh.T)
+        assert np.max(np.abs(al - a[k])) <= 1e-12 * np.max(np.abs(a))
     del K
     torch.cuda.empty_cache()
+
+
+def im_err(a, ref):
+    floor = 1e-3 * np.max(np.abs(np.asarray(ref).imag))
+    return np.abs(np.asarray(a).imag - np.asarray(ref).imag) / np.maximum(np.abs(np.asarray(ref).imag), floor)
