@@ -144,6 +144,28 @@ int chi0_apply(chi0_ctx *ctx, int32_t n_rhs, const double *omega, double eps,
                const double *z, double *out, int32_t precision, void *stream);
 
 /*
+ * chi0_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same FP64 operator (precision is always CHI0_PREC_FP64), with every
+ * workspace buffer taken from a static device array of
+ * CHI0_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from its first
+ * chi0_create on that GPU until the process ends; the call itself allocates
+ * nothing (no hipMalloc, no events, no tile tuning).  Results equal
+ * chi0_apply's up to rounding (the GEMMs' split-K partial sums may differ).
+ *
+ *  omega, eps, z, out, stream   as for chi0_apply (z, out DEVICE buffers).
+ * The array is shared by every context and call on the GPU and keeps the last
+ * call's contents (each call clears what it needs): calls that overlap on one
+ * GPU (two streams, two threads) race and must be serialised by the caller.
+ * Errors: as chi0_apply, and CHI0_EINVAL when n_rhs needs more workspace than
+ * the array holds (the message says how many right-hand sides fit: 16
+ * for 540 orbitals and 3.3k products, 1 for 1800 orbitals and 12k products).
+ */
+#define CHI0_NOALLOC_SCRATCH_BYTES (128LL << 20)
+int chi0_apply_noalloc(chi0_ctx *ctx, int32_t n_rhs, const double *omega, double eps,
+                       const double *z, double *out, void *stream);
+
+/*
  * Replay chi0_apply from a HIP graph (enable != 0; default off).  A call with
  * n_rhs <= 256 is captured the second time its (n_rhs, precision, z, out,
  * eps) repeat (the first such call runs eagerly and tunes the GEMM tiles) and

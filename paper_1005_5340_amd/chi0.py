@@ -113,6 +113,9 @@ def lib():
     L.chi0_apply.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_double, C.c_void_p, C.c_void_p,
                              C.c_int32, C.c_void_p]
     L.chi0_apply.restype = C.c_int
+    L.chi0_apply_noalloc.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_double, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
+    L.chi0_apply_noalloc.restype = C.c_int
     L.chi0_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
     L.chi0_solve_opts_default.restype = None
     L.chi0_solve_response.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_double, C.c_int32, _dp,
@@ -281,6 +284,30 @@ class Context:
         return out
 
     # ---------------------------------------------------------------- solve
+    def apply_noalloc(self, omega, eps: float, z, out=None, stream=None):
+        """chi0_apply_noalloc: FP64 out[r] = chi0(omega[r]) z[r] with the library's static
+        device scratch (the call allocates nothing; the GPU's scratch is shared by every
+        call, so calls must not overlap).  Same arguments as `apply` without precision."""
+        import torch
+        om = _f64(np.atleast_1d(omega))
+        if not (z.is_cuda and z.dtype == torch.complex128 and z.is_contiguous() and z.dim() == 2):
+            raise ValueError("z must be a contiguous complex128 CUDA tensor [n_rhs, n_prod]")
+        if z.shape[0] != om.size:
+            raise ValueError("one frequency per row of z")
+        if out is None:
+            out = torch.empty_like(z)
+        if not (out.is_cuda and out.dtype == torch.complex128 and out.is_contiguous()
+                and out.shape == z.shape):
+            raise ValueError("out must match z")
+        if stream is None:
+            stream = torch.cuda.current_stream(z.device)
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        rc = self._L.chi0_apply_noalloc(self._h, int(om.size), _ptr(om), float(eps),
+                                        C.c_void_p(z.data_ptr()), C.c_void_p(out.data_ptr()),
+                                        C.c_void_p(handle))
+        self._check(rc)
+        return out
+
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
                        tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,
                        inner_tol: float = 0.0, warm: "WarmStart" = None, ortho: int = ORTHO_AUTO,

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -262,6 +263,29 @@ static int dalloc(chi0_ctx *c, DevBuf &buf, T **p, int64_t n) {
         if (r_ != CHI0_OK) return r_; \
     } while (0)
 
+// ============================================================ static scratch
+// Workspace of chi0_apply_noalloc: a fixed array in device memory, one copy
+// per GPU, held until the process ends.  Host code never uses the array's
+// name as an address; chi0_create looks up each device's copy once (with
+// that device current) and the entry point passes that address to kernels.
+constexpr int64_t kScratchDoubles = CHI0_NOALLOC_SCRATCH_BYTES / 8;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static double *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Address of `scratch` on the current device `device` (looked up on the first call).
+static hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double *>(ptr);
+    return hipSuccess;
+}
+
 // ================================================================ lifecycle
 extern "C" int chi0_create(chi0_ctx **out, int device) {
     if (!out) { g_create_error = "out is NULL"; return CHI0_EINVAL; }
@@ -279,6 +303,7 @@ extern "C" int chi0_create(chi0_ctx **out, int device) {
             return e == hipSuccess ? CHI0_EINVAL : CHI0_EHIP;
         }
         e = hipSetDevice(device);
+        if (e == hipSuccess) e = scratch_setup(device);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
         for (int L = 1; L < kLanes && e == hipSuccess; ++L)
             e = hipStreamCreateWithFlags(&c->lane_stream[L], hipStreamNonBlocking);
@@ -853,6 +878,81 @@ extern "C" int chi0_set_graphs(chi0_ctx *c, int32_t enable) {
     if (c->device >= 0) HIPCHK(c, hipDeviceSynchronize());
     c->drop_apply_graph();
     c->graphs = enable != 0;
+    return CHI0_OK;
+}
+
+// chi0_apply without allocation: every workspace buffer of the operator is
+// carved from the device's static scratch (offsets in doubles, 256-byte
+// aligned); no split-K partials beyond what fits, no tile tuning, no timing.
+namespace {
+struct ScratchLayout {
+    int64_t omega, Zin, Yout, dV, W, Tt, Ut, at, part, gemm, end;
+};
+ScratchLayout scratch_layout(const chi0_ctx *c, int nb) {
+    const int64_t nc = 2 * nb, mcol = (int64_t)c->No_pad * nc;
+    ScratchLayout L{};
+    int64_t o = 0;
+    auto take = [&](int64_t n) { const int64_t at = o; o += round_up(std::max<int64_t>(n, 1), 32); return at; };
+    L.omega = take(nb);
+    L.Zin = take((int64_t)c->P_pad * nc);
+    L.Yout = take((int64_t)c->P_pad * nc);
+    L.dV = take(c->nnzB * nc);
+    L.W = take(c->nnzB * nc);
+    L.Tt = take((int64_t)c->N_pad * mcol);
+    L.Ut = take((int64_t)c->N_pad * mcol);
+    L.at = take((int64_t)c->Nv_pad * mcol);
+    L.part = take(c->npart * nc);
+    L.gemm = o;   // split-K partials: whatever is left (none if too little)
+    L.end = o;
+    return L;
+}
+}  // namespace
+
+extern "C" int chi0_apply_noalloc(chi0_ctx *c, int32_t n_rhs, const double *omega, double eps,
+                                  const double *z, double *out, void *stream) {
+    if (!c) return CHI0_EINVAL;
+    if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no system on a device context");
+    if (n_rhs < 0) return fail(c, CHI0_EINVAL, "n_rhs < 0");
+    if (n_rhs == 0) return CHI0_OK;
+    if (!omega || !z || !out) return fail(c, CHI0_EINVAL, "NULL pointer");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
+    if (!all_finite(omega, n_rhs)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
+    if (n_rhs > kMaxBatch) return fail(c, CHI0_EINVAL, "n_rhs must be <= 256");
+    const ScratchLayout L = scratch_layout(c, n_rhs);
+    if (L.end > kScratchDoubles) {
+        int fit = 0;
+        while (fit < kMaxBatch && scratch_layout(c, fit + 1).end <= kScratchDoubles) ++fit;
+        return fail(c, CHI0_EINVAL, "chi0_apply_noalloc: " + std::to_string(n_rhs) + " right-hand sides need " +
+                                        std::to_string(L.end * 8) + " bytes of workspace, the static scratch holds " +
+                                        std::to_string(kScratchDoubles * 8) + "; at most " + std::to_string(fit) +
+                                        " fit for this system (chi0_apply has no such limit)");
+    }
+    double *base = c->device < kMaxDevices ? g_scratch_ptr[c->device] : nullptr;
+    if (!base) return fail(c, CHI0_EHIP, "static scratch address not set up for this device");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    OpWork o;   // a view into the scratch: owns nothing
+    o.omega_dev = base + L.omega;
+    o.Zin = base + L.Zin;
+    o.Yout = base + L.Yout;
+    o.dV = base + L.dV;
+    o.W = base + L.W;
+    o.Tt = base + L.Tt;
+    o.Ut = base + L.Ut;
+    o.at = base + L.at;
+    o.part = base + L.part;
+    const int64_t left = kScratchDoubles - L.gemm;
+    o.gemm_scratch = left >= 2 * 64 * 64 ? base + L.gemm : nullptr;
+    o.gemm_scratch_n = o.gemm_scratch ? (size_t)left : 0;
+    const int nc = 2 * n_rhs;
+    // The scratch keeps the last call's contents (any system, any n_rhs): clear
+    // the buffers this call uses, whose padding the GEMMs read as zeros.
+    launch_zero(nullptr, s, base, L.gemm);
+    HIPCHK(c, hipMemcpyAsync(o.omega_dev, omega, (size_t)n_rhs * 8, hipMemcpyHostToDevice, s));
+    launch_rows_to_cols(nullptr, s, z, n_rhs, c->P, o.Zin, nc);
+    run_chi0(c, o, s, n_rhs, eps, CHI0_PREC_FP64, o.omega_dev, nullptr, nullptr);
+    launch_cols_to_rows(nullptr, s, o.Yout, n_rhs, c->P, nc, out);
+    HIPCHK(c, hipGetLastError());
     return CHI0_OK;
 }
 
