@@ -211,6 +211,10 @@ typedef struct chi0_solve_opts {
                              (omega_i, drive k) starts from x0[i][k] instead of 0 (for example the
                              solution at a neighbouring frequency), unless
                              ||chi0 d - A x0|| >= ||chi0 d||, then from 0; not with `warm` */
+    const chi0_ws *const *warm_drive;   /* NULL, or host [n_drive]: a learned warm start for each
+                             drive (an entry may be NULL: that drive starts from 0), each fitted on
+                             this context and system, typically on its own drive's solutions; not
+                             with `warm` or `x0` */
     int32_t mixed;        /* precision != FP64 only: CHI0_MIXED_REFINE (default) or _RELAXED */
     double  relax;        /* CHI0_MIXED_RELAXED: switch to `precision` once the residual estimate is
                              at most relax tol ||chi0 d|| / u, u the low-precision operator's

@@ -83,27 +83,29 @@ def transition_vertices(sys, occ=None) -> np.ndarray:
     return out
 
 
-def _occ_chunks(sys, max_bytes=1 << 29):
+def _occ_chunks(sys, occ_subset=None, max_bytes=1 << 29):
+    states = np.arange(sys.n_occ) if occ_subset is None else np.asarray(occ_subset)
     nv = sys.n_orb - sys.n_occ
     per_e = max(1, sys.n_prod * nv * 8)
-    step = max(1, min(sys.n_occ, max_bytes // per_e))
-    for e0 in range(0, sys.n_occ, step):
-        yield np.arange(e0, min(sys.n_occ, e0 + step))
+    step = max(1, min(states.size, max_bytes // per_e))
+    for e0 in range(0, states.size, step):
+        yield states[e0:e0 + step]
 
 
-def chi0_matrix(sys, omega: float, eps: float | None = None) -> np.ndarray:
+def chi0_matrix(sys, omega: float, eps: float | None = None, occ_subset=None) -> np.ndarray:
     """Dense chi0_{mu nu}(w) of eq. response-mat, [n_prod, n_prod] complex.
 
     chi0 = sum_{E,F} v^{EF} L_EF v^{EF}^T, accumulated over chunks of
     occupied states so that the transition vertices never need to be held
-    in full.
+    in full.  occ_subset (default: all occupied states) restricts the sum to
+    the transitions out of those states: the part of chi0 they contribute.
     """
     eps = sys.eps if eps is None else eps
     D = transition_energies(sys)
     P = sys.n_prod
     re = np.zeros((P, P))
     im = np.zeros((P, P))
-    for occ in _occ_chunks(sys):
+    for occ in _occ_chunks(sys, occ_subset):
         Vt = transition_vertices(sys, occ).reshape(P, -1)
         L = lorentzian(omega, eps, D[occ], sys.occ_factor).ravel()
         re += (Vt * L.real) @ Vt.T

@@ -42,7 +42,7 @@ class SolveOpts(C.Structure):
                 ("precision", C.c_int32), ("batch", C.c_int32), ("inner_tol", C.c_double),
                 ("warm", C.c_void_p), ("ortho", C.c_int32), ("lanes", C.c_int32),
                 ("stop", C.c_int32), ("alpha_form", C.c_int32), ("x0", C.c_void_p),
-                ("mixed", C.c_int32), ("relax", C.c_double)]
+                ("warm_drive", C.POINTER(C.c_void_p)), ("mixed", C.c_int32), ("relax", C.c_double)]
 
 
 class WsCfg(C.Structure):
@@ -318,7 +318,8 @@ class Context:
         Returns (alpha [n_omega, n_drive, n_drive] complex, stats [n_omega, n_drive], rc)
         where rc is 0 or NOT_CONVERGED; with return_x also the solutions
         x [n_omega, n_drive, n_prod] complex (chi0_solve_response_x).  x0: optional start
-        vectors, a contiguous complex128 device tensor [n_omega, n_drive, n_prod].
+        vectors, a contiguous complex128 device tensor [n_omega, n_drive, n_prod].  warm: a
+        WarmStart for every drive, or a list with one WarmStart (or None) per drive.
         """
         om = _f64(np.atleast_1d(omega))
         D = _f64(np.atleast_2d(V_ext))
@@ -327,7 +328,13 @@ class Context:
         self._L.chi0_solve_opts_default(C.byref(o))
         o.restart, o.max_iter, o.tol = int(restart), int(max_iter), float(tol)
         o.batch, o.precision, o.inner_tol = int(batch), int(precision), float(inner_tol)
-        o.warm = warm._h if warm is not None else None
+        if isinstance(warm, (list, tuple)):     # one warm start per drive (None: zero start)
+            if len(warm) != nd:
+                raise ValueError("one warm start (or None) per drive")
+            wd = (C.c_void_p * nd)(*[w._h if w is not None else None for w in warm])
+            o.warm_drive = C.cast(wd, C.POINTER(C.c_void_p))
+        else:
+            o.warm = warm._h if warm is not None else None
         o.ortho = int(ortho)
         o.lanes = int(lanes)
         o.stop = int(stop)

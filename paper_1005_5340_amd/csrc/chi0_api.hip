@@ -1132,11 +1132,18 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     const bool use_eps = o.stop != CHI0_STOP_RESIDUAL;
     if (use_eps && (!dcgs || o.precision != CHI0_PREC_FP64))
         return fail(c, CHI0_EINVAL, "the eps_P / eps_X stopping tests need DCGS2 steps in FP64");
-    chi0_ws *ws = const_cast<chi0_ws *>(o.warm);
-    if (ws && ws->ctx != c) return fail(c, CHI0_EINVAL, "warm start belongs to another context");
+    // learned warm start of each drive: `warm` for all of them, or one per drive
+    if (o.warm && o.warm_drive) return fail(c, CHI0_EINVAL, "warm and warm_drive are exclusive");
+    std::vector<chi0_ws *> wsd(n_drive, nullptr);
+    for (int i = 0; i < n_drive; ++i) {
+        wsd[i] = const_cast<chi0_ws *>(o.warm_drive ? o.warm_drive[i] : o.warm);
+        if (wsd[i] && wsd[i]->ctx != c) return fail(c, CHI0_EINVAL, "warm start belongs to another context");
+    }
+    const bool any_ws = std::any_of(wsd.begin(), wsd.end(), [](chi0_ws *w) { return w != nullptr; });
     const double *x0 = o.x0;
-    if (ws && x0) return fail(c, CHI0_EINVAL, "a learned warm start and x0 are exclusive");
-    const bool warm_any = ws || x0;
+    if (any_ws && x0) return fail(c, CHI0_EINVAL, "a learned warm start and x0 are exclusive");
+    // whether point p starts from a given vector (x0 or its drive's network) rather than 0
+    auto started = [&](int p) { return x0 != nullptr || wsd[p % n_drive] != nullptr; };
     const double inner_tol = o.inner_tol > 0.0 ? o.inner_tol
                              : (o.precision == CHI0_PREC_FP32 ? 1e-6 : 1e-4);
     // relaxed low precision: a point's Arnoldi steps leave FP64 once the
@@ -1276,7 +1283,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                     sum_j1 += jb.j + 1;
                 } else {
                     jb.type = ss.state == S_RHS ? JOB_RHS : JOB_RESID;
-                    jb.j = jb.type == JOB_RHS ? (warm_any ? 1 : 0) : 0;
+                    jb.j = jb.type == JOB_RHS ? (started(ss.point) ? 1 : 0) : 0;
                     ss.busy = true;
                 }
                 jobs_h[nb] = jb;
@@ -1382,11 +1389,11 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 if (!(st.value > 0.0) || !std::isfinite(st.value)) {
                     pt.rel = st.value == 0.0 ? 0.0 : NAN;
                     pt.converged = st.value == 0.0;
-                    if (warm_any) ln.rst.push_back({jb.slot, 0, 0, 0});   // x = 0 is the answer
+                    if (started(ss.point)) ln.rst.push_back({jb.slot, 0, 0, 0});   // x = 0 is the answer
                     ln.fin.push_back({jb.slot, 0, ss.point, 0});
                     ss.state = S_FREE;
                     ++done;
-                } else if (warm_any) {
+                } else if (started(ss.point)) {
                     ss.state = S_RESID;       // r0 = b - A x0 decides on the warm start
                     ss.warm_check = true;
                 } else {
@@ -1493,17 +1500,31 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
             HIPCHK(c, hipMemcpyAsync(c->slots.x + (int64_t)jn.slot * c->P_pad * 2, x0 + (int64_t)jn.j * P * 2,
                                      (size_t)P * 16, hipMemcpyDeviceToDevice, s));
         ln.xnew.clear();
-        // warm-started points new in this lane's slots get x0 = U c(omega) now
+        // warm-started points new in this lane's slots get x0 = U c(omega) now,
+        // from the network of their drive (one inference per network)
         if (!ln.wnew.empty()) {
-            // the network's buffers are shared by the lanes: this stream finishes
-            // its inference before the host moves on
-            HIPCHK(c, hipStreamSynchronize(s));   // fin_h copies done; reuse fin_h
-            std::copy(ln.wnew.begin(), ln.wnew.end(), fin_h);
-            HIPCHK(c, hipMemcpyAsync(ws->jobs_dev, fin_h, sizeof(Job) * ln.wnew.size(), hipMemcpyHostToDevice, s));
-            CHK(ws_infer(ws, s, (int)ln.wnew.size(), ln.wom.data()));
-            launch_ws_apply(s, ws->jobs_dev, (int)ln.wnew.size(), ws->out, ws->O, ws->mean, ws->sdev, ws->r,
-                            ws->U, (int64_t)c->P_pad * 2, c->slots.x, (int64_t)c->P_pad * 2, P);
-            HIPCHK(c, hipStreamSynchronize(s));
+            std::vector<Job> grp;
+            std::vector<double> gom;
+            for (int d = 0; d < n_drive; ++d) {
+                chi0_ws *ws = wsd[d];
+                grp.clear();
+                gom.clear();
+                for (size_t q = 0; q < ln.wnew.size(); ++q)
+                    if (ln.wnew[q].drive == d) {
+                        grp.push_back(ln.wnew[q]);
+                        gom.push_back(ln.wom[q]);
+                    }
+                if (grp.empty() || !ws) continue;
+                // the network's buffers are shared by the lanes: this stream finishes
+                // its inference before the host moves on (and fin_h is reused)
+                HIPCHK(c, hipStreamSynchronize(s));
+                std::copy(grp.begin(), grp.end(), fin_h);
+                HIPCHK(c, hipMemcpyAsync(ws->jobs_dev, fin_h, sizeof(Job) * grp.size(), hipMemcpyHostToDevice, s));
+                CHK(ws_infer(ws, s, (int)grp.size(), gom.data()));
+                launch_ws_apply(s, ws->jobs_dev, (int)grp.size(), ws->out, ws->O, ws->mean, ws->sdev, ws->r,
+                                ws->U, (int64_t)c->P_pad * 2, c->slots.x, (int64_t)c->P_pad * 2, P);
+                HIPCHK(c, hipStreamSynchronize(s));
+            }
             ln.wnew.clear();
             ln.wom.clear();
         }
@@ -1522,9 +1543,9 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 sl[k].epoch += 1;
                 sl[k].warm_check = false;
                 sl[k].eps_met = false;
-                if (ws) {
+                if (wsd[sl[k].point % n_drive]) {
                     LaneState &ln = lanes[k % nl];
-                    ln.wnew.push_back({k, 0, sl[k].point, 0});
+                    ln.wnew.push_back({k, 0, sl[k].point, sl[k].point % n_drive});
                     ln.wom.push_back(omega[sl[k].point / n_drive]);
                 } else if (x0) {
                     lanes[k % nl].xnew.push_back({k, 0, sl[k].point, 0});

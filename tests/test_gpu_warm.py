@@ -91,28 +91,32 @@ def test_warm_started_solves_are_exact(fitted):
     assert np.max(np.abs(a0 - ref)) < 1e-9 * np.max(np.abs(ref))
     assert (s1["warm_start"] == 1).all() and (s0["warm_start"] == 0).all()
     assert (s1["warm_rel0"] < 1.0).all()
-    # At 1e-12 nearly all iterations go into directions the low-rank x0 does
-    # not resolve, so the two starts need the same work to within rounding of
-    # the stopping step; the saving itself is tested by tolerance below.
-    assert s1["iterations"].sum() <= 1.01 * s0["iterations"].sum()
+    # No ordering of the iteration counts follows from the method: the warm
+    # start's Krylov space K(A, b - A x0) is not the zero start's K(A, b), so
+    # either may need more steps to a given tolerance.  What the start saves
+    # is measured by tolerance below.
 
 
 def test_warm_start_gain_by_tolerance(fitted):
     """The saving shrinks as the tolerance tightens: x0 removes the smooth part
     of the error, while the GMRES work at tight tolerances goes into the
-    slowly resolved directions of the badly conditioned (1 - chi0 K)."""
+    slowly resolved directions of the badly conditioned (1 - chi0 K).  The
+    counts are reproducible (fixed-order reductions, seeded inputs), so the
+    measured gains are asserted: > 10 % at 1e-3 and > 0 at 1e-8, the learned
+    warm start's tolerance in the 400-atom workload."""
     sys, ctx, ws, _ = fitted
     d = sys.drives("z")
     om = np.linspace(0.05, 1.45, 16)
     gains = {}
-    for tol in (1e-3, 1e-6, 1e-9):
+    for tol in (1e-3, 1e-6, 1e-8):
         _, s0, _ = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=tol, batch=16)
         _, s1, _ = ctx.solve_response(om, sys.eps, d, restart=sys.n_prod, tol=tol, batch=16, warm=ws)
         i0, i1 = int(s0["iterations"].sum()), int(s1["iterations"].sum())
         gains[tol] = 1.0 - i1 / i0
         print(f"[warm] tol {tol:.0e}: iterations zero start {i0} warm {i1} (saved {100 * gains[tol]:.1f}%)",
               flush=True)
-    assert gains[1e-3] > 0.0
+    assert gains[1e-3] > 0.10
+    assert gains[1e-8] > 0.0
 
 
 def test_rejected_warm_start_falls_back_to_zero(fitted):
@@ -126,3 +130,27 @@ def test_rejected_warm_start_falls_back_to_zero(fitted):
     ref = orc.polarizability(sys, om, d)
     assert rc == 0 and (st["warm_start"] == 2).all()
     assert np.max(np.abs(a - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_one_warm_start_per_drive(fitted):
+    """A network per drive (x fitted here, z from the fixture, y none): one batched
+    x/y/z solve starts the x and z points from their own drive's network and the
+    y points from zero, and the tensor is the oracle's."""
+    from paper_1005_5340_amd import chi0
+    sys, ctx, ws_z, om_train = fitted
+    D = sys.drives("xyz")
+    ws_x = chi0.WarmStart(ctx, om_train, sys.eps, D[0], rank=32, width=128, epochs=2000,
+                          restart=sys.n_prod, batch=32, tol=1e-12)
+    om = np.array([0.12, 0.55, 1.3])
+    a, st, rc = ctx.solve_response(om, sys.eps, D, restart=sys.n_prod, tol=1e-12, batch=9,
+                                   warm=[ws_x, None, ws_z])
+    ws_x.close()
+    ref = orc.polarizability(sys, om, D)
+    print(f"[warm] per drive: warm_start flags {st['warm_start'].tolist()} "
+          f"x0 residuals {np.round(st['warm_rel0'], 3).tolist()}", flush=True)
+    assert rc == 0 and st["converged"].all()
+    assert (st["warm_start"][:, 0] == 1).all() and (st["warm_start"][:, 2] == 1).all()
+    assert (st["warm_start"][:, 1] == 0).all()
+    assert np.max(np.abs(a - ref)) < 1e-9 * np.max(np.abs(ref))
+    with pytest.raises(ValueError):
+        ctx.solve_response(om, sys.eps, D, warm=[ws_z])

@@ -200,3 +200,20 @@ def test_residual_norm_of_exact_solution(a4):
     x = orc.solve_response(a4, 0.8, d[None, :])[0]
     assert orc.residual_norm(a4, 0.8, d, x) < 1e-13
     assert orc.residual_norm(a4, 0.8, d, 1.001 * x) > 1e-5
+
+
+def test_chi0_partial_sums_over_occupied_states_add_up():
+    """chi0 restricted to disjoint sets of occupied states (the transitions out of
+    each set) adds up to the whole chi0 of eq. response-mat; the sets partition
+    the sum over E, so this holds at any frequency."""
+    import gpu_systems
+    s = gpu_systems.get("atoms12_orb9")
+    rng = np.random.default_rng(4)
+    perm = rng.permutation(s.n_occ)
+    parts = [perm[:7], perm[7:30], perm[30:]]
+    for w in (0.0, 0.37):
+        full = orc.chi0_matrix(s, w)
+        tot = sum(orc.chi0_matrix(s, w, occ_subset=p) for p in parts)
+        assert np.max(np.abs(tot - full)) < 1e-12 * np.max(np.abs(full))
+        one = orc.chi0_matrix(s, w, occ_subset=parts[0])
+        assert np.max(np.abs(one)) > 1e-3 * np.max(np.abs(full))   # a real part of the sum
