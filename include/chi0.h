@@ -418,8 +418,10 @@ typedef struct chi0_lanczos_opts {
     const double *omega_x;   /* host [n_x], Ha */
     double *x;            /* host [n_x][n_drive][n_prod] complex, or NULL: x_i(w) = -B Q_k y(w),
                              B = V_t S, y = |c_i| (T_k - (w + i eps)^2)^-1 e_1, k = len[i]; with
-                             CHI0_LZ_REORTH_PARTIAL the basis, and so x, is orthogonal only to about
-                             sqrt(machine epsilon) (1e-8 relative); _FULL keeps it to rounding */
+                             CHI0_LZ_REORTH_PARTIAL (the default) the basis is orthogonal only to
+                             about sqrt(machine epsilon) and x, alpha_x are good to ~1e-7 relative
+                             (what the tests hold them to); use CHI0_LZ_REORTH_FULL, which keeps the
+                             basis orthogonal to rounding, for solutions at the FP64 bar */
     double *alpha_x;      /* host [n_x][n_drive][n_drive] complex, or NULL: the full tensor
                              alpha_ki(w) = -d_k . x_i(w) (eq. eqpolarizability, alpha = -P) */
     int32_t reserved[2];  /* must be zero */

@@ -52,6 +52,14 @@ int chi0_ws_debug_params(chi0_ws *ws, float *host, int64_t n, int32_t set);
  * with respect to every parameter, computed by the GPU kernels (no update). */
 int chi0_ws_debug_loss_grad(chi0_ws *ws, int32_t n, const double *omega, const float *target,
                             float *loss, float *grads);
+/* The last chi0_lanczos with CHI0_LZ_REORTH_PARTIAL run while kernel timing
+ * was on (its host reads the device decision every step): passes[j] = 1 if
+ * step j ran the reorthogonalisation pass, and b_pre[j * n_drive + s] the
+ * norm b_j of the three-term residual of drive s that the decision used
+ * (before the pass).  Copies min(cap, steps) steps; returns the number of
+ * steps recorded (0 if none).  Either pointer may be NULL. */
+int chi0_debug_lz_passes(const chi0_ctx *ctx, int32_t *passes, double *b_pre, int32_t cap);
+
 /* Host eigen-decomposition of a Hermitian n x n matrix (row-major interleaved
  * complex): eigenvalues descending in w[n], eigenvectors as columns of V. */
 int chi0_debug_eigh(int32_t n, const double *A, double *w, double *V);

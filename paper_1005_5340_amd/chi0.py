@@ -153,6 +153,8 @@ def lib():
     L.chi0_ws_debug_loss_grad.argtypes = [C.c_void_p, C.c_int32, _dp, C.POINTER(C.c_float),
                                           C.POINTER(C.c_float), C.POINTER(C.c_float)]
     L.chi0_ws_debug_loss_grad.restype = C.c_int
+    L.chi0_debug_lz_passes.argtypes = [C.c_void_p, _i32p, _dp, C.c_int32]
+    L.chi0_debug_lz_passes.restype = C.c_int
     L.chi0_debug_eigh.argtypes = [C.c_int32, _dp, _dp, _dp]
     L.chi0_debug_eigh.restype = C.c_int
     L.chi0_lanczos_opts_default.argtypes = [C.POINTER(LanczosOpts)]
@@ -415,6 +417,15 @@ class Context:
         self._check(self._L.chi0_lanczos_spectrum(self._h, nd, ld, _ptr(a), _ptr(b), _ptr(cn2), _ptr(ln, _i32p),
                                                   int(om.size), _ptr(om), float(eps), _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]
+
+    def debug_lz_passes(self, n_drive: int):
+        """Test hook: per step of the last timed partial-reorthogonalisation recursion,
+        whether the pass ran and the pre-pass b_j of each drive ([steps], [steps, n_drive])."""
+        n = self._L.chi0_debug_lz_passes(self._h, None, None, 0)
+        p = np.zeros(max(n, 1), np.int32)
+        b = np.zeros((max(n, 1), n_drive))
+        self._L.chi0_debug_lz_passes(self._h, _ptr(p, _i32p), _ptr(b), n)
+        return p[:n], b[:n]
 
     def set_graphs(self, enable: bool):
         """Replay repeated chi0_apply calls from a HIP graph (chi0_set_graphs)."""

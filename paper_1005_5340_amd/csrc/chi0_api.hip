@@ -178,6 +178,11 @@ struct chi0_ctx {
     float *Xo32 = nullptr, *Xv32 = nullptr, *Xvt32 = nullptr;
     uint16_t *Xv_hi = nullptr, *Xv_lo = nullptr, *Xvt_hi = nullptr, *Xvt_lo = nullptr;
 
+    // partial reorthogonalisation with kernel timing on: per step, whether the
+    // pass ran and the b_j (one per drive) that the device decision used
+    std::vector<int32_t> lz_pass_rec;
+    std::vector<double> lz_bpre_rec;
+
     // solver workspace
     DevBuf slotbuf;
     int slot_n = 0, slot_m = 0;
@@ -2041,6 +2046,18 @@ extern "C" int chi0_ws_debug_loss_grad(chi0_ws *w, int32_t n, const double *omeg
     return CHI0_OK;
 }
 
+extern "C" int chi0_debug_lz_passes(const chi0_ctx *c, int32_t *passes, double *b_pre, int32_t cap) {
+    if (!c) return CHI0_EINVAL;
+    const int n = (int)c->lz_pass_rec.size();
+    const int nc = n > 0 ? (int)(c->lz_bpre_rec.size() / n) : 0;
+    for (int j = 0; j < std::min(n, cap); ++j) {
+        if (passes) passes[j] = c->lz_pass_rec[j];
+        if (b_pre)
+            for (int s = 0; s < nc; ++s) b_pre[(int64_t)j * nc + s] = c->lz_bpre_rec[(int64_t)j * nc + s];
+    }
+    return n;
+}
+
 extern "C" int chi0_debug_eigh(int32_t n, const double *A, double *w, double *V) {
     if (n < 1 || !A || !w || !V) return CHI0_EINVAL;
     std::vector<double> a(A, A + (size_t)2 * n * n), lam, vec;
@@ -2336,6 +2353,8 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
             HIPCHK(c, hipMemcpy(L.omega + (int64_t)sq * (kmax + 2), &one, 8, hipMemcpyHostToDevice));
         if (c->tracer.on) HIPCHK(c, hipHostMalloc((void **)&flag_h, sizeof(int), 0));
     }
+    c->lz_pass_rec.clear();
+    c->lz_bpre_rec.clear();
     int steps = 0;
     for (int j = 0; j < kmax; ++j) {
         if (partial) {
@@ -2347,6 +2366,10 @@ extern "C" int chi0_lanczos(chi0_ctx *c, int32_t n_drive, const double *drives, 
                 launch_lz_step_head(&c->tracer, s, L, j);
                 HIPCHK(c, hipMemcpyAsync(flag_h, L.flag, sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(c, hipStreamSynchronize(s));
+                c->lz_pass_rec.push_back(*flag_h ? 1 : 0);
+                c->lz_bpre_rec.resize(c->lz_bpre_rec.size() + nc);
+                HIPCHK(c, hipMemcpy(c->lz_bpre_rec.data() + c->lz_bpre_rec.size() - nc, L.b + (int64_t)j * nc,
+                                    sizeof(double) * nc, hipMemcpyDeviceToHost));
                 launch_lz_step_tail(&c->tracer, s, L, j, *flag_h ? 1 : 0, part2, h, part3);
             } else {
                 launch_lz_step_partial(&c->tracer, s, L, j, part2, h, part3);

@@ -376,3 +376,66 @@ def test_partial_timed_matches_gated():
     assert 0 < npass < steps, (npass, steps)
     assert stats["lanczos_reorth_update"]["launches"] == npass
     print(f"[lanczos] {steps} steps, {npass} reorthogonalisation passes", flush=True)
+
+
+def _simon_decisions(a, b, b_pre):
+    """Partial reorthogonalisation decisions from Simon's omega recurrence, replayed
+    in NumPy from the recursion's coefficients: w[j+1][i] estimates q_{j+1} . q_i
+    from the three-term relation, a pass runs when max |w[j+1][i]| exceeds
+    sqrt(eps) (and the step after it too), and a pass resets the row to eps.
+    Returns the decisions and the max |w| of each step."""
+    eps, thr = np.finfo(float).eps, np.sqrt(np.finfo(float).eps)
+    k = b_pre.size
+    w_prev, w_cur = np.zeros(k + 2), np.zeros(k + 2)
+    w_cur[0] = 1.0
+    anorm, carry, out, mxs = 0.0, False, [], []
+    for j in range(k):
+        aj, bj = a[j], b_pre[j]
+        bm = b[j - 1] if j > 0 else 0.0
+        an = max(anorm, abs(aj) + bj + bm)
+        i = np.arange(j)
+        tv = b[i] * w_cur[i + 1] + (a[i] - aj) * w_cur[i] - bm * w_prev[i]
+        tv[1:] += b[i[1:] - 1] * w_cur[i[1:] - 1]
+        v = (tv + np.where(tv >= 0.0, 1.0, -1.0) * 2.0 * eps * an) / bj
+        w_next = np.zeros(k + 2)
+        w_next[:j] = v
+        w_next[j] = eps * an / bj
+        w_next[j + 1] = 1.0
+        mx = float(np.max(np.abs(v))) if j else 0.0
+        need = carry or mx > thr
+        if need:
+            w_next[:j + 1] = eps
+        carry = (not carry) if need else False
+        anorm = an
+        out.append(need)
+        mxs.append(mx)
+        w_prev, w_cur = w_cur, w_next
+    return np.array(out), np.array(mxs)
+
+
+def test_partial_decisions_follow_simons_recurrence():
+    """The device-side decision of partial reorthogonalisation (12-atom system, 600
+    steps) equals an independent NumPy replay of Simon's recurrence from the
+    returned coefficients (and the pre-pass b_j the device used), step by step;
+    a first disagreement may only sit at a margin case (|w| within 1e-6 of
+    sqrt(eps), where the two evaluation orders can round differently)."""
+    from paper_1005_5340_amd import chi0
+    sys = gpu_systems.get("atoms12_orb9")
+    d = sys.drives("z")
+    ctx = _ctx(sys)
+    ctx.set_timing(True)
+    res = ctx.lanczos(d, k_max=600, reorth=chi0.LZ_REORTH_PARTIAL, tol=1e300, check_every=100,
+                      omega_check=[0.5], eps=sys.eps)
+    ctx.set_timing(False)
+    passes, b_pre = ctx.debug_lz_passes(1)
+    ctx.close()
+    k = int(res["len"][0])
+    assert passes.size == k and 0 < passes.sum() < k
+    dec, mxs = _simon_decisions(res["a"][0, :k], res["b"][0, :k], b_pre[:, 0])
+    same = passes.astype(bool) == dec
+    print(f"[lanczos] {k} steps: {int(passes.sum())} device passes, {int(dec.sum())} from the NumPy "
+          f"recurrence, {int((~same).sum())} steps differ", flush=True)
+    if not same.all():
+        j = int(np.argmin(same))
+        assert abs(mxs[j] - np.sqrt(np.finfo(float).eps)) <= 1e-6 * np.sqrt(np.finfo(float).eps), (j, mxs[j])
+    assert abs(int(passes.sum()) - int(dec.sum())) <= max(2, k // 100)
