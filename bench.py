@@ -420,6 +420,57 @@ def measure_forms(a, s, ctx, omegas, grid, drives, drive_letters, ref, ref_idx, 
     return out
 
 
+def spectrum_part(a, s, ctx, drives, ref, ref_idx, ref_drive):
+    """Half of the workload's whole grid (part 0: the lower half of the frequencies,
+    part 1: the upper), every drive, unrestarted GMRES at the workload tolerance, in
+    chunks of frequencies solved as one batch each: 4 frequencies below 0.3 Ha (points
+    there need up to ~10^4 iterations), 32 above; one line per chunk.  alpha goes to
+    --dump-alpha (.npz) and is checked against every stored oracle frequency solved."""
+    import torch
+    nw = s.omegas.size
+    idx = np.arange(nw // 2) if a.spectrum_part == 0 else np.arange(nw // 2, nw)
+    chunks, k = [], 0
+    while k < idx.size:
+        n = 4 if s.omegas[idx[k]] < 0.3 else 32
+        chunks.append(idx[k:k + n])
+        k += n
+    nd = drives.shape[0]
+    alpha = np.zeros((idx.size, nd, nd), complex)
+    iters = np.zeros((idx.size, nd), int)
+    conv = np.zeros((idx.size, nd), int)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for c in chunks:
+        t0 = time.perf_counter()
+        al, st, _ = ctx.solve_response(s.omegas[c], s.eps, drives, restart=s.n_prod, tol=a.tol or s.workload.tol,
+                                       batch=min(96, nd * c.size), max_iter=s.n_prod, lanes=1)
+        sel = c - idx[0]
+        alpha[sel], iters[sel], conv[sel] = al, st["iterations"], st["converged"]
+        print(f"[bench] chunk omega[{c[0]}..{c[-1]}] ({s.omegas[c[0]]:.3f}-{s.omegas[c[-1]]:.3f} Ha): "
+              f"{time.perf_counter() - t0:.1f} s, iterations max {st['iterations'].max()} mean "
+              f"{st['iterations'].mean():.0f}, converged {int(st['converged'].sum())}/{st['converged'].size}",
+              file=sys.stderr, flush=True)
+    sec = time.perf_counter() - t_all
+    if a.dump_alpha:
+        np.savez(a.dump_alpha, idx=idx, alpha=alpha, iters=iters, conv=conv, seconds=sec)
+    acc = None
+    if ref is not None:
+        errs = []
+        for n, kref in enumerate(ref_idx):
+            if kref in idx:
+                al = alpha[kref - idx[0]]
+                for i in range(nd):
+                    fl = 1e-3 * np.max(np.abs(ref[:, ref_drive[i], ref_drive[i]].imag))
+                    r0 = ref[n, ref_drive[i], ref_drive[i]]
+                    errs.append(abs(al[i, i].imag - r0.imag) / max(abs(r0.imag), fl))
+        acc = {"oracle_points": len(errs), "max_im_rel_err": float(max(errs)) if errs else None}
+    print(json.dumps({"spectrum_part": a.spectrum_part, "workload": a.workload, "points": int(idx.size * nd),
+                      "seconds": sec, "points_per_s": idx.size * nd / sec, "converged": int(conv.sum()),
+                      "iterations": {"mean": float(iters.mean()), "max": int(iters.max()), "total": int(iters.sum())},
+                      "accuracy": acc}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -493,6 +544,9 @@ def main():
     ap.add_argument("--lz-full", action="store_true",
                     help="Lanczos: reorthogonalise every step (default: partial reorthogonalisation, "
                          "Simon's estimates decided on the host)")
+    ap.add_argument("--spectrum-part", type=int, default=-1, choices=[0, 1],
+                    help="solve half of the workload's whole grid (0: lower, 1: upper half of the "
+                         "frequencies) x every drive in chunks, one line per chunk (no timed steps)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 device copies of MIB MiB (reference for HBM traffic counters)")
     a = ap.parse_args()
@@ -557,6 +611,8 @@ def main():
     if a.lanczos:
         return lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx,
                             ref_drive if ref is not None else None)
+    if a.spectrum_part >= 0:
+        return spectrum_part(a, s, ctx, drives, ref, ref_idx, ref_drive if ref is not None else None)
 
     prec = {"fp64": chi0.PREC_FP64, "fp32": chi0.PREC_FP32, "bf16x3": chi0.PREC_BF16X3}[a.precision]
     ws, warm_info = None, None

@@ -513,8 +513,8 @@ int chi0_set_timing_filter(chi0_ctx *ctx, const char *names);
  * first GEMM of a new shape class (kernel, M, K, split count, N within a half
  * octave) on a context times each valid tile variant (64x64, 64x128, 128x64,
  * 128x128 outputs per workgroup with k tiles of 16; 64x64 and 64x128 with k
- * tiles of 32) once after a warm launch, on the call's
- * stream, and keeps the fastest for that class.  All variants accumulate each
+ * tiles of 32) after a warm launch (the best of three timed launches), on the
+ * call's stream, and keeps the fastest for that class.  All variants accumulate each
  * output element in the same order, so tuning never changes a result, only
  * the time; it does add a synchronisation of the stream on each new class.
  * chi0_set_autotune(ctx, mode): 1 tunes (default), 0 uses the 64x64 variant

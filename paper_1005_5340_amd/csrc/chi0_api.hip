@@ -1310,7 +1310,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
             const int nc = 2 * gn;
             const Job *jg = jobs_d + g0;
             launch_gather_jobs(t, s, jg, gn, c->slots, ow.Vb, nc, P);
-            if (nc <= 16)
+            if (nc <= 32)
                 launch_kmatvec_skinny(t, s, c->P_pad, c->K, ow.Vb, ow.Zin, nc, (double)P);
             else
                 launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, ow.Vb, nc, ow.Zin,

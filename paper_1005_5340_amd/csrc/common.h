@@ -99,8 +99,8 @@ void launch_occ_back(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atom
 // Tile-shape autotuner of the dense GEMMs (one per context).  The first call
 // of a GEMM whose (name, M, K, split count, N within a half octave) has not
 // been seen times every tile variant valid for it (HIP events, one warm and
-// one timed launch each, outside the tracer) and keeps the fastest for the
-// key.  Tile variants give bit-identical results, so the choice never changes
+// the best of three timed launches each, outside the tracer) and keeps the
+// fastest for the key.  Tile variants give bit-identical results, so the choice never changes
 // a number, only the time.
 struct GemmTuner {
     struct Entry {

@@ -357,14 +357,19 @@ static int pick_variant(GemmTuner *tu, hipStream_t s, const char *name, int S, i
     for (int v = 0; v < GEMM_VARIANTS; ++v) {
         if (M % kVarBM[v] != 0 || K % kVarBK[v] != 0) continue;
         launch_variant<T, LZ>(v, s, dim3(1, S), M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
-        (void)hipEventRecord(tu->ev[0], s);
-        launch_variant<T, LZ>(v, s, dim3(1, S), M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
-        (void)hipEventRecord(tu->ev[1], s);
-        float ms = 0.f;
-        if (hipEventSynchronize(tu->ev[1]) != hipSuccess ||
-            hipEventElapsedTime(&ms, tu->ev[0], tu->ev[1]) != hipSuccess)
-            return 0;
-        e.us[v] = 1e3f * ms;
+        // best of three timed launches: one launch's time varies by several per cent
+        float tmin = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(tu->ev[0], s);
+            launch_variant<T, LZ>(v, s, dim3(1, S), M, N, K, A, lda, B, ldb, C, ldc, m_fastest, la);
+            (void)hipEventRecord(tu->ev[1], s);
+            float ms = 0.f;
+            if (hipEventSynchronize(tu->ev[1]) != hipSuccess ||
+                hipEventElapsedTime(&ms, tu->ev[0], tu->ev[1]) != hipSuccess)
+                return 0;
+            tmin = rep == 0 ? ms : std::min(tmin, ms);
+        }
+        e.us[v] = 1e3f * tmin;
         if (best == 0.f || e.us[v] < best) {
             best = e.us[v];
             e.variant = v;
@@ -723,7 +728,8 @@ void k_kmatvec_lanes(int P_pad, const double *__restrict__ K, const double *__re
 constexpr int KMV_RT = 2;   // 16-row tiles per workgroup of the MFMA form
 constexpr int KMV_U = 8;    // column pairs per lane and row tile in flight
 
-// 5..16 real columns on the FP64 matrix cores.  A workgroup owns 16 RT rows;
+// 5..32 real columns on the FP64 matrix cores (CT 16-column tiles).  A
+// workgroup owns 16 RT rows;
 // its four waves split the reduction over nu in interleaved chunks of 8 U
 // columns and add their 16x16 accumulators in a fixed order through LDS at
 // the end.  Each lane streams K as 16-byte (non-temporal) loads of two
@@ -733,22 +739,23 @@ constexpr int KMV_U = 8;    // column pairs per lane and row tile in flight
 // (Measured on the 12.4k-product kernel, 1.2 GB: 4.0-4.3 TB/s for 6-16
 // columns, against 0.25-3.4 for the LDS-staged form; non-temporal loads of K
 // were 10 % slower here.)
-template <int RT, int U>
+template <int RT, int CT, int U>
 __global__ __launch_bounds__(256)
 void k_kmatvec_mfma(int P_pad, const double *__restrict__ K, const double *__restrict__ Zin,
                     double *__restrict__ Zout, int nc) {
-    __shared__ dbl4 red[3][RT][64];
+    __shared__ dbl4 red[3][RT][CT][64];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int row0 = blockIdx.x * 16 * RT;
     const int lr = lane & 15, lk = lane >> 4;
-    const bool cv = lr < nc;
-    dbl4 acc[RT];
+    dbl4 acc[RT][CT];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) acc[r] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[r][c] = dbl4{0.0, 0.0, 0.0, 0.0};
     constexpr int KW = 8 * U;
     for (int k0 = wv * KW; k0 < P_pad; k0 += 4 * KW) {
         double2 a[U][RT];
-        double b0[U], b1[U];
+        double b0[U][CT], b1[U][CT];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kk = k0 + 8 * u + 2 * lk;   // even; P_pad is a multiple of 64
@@ -757,32 +764,43 @@ void k_kmatvec_mfma(int P_pad, const double *__restrict__ K, const double *__res
             for (int r = 0; r < RT; ++r)
                 a[u][r] = ok ? *reinterpret_cast<const double2 *>(K + (int64_t)(row0 + 16 * r + lr) * P_pad + kk)
                               : make_double2(0.0, 0.0);
-            b0[u] = (ok && cv) ? Zin[(int64_t)kk * nc + lr] : 0.0;
-            b1[u] = (ok && cv) ? Zin[(int64_t)(kk + 1) * nc + lr] : 0.0;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int col = 16 * c + lr;
+                b0[u][c] = (ok && col < nc) ? Zin[(int64_t)kk * nc + col] : 0.0;
+                b1[u][c] = (ok && col < nc) ? Zin[(int64_t)(kk + 1) * nc + col] : 0.0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][r].x, b0[u], acc[r], 0, 0, 0);
-                acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][r].y, b1[u], acc[r], 0, 0, 0);
-            }
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][r].x, b0[u][c], acc[r][c], 0, 0, 0);
+                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][r].y, b1[u][c], acc[r][c], 0, 0, 0);
+                }
     }
     if (wv > 0)
 #pragma unroll
-        for (int r = 0; r < RT; ++r) red[wv - 1][r][lane] = acc[r];
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) red[wv - 1][r][c][lane] = acc[r][c];
     __syncthreads();
     if (wv != 0) return;
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-        dbl4 v = acc[r];
-        v += red[0][r][lane];
-        v += red[1][r][lane];
-        v += red[2][r][lane];
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (cv) Zout[(int64_t)(row0 + 16 * r + 4 * e + lk) * nc + lr] = v[e];
-    }
+        for (int c = 0; c < CT; ++c) {
+            dbl4 v = acc[r][c];
+            v += red[0][r][c][lane];
+            v += red[1][r][c][lane];
+            v += red[2][r][c][lane];
+            const int col = 16 * c + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (col < nc) Zout[(int64_t)(row0 + 16 * r + 4 * e + lk) * nc + col] = v[e];
+        }
 }
 
 void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
@@ -796,9 +814,12 @@ void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
         hipLaunchKernelGGL((k_kmatvec_lanes<3, 1>), dim3(P_pad / 4), dim3(256), 0, s, P_pad, K, Zin, Zout);
     else if (nc == 4)
         hipLaunchKernelGGL((k_kmatvec_lanes<4, 2>), dim3(P_pad / 8), dim3(256), 0, s, P_pad, K, Zin, Zout);
+    else if (nc <= 16)
+        hipLaunchKernelGGL((k_kmatvec_mfma<KMV_RT, 1, KMV_U>), dim3(P_pad / (16 * KMV_RT)), dim3(256), 0, s, P_pad,
+                           K, Zin, Zout, nc);
     else
-        hipLaunchKernelGGL((k_kmatvec_mfma<KMV_RT, KMV_U>), dim3(P_pad / (16 * KMV_RT)), dim3(256), 0, s, P_pad, K,
-                           Zin, Zout, nc);
+        hipLaunchKernelGGL((k_kmatvec_mfma<KMV_RT, 2, KMV_U / 2>), dim3(P_pad / (16 * KMV_RT)), dim3(256), 0, s,
+                           P_pad, K, Zin, Zout, nc);
     trace_end(t, s, 2.0 * P * P * nc, 8.0 * (P * P + 2.0 * P * nc));
 }
 
