@@ -471,6 +471,73 @@ def spectrum_part(a, s, ctx, drives, ref, ref_idx, ref_drive):
     ctx.close()
 
 
+def warm_experiment(a, s, ctx, drives, restart, tol):
+    """Learned warm start against the zero start and the previous-frequency start on
+    one drive: `--warm` seeded training frequencies (uniform on [--band-lo, omega_max],
+    seed 1000) give the network (plain FP64 solves at the test tolerance); the
+    `--omega-sample` test frequencies are evenly spaced grid points of the same band.
+    Each start solves the test points once, batched, in the requested precision; the
+    zero-start solve judges the others' error (the plain solve at the same tolerance).
+    The previous-frequency start uses the solution at the next lower grid point,
+    solved first (its cost is reported apart)."""
+    import torch
+    from paper_1005_5340_amd import chi0
+    d = drives[:1]
+    prec = {"fp64": chi0.PREC_FP64, "fp32": chi0.PREC_FP32, "bf16x3": chi0.PREC_BF16X3}[a.precision]
+    kw = dict(restart=restart, max_iter=a.max_iter, tol=tol, batch=a.batch, precision=prec, lanes=1,
+              mixed=chi0.MIXED_RELAXED if a.mixed == "relaxed" else chi0.MIXED_REFINE, relax=a.relax)
+    band = s.omegas >= a.band_lo
+    gi = np.flatnonzero(band)
+    test = gi[np.round(np.linspace(1, gi.size - 1, a.omega_sample)).astype(int)]
+    om = s.omegas[test]
+    rng = np.random.default_rng(1000)
+    om_train = np.sort(rng.uniform(a.band_lo, float(s.omegas.max()), a.warm))
+    out = {"workload": a.workload, "drive": a.drives or "first", "tol": tol, "precision": a.precision,
+           "mixed": a.mixed, "restart": restart, "max_iter": a.max_iter, "test_grid_indices": test.tolist(),
+           "train_frequencies": om_train.tolist()}
+
+    def solve(name, **extra):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        al, st, rc = ctx.solve_response(om, s.eps, d, **kw, **extra)
+        torch.cuda.synchronize()
+        r = {"seconds": time.perf_counter() - t0, "iterations": int(st["iterations"].sum()),
+             "max_iterations": int(st["iterations"].max()), "converged": int(st["converged"].sum()),
+             "alpha": al[:, 0, 0]}
+        print(f"[bench] warm experiment: {name}: {r['seconds']:.1f} s, iterations {r['iterations']} "
+              f"(max {r['max_iterations']}), converged {r['converged']}/{om.size}", file=sys.stderr, flush=True)
+        return r, st
+
+    zero, _ = solve("zero start")
+    t0 = time.perf_counter()
+    ws = chi0.WarmStart(ctx, om_train, s.eps, d[0], rank=min(64, a.warm), width=256, epochs=3000,
+                        restart=restart, batch=min(a.warm, a.batch), tol=tol)
+    t_fit = time.perf_counter() - t0
+    print(f"[bench] warm experiment: network fitted in {t_fit:.1f} s", file=sys.stderr, flush=True)
+    learned, stl = solve("learned start", warm=ws)
+    ws.close()
+    t0 = time.perf_counter()
+    _, _, _, xp = ctx.solve_response(s.omegas[test - 1], s.eps, d, return_x=True, **kw)
+    t_prev = time.perf_counter() - t0
+    x0 = torch.from_numpy(np.ascontiguousarray(xp)).to("cuda")
+    prev, stp = solve("previous-frequency start", x0=x0)
+    ref = zero["alpha"]
+    floor = 1e-3 * np.max(np.abs(ref.imag))
+    for name, r, st in (("zero_start", zero, None), ("learned", learned, stl), ("previous_frequency", prev, stp)):
+        al = r.pop("alpha")
+        r["max_im_rel_diff_vs_zero_start"] = float(np.max(np.abs(al.imag - ref.imag) /
+                                                        np.maximum(np.abs(ref.imag), floor)))
+        r["saved_vs_zero_start"] = 1.0 - r["iterations"] / zero["iterations"]
+        if st is not None:
+            r["median_rel_residual_of_x0"] = float(np.median(st["warm_rel0"]))
+            r["rejected"] = int((st["warm_start"] == 2).sum())
+        out[name] = r
+    out["learned"]["fit_seconds"] = t_fit
+    out["previous_frequency"]["seconds_neighbour_solves"] = t_prev
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -544,6 +611,10 @@ def main():
     ap.add_argument("--lz-full", action="store_true",
                     help="Lanczos: reorthogonalise every step (default: partial reorthogonalisation, "
                          "Simon's estimates decided on the host)")
+    ap.add_argument("--warm-experiment", action="store_true",
+                    help="learned warm start vs zero start vs previous-frequency start on one drive "
+                         "(--warm training and --omega-sample test frequencies in [--band-lo, omega_max])")
+    ap.add_argument("--band-lo", type=float, default=0.0, help="lower end of the warm experiment's band (Ha)")
     ap.add_argument("--spectrum-part", type=int, default=-1, choices=[0, 1],
                     help="solve half of the workload's whole grid (0: lower, 1: upper half of the "
                          "frequencies) x every drive in chunks, one line per chunk (no timed steps)")
@@ -613,6 +684,8 @@ def main():
                             ref_drive if ref is not None else None)
     if a.spectrum_part >= 0:
         return spectrum_part(a, s, ctx, drives, ref, ref_idx, ref_drive if ref is not None else None)
+    if a.warm_experiment:
+        return warm_experiment(a, s, ctx, drives, restart, tol)
 
     prec = {"fp64": chi0.PREC_FP64, "fp32": chi0.PREC_FP32, "bf16x3": chi0.PREC_BF16X3}[a.precision]
     ws, warm_info = None, None
