@@ -275,7 +275,7 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
                 "achieved": work / (rec["ms"] * 1e-3) / scale, "peak": peak / scale, "unit": unit,
                 "frac": work / (rec["ms"] * 1e-3) / peak, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
-                "traffic_over_algorithmic": (traffic / (work / rec["launches"])) if traffic else None,
+                "traffic_over_algorithmic": (traffic / (rec["bytes"] / rec["launches"])) if traffic and rec["bytes"] else None,
                 "launches": rec["launches"], "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
                 "share_of_gpu_time": rec["ms"] / tot,
                 "note": "from the eager breakdown run (every kernel timed)"}
@@ -331,8 +331,9 @@ def lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, r
 
 def measure_forms(a, s, ctx, omegas, grid, drives, drive_letters, ref, ref_idx, ref_drive, restart, tol,
                   batched):
-    """The method's forms on the points of the timed steps, each solved once with
-    every kernel timed (HIP events on every launch, a few per cent of overhead):
+    """The method's forms on the points of the timed steps, each timed by the wall
+    clock over one solve with the kernel timer off, then solved again with every
+    kernel timed (HIP events on every launch) for its dominant kernel:
     plain = FP64, one point per solve (the paper's order of work); batched = the
     timed steps; batched + mixed = split-BF16x3 transforms, relaxed; batched +
     mixed + warm = the same with a learned warm start, one network per drive
@@ -352,14 +353,21 @@ def measure_forms(a, s, ctx, omegas, grid, drives, drive_letters, ref, ref_idx, 
         return np.stack([im_errors(d[:, i], rd[:, i]) for i in range(len(dsel))], 1)
 
     def solve_timed(calls):
-        """calls: list of (drive indices, solve kwargs); one solve_response per entry."""
-        ctx.set_timing(True)
+        """calls: list of (drive indices, solve kwargs); one solve_response per entry.
+        Solved twice: wall-clock time with the kernel timer off (as in the timed
+        steps), then the per-kernel record with every launch timed."""
+        def once():
+            return [(dsel, ctx.solve_response(omegas, s.eps, drives[dsel], restart=restart, max_iter=a.max_iter,
+                                              tol=tol, lanes=1, **kw)) for dsel, kw in calls]
+        ctx.set_timing(False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = [(dsel, ctx.solve_response(omegas, s.eps, drives[dsel], restart=restart, max_iter=a.max_iter,
-                                         tol=tol, lanes=1, **kw)) for dsel, kw in calls]
+        res = once()
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
+        ctx.set_timing(True)
+        once()
+        torch.cuda.synchronize()
         ks = ctx.kernel_stats()
         ctx.set_timing(False)
         return res, sec, ks
@@ -378,7 +386,8 @@ def measure_forms(a, s, ctx, omegas, grid, drives, drive_letters, ref, ref_idx, 
         sc = 1e9 if b == "hbm" else 1e12
         rec = {"points_per_s": passing / sec, "seconds": sec, "passing": passing, "bar": bar, "points": npts,
                "max_im_rel_err": None if e[0] is None else float(max(x.max() for x in e)),
-               "iterations": {"mean": float(its.mean()), "max": int(its.max()), "total": int(its.sum())},
+               "iterations": {"mean": float(its.mean()), "max": int(its.max()), "total": int(its.sum()),
+                              "reduced_precision": int(sum(st["low_prec_steps"].sum() for _, (al, st, rc) in res))},
                "converged": int(sum(st["converged"].sum() for _, (al, st, rc) in res)),
                "chi0_tflops": F * apps / (chi0_ms * 1e-3) / 1e12 if chi0_ms > 0 else None,
                "dominant": {"kernel": dom, "achieved": work / (ks[dom]["ms"] * 1e-3) / sc, "peak": peak / sc,
@@ -420,15 +429,18 @@ def measure_forms(a, s, ctx, omegas, grid, drives, drive_letters, ref, ref_idx, 
     return out
 
 
-def spectrum_part(a, s, ctx, drives, ref, ref_idx, ref_drive):
-    """Half of the workload's whole grid (part 0: the lower half of the frequencies,
-    part 1: the upper), every drive, unrestarted GMRES at the workload tolerance, in
-    chunks of frequencies solved as one batch each: 4 frequencies below 0.3 Ha (points
-    there need up to ~10^4 iterations), 32 above; one line per chunk.  alpha goes to
-    --dump-alpha (.npz) and is checked against every stored oracle frequency solved."""
+def spectrum_range(a, s, ctx, drives, ref, ref_idx, ref_drive):
+    """The grid points lo..hi-1 of the workload's whole grid (--spectrum-range lo:hi),
+    every drive, unrestarted GMRES at the workload tolerance, in chunks of frequencies
+    solved as one batch each: 4 frequencies below 0.3 Ha (points there need up to ~10^4
+    iterations), 32 above; one line per chunk.  alpha goes to --dump-alpha (.npz) and is
+    checked against every stored oracle frequency in the range."""
     import torch
     nw = s.omegas.size
-    idx = np.arange(nw // 2) if a.spectrum_part == 0 else np.arange(nw // 2, nw)
+    lo, hi = (int(v) for v in a.spectrum_range.split(":"))
+    if not 0 <= lo < hi <= nw:
+        raise SystemExit(f"--spectrum-range must satisfy 0 <= lo < hi <= {nw}")
+    idx = np.arange(lo, hi)
     chunks, k = [], 0
     while k < idx.size:
         n = 4 if s.omegas[idx[k]] < 0.3 else 32
@@ -464,7 +476,7 @@ def spectrum_part(a, s, ctx, drives, ref, ref_idx, ref_drive):
                     r0 = ref[n, ref_drive[i], ref_drive[i]]
                     errs.append(abs(al[i, i].imag - r0.imag) / max(abs(r0.imag), fl))
         acc = {"oracle_points": len(errs), "max_im_rel_err": float(max(errs)) if errs else None}
-    print(json.dumps({"spectrum_part": a.spectrum_part, "workload": a.workload, "points": int(idx.size * nd),
+    print(json.dumps({"spectrum_range": [lo, hi], "workload": a.workload, "points": int(idx.size * nd),
                       "seconds": sec, "points_per_s": idx.size * nd / sec, "converged": int(conv.sum()),
                       "iterations": {"mean": float(iters.mean()), "max": int(iters.max()), "total": int(iters.sum())},
                       "accuracy": acc}), flush=True)
@@ -615,9 +627,9 @@ def main():
                     help="learned warm start vs zero start vs previous-frequency start on one drive "
                          "(--warm training and --omega-sample test frequencies in [--band-lo, omega_max])")
     ap.add_argument("--band-lo", type=float, default=0.0, help="lower end of the warm experiment's band (Ha)")
-    ap.add_argument("--spectrum-part", type=int, default=-1, choices=[0, 1],
-                    help="solve half of the workload's whole grid (0: lower, 1: upper half of the "
-                         "frequencies) x every drive in chunks, one line per chunk (no timed steps)")
+    ap.add_argument("--spectrum-range", default="", metavar="LO:HI",
+                    help="solve the grid points LO..HI-1 of the workload's whole grid x every drive in "
+                         "chunks, one line per chunk (no timed steps)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 device copies of MIB MiB (reference for HBM traffic counters)")
     a = ap.parse_args()
@@ -682,8 +694,8 @@ def main():
     if a.lanczos:
         return lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx,
                             ref_drive if ref is not None else None)
-    if a.spectrum_part >= 0:
-        return spectrum_part(a, s, ctx, drives, ref, ref_idx, ref_drive if ref is not None else None)
+    if a.spectrum_range:
+        return spectrum_range(a, s, ctx, drives, ref, ref_idx, ref_drive if ref is not None else None)
     if a.warm_experiment:
         return warm_experiment(a, s, ctx, drives, restart, tol)
 
@@ -801,7 +813,7 @@ def main():
                 "achieved": achieved / scale, "peak": peak / scale,
                 "unit": unit, "frac": achieved / peak, "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
-                "traffic_over_algorithmic": (traffic / (work / rec["launches"])) if traffic else None,
+                "traffic_over_algorithmic": (traffic / (rec["bytes"] / rec["launches"])) if traffic and rec["bytes"] else None,
                 "launches": rec["launches"] // a.steps, "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
                 "share_of_gpu_time": (ks_all[dom]["ms"] / tot_all) if dom in ks_all else None,
                 "lanes": a.lanes or ("auto: 2" if a.batch >= 16 else "auto: 1"),

@@ -295,6 +295,9 @@ typedef struct chi0_point_stats {
     double  warm_rel0;    /* ||b - A x0|| / ||b|| of the warm start (0 if none) */
     double  eps_x;        /* CHI0_STOP_EPS_*: the last eps_X and eps_P estimates seen (else 0) */
     double  eps_p;
+    int32_t low_prec_steps; /* of `iterations`, the Arnoldi steps that applied chi0 with the
+                               reduced-precision transforms (0 for CHI0_PREC_FP64) */
+    int32_t reserved;
 } chi0_point_stats;
 
 void chi0_solve_opts_default(chi0_solve_opts *opts);

@@ -56,7 +56,8 @@ class PointStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("breakdown", C.c_int32), ("fallback", C.c_int32), ("warm_start", C.c_int32),
                 ("rel_residual", C.c_double), ("warm_rel0", C.c_double),
-                ("eps_x", C.c_double), ("eps_p", C.c_double)]
+                ("eps_x", C.c_double), ("eps_p", C.c_double), ("low_prec_steps", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class LanczosOpts(C.Structure):
@@ -79,7 +80,7 @@ class KernelRecord(C.Structure):
 SolveStats = np.dtype([("iterations", np.int32), ("restarts", np.int32), ("converged", np.int32),
                        ("breakdown", np.int32), ("fallback", np.int32), ("warm_start", np.int32),
                        ("rel_residual", np.float64), ("warm_rel0", np.float64),
-                       ("eps_x", np.float64), ("eps_p", np.float64)])
+                       ("eps_x", np.float64), ("eps_p", np.float64), ("low_prec_steps", np.int32)])
 
 _LIB = None
 
@@ -365,7 +366,7 @@ class Context:
         for i in range(om.size * nd):
             flat[i] = (st[i].iterations, st[i].restarts, st[i].converged, st[i].breakdown,
                        st[i].fallback, st[i].warm_start, st[i].rel_residual, st[i].warm_rel0,
-                       st[i].eps_x, st[i].eps_p)
+                       st[i].eps_x, st[i].eps_p, st[i].low_prec_steps)
         a = alpha[..., 0] + 1j * alpha[..., 1]
         if return_x:
             return a, stats, rc, x[..., 0] + 1j * x[..., 1]

@@ -1032,7 +1032,7 @@ struct SlotState {
     bool eps_met = false;        // the cycle ended by the eps_P / eps_X test
 };
 struct PointState {
-    int iters = 0, restarts = 0, converged = 0, breakdown = 0, fallback = 0, warm = 0;
+    int iters = 0, restarts = 0, converged = 0, breakdown = 0, fallback = 0, warm = 0, low = 0;
     double rel = NAN, warm_rel0 = 0.0, eps_x = 0.0, eps_p = 0.0;
 };
 }  // namespace
@@ -1246,7 +1246,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
     // Hessenberg columns and rotations beyond the cycle's length L, which the
     // update of x never reads.  b and residual jobs are never launched ahead.
     struct InFlight {
-        int nb = 0;
+        int nb = 0, nb64 = 0;   // jobs [nb64, nb) are reduced-precision Arnoldi steps
         int64_t seq = 0;
         std::vector<int> epoch;
     } fl[kSets];
@@ -1298,6 +1298,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 if (pass == 0) ++nb64;
             }
         f.nb = nb;
+        f.nb64 = nb64;
         f.seq = seq++;
         if (nb == 0) return CHI0_OK;
         Job *jobs_d = c->jobs_dev(q);
@@ -1355,6 +1356,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 PointState &pt = ps[ss.point];
                 ss.pend -= 1;
                 pt.iters += 1;
+                if (r >= f.nb64) pt.low += 1;
                 double stop = o.tol * ss.bnorm;
                 if (relaxed) {
                     if (ss.prec == CHI0_PREC_FP64 && !pt.fallback && st.value <= relax_at * ss.bnorm)
@@ -1616,6 +1618,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
                 r.warm_rel0 = ps[p].warm_rel0;
                 r.eps_x = ps[p].eps_x;
                 r.eps_p = ps[p].eps_p;
+                r.low_prec_steps = ps[p].low;
             }
         }
     c->err.clear();
