@@ -483,10 +483,15 @@ def spectrum_range(a, s, ctx, drives, ref, ref_idx, ref_drive):
                     r0 = ref[n, ref_drive[i], ref_drive[i]]
                     errs.append(abs(al[i, i].imag - r0.imag) / max(abs(r0.imag), fl))
         acc = {"oracle_points": len(errs), "max_im_rel_err": float(max(errs)) if errs else None}
+    pos = s.omegas[idx] > 0
+    scale = float(np.max(np.abs(alpha)))
+    checks = {"max_asymmetry_rel": float(np.max(np.abs(alpha - np.swapaxes(alpha, 1, 2)))) / scale,
+              "min_im_alpha_diag_over_max": float(min(alpha[pos, i, i].imag.min() for i in range(nd))) / scale
+              if pos.any() else None}
     print(json.dumps({"spectrum_range": [lo, hi], "workload": a.workload, "points": int(idx.size * nd),
                       "seconds": sec, "points_per_s": idx.size * nd / sec, "converged": int(conv.sum()),
                       "iterations": {"mean": float(iters.mean()), "max": int(iters.max()), "total": int(iters.sum())},
-                      "accuracy": acc}), flush=True)
+                      "accuracy": acc, "checks": checks}), flush=True)
     ctx.close()
 
 

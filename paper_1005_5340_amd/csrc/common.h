@@ -28,7 +28,6 @@
 namespace chi0 {
 
 constexpr int TILE = 64;     // M/N tile of the dense GEMMs, E tile of the gathered ones
-constexpr int JT = 16;       // column tile of the gathered GEMMs and of ncp
 constexpr int NB_MAX = 16;   // maximum orbitals per atom supported by the gathered GEMMs
 constexpr int GEMM_VARIANTS = 6;   // tile shapes of the dense GEMM (see GemmTuner)
 

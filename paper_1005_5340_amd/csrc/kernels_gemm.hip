@@ -445,49 +445,61 @@ template <class T> struct OccMma { typedef Mma<T> type; };
 template <> struct OccMma<double> { typedef Mma16d type; };
 
 // ------------------------------------------------------- (b1) occupied transform
+// The gathered transforms multiply by one atom's orbitals b at a time, for every
+// column j; their output columns are the packed pairs n = b nc + j of the column
+// atom (nB nc of them), cut into 16-column MFMA tiles, OCC_NT tiles per
+// workgroup.  A few right-hand sides therefore fill the tiles: one complex
+// vector (nc = 2) on a 9-orbital atom is 18 pairs, two tiles, not nine tiles of
+// which 2 columns are used.
+constexpr int OCC_NT = 9;              // 16-column tiles per workgroup
+constexpr int OCC_NW = 16 * OCC_NT;    // packed (b, j) pairs per workgroup
+
 // Tt[b][E*nc + j] = sum_{A in nbr(B)} sum_{a in A} Xo[a][E] dV[(k(A,B), a, b)][j]
-// One workgroup: column atom B, 64 occupied states, 16 columns.  Wave w owns
-// states 16w..16w+15 and every orbital b of B (one accumulator per b; NBT is
-// the system's largest atom: 4, 8, 9, 12, 13 or 16).  The gathered rows
-// come in chunks of 16; the next chunk's global loads are issued before the
-// current chunk's MFMAs so their latency overlaps the arithmetic.
-// T is the arithmetic type (FP64, or FP32 for the low-precision operator);
-// dV is always FP64 and is rounded to T when staged.
-template <class T, int NBT>
+// One workgroup: column atom B, 64 occupied states, OCC_NW packed pairs.  Wave w
+// owns states 16w..16w+15.  The gathered rows come in chunks of 16; the next
+// chunk's global loads are issued before the current chunk's MFMAs so their
+// latency overlaps the arithmetic.  Row g of dV holds the pairs of B
+// contiguously (dV[(k, a, b)][j] = dV[k_a nc + n]), so a chunk's pairs are one
+// coalesced run per gathered row.  T is the arithmetic type (FP64, or FP32 for
+// the low-precision operator); dV is always FP64 and is rounded to T when staged.
+template <class T>
 __global__ __launch_bounds__(256)
 void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
                      const double *__restrict__ dV, T *__restrict__ Tt, int nc) {
     typedef typename OccMma<T>::type MM;
-    const int B = blockIdx.x, e0 = blockIdx.y * 64, j0 = blockIdx.z * JT;
+    const int B = blockIdx.x, e0 = blockIdx.y * 64, n0 = blockIdx.z * OCC_NW;
     const int g0 = bm.col_gstart[B], g1 = bm.col_gstart[B + 1];
     const int boff = bm.atom_off[B], nB = bm.atom_off[B + 1] - boff;
+    const int nn = nB * nc;
+    if (n0 >= nn) return;
+    const int ntile = min(OCC_NT, (nn - n0 + 15) / 16);
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     __shared__ T Xs[16][64 + 1];
-    __shared__ T Ds[16][NBT][JT];
+    __shared__ T Ds[16][OCC_NW];
 
-    typename MM::acc acc[NBT];
+    typename MM::acc acc[OCC_NT];
 #pragma unroll
-    for (int b = 0; b < NBT; ++b) acc[b] = MM::zero();
+    for (int i = 0; i < OCC_NT; ++i) acc[i] = MM::zero();
 
-    // register staging of one chunk: 4 X values and the nB dV values of (row, column)
+    // register staging of one chunk: 4 X values and OCC_NT dV values of one row
     const int xr = t / 16, xc = (t % 16) * 4;
-    const int dr = t / JT, djj = t % JT, dj = j0 + djj;
-    T xv[4], dv[NBT];
+    const int dr = t / 16, dn = t % 16;
+    T xv[4], dv[OCC_NT];
     auto fetch = [&](int gc) {
         const int gx = gc + xr;
         xv[0] = xv[1] = xv[2] = xv[3] = T(0);
         if (gx < g1) load4(Xo + (int64_t)bm.g_xrow[gx] * no_pad + e0 + xc, xv);
         const int gd = gc + dr;
-        const bool ok = gd < g1 && dj < nc;
-        const double *src = dV + (ok ? (bm.g_ent[gd] * (int64_t)nc + dj) : 0);
+        const double *src = dV + (gd < g1 ? (int64_t)bm.g_ent[gd] * nc : 0) + n0 + dn;
 #pragma unroll
-        for (int b = 0; b < NBT; ++b) dv[b] = (ok && b < nB) ? (T)src[(int64_t)b * nc] : T(0);
+        for (int i = 0; i < OCC_NT; ++i)
+            dv[i] = (gd < g1 && n0 + 16 * i + dn < nn) ? (T)src[16 * i] : T(0);
     };
     fetch(g0);
     for (int gc = g0; gc < g1; gc += 16) {
         Xs[xr][xc] = xv[0]; Xs[xr][xc + 1] = xv[1]; Xs[xr][xc + 2] = xv[2]; Xs[xr][xc + 3] = xv[3];
 #pragma unroll
-        for (int b = 0; b < NBT; ++b) Ds[dr][b][djj] = dv[b];
+        for (int i = 0; i < OCC_NT; ++i) Ds[dr][16 * i + dn] = dv[i];
         __syncthreads();
         if (gc + 16 < g1) fetch(gc + 16);
 #pragma unroll
@@ -497,51 +509,38 @@ void k_occ_transform(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
 #pragma unroll
             for (int r = 0; r < MM::NA; ++r) a[r] = Xs[kk][wv * 16 + MM::a_row(lane, r)];
 #pragma unroll
-            for (int b = 0; b < NBT; ++b)
-                if (b < nB) acc[b] = MM::op(a, Ds[kk][b][lane & 15], acc[b]);
+            for (int i = 0; i < OCC_NT; ++i)
+                if (i < ntile) acc[i] = MM::op(a, Ds[kk][16 * i + (lane & 15)], acc[i]);
         }
         __syncthreads();
     }
     const int64_t ldT = (int64_t)no_pad * nc;
-    const int j = j0 + (lane & 15);
-    if (j < nc) {
 #pragma unroll
-        for (int b = 0; b < NBT; ++b) {
-            if (b < nB) {
+    for (int i = 0; i < OCC_NT; ++i) {
+        const int n = n0 + 16 * i + (lane & 15);
+        if (i < ntile && n < nn) {
+            const int b = n / nc, j = n - b * nc;
+            T *dst = Tt + (int64_t)(boff + b) * ldT + j;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int E = e0 + wv * 16 + MM::row(lane, r);
-                    Tt[(int64_t)(boff + b) * ldT + (int64_t)E * nc + j] = acc[b][r];
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int E = e0 + wv * 16 + MM::row(lane, r);
+                dst[(int64_t)E * nc] = acc[i][r];
             }
         }
     }
 }
 
-template <class T, int NBT>
-static void occ_transform_nbt(hipStream_t s, dim3 grid, const BlockMapDev &bm, const T *Xo, int no_pad,
-                              const double *dV, T *Tt, int nc) {
-    hipLaunchKernelGGL((k_occ_transform<T, NBT>), grid, dim3(256), 0, s, bm, Xo, no_pad, dV, Tt, nc);
+static inline int occ_pair_blocks(const BlockMapDev &bm, int nc) {
+    return (bm.nb_max * nc + OCC_NW - 1) / OCC_NW;
 }
 
 template <class T>
 static void occ_transform_any(Tracer *t, hipStream_t s, const char *name, const BlockMapDev &bm,
                               int n_atoms, const T *Xo, int no_pad, const double *dV, T *Tt, int nc,
                               const WorkSizes &ws) {
-    dim3 grid(n_atoms, no_pad / 64, (nc + JT - 1) / JT);
+    dim3 grid(n_atoms, no_pad / 64, occ_pair_blocks(bm, nc));
     trace_begin(t, name, s);
-    if (bm.nb_max <= 4)
-        occ_transform_nbt<T, 4>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
-    else if (bm.nb_max <= 8)
-        occ_transform_nbt<T, 8>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
-    else if (bm.nb_max <= 9)
-        occ_transform_nbt<T, 9>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
-    else if (bm.nb_max <= 12)
-        occ_transform_nbt<T, 12>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
-    else if (bm.nb_max <= 13)
-        occ_transform_nbt<T, 13>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
-    else
-        occ_transform_nbt<T, 16>(s, grid, bm, Xo, no_pad, dV, Tt, nc);
+    hipLaunchKernelGGL((k_occ_transform<T>), grid, dim3(256), 0, s, bm, Xo, no_pad, dV, Tt, nc);
     trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
               8.0 * ws.nnzB * nc + sizeof(T) * (ws.N * ws.No + ws.N * ws.No * nc));
 }
@@ -560,99 +559,96 @@ void launch_occ_transform_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, i
 
 // ------------------------------------------------------ (b4) back to the pattern
 // W[(k(A,B), a, b)][j] = sum_E Xo[a][E] Ut[b][E*nc + j] for (A, B) in the pattern.
-// One workgroup: column atom B, 64 of its gathered rows (A, a), 16 columns;
-// the occupied states come in chunks of 16 with the next chunk's global loads
-// issued before the current chunk's MFMAs.  Accumulation in T; W is FP64.
-template <class T, int NBT>
+// One workgroup: column atom B, 64 of its gathered rows (A, a), OCC_NW packed
+// pairs n = b nc + j; the occupied states come in chunks of 16 with the next
+// chunk's global loads issued before the current chunk's MFMAs.  A wave whose
+// 16 rows lie past the atom's last gathered row stages its share of the
+// operands and skips the MFMAs.  Accumulation in T; W is FP64.
+template <class T>
 __global__ __launch_bounds__(256)
 void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
                 const T *__restrict__ Ut, double *__restrict__ W, int nc) {
     typedef typename OccMma<T>::type MM;
-    const int B = blockIdx.x, j0 = blockIdx.z * JT;
+    const int B = blockIdx.x, n0 = blockIdx.z * OCC_NW;
     const int g1 = bm.col_gstart[B + 1];
     const int g0 = bm.col_gstart[B] + blockIdx.y * 64;
     if (g0 >= g1) return;
     const int boff = bm.atom_off[B], nB = bm.atom_off[B + 1] - boff;
+    const int nn = nB * nc;
+    if (n0 >= nn) return;
+    const int ntile = min(OCC_NT, (nn - n0 + 15) / 16);
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const bool live = g0 + wv * 16 < g1;
     const int64_t ldT = (int64_t)no_pad * nc;
     __shared__ T Xs[64][16 + 1];
-    __shared__ T Us[NBT][16][JT];
+    __shared__ T Us[16][OCC_NW];
 
-    typename MM::acc acc[NBT];
+    typename MM::acc acc[OCC_NT];
 #pragma unroll
-    for (int b = 0; b < NBT; ++b) acc[b] = MM::zero();
+    for (int i = 0; i < OCC_NT; ++i) acc[i] = MM::zero();
 
     const int xr = t / 4, xc = (t % 4) * 4, xg = g0 + xr;
     const T *xsrc = (xg < g1) ? Xo + (int64_t)bm.g_xrow[xg] * no_pad + xc : nullptr;
-    const int ue = t / JT, ujj = t % JT, uj = j0 + ujj;
-    const bool uok = uj < nc;
-    const T *usrc = Ut + (int64_t)boff * ldT + (int64_t)ue * nc + (uok ? uj : 0);
-    T xv[4], uv[NBT];
+    // pair i of this thread: n = n0 + 16 i + un, at Ut[(boff + b) ldT + E nc + j]
+    const int ue = t / 16, un = t % 16;
+    int64_t uoff[OCC_NT];
+#pragma unroll
+    for (int i = 0; i < OCC_NT; ++i) {
+        const int n = n0 + 16 * i + un;
+        const int b = n / nc, j = n - b * nc;
+        uoff[i] = n < nn ? (int64_t)(boff + b) * ldT + (int64_t)ue * nc + j : -1;
+    }
+    T xv[4], uv[OCC_NT];
     auto fetch = [&](int E0) {
         xv[0] = xv[1] = xv[2] = xv[3] = T(0);
         if (xsrc) load4(xsrc + E0, xv);
 #pragma unroll
-        for (int b = 0; b < NBT; ++b)
-            uv[b] = (uok && b < nB) ? usrc[(int64_t)b * ldT + (int64_t)E0 * nc] : T(0);
+        for (int i = 0; i < OCC_NT; ++i)
+            uv[i] = uoff[i] >= 0 ? Ut[uoff[i] + (int64_t)E0 * nc] : T(0);
     };
     fetch(0);
     for (int E0 = 0; E0 < no_pad; E0 += 16) {
         Xs[xr][xc] = xv[0]; Xs[xr][xc + 1] = xv[1]; Xs[xr][xc + 2] = xv[2]; Xs[xr][xc + 3] = xv[3];
 #pragma unroll
-        for (int b = 0; b < NBT; ++b) Us[b][ue][ujj] = uv[b];
+        for (int i = 0; i < OCC_NT; ++i) Us[ue][16 * i + un] = uv[i];
         __syncthreads();
         if (E0 + 16 < no_pad) fetch(E0 + 16);
+        if (live) {
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int kk = ks * 4 + (lane >> 4);
-            T a[MM::NA];
+            for (int ks = 0; ks < 4; ++ks) {
+                const int kk = ks * 4 + (lane >> 4);
+                T a[MM::NA];
 #pragma unroll
-            for (int r = 0; r < MM::NA; ++r) a[r] = Xs[wv * 16 + MM::a_row(lane, r)][kk];
+                for (int r = 0; r < MM::NA; ++r) a[r] = Xs[wv * 16 + MM::a_row(lane, r)][kk];
 #pragma unroll
-            for (int b = 0; b < NBT; ++b)
-                if (b < nB) acc[b] = MM::op(a, Us[b][kk][lane & 15], acc[b]);
+                for (int i = 0; i < OCC_NT; ++i)
+                    if (i < ntile) acc[i] = MM::op(a, Us[kk][16 * i + (lane & 15)], acc[i]);
+            }
         }
         __syncthreads();
     }
-    const int j = j0 + (lane & 15);
-    if (j < nc) {
+    if (!live) return;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int g = g0 + wv * 16 + MM::row(lane, r);
-            if (g < g1) {
-                const int64_t base = bm.g_ent[g];
+    for (int r = 0; r < 4; ++r) {
+        const int g = g0 + wv * 16 + MM::row(lane, r);
+        if (g < g1) {
+            double *dst = W + (int64_t)bm.g_ent[g] * nc;   // row (k, a, b) = g_ent[g] + b: column b nc + j
 #pragma unroll
-                for (int b = 0; b < NBT; ++b)
-                    if (b < nB) W[(base + b) * nc + j] = (double)acc[b][r];
+            for (int i = 0; i < OCC_NT; ++i) {
+                const int n = n0 + 16 * i + (lane & 15);
+                if (i < ntile && n < nn) dst[n] = (double)acc[i][r];
             }
         }
     }
-}
-
-template <class T, int NBT>
-static void occ_back_nbt(hipStream_t s, dim3 grid, const BlockMapDev &bm, const T *Xo, int no_pad,
-                         const T *Ut, double *W, int nc) {
-    hipLaunchKernelGGL((k_occ_back<T, NBT>), grid, dim3(256), 0, s, bm, Xo, no_pad, Ut, W, nc);
 }
 
 template <class T>
 static void occ_back_any(Tracer *t, hipStream_t s, const char *name, const BlockMapDev &bm,
                          int n_atoms, int max_rows, const T *Xo, int no_pad, const T *Ut, double *W,
                          int nc, const WorkSizes &ws) {
-    dim3 grid(n_atoms, (max_rows + 63) / 64, (nc + JT - 1) / JT);
+    dim3 grid(n_atoms, (max_rows + 63) / 64, occ_pair_blocks(bm, nc));
     trace_begin(t, name, s);
-    if (bm.nb_max <= 4)
-        occ_back_nbt<T, 4>(s, grid, bm, Xo, no_pad, Ut, W, nc);
-    else if (bm.nb_max <= 8)
-        occ_back_nbt<T, 8>(s, grid, bm, Xo, no_pad, Ut, W, nc);
-    else if (bm.nb_max <= 9)
-        occ_back_nbt<T, 9>(s, grid, bm, Xo, no_pad, Ut, W, nc);
-    else if (bm.nb_max <= 12)
-        occ_back_nbt<T, 12>(s, grid, bm, Xo, no_pad, Ut, W, nc);
-    else if (bm.nb_max <= 13)
-        occ_back_nbt<T, 13>(s, grid, bm, Xo, no_pad, Ut, W, nc);
-    else
-        occ_back_nbt<T, 16>(s, grid, bm, Xo, no_pad, Ut, W, nc);
+    hipLaunchKernelGGL((k_occ_back<T>), grid, dim3(256), 0, s, bm, Xo, no_pad, Ut, W, nc);
     trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
               sizeof(T) * (ws.N * ws.No * nc + ws.N * ws.No) + 8.0 * ws.nnzB * nc);
 }
@@ -732,14 +728,15 @@ constexpr int KMV_U = 8;    // column pairs per lane and row tile in flight
 // workgroup owns 16 RT rows;
 // its four waves split the reduction over nu in interleaved chunks of 8 U
 // columns and add their 16x16 accumulators in a fixed order through LDS at
-// the end.  Each lane streams K as 16-byte (non-temporal) loads of two
-// adjacent columns; the two columns feed two 16x16x4 MFMAs whose k slots are
-// the lanes' even and odd columns, with Zin rows taken in the same order.
-// Zin (P_pad x nc, a few MB) is read through the cache; no barrier in the loop.
-// (Measured on the 12.4k-product kernel, 1.2 GB: 4.0-4.3 TB/s for 6-16
-// columns, against 0.25-3.4 for the LDS-staged form; non-temporal loads of K
-// were 10 % slower here.)
-template <int RT, int CT, int U>
+// the end.  Each lane streams K as 16-byte loads of two adjacent columns; the
+// two columns feed two 16x16x4 MFMAs whose k slots are the lanes' even and odd
+// columns, with Zin rows taken in the same order.  Zin (P_pad x nc, a few MB)
+// is read through the cache; no barrier in the loop.  With PF the loads of the
+// wave's next chunk are issued before the MFMAs of the current one (one
+// 16-column tile: 4.3-4.4 TB/s against 4.0-4.2 without, on the 12.4k-product
+// kernel, 1.2 GB; with two tiles the doubled registers make it slower).
+// (LDS-staged form: 0.25-3.4 TB/s; non-temporal loads of K were 10 % slower.)
+template <int RT, int CT, int U, bool PF>
 __global__ __launch_bounds__(256)
 void k_kmatvec_mfma(int P_pad, const double *__restrict__ K, const double *__restrict__ Zin,
                     double *__restrict__ Zout, int nc) {
@@ -753,9 +750,9 @@ void k_kmatvec_mfma(int P_pad, const double *__restrict__ K, const double *__res
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[r][c] = dbl4{0.0, 0.0, 0.0, 0.0};
     constexpr int KW = 8 * U;
-    for (int k0 = wv * KW; k0 < P_pad; k0 += 4 * KW) {
-        double2 a[U][RT];
-        double b0[U][CT], b1[U][CT];
+    double2 a[U][RT];
+    double b0[U][CT], b1[U][CT];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kk = k0 + 8 * u + 2 * lk;   // even; P_pad is a multiple of 64
@@ -771,15 +768,39 @@ void k_kmatvec_mfma(int P_pad, const double *__restrict__ K, const double *__res
                 b1[u][c] = (ok && col < nc) ? Zin[(int64_t)(kk + 1) * nc + col] : 0.0;
             }
         }
+    };
+    auto mma = [&](const double2 (&ca)[U][RT], const double (&c0)[U][CT], const double (&c1)[U][CT]) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int r = 0; r < RT; ++r)
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
-                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][r].x, b0[u][c], acc[r][c], 0, 0, 0);
-                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][r].y, b1[u][c], acc[r][c], 0, 0, 0);
+                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u][r].x, c0[u][c], acc[r][c], 0, 0, 0);
+                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[u][r].y, c1[u][c], acc[r][c], 0, 0, 0);
                 }
+    };
+    if constexpr (PF) {
+        int k0 = wv * KW;
+        if (k0 < P_pad) fetch(k0);
+        for (; k0 < P_pad; k0 += 4 * KW) {
+            double2 ca[U][RT];
+            double c0[U][CT], c1[U][CT];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r) ca[u][r] = a[u][r];
+#pragma unroll
+                for (int c = 0; c < CT; ++c) { c0[u][c] = b0[u][c]; c1[u][c] = b1[u][c]; }
+            }
+            if (k0 + 4 * KW < P_pad) fetch(k0 + 4 * KW);
+            mma(ca, c0, c1);
+        }
+    } else {
+        for (int k0 = wv * KW; k0 < P_pad; k0 += 4 * KW) {
+            fetch(k0);
+            mma(a, b0, b1);
+        }
     }
     if (wv > 0)
 #pragma unroll
@@ -815,11 +836,11 @@ void launch_kmatvec_skinny(Tracer *t, hipStream_t s, int P_pad, const double *K,
     else if (nc == 4)
         hipLaunchKernelGGL((k_kmatvec_lanes<4, 2>), dim3(P_pad / 8), dim3(256), 0, s, P_pad, K, Zin, Zout);
     else if (nc <= 16)
-        hipLaunchKernelGGL((k_kmatvec_mfma<KMV_RT, 1, KMV_U>), dim3(P_pad / (16 * KMV_RT)), dim3(256), 0, s, P_pad,
-                           K, Zin, Zout, nc);
-    else
-        hipLaunchKernelGGL((k_kmatvec_mfma<KMV_RT, 2, KMV_U / 2>), dim3(P_pad / (16 * KMV_RT)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_kmatvec_mfma<KMV_RT, 1, KMV_U, true>), dim3(P_pad / (16 * KMV_RT)), dim3(256), 0, s,
                            P_pad, K, Zin, Zout, nc);
+    else
+        hipLaunchKernelGGL((k_kmatvec_mfma<KMV_RT, 2, KMV_U / 2, false>), dim3(P_pad / (16 * KMV_RT)), dim3(256), 0,
+                           s, P_pad, K, Zin, Zout, nc);
     trace_end(t, s, 2.0 * P * P * nc, 8.0 * (P * P + 2.0 * P * nc));
 }
 
