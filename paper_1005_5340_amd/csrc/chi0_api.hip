@@ -139,6 +139,9 @@ struct chi0_ctx {
     bool has_system = false;
     int n_atoms = 0, N = 0, No = 0, Nv = 0, P = 0;
     int N_pad = 0, No_pad = 0, Nv_pad = 0, P_pad = 0;
+    // the orbital counts rounded to the 16 of an MFMA k step: the extents the dense
+    // transforms and the occupied sum of (b4) run over (the buffers keep the padding)
+    int N16 = 0, No16 = 0, Nv16 = 0;
     double occ = 2.0;
     int n_blk = 0, n_g = 0, max_rows = 0, max_nprod = 0;
     int64_t nnzB = 0, npart = 0;
@@ -610,6 +613,9 @@ extern "C" int chi0_set_system(chi0_ctx *c, int32_t n_atoms, const double *posit
     c->No_pad = (int)round_up(n_occ, TILE);
     c->Nv_pad = (int)round_up(n_orb - n_occ, TILE);
     c->P_pad = (int)round_up(n_prod, TILE);
+    c->N16 = (int)round_up(n_orb, 16);
+    c->No16 = (int)round_up(n_occ, 16);
+    c->Nv16 = (int)round_up(n_orb - n_occ, 16);
     c->occ = occ_factor;
     c->n_blk = nblk; c->n_g = (int)hm.g_xrow.size(); c->max_rows = hm.max_rows;
     c->max_nprod = *std::max_element(hm.blk_nprod.begin(), hm.blk_nprod.end());
@@ -771,20 +777,23 @@ static void run_chi0(chi0_ctx *c, OpWork &o, hipStream_t s, int nb, double eps, 
     const int nc = 2 * nb;
     const WorkSizes &w = c->ws;
     const int64_t mcol = (int64_t)c->No_pad * nc;
+    // the dense transforms' columns (E, j) for E < No16 and sums over k < N16 / Nv16:
+    // the rest of the padded layout holds zeros and is not multiplied
+    const int ncol = c->No16 * nc;
     // algorithmic work of the two dense transforms (unpadded sizes)
     const double fl = 2.0 * w.N * w.Nv * w.No * nc;
     launch_vertex_gather(t, s, c->bm, c->n_blk, o.Zin, o.dV, nc, w);
     if (prec == CHI0_PREC_FP64) {
         launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, o.dV, o.Tt, nc, w);
-        launch_dgemm_lorentz(t, s, c->Nv_pad, (int)mcol, c->N_pad, c->Xvt, c->N_pad, o.Tt, (int)mcol,
+        launch_dgemm_lorentz(t, s, c->Nv_pad, ncol, c->N16, c->N_pad, c->Xvt, c->N_pad, o.Tt, (int)mcol,
                              o.at, (int)mcol, c->Dlt, c->Nv_pad, omega, eps, c->occ, nc,
                              fl + 6.0 * w.No * w.Nv * nb,
                              8.0 * (w.N * w.No * nc + w.Nv * w.No * nc + w.N * w.Nv + w.No * w.Nv),
                              o.gemm_scratch, o.gemm_scratch_n, tu);
-        launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, o.at, (int)mcol,
+        launch_dgemm(t, s, "virt_back", c->N_pad, ncol, c->Nv16, c->Nv_pad, c->Xv, c->Nv_pad, o.at, (int)mcol,
                      o.Ut, (int)mcol, fl, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv),
                      o.gemm_scratch, o.gemm_scratch_n, tu);
-        launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, o.Ut, o.W, nc, w);
+        launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, c->No16, o.Ut, o.W, nc, w);
     } else {
         launch_occ_transform_f32(t, s, c->bm, c->n_atoms, c->Xo32, c->No_pad, o.dV, o.Tt32, nc, w);
         LorentzArgs la{c->Dlt, omega, c->Nv_pad, nc, eps, c->occ};
@@ -805,7 +814,7 @@ static void run_chi0(chi0_ctx *c, OpWork &o, hipStream_t s, int nb, double eps, 
                           c->Nv_pad, o.at32, (int)mcol, o.Bhi, o.Blo, o.Ut32, (int)mcol, 3.0 * fl,
                           by + 4.0 * w.N * w.Nv, nullptr, o.gemm_scratch, sb);
         }
-        launch_occ_back_f32(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo32, c->No_pad, o.Ut32, o.W, nc, w);
+        launch_occ_back_f32(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo32, c->No_pad, c->No16, o.Ut32, o.W, nc, w);
     }
     launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, o.W, o.part, o.Yout, nc, w, c->max_nprod);
 }
@@ -1314,7 +1323,7 @@ static int solve_impl(chi0_ctx *c, int32_t n_omega, const double *omega, double 
             if (nc <= 32)
                 launch_kmatvec_skinny(t, s, c->P_pad, c->K, ow.Vb, ow.Zin, nc, (double)P);
             else
-                launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->K, c->P_pad, ow.Vb, nc, ow.Zin,
+                launch_dgemm(t, s, "kernel_matmul", c->P_pad, nc, c->P_pad, c->P_pad, c->K, c->P_pad, ow.Vb, nc, ow.Zin,
                              nc, 2.0 * P * (double)P * nc, 8.0 * ((double)P * P + 2.0 * P * nc),
                              ow.gemm_scratch, ow.gemm_scratch_n, &c->tuner);
             launch_put_drive(t, s, jg, gn, drives, c->P_pad, ow.Zin, nc, P);
@@ -2086,7 +2095,7 @@ void lz_front(chi0_ctx *c, OpWork &o, hipStream_t s, int nc) {
     const int64_t mcol = (int64_t)c->No_pad * nc;
     launch_vertex_gather(t, s, c->bm, c->n_blk, o.Zin, o.dV, nc, w);
     launch_occ_transform(t, s, c->bm, c->n_atoms, c->Xo, c->No_pad, o.dV, o.Tt, nc, w);
-    launch_dgemm(t, s, "casida_front", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt, c->N_pad, o.Tt, (int)mcol, o.at,
+    launch_dgemm(t, s, "casida_front", c->Nv_pad, c->No16 * nc, c->N16, c->N_pad, c->Xvt, c->N_pad, o.Tt, (int)mcol, o.at,
                  (int)mcol, 2.0 * w.N * w.Nv * w.No * nc, 8.0 * (w.N * w.No * nc + w.Nv * w.No * nc + w.N * w.Nv),
                  o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
 }
@@ -2096,10 +2105,11 @@ void lz_back(chi0_ctx *c, OpWork &o, hipStream_t s, int nc) {
     Tracer *t = &c->tracer;
     const WorkSizes &w = c->ws;
     const int64_t mcol = (int64_t)c->No_pad * nc;
-    launch_dgemm(t, s, "virt_back", c->N_pad, (int)mcol, c->Nv_pad, c->Xv, c->Nv_pad, o.at, (int)mcol, o.Ut,
-                 (int)mcol, 2.0 * w.N * w.Nv * w.No * nc, 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv),
-                 o.gemm_scratch, o.gemm_scratch_n, &c->tuner);
-    launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, o.Ut, o.W, nc, w);
+    launch_dgemm(t, s, "virt_back", c->N_pad, c->No16 * nc, c->Nv16, c->Nv_pad, c->Xv, c->Nv_pad, o.at, (int)mcol,
+                 o.Ut, (int)mcol, 2.0 * w.N * w.Nv * w.No * nc,
+                 8.0 * (w.Nv * w.No * nc + w.N * w.No * nc + w.N * w.Nv), o.gemm_scratch, o.gemm_scratch_n,
+                 &c->tuner);
+    launch_occ_back(t, s, c->bm, c->n_atoms, c->max_rows, c->Xo, c->No_pad, c->No16, o.Ut, o.W, nc, w);
     launch_vertex_contract(t, s, c->bm, c->n_blk, c->P, o.W, o.part, o.Yout, nc, w, c->max_nprod);
 }
 

@@ -91,9 +91,10 @@ void launch_vertex_contract(Tracer *t, hipStream_t s, const BlockMapDev &bm, int
 void launch_occ_transform(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms,
                           const double *Xo, int no_pad, const double *dV, double *Tt,
                           int nc, const WorkSizes &ws);
-// (b4) W = X_occ Ut restricted to the block pattern.
+// (b4) W = X_occ Ut restricted to the block pattern; the sum over occupied
+// states runs over E < no_sum (a multiple of 16, at most no_pad).
 void launch_occ_back(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
-                     const double *Xo, int no_pad, const double *Ut, double *W, int nc,
+                     const double *Xo, int no_pad, int no_sum, const double *Ut, double *W, int nc,
                      const WorkSizes &ws);
 // Tile-shape autotuner of the dense GEMMs (one per context).  The first call
 // of a GEMM whose (name, M, K, split count, N within a half octave) has not
@@ -115,13 +116,15 @@ struct GemmTuner {
 extern const char *const kGemmVariantNames[GEMM_VARIANTS];
 
 // Dense FP64 MFMA GEMM C = A B (row-major, M%64 == K%16 == 0, N masked).
-// scratch (may be NULL) holds split-K partial products when the tile count is low.
-void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
+// kpad >= K: A's columns and B's rows exist (zero beyond K) up to kpad, so
+// split-K ranges may run past K into them.  scratch (may be NULL) holds split-K
+// partial products when the tile count is low.
+void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K, int kpad,
                   const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                   double flops, double bytes, double *scratch, size_t scratch_doubles,
                   GemmTuner *tu = nullptr);
 // (b2)+(c) at = Xvt Tt with the Lorentzian factor of column (E, j) and row F applied.
-void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K,
+void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K, int kpad,
                           const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                           const double *Dlt, int nv_pad, const double *omega, double eps,
                           double occ, int ncp, double flops, double bytes, double *scratch,
@@ -131,7 +134,7 @@ void launch_occ_transform_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, i
                               const float *Xo, int no_pad, const double *dV, float *Tt,
                               int nc, const WorkSizes &ws);
 void launch_occ_back_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
-                         const float *Xo, int no_pad, const float *Ut, double *W, int nc,
+                         const float *Xo, int no_pad, int no_sum, const float *Ut, double *W, int nc,
                          const WorkSizes &ws);
 void launch_sgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
                   const float *A, int lda, const float *B, int ldb, float *C, int ldc,

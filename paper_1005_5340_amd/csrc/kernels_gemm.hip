@@ -269,14 +269,19 @@ void k_splitk_reduce(int M, int N, int S, const T *__restrict__ part, int64_t sl
 }
 
 // Number of K splits: enough workgroups to fill 256 CUs a few times over,
-// each split keeping >= 4 K tiles of `ktile`; limited by the scratch capacity.
-static int choose_splits(int M, int N, int K, int ktile, size_t scratch_elems) {
+// each split keeping >= 4 K tiles of 16; limited by the scratch capacity.  The
+// splits have equal lengths *ks of whole tiles; S *ks may exceed K (the last
+// split then sums zero padding) but not kpad, the operands' K extent.
+static int choose_splits(int M, int N, int K, int kpad, size_t scratch_elems, int *ks) {
     const int tiles = (M / 64) * ((N + 63) / 64);
-    const int KT = K / ktile;
+    const int KT = K / 16;
     int S = 1;
-    while (S < 16 && tiles * S < 1024 && KT % (2 * S) == 0 && KT / (2 * S) >= 4 &&
-           (size_t)(2 * S) * M * (size_t)N <= scratch_elems)
-        S *= 2;
+    while (S < 16 && tiles * S < 1024) {
+        const int S2 = 2 * S, kt2 = (KT + S2 - 1) / S2;
+        if (kt2 < 4 || (int64_t)S2 * kt2 * 16 > kpad || (size_t)S2 * M * (size_t)N > scratch_elems) break;
+        S = S2;
+    }
+    *ks = (KT + S - 1) / S * 16;
     return S;
 }
 
@@ -380,11 +385,12 @@ static int pick_variant(GemmTuner *tu, hipStream_t s, const char *name, int S, i
 }
 
 template <class T>
-static void gemm_any(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
+static void gemm_any(Tracer *t, hipStream_t s, const char *name, int M, int N, int K, int kpad,
                      const T *A, int lda, const T *B, int ldb, T *C, int ldc,
                      double flops, double bytes, bool lorentz, const LorentzArgs &la,
                      void *scratch, size_t scratch_bytes, GemmTuner *tu) {
-    const int S = scratch ? choose_splits(M, N, K, 16, scratch_bytes / sizeof(T)) : 1;
+    int ks = K;
+    const int S = scratch ? choose_splits(M, N, K, kpad, scratch_bytes / sizeof(T), &ks) : 1;
     const int m_fastest = (M / 64) <= ((N + 63) / 64);
     if (S == 1) {
         if (lorentz) {
@@ -401,28 +407,28 @@ static void gemm_any(Tracer *t, hipStream_t s, const char *name, int M, int N, i
     }
     // partial products with ldc = N into scratch, then the reduction (+ epilogue)
     T *part = static_cast<T *>(scratch);
-    const int v = pick_variant<T, false>(tu, s, name, S, M, N, K / S, A, lda, B, ldb, part, N, m_fastest, la);
+    const int v = pick_variant<T, false>(tu, s, name, S, M, N, ks, A, lda, B, ldb, part, N, m_fastest, la);
     trace_begin(t, name, s);
-    launch_variant<T, false>(v, s, dim3(1, S), M, N, K / S, A, lda, B, ldb, part, N, m_fastest, la);
+    launch_variant<T, false>(v, s, dim3(1, S), M, N, ks, A, lda, B, ldb, part, N, m_fastest, la);
     trace_end(t, s, flops, bytes);
     reduce_splits<T>(t, s, M, N, S, part, C, ldc, lorentz, la);
 }
 
-void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K,
+void launch_dgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int K, int kpad,
                   const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                   double flops, double bytes, double *scratch, size_t scratch_doubles, GemmTuner *tu) {
     LorentzArgs la{};
-    gemm_any<double>(t, s, name, M, N, K, A, lda, B, ldb, C, ldc, flops, bytes, false, la, scratch,
+    gemm_any<double>(t, s, name, M, N, K, kpad, A, lda, B, ldb, C, ldc, flops, bytes, false, la, scratch,
                      scratch_doubles * sizeof(double), tu);
 }
 
-void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K,
+void launch_dgemm_lorentz(Tracer *t, hipStream_t s, int M, int N, int K, int kpad,
                           const double *A, int lda, const double *B, int ldb, double *C, int ldc,
                           const double *Dlt, int nv_pad, const double *omega, double eps,
                           double occ, int ncp, double flops, double bytes, double *scratch,
                           size_t scratch_doubles, GemmTuner *tu) {
     LorentzArgs la{Dlt, omega, nv_pad, ncp, eps, occ};
-    gemm_any<double>(t, s, "virt_transform_lorentz", M, N, K, A, lda, B, ldb, C, ldc, flops, bytes,
+    gemm_any<double>(t, s, "virt_transform_lorentz", M, N, K, kpad, A, lda, B, ldb, C, ldc, flops, bytes,
                      true, la, scratch, scratch_doubles * sizeof(double), tu);
 }
 
@@ -437,7 +443,7 @@ void launch_sgemm(Tracer *t, hipStream_t s, const char *name, int M, int N, int 
                   double flops, double bytes, const LorentzArgs *la, void *scratch,
                   size_t scratch_bytes, GemmTuner *tu) {
     LorentzArgs none{};
-    gemm_any<float>(t, s, name, M, N, K, A, lda, B, ldb, C, ldc, flops, bytes, la != nullptr,
+    gemm_any<float>(t, s, name, M, N, K, K, A, lda, B, ldb, C, ldc, flops, bytes, la != nullptr,
                     la ? *la : none, scratch, scratch_bytes, tu);
 }
 
@@ -560,13 +566,13 @@ void launch_occ_transform_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, i
 // ------------------------------------------------------ (b4) back to the pattern
 // W[(k(A,B), a, b)][j] = sum_E Xo[a][E] Ut[b][E*nc + j] for (A, B) in the pattern.
 // One workgroup: column atom B, 64 of its gathered rows (A, a), OCC_NW packed
-// pairs n = b nc + j; the occupied states come in chunks of 16 with the next
+// pairs n = b nc + j; the occupied states E < no_sum come in chunks of 16 with the next
 // chunk's global loads issued before the current chunk's MFMAs.  A wave whose
 // 16 rows lie past the atom's last gathered row stages its share of the
 // operands and skips the MFMAs.  Accumulation in T; W is FP64.
 template <class T>
 __global__ __launch_bounds__(256)
-void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
+void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad, int no_sum,
                 const T *__restrict__ Ut, double *__restrict__ W, int nc) {
     typedef typename OccMma<T>::type MM;
     const int B = blockIdx.x, n0 = blockIdx.z * OCC_NW;
@@ -607,12 +613,12 @@ void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
             uv[i] = uoff[i] >= 0 ? Ut[uoff[i] + (int64_t)E0 * nc] : T(0);
     };
     fetch(0);
-    for (int E0 = 0; E0 < no_pad; E0 += 16) {
+    for (int E0 = 0; E0 < no_sum; E0 += 16) {
         Xs[xr][xc] = xv[0]; Xs[xr][xc + 1] = xv[1]; Xs[xr][xc + 2] = xv[2]; Xs[xr][xc + 3] = xv[3];
 #pragma unroll
         for (int i = 0; i < OCC_NT; ++i) Us[ue][16 * i + un] = uv[i];
         __syncthreads();
-        if (E0 + 16 < no_pad) fetch(E0 + 16);
+        if (E0 + 16 < no_sum) fetch(E0 + 16);
         if (live) {
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
@@ -644,25 +650,25 @@ void k_occ_back(BlockMapDev bm, const T *__restrict__ Xo, int no_pad,
 
 template <class T>
 static void occ_back_any(Tracer *t, hipStream_t s, const char *name, const BlockMapDev &bm,
-                         int n_atoms, int max_rows, const T *Xo, int no_pad, const T *Ut, double *W,
-                         int nc, const WorkSizes &ws) {
+                         int n_atoms, int max_rows, const T *Xo, int no_pad, int no_sum, const T *Ut,
+                         double *W, int nc, const WorkSizes &ws) {
     dim3 grid(n_atoms, (max_rows + 63) / 64, occ_pair_blocks(bm, nc));
     trace_begin(t, name, s);
-    hipLaunchKernelGGL((k_occ_back<T>), grid, dim3(256), 0, s, bm, Xo, no_pad, Ut, W, nc);
+    hipLaunchKernelGGL((k_occ_back<T>), grid, dim3(256), 0, s, bm, Xo, no_pad, no_sum, Ut, W, nc);
     trace_end(t, s, 2.0 * ws.No * ws.nnzB * nc,
               sizeof(T) * (ws.N * ws.No * nc + ws.N * ws.No) + 8.0 * ws.nnzB * nc);
 }
 
 void launch_occ_back(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
-                     const double *Xo, int no_pad, const double *Ut, double *W, int nc,
+                     const double *Xo, int no_pad, int no_sum, const double *Ut, double *W, int nc,
                      const WorkSizes &ws) {
-    occ_back_any<double>(t, s, "occ_back", bm, n_atoms, max_rows, Xo, no_pad, Ut, W, nc, ws);
+    occ_back_any<double>(t, s, "occ_back", bm, n_atoms, max_rows, Xo, no_pad, no_sum, Ut, W, nc, ws);
 }
 
 void launch_occ_back_f32(Tracer *t, hipStream_t s, const BlockMapDev &bm, int n_atoms, int max_rows,
-                         const float *Xo, int no_pad, const float *Ut, double *W, int nc,
+                         const float *Xo, int no_pad, int no_sum, const float *Ut, double *W, int nc,
                          const WorkSizes &ws) {
-    occ_back_any<float>(t, s, "occ_back_f32", bm, n_atoms, max_rows, Xo, no_pad, Ut, W, nc, ws);
+    occ_back_any<float>(t, s, "occ_back_f32", bm, n_atoms, max_rows, Xo, no_pad, no_sum, Ut, W, nc, ws);
 }
 
 // ---------------------------------------------------------- (e) skinny K z
