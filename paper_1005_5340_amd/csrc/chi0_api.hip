@@ -800,17 +800,17 @@ static void run_chi0(chi0_ctx *c, OpWork &o, hipStream_t s, int nb, double eps, 
         const size_t sb = o.gemm_scratch_n * sizeof(double);
         const double by = 4.0 * (w.N * w.No * nc + w.Nv * w.No * nc);
         if (prec == CHI0_PREC_FP32) {
-            launch_sgemm(t, s, "virt_transform_lorentz_f32", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt32,
+            launch_sgemm(t, s, "virt_transform_lorentz_f32", c->Nv_pad, ncol, c->N_pad, c->Xvt32,
                          c->N_pad, o.Tt32, (int)mcol, o.at32, (int)mcol, fl + 6.0 * w.No * w.Nv * nb,
                          by + 4.0 * w.N * w.Nv, &la, o.gemm_scratch, sb, tu);
-            launch_sgemm(t, s, "virt_back_f32", c->N_pad, (int)mcol, c->Nv_pad, c->Xv32, c->Nv_pad,
+            launch_sgemm(t, s, "virt_back_f32", c->N_pad, ncol, c->Nv_pad, c->Xv32, c->Nv_pad,
                          o.at32, (int)mcol, o.Ut32, (int)mcol, fl, by + 4.0 * w.N * w.Nv, nullptr,
                          o.gemm_scratch, sb, tu);
         } else {   // split BF16 x 3: three BF16 products per multiply-add
-            launch_bgemm3(t, s, "virt_transform_lorentz_bf16x3", c->Nv_pad, (int)mcol, c->N_pad, c->Xvt_hi,
+            launch_bgemm3(t, s, "virt_transform_lorentz_bf16x3", c->Nv_pad, ncol, c->N_pad, c->Xvt_hi,
                           c->Xvt_lo, c->N_pad, o.Tt32, (int)mcol, o.Bhi, o.Blo, o.at32, (int)mcol, 3.0 * fl,
                           by + 4.0 * w.N * w.Nv, &la, o.gemm_scratch, sb);
-            launch_bgemm3(t, s, "virt_back_bf16x3", c->N_pad, (int)mcol, c->Nv_pad, c->Xv_hi, c->Xv_lo,
+            launch_bgemm3(t, s, "virt_back_bf16x3", c->N_pad, ncol, c->Nv_pad, c->Xv_hi, c->Xv_lo,
                           c->Nv_pad, o.at32, (int)mcol, o.Bhi, o.Blo, o.Ut32, (int)mcol, 3.0 * fl,
                           by + 4.0 * w.N * w.Nv, nullptr, o.gemm_scratch, sb);
         }
