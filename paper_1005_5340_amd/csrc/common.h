@@ -28,7 +28,7 @@
 namespace chi0 {
 
 constexpr int TILE = 64;     // M/N tile of the dense GEMMs, E tile of the gathered ones
-constexpr int NB_MAX = 16;   // maximum orbitals per atom supported by the gathered GEMMs
+constexpr int NB_MAX = 16;   // maximum orbitals per atom (a vertex block's n_A n_B rows <= 256)
 constexpr int GEMM_VARIANTS = 6;   // tile shapes of the dense GEMM (see GemmTuner)
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
