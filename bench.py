@@ -658,7 +658,7 @@ def main():
         print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 3}))
         return
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {a.gpus} is not supported "
               "(the (frequency, drive) points would be sharded across GPUs with no exchange "
               "but the final gather of alpha; see the design notes).", file=sys.stderr)
         sys.exit(2)
