@@ -531,7 +531,7 @@ typedef struct chi0_tune_record {
     char    tile[16];     /* chosen variant, e.g. "64x128" */
     int32_t variant;      /* its index 0..5 */
     float   us[8];        /* timed launch of each variant in microseconds; 0 = not valid for the
-                             shape (or beyond the variants of this build) */
+                             shape (or beyond the library's variants) */
 } chi0_tune_record;
 
 int chi0_set_autotune(chi0_ctx *ctx, int32_t mode);
