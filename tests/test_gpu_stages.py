@@ -53,7 +53,10 @@ def _close(name, got, ref, tol=1e-12):
     return err < tol
 
 
-@pytest.mark.parametrize("name,nb", [("tiny3", 1), ("atoms12_orb9", 3), ("atoms8_orb13", 9)])
+# 2, 6, 18 and 40 real columns: the vertex kernels' one-, two- and four-block
+# column shapes, each with a ragged last block
+@pytest.mark.parametrize("name,nb", [("tiny3", 1), ("atoms12_orb9", 3), ("atoms8_orb13", 9),
+                                     ("atoms12_orb9", 20)])
 def test_every_stage(name, nb):
     import torch
     from paper_1005_5340_amd import chi0
