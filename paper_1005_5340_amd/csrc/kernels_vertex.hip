@@ -26,10 +26,10 @@ __device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c) {
 // output.  Each round issues the operand loads of KU k-steps before their
 // MFMAs, so a round costs about one memory latency and the longest block
 // (a diagonal block (A, A), which carries every product that involves atom
-// A) runs few rounds.  The three shapes below hold the same registers: with
-// few columns, fewer accumulators leave room for more loads in flight.
-// Every shape accumulates each output over k in the same order, so all of
-// them give bit-identical results.
+// A) runs few rounds.  The narrow shapes (VC = 1, 2) hold fewer
+// accumulators, which leaves registers for 8 k-steps' loads per round
+// instead of 4 at two waves per SIMD.  Every shape accumulates each output
+// over k in the same order, so all of them give bit-identical results.
 constexpr int VRB = 4;     // 16-row MFMA blocks per wave (rows <= 256 = NB_MAX^2)
 constexpr int PCH = 256;   // product ids staged in LDS per chunk
 
