@@ -562,6 +562,91 @@ def warm_experiment(a, s, ctx, drives, restart, tol):
     ctx.close()
 
 
+def bilanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx, ref_drive, tol):
+    """One step = the two-sided Lanczos solve of every (omega, drive) point (chi0_solve_bilanczos);
+    afterwards, untimed, the GMRES solve of the same points for comparison."""
+    import torch
+    npts = omegas.size * drives.shape[0]
+
+    def run():
+        return ctx.solve_bilanczos(omegas, s.eps, drives, tol=tol, max_steps=a.bl_max_steps)
+
+    print(f"[bench] two-sided lanczos {a.workload}: {npts} points, tol {tol:g}", file=sys.stderr, flush=True)
+    ks_all = {}
+    if not a.no_timing:
+        ctx.set_timing(True)
+        run()
+        ks_all = ctx.kernel_stats()
+        ctx.set_timing(False)
+    for _ in range(a.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        alpha, steps, status, rc = run()
+        print(f"[bench] step {i} done: steps mean {steps.mean():.0f} max {steps.max()}, rc {rc}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    acc = {"checked": False}
+    passing = npts
+    if ref is not None and np.all(np.isin(ref_idx, grid)):
+        diag = alpha[np.searchsorted(grid, ref_idx)]
+        rdiag = np.stack([ref[:, ref_drive[i], ref_drive[i]] for i in range(drives.shape[0])], 1)
+        err = np.stack([im_errors(diag[:, i], rdiag[:, i]) for i in range(drives.shape[0])], 1)
+        full = ref_idx.size == grid.size
+        passing = int((err <= 1e-6).sum()) if full else npts * float((err <= 1e-6).mean())
+        acc = {"checked": True, "max_im_rel_err": float(err.max()), "median_im_rel_err": float(np.median(err)),
+               "points_passing_1e-6": int((err <= 1e-6).sum()), "points_passing_1e-10": int((err <= 1e-10).sum()),
+               "points_checked": int(err.size)}
+    roof = None
+    if ks_all:
+        tot = sum(v["ms"] for v in ks_all.values())
+        dom = max(ks_all, key=lambda k: ks_all[k]["ms"])
+        rec = ks_all[dom]
+        bound = bound_of(dom)
+        peak, unit = PEAK[bound]
+        work = rec["bytes"] if bound == "hbm" else rec["flops"]
+        scale = 1e9 if bound == "hbm" else 1e12
+        roof = {"kernel": dom, "bound": "hbm" if bound == "hbm" else "mfma",
+                "achieved": work / (rec["ms"] * 1e-3) / scale, "peak": peak / scale, "unit": unit,
+                "frac": work / (rec["ms"] * 1e-3) / peak, "traffic": None,
+                "launches": rec["launches"], "mean_launch_us": 1e3 * rec["ms"] / rec["launches"],
+                "share_of_gpu_time": rec["ms"] / tot,
+                "note": "from an eager run with every kernel timed"}
+        for k, v in sorted(ks_all.items(), key=lambda kv: -kv[1]["ms"])[:8]:
+            print(f"[bench] {k:30s} {int(v['launches']):8d} {v['ms']:9.2f} {100 * v['ms'] / tot:6.1f}%",
+                  file=sys.stderr)
+    # the GMRES solve of the same points (one batch, unrestarted), untimed by the step clock
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ag, st, rcg = ctx.solve_response(omegas, s.eps, drives, restart=s.n_prod, tol=tol, batch=a.batch,
+                                     max_iter=a.max_iter)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    gdiag = np.stack([ag[:, i, i] for i in range(drives.shape[0])], 1)
+    out = {
+        "metric": "spectrum points/s at 1e-6 rel err in Im alpha vs FP64 oracle",
+        "value": passing / dt, "unit": "spectrum points/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": a.workload, "seed": a.seed, "method": "two-sided (biorthogonal) lanczos",
+                   "n_orb": s.n_orb, "n_occ": s.n_occ, "n_prod": s.n_prod, "n_omega": int(omegas.size),
+                   "drives": drive_letters, "eps": s.eps, "points": npts, "tol": tol,
+                   "max_steps": a.bl_max_steps, "omega_index": grid.tolist()},
+        "recursion_steps": {"mean": float(steps.mean()), "max": int(steps.max()),
+                            "per_point": steps.tolist()},
+        "status_counts": {str(k): int((status == k).sum()) for k in (0, 1, 2)},
+        "accuracy": acc, "roofline": roof,
+        "gmres_same_points": {"seconds": tg, "points_per_s": npts / tg,
+                              "iterations_mean": float(st["iterations"].mean()),
+                              "iterations_max": int(st["iterations"].max()),
+                              "max_rel_diff_vs_bilanczos": float(np.max(np.abs(gdiag - alpha) / np.abs(gdiag)))},
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -614,6 +699,10 @@ def main():
     ap.add_argument("--lanczos", action="store_true",
                     help="the spectrum from one Lanczos recursion per drive in transition space instead of "
                          "a GMRES solve per frequency (same workload, error measure and JSON line)")
+    ap.add_argument("--bilanczos", action="store_true",
+                    help="one two-sided (biorthogonal) Lanczos recursion per point instead of GMRES "
+                         "(chi0_solve_bilanczos), compared with the GMRES solve of the same points")
+    ap.add_argument("--bl-max-steps", type=int, default=20000, help="two-sided Lanczos: most steps per point")
     ap.add_argument("--no-lanczos", action="store_true",
                     help="skip the untimed comparison with the Lanczos route after the timed steps")
     ap.add_argument("--warm-prev", action="store_true",
@@ -711,6 +800,9 @@ def main():
     if a.lanczos:
         return lanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx,
                             ref_drive if ref is not None else None)
+    if a.bilanczos:
+        return bilanczos_mode(a, s, ctx, drives, drive_letters, omegas, grid, ref, ref_idx,
+                              ref_drive if ref is not None else None, tol)
     if a.spectrum_range:
         return spectrum_range(a, s, ctx, drives, ref, ref_idx, ref_drive if ref is not None else None)
     if a.warm_experiment:

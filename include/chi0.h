@@ -483,6 +483,39 @@ int chi0_lanczos_poles(int32_t k, const double *a, const double *b, double c_nor
                        double *resid);
 
 /*
+ * Polarizability by the two-sided (biorthogonal) Lanczos recursion on
+ * A = 1 - chi0(w) K: the Krylov method that the Sec. 4 introduction says the
+ * authors used before the solve of eq. sle, there to build a representation
+ * of A that is easy to invert within its Krylov subspace.  One recursion per
+ * (omega, drive) point, in the bilinear form x^T y: right start chi0 d, left
+ * start d, T_k complex symmetric tridiagonal, and
+ *     alpha_ii(w) = -beta_1^2 e_1^T T_k^-1 e_1     (beta_1^2 = d^T chi0 d).
+ * Each step applies A and A^T = 1 - K chi0 (two K products and one chi0 pass
+ * over two vectors per point) and keeps three vectors per side: no stored
+ * basis and no reorthogonalisation.  A point stops when the residual
+ * |chi0 d - A x_k| / |chi0 d| of x_k = V_k T_k^-1 beta_1 e_1 (evaluated from
+ * the recurrence, checked every 10 steps but per step) is <= tol, at a
+ * breakdown (s^T r exactly zero, or an invariant subspace: |r| <= 1e-13 |A v|;
+ * there is no look-ahead), or after max_steps.  Up to 64 points run at once.
+ *
+ *  omega      host [n_omega] (Ha); eps > 0 (Ha).
+ *  n_drive    1..3; drives host [n_drive][n_prod] real.
+ *  tol        > 0; max_steps >= 1 (the coefficients of max_steps steps per
+ *             point are held on the device: 40 bytes per step and point).
+ *  alpha      host [n_omega][n_drive] complex (interleaved), alpha_ii of each
+ *             point at its last step, written.
+ *  steps      host [n_omega][n_drive] steps taken, may be NULL.
+ *  status     host [n_omega][n_drive]: 0 converged, 1 max_steps reached,
+ *             2 breakdown before tol; may be NULL.
+ * Returns CHI0_OK, CHI0_NOT_CONVERGED (some point has status 1 or 2), or an
+ * error (CHI0_EINVAL, CHI0_ENONFINITE, CHI0_ENOSYS, CHI0_ENOMEM, CHI0_EHIP).
+ * Synchronous; uses the context's own stream.
+ */
+int chi0_solve_bilanczos(chi0_ctx *ctx, int32_t n_omega, const double *omega, double eps, int32_t n_drive,
+                         const double *drives, double tol, int32_t max_steps, double *alpha, int32_t *steps,
+                         int32_t *status);
+
+/*
  * Kernel timing (tracing).  When enabled, every kernel launch of the
  * library is bracketed by HIP events on the stream it runs on, and the
  * durations are accumulated per kernel name, together with the algorithmic

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchi0.so")
 SOURCES = ["chi0_api.hip", "kernels_gemm.hip", "kernels_vertex.hip", "kernels_krylov.hip",
-           "kernels_bf16.hip", "kernels_mlp.hip", "kernels_lanczos.hip"]
+           "kernels_bf16.hip", "kernels_mlp.hip", "kernels_lanczos.hip", "kernels_bilanczos.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -167,6 +167,9 @@ def lib():
     L.chi0_lanczos_spectrum.restype = C.c_int
     L.chi0_lanczos_poles.argtypes = [C.c_int32, _dp, _dp, C.c_double, _dp, _dp]
     L.chi0_lanczos_poles.restype = C.c_int
+    L.chi0_solve_bilanczos.argtypes = [C.c_void_p, C.c_int32, _dp, C.c_double, C.c_int32, _dp, C.c_double,
+                                       C.c_int32, _dp, _i32p, _i32p]
+    L.chi0_solve_bilanczos.restype = C.c_int
     _LIB = L
     return L
 
@@ -310,6 +313,25 @@ class Context:
                                         C.c_void_p(handle))
         self._check(rc)
         return out
+
+    def solve_bilanczos(self, omega, eps: float, V_ext, tol: float = 1e-10, max_steps: int = 20000):
+        """Two-sided Lanczos polarizability (chi0_solve_bilanczos).
+
+        Returns (alpha [n_omega, n_drive] complex (alpha_ii), steps [n_omega, n_drive],
+        status [n_omega, n_drive] (0 converged, 1 max_steps, 2 breakdown), rc) where rc is
+        0 or NOT_CONVERGED.
+        """
+        om = _f64(np.atleast_1d(omega))
+        D = _f64(np.atleast_2d(V_ext))
+        nd = D.shape[0]
+        alpha = np.zeros((om.size, nd, 2))
+        steps = np.zeros((om.size, nd), np.int32)
+        status = np.zeros((om.size, nd), np.int32)
+        rc = self._L.chi0_solve_bilanczos(self._h, int(om.size), _ptr(om), float(eps), int(nd), _ptr(D),
+                                          float(tol), int(max_steps), _ptr(alpha), _ptr(steps, _i32p),
+                                          _ptr(status, _i32p))
+        self._check(rc, allow_warning=True)
+        return alpha[..., 0] + 1j * alpha[..., 1], steps, status, rc
 
     def solve_response(self, omega, eps: float, V_ext, restart: int = 30, max_iter: int = 10000,
                        tol: float = 1e-10, batch: int = 1, precision: int = PREC_FP64,

@@ -2533,3 +2533,204 @@ extern "C" int chi0_lanczos_poles(int32_t k, const double *a, const double *b, d
     }
     return CHI0_OK;
 }
+
+// ============================================================ two-sided Lanczos
+// chi0_solve_bilanczos: one recursion per (omega, drive) point, up to kBlBatch
+// points at once.  Per step: K v, then chi0 over [K v, w] (two complex
+// columns per point, each point at its own frequency), then K chi0 w, then
+// the per-point vector work (kernels_bilanczos.hip).  The coefficients stay
+// on the device; every kBlCheck steps the host copies the new ones and runs,
+// per point, the LDL^T recurrences of T_k (no pivoting):
+//   d_1 = alpha_1,  d_j = alpha_j - beta_j^2 / d_{j-1},
+//   z_1 = 1,        z_j = -(beta_j / d_{j-1}) z_{j-1},
+//   P_k = beta_1^2 sum_{j <= k} z_j^2 / d_j          (= beta_1^2 e_1^T T_k^-1 e_1),
+//   e_k^T T_k^-1 beta_1 e_1 = beta_1 z_k / d_k,
+// so the residual |b - A x_k| = |beta_1 z_k / d_k| |r_k| costs O(1) per step.
+namespace {
+constexpr int kBlBatch = 64;   // points per batch: 128 complex chi0 columns per step
+constexpr int kBlCheck = 10;   // steps between host checks
+
+struct BlPoint {
+    double d_r = 0, d_i = 0, z_r = 1, z_i = 0, P_r = 0, P_i = 0;
+    int steps = 0, status = 1;
+    bool done = false;
+};
+}  // namespace
+
+extern "C" int chi0_solve_bilanczos(chi0_ctx *c, int32_t n_omega, const double *omega, double eps, int32_t n_drive,
+                                    const double *drives, double tol, int32_t max_steps, double *alpha,
+                                    int32_t *steps, int32_t *status) {
+    if (!c) return CHI0_EINVAL;
+    if (!c->has_system || c->device < 0) return fail(c, CHI0_ENOSYS, "no system on a device context");
+    if (n_omega < 0) return fail(c, CHI0_EINVAL, "n_omega < 0");
+    if (n_drive < 1 || n_drive > 3) return fail(c, CHI0_EINVAL, "n_drive must be 1..3");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(c, CHI0_EINVAL, "tol must be finite and > 0");
+    if (max_steps < 1) return fail(c, CHI0_EINVAL, "max_steps < 1");
+    if (n_omega == 0) return CHI0_OK;
+    if (!omega || !drives || !alpha) return fail(c, CHI0_EINVAL, "NULL pointer");
+    if (!all_finite(omega, n_omega)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
+    const int P = c->P, P_pad = c->P_pad;
+    if (!all_finite(drives, (int64_t)n_drive * P)) return fail(c, CHI0_ENONFINITE, "non-finite drive");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    Tracer *t = &c->tracer;
+    const int npt = n_omega * n_drive;
+    const int NB = std::min(npt, kBlBatch);
+    const int ms = max_steps;
+    OpWork &ow = c->op[0];
+    CHK(ensure_ws(c, ow, std::max(4 * NB, ow.nc_cap)));
+    {
+        size_t fr = 0, tot = 0;
+        HIPCHK(c, hipMemGetInfo(&fr, &tot));
+        const double need = 8.0 * ((double)P_pad * 2 * NB * 7 + (double)n_drive * P_pad + 5.0 * NB * (ms + 1));
+        if (need > 0.9 * (double)fr) return fail(c, CHI0_ENOMEM, "the recursion's workspace does not fit (max_steps?)");
+    }
+    DevScope ws;
+    double *D = nullptr, *V[2] = {}, *W[2] = {}, *KV = nullptr, *CW = nullptr, *KCW = nullptr, *om2 = nullptr;
+    double *al = nullptr, *be = nullptr, *rn = nullptr, *bn = nullptr;
+    int *flag = nullptr;
+    const int64_t vn = (int64_t)P_pad * 2 * NB;
+    CHK(dalloc(c, ws.buf, &D, (int64_t)n_drive * P_pad));
+    for (int i = 0; i < 2; ++i) {
+        CHK(dalloc(c, ws.buf, &V[i], vn));
+        CHK(dalloc(c, ws.buf, &W[i], vn));
+    }
+    CHK(dalloc(c, ws.buf, &KV, vn));
+    CHK(dalloc(c, ws.buf, &CW, vn));
+    CHK(dalloc(c, ws.buf, &KCW, vn));
+    CHK(dalloc(c, ws.buf, &om2, 2 * NB));
+    const int ldal = 2 * ms, ldbe = 2 * (ms + 1), ldrn = ms;
+    CHK(dalloc(c, ws.buf, &al, (int64_t)NB * ldal));
+    CHK(dalloc(c, ws.buf, &be, (int64_t)NB * ldbe));
+    CHK(dalloc(c, ws.buf, &rn, (int64_t)NB * ldrn));
+    CHK(dalloc(c, ws.buf, &bn, NB));
+    CHK(dalloc(c, ws.buf, &flag, NB));
+    {
+        std::vector<double> dh((size_t)n_drive * P_pad, 0.0);
+        for (int i = 0; i < n_drive; ++i)
+            std::copy(drives + (size_t)i * P, drives + (size_t)(i + 1) * P, dh.begin() + (size_t)i * P_pad);
+        HIPCHK(c, hipMemcpy(D, dh.data(), dh.size() * 8, hipMemcpyHostToDevice));
+    }
+    auto kprod = [&](const double *X, double *Y, int nc) {
+        if (nc <= 32)
+            launch_kmatvec_skinny(t, s, P_pad, c->K, X, Y, nc, (double)P);
+        else
+            launch_dgemm(t, s, "kernel_matmul", P_pad, nc, P_pad, P_pad, c->K, P_pad, X, nc, Y, nc,
+                         2.0 * P * (double)P * nc, 8.0 * ((double)P * P + 2.0 * P * nc), ow.gemm_scratch,
+                         ow.gemm_scratch_n, &c->tuner);
+    };
+    std::vector<double> omh(2 * NB), alh((size_t)NB * ldal), beh((size_t)NB * ldbe), rnh((size_t)NB * ldrn),
+        bnh(NB);
+    std::vector<int> flh(NB);
+    int rc = CHI0_OK;
+    for (int p0 = 0; p0 < npt; p0 += NB) {
+        const int np = std::min(NB, npt - p0);
+        const int nc = 2 * np;   // real columns of one vector per point
+        for (int q = 0; q < np; ++q) omh[q] = omh[np + q] = omega[(p0 + q) / n_drive];
+        HIPCHK(c, hipMemcpyAsync(om2, omh.data(), (size_t)2 * np * 8, hipMemcpyHostToDevice, s));
+        // b = chi0 d, then the start vectors
+        launch_bl_drives(s, P, P_pad, np, p0, n_drive, D, ow.Zin);
+        run_chi0(c, ow, s, np, eps, CHI0_PREC_FP64, om2, t, &c->tuner);
+        launch_bl_init(s, P, np, p0, n_drive, D, P_pad, ow.Yout, nc, V[0], W[0], V[1], W[1], nc, be, ldbe, bn, flag);
+        HIPCHK(c, hipMemcpyAsync(flh.data(), flag, (size_t)np * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(bnh.data(), bn, (size_t)np * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpy2DAsync(beh.data(), ldbe * 8, be, ldbe * 8, 16, np, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        HIPCHK(c, hipGetLastError());
+        std::vector<BlPoint> pt(np);
+        int active = 0;
+        for (int q = 0; q < np; ++q) {
+            if (flh[q] == -1) {   // zero right-hand side: x = 0; else d^T chi0 d = 0 before any step
+                pt[q].done = true;
+                pt[q].status = bnh[q] == 0.0 ? 0 : 2;
+            } else {
+                ++active;
+            }
+        }
+        int cur = 0, k0 = 0;
+        for (int k = 0; k < ms && active > 0; ++k) {
+            kprod(V[cur], KV, nc);
+            launch_bl_pack(s, P_pad, nc, KV, W[cur], ow.Zin);
+            run_chi0(c, ow, s, 2 * np, eps, CHI0_PREC_FP64, om2, t, &c->tuner);
+            launch_bl_unpack(s, P, P_pad, nc, ow.Yout, CW);
+            kprod(CW, KCW, nc);
+            launch_bl_step(s, np, P, k, ow.Yout, KCW, V[cur], W[cur], V[cur ^ 1], W[cur ^ 1], nc, al, ldal, be, ldbe,
+                           rn, ldrn, flag);
+            cur ^= 1;
+            if ((k + 1) % kBlCheck != 0 && k + 1 != ms) continue;
+            // the coefficients of steps k0..k
+            const int nk = k - k0 + 1;
+            HIPCHK(c, hipMemcpy2DAsync(alh.data() + 2 * k0, ldal * 8, al + 2 * k0, ldal * 8, (size_t)nk * 16, np,
+                                       hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpy2DAsync(beh.data() + 2 * (k0 + 1), ldbe * 8, be + 2 * (k0 + 1), ldbe * 8,
+                                       (size_t)nk * 16, np, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpy2DAsync(rnh.data() + k0, ldrn * 8, rn + k0, ldrn * 8, (size_t)nk * 8, np,
+                                       hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(flh.data(), flag, (size_t)np * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            HIPCHK(c, hipGetLastError());
+            bool newly = false;
+            for (int q = 0; q < np; ++q) {
+                BlPoint &p = pt[q];
+                if (p.done) continue;
+                const double b1r = beh[(size_t)q * ldbe], b1i = beh[(size_t)q * ldbe + 1];
+                const double b1sr = b1r * b1r - b1i * b1i, b1si = 2.0 * b1r * b1i;   // beta_1^2
+                const int brk = flh[q] >= 2 ? flh[q] - 2 : -1;                        // breakdown after this step
+                for (int j = k0; j <= k && !p.done; ++j) {
+                    const double ar = alh[(size_t)q * ldal + 2 * j], ai = alh[(size_t)q * ldal + 2 * j + 1];
+                    double dr, di, zr, zi;
+                    if (j == 0) {
+                        dr = ar, di = ai, zr = 1.0, zi = 0.0;
+                    } else {
+                        const double br = beh[(size_t)q * ldbe + 2 * j], bi = beh[(size_t)q * ldbe + 2 * j + 1];
+                        const double den = p.d_r * p.d_r + p.d_i * p.d_i;
+                        const double lr = (br * p.d_r + bi * p.d_i) / den, li = (bi * p.d_r - br * p.d_i) / den;
+                        dr = ar - (br * lr - bi * li);
+                        di = ai - (br * li + bi * lr);
+                        zr = -(lr * p.z_r - li * p.z_i);
+                        zi = -(lr * p.z_i + li * p.z_r);
+                    }
+                    // P += beta_1^2 z^2 / d
+                    const double z2r = zr * zr - zi * zi, z2i = 2.0 * zr * zi;
+                    const double dd = dr * dr + di * di;
+                    const double qr = (z2r * dr + z2i * di) / dd, qi = (z2i * dr - z2r * di) / dd;
+                    p.P_r += b1sr * qr - b1si * qi;
+                    p.P_i += b1sr * qi + b1si * qr;
+                    p.d_r = dr, p.d_i = di, p.z_r = zr, p.z_i = zi;
+                    p.steps = j + 1;
+                    // |beta_1 z / d| |r| / |b|
+                    const double res = std::sqrt((b1r * b1r + b1i * b1i) * (zr * zr + zi * zi) / dd) *
+                                       rnh[(size_t)q * ldrn + j] / bnh[q];
+                    const bool bad = !(dd > 0.0) || !std::isfinite(p.P_r) || !std::isfinite(p.P_i);
+                    if (!bad && res <= tol) {
+                        p.done = true, p.status = 0;
+                    } else if (bad || j == brk) {
+                        p.done = true, p.status = 2;
+                    }
+                }
+                if (p.done) {
+                    newly = true;
+                    --active;
+                    if (flh[q] == 0) flh[q] = 1;
+                }
+            }
+            if (newly && active > 0)
+                HIPCHK(c, hipMemcpyAsync(flag, flh.data(), (size_t)np * sizeof(int), hipMemcpyHostToDevice, s));
+            k0 = k + 1;
+        }
+        for (int q = 0; q < np; ++q) {
+            const BlPoint &p = pt[q];
+            const int64_t g = p0 + q;
+            alpha[2 * g] = -p.P_r;
+            alpha[2 * g + 1] = -p.P_i;
+            if (steps) steps[g] = p.steps;
+            const int st_q = p.done ? p.status : 1;
+            if (status) status[g] = st_q;
+            if (st_q != 0) rc = CHI0_NOT_CONVERGED;
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipGetLastError());
+    return rc;
+}

@@ -320,6 +320,17 @@ void launch_lz_solution_out(hipStream_t s, const double *Yb, int nc, int nw, int
 void launch_lz_cfrac(hipStream_t s, const double *a, const double *b, int nc, int kuse, const int *len,
                      const double *cn2, const double *omega, int n_omega, double eps, double *out);
 
+// two-sided Lanczos (chi0_solve_bilanczos): per-point vector work of the recursion
+void launch_bl_drives(hipStream_t s, int P, int P_pad, int np, int p0, int n_drive, const double *D, double *Zin);
+void launch_bl_init(hipStream_t s, int P, int npts, int p0, int n_drive, const double *D, int P_pad,
+                    const double *Yb, int ldb, double *V1, double *W1, double *V0, double *W0, int ld,
+                    double *beta, int ldbeta, double *bnorm, int *flag);
+void launch_bl_pack(hipStream_t s, int P_pad, int nc, const double *KV, const double *W1, double *Zin);
+void launch_bl_unpack(hipStream_t s, int P, int P_pad, int nc, const double *Yout, double *CW);
+void launch_bl_step(hipStream_t s, int npts, int P, int k, const double *Yout, const double *KCW,
+                    const double *V1, const double *W1, double *V0, double *W0, int ld, double *alpha,
+                    int ldalpha, double *beta, int ldbeta, double *rnorm, int ldrn, int *flag);
+
 // apply: caller rows [r][P] complex <-> operator columns [P_pad][ncp]
 void launch_rows_to_cols(Tracer *t, hipStream_t s, const double *z, int nb, int P,
                          double *Zin, int ncp);

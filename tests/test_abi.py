@@ -142,3 +142,13 @@ def test_lanczos_defaults_and_host_context(L):
             ctx.lanczos_spectrum(res, [0.5], 0.01)
         assert e.value.code == -2
     assert L.chi0_lanczos(None, 1, None, None, None, None, None, None) == -1
+
+
+def test_bilanczos_host_context(L):
+    s = synth.make_system("atoms4_orb4", seed=0)
+    with chi0.Context(-1) as ctx:
+        ctx.set_system_from(s)
+        with pytest.raises(chi0.Chi0Error) as e:      # host-only: no device to run on
+            ctx.solve_bilanczos([0.5], 0.01, s.drives("z"))
+        assert e.value.code == -2
+    assert L.chi0_solve_bilanczos(None, 1, None, 0.01, 1, None, 1e-10, 10, None, None, None) == -1
