@@ -493,8 +493,9 @@ int chi0_lanczos_poles(int32_t k, const double *a, const double *b, double c_nor
  * Each step applies A and A^T = 1 - K chi0 (two K products and one chi0 pass
  * over two vectors per point) and keeps three vectors per side: no stored
  * basis and no reorthogonalisation.  A point stops when the residual
- * |chi0 d - A x_k| / |chi0 d| of x_k = V_k T_k^-1 beta_1 e_1 (evaluated from
- * the recurrence, checked every 10 steps but per step) is <= tol, at a
+ * |chi0 d - A x_k| / |chi0 d| of x_k = V_k T_k^-1 beta_1 e_1 (evaluated for
+ * every step from the recurrence; the host reads the coefficients back every
+ * 10 steps, so a point may run up to 9 steps past its answer) is <= tol, at a
  * breakdown (s^T r exactly zero, or an invariant subspace: |r| <= 1e-13 |A v|;
  * there is no look-ahead), or after max_steps.  Up to 64 points run at once.
  *
