@@ -2567,6 +2567,7 @@ extern "C" int chi0_solve_bilanczos(chi0_ctx *c, int32_t n_omega, const double *
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(c, CHI0_EINVAL, "eps must be finite and > 0");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(c, CHI0_EINVAL, "tol must be finite and > 0");
     if (max_steps < 1) return fail(c, CHI0_EINVAL, "max_steps < 1");
+    if ((int64_t)n_omega * n_drive > INT32_MAX) return fail(c, CHI0_EINVAL, "too many points");
     if (n_omega == 0) return CHI0_OK;
     if (!omega || !drives || !alpha) return fail(c, CHI0_EINVAL, "NULL pointer");
     if (!all_finite(omega, n_omega)) return fail(c, CHI0_ENONFINITE, "non-finite omega");
