@@ -2624,6 +2624,18 @@ extern "C" int chi0_solve_bilanczos(chi0_ctx *c, int32_t n_omega, const double *
     std::vector<double> omh(2 * NB), alh((size_t)NB * ldal), beh((size_t)NB * ldbe), rnh((size_t)NB * ldrn),
         bnh(NB);
     std::vector<int> flh(NB);
+    // pinned staging of the device-to-host copies: the new coefficients of a check
+    // window (at most kBlCheck steps), the start values and the flags
+    struct Pinned {
+        void *p = nullptr;
+        ~Pinned() {
+            if (p) (void)hipHostFree(p);
+        }
+    } pin;
+    const size_t n_al = (size_t)NB * 2 * kBlCheck, n_be = (size_t)NB * 2 * kBlCheck, n_rn = (size_t)NB * kBlCheck;
+    HIPCHK(c, hipHostMalloc(&pin.p, (n_al + n_be + n_rn + 2 * (size_t)NB) * 8, 0));
+    double *s_al = static_cast<double *>(pin.p), *s_be = s_al + n_al, *s_rn = s_be + n_be, *s_bn = s_rn + n_rn;
+    int *s_fl = reinterpret_cast<int *>(s_bn + NB);
     int rc = CHI0_OK;
     for (int p0 = 0; p0 < npt; p0 += NB) {
         const int np = std::min(NB, npt - p0);
@@ -2634,11 +2646,17 @@ extern "C" int chi0_solve_bilanczos(chi0_ctx *c, int32_t n_omega, const double *
         launch_bl_drives(s, P, P_pad, np, p0, n_drive, D, ow.Zin);
         run_chi0(c, ow, s, np, eps, CHI0_PREC_FP64, om2, t, &c->tuner);
         launch_bl_init(s, P, np, p0, n_drive, D, P_pad, ow.Yout, nc, V[0], W[0], V[1], W[1], nc, be, ldbe, bn, flag);
-        HIPCHK(c, hipMemcpyAsync(flh.data(), flag, (size_t)np * sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpyAsync(bnh.data(), bn, (size_t)np * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpy2DAsync(beh.data(), ldbe * 8, be, ldbe * 8, 16, np, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(s_fl, flag, (size_t)np * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(s_bn, bn, (size_t)np * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpy2DAsync(s_be, 16, be, ldbe * 8, 16, np, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
         HIPCHK(c, hipGetLastError());
+        for (int q = 0; q < np; ++q) {
+            flh[q] = s_fl[q];
+            bnh[q] = s_bn[q];
+            beh[(size_t)q * ldbe] = s_be[2 * q];
+            beh[(size_t)q * ldbe + 1] = s_be[2 * q + 1];
+        }
         std::vector<BlPoint> pt(np);
         int active = 0;
         for (int q = 0; q < np; ++q) {
@@ -2662,15 +2680,22 @@ extern "C" int chi0_solve_bilanczos(chi0_ctx *c, int32_t n_omega, const double *
             if ((k + 1) % kBlCheck != 0 && k + 1 != ms) continue;
             // the coefficients of steps k0..k
             const int nk = k - k0 + 1;
-            HIPCHK(c, hipMemcpy2DAsync(alh.data() + 2 * k0, ldal * 8, al + 2 * k0, ldal * 8, (size_t)nk * 16, np,
+            HIPCHK(c, hipMemcpy2DAsync(s_al, (size_t)nk * 16, al + 2 * k0, ldal * 8, (size_t)nk * 16, np,
                                        hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipMemcpy2DAsync(beh.data() + 2 * (k0 + 1), ldbe * 8, be + 2 * (k0 + 1), ldbe * 8,
-                                       (size_t)nk * 16, np, hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipMemcpy2DAsync(rnh.data() + k0, ldrn * 8, rn + k0, ldrn * 8, (size_t)nk * 8, np,
+            HIPCHK(c, hipMemcpy2DAsync(s_be, (size_t)nk * 16, be + 2 * (k0 + 1), ldbe * 8, (size_t)nk * 16, np,
                                        hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipMemcpyAsync(flh.data(), flag, (size_t)np * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpy2DAsync(s_rn, (size_t)nk * 8, rn + k0, ldrn * 8, (size_t)nk * 8, np,
+                                       hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(s_fl, flag, (size_t)np * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(c, hipStreamSynchronize(s));
             HIPCHK(c, hipGetLastError());
+            for (int q = 0; q < np; ++q) {
+                std::copy(s_al + (size_t)q * 2 * nk, s_al + (size_t)(q + 1) * 2 * nk, alh.begin() + (size_t)q * ldal + 2 * k0);
+                std::copy(s_be + (size_t)q * 2 * nk, s_be + (size_t)(q + 1) * 2 * nk,
+                          beh.begin() + (size_t)q * ldbe + 2 * (k0 + 1));
+                std::copy(s_rn + (size_t)q * nk, s_rn + (size_t)(q + 1) * nk, rnh.begin() + (size_t)q * ldrn + k0);
+                flh[q] = s_fl[q];
+            }
             bool newly = false;
             for (int q = 0; q < np; ++q) {
                 BlPoint &p = pt[q];
@@ -2716,8 +2741,10 @@ extern "C" int chi0_solve_bilanczos(chi0_ctx *c, int32_t n_omega, const double *
                     if (flh[q] == 0) flh[q] = 1;
                 }
             }
-            if (newly && active > 0)
-                HIPCHK(c, hipMemcpyAsync(flag, flh.data(), (size_t)np * sizeof(int), hipMemcpyHostToDevice, s));
+            if (newly && active > 0) {
+                std::copy(flh.begin(), flh.begin() + np, s_fl);
+                HIPCHK(c, hipMemcpyAsync(flag, s_fl, (size_t)np * sizeof(int), hipMemcpyHostToDevice, s));
+            }
             k0 = k + 1;
         }
         for (int q = 0; q < np; ++q) {
